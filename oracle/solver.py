@@ -1,0 +1,161 @@
+"""Plain FP64 spectral Poisson solve, projection and extension (test oracle).
+
+The paper (section 3.2) solves the constant-coefficient second-order
+finite-difference Poisson equation with an FFT-based direct method and
+(section 3.6) re-uses it for the Stefan-flow potential.  A direct method
+reaches exactly the solution of the discrete problem, so the oracle is that
+definition computed in the most transparent way available:
+
+1. x and y: library transforms that diagonalise the 1-D second difference --
+   a complex DFT for periodic directions (numpy.fft.fft) and an orthonormal
+   DCT-II for wall directions with zero normal gradient (scipy.fft.dct).
+   Their eigenvalues are -(4/h^2) sin^2(pi m / n) and -(4/h^2) sin^2(pi m / (2n)).
+2. z: the tridiagonal z operator A = W^-1 S (S symmetric, W = diag(dzf)) is
+   diagonalised by the generalised symmetric eigenproblem S v = mu W v
+   (scipy.linalg.eigh), so (A + lambda I)^-1 = V diag(1/(mu+lambda)) V^T W.
+   No tridiagonal sweep is used anywhere in the oracle.
+3. The single zero eigenvalue (the constant mode, reached only on the
+   (kx, ky) = (0, 0) line) is dropped: this is the W-weighted pseudo-inverse.
+   The volume-weighted mean is also subtracted explicitly from the
+   right-hand side before, and from the solution after, so that a large
+   constant offset cannot leak through the numerically computed null vector.
+4. Inverse transforms.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+import scipy.linalg as sla
+
+from .grid import Grid
+from .stencils import grad, div, face_density
+
+
+def eigenvalues_1d(n: int, h: float, letter: str) -> np.ndarray:
+    """Eigenvalues of the 1-D second difference in the library transform's order."""
+    m = np.arange(n, dtype=np.float64)
+    if letter == "P":
+        return -(4.0 / (h * h)) * np.sin(np.pi * m / n) ** 2
+    return -(4.0 / (h * h)) * np.sin(np.pi * m / (2.0 * n)) ** 2
+
+
+def z_operator_dense(g: Grid):
+    """S (symmetric) and W = diag(dzf) with A_z = W^-1 S the z second difference.
+
+    Row k of A_z: [(p[k+1]-p[k]) / dzc[k] - (p[k]-p[k-1]) / dzc[k-1]] / dzf[k],
+    with zero flux through walls, or wrapped couplings when z is periodic.
+    """
+    nz = g.nz
+    S = np.zeros((nz, nz))
+    for k in range(nz - 1):
+        c = 1.0 / g.dzc[k]
+        S[k, k + 1] += c
+        S[k + 1, k] += c
+        S[k, k] -= c
+        S[k + 1, k + 1] -= c
+    if g.bc[2] == "P":
+        c = 1.0 / g.dzc[nz - 1]
+        S[nz - 1, 0] += c
+        S[0, nz - 1] += c
+        S[nz - 1, nz - 1] -= c
+        S[0, 0] -= c
+    return S, np.diag(g.dzf)
+
+
+def _fwd(a, axis, letter):
+    if letter == "P":
+        return np.fft.fft(a, axis=axis)
+    return sfft.dct(a, type=2, norm="ortho", axis=axis)
+
+
+def _inv(a, axis, letter):
+    if letter == "P":
+        return np.fft.ifft(a, axis=axis)
+    return sfft.idct(a, type=2, norm="ortho", axis=axis)
+
+
+def solve(f, g: Grid, return_mean: bool = False):
+    """p with L_h p = f - mean_W(f) and sum(dV p) = 0 (FP64, any bc in P/N)."""
+    f = np.asarray(f, dtype=np.float64)
+    if f.shape != g.shape:
+        raise ValueError(f"rhs shape {f.shape} != grid {g.shape}")
+    # the definition: right-hand side minus its volume-weighted mean
+    fbar = g.weighted_mean(f)
+    F = (f - fbar).astype(np.complex128)
+    F = _fwd(F, 2, g.bc[0])
+    F = _fwd(F, 1, g.bc[1])
+    lam = (eigenvalues_1d(g.ny, g.dy, g.bc[1])[:, None]
+           + eigenvalues_1d(g.nx, g.dx, g.bc[0])[None, :]).reshape(-1)
+
+    S, W = z_operator_dense(g)
+    mu, V = sla.eigh(S, W)
+    null = int(np.argmin(np.abs(mu)))
+    # the constant mode is the only (numerically) zero eigenvalue
+    rest = np.delete(np.abs(mu), null)
+    if rest.size and not np.abs(mu[null]) < 1e-6 * rest.min():
+        raise RuntimeError("z operator has no isolated null mode")
+
+    B = F.reshape(g.nz, -1)
+    C = V.T @ (g.dzf[:, None] * B)
+    den = mu[:, None] + lam[None, :]
+    inv = np.zeros_like(den)
+    nonzero = np.ones_like(den, dtype=bool)
+    nonzero[null, 0] = False  # line (0, 0): lam == 0 exactly
+    inv[nonzero] = 1.0 / den[nonzero]
+    P = (V @ (C * inv)).reshape(g.shape)
+
+    P = _inv(P, 1, g.bc[1])
+    P = _inv(P, 2, g.bc[0])
+    p = P.real.copy()
+    # the gauge: zero volume-weighted mean (removes only round-off here)
+    p -= g.weighted_mean(p)
+    if return_mean:
+        return p, fbar
+    return p
+
+
+def assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
+    """Right-hand side b of L_h p = b (section 3.2, pressure equation x rho0).
+
+    b = rho0 D[(1/rho0 - 1/rho_f) G p_hat] + (rho0/dt) (D u* - s), with
+    s = mdot (1/rho2 - 1/rho1) delta_Gamma the phase-change source.
+    """
+    gx, gy, gz = grad(phat, g)
+    rfx, rfy, rfz = face_density(rho, g)
+    cx = (1.0 / rho0 - 1.0 / rfx) * gx
+    cy = (1.0 / rho0 - 1.0 / rfy) * gy
+    cz = (1.0 / rho0 - 1.0 / rfz) * gz
+    return rho0 * div(cx, cy, cz, g) + (rho0 / dt) * (div(ustar, vstar, wstar, g) - src)
+
+
+def project(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
+    """Pressure-split projection step (section 3.2).
+
+    Returns (u, v, w, p): p solves L_h p = b (assemble_pressure_rhs) and
+    u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ].
+    """
+    b = assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g)
+    p = solve(b, g)
+    gpx, gpy, gpz = grad(p, g)
+    ghx, ghy, ghz = grad(phat, g)
+    rfx, rfy, rfz = face_density(rho, g)
+    u = ustar - dt * (gpx / rho0 + (1.0 / rfx - 1.0 / rho0) * ghx)
+    v = vstar - dt * (gpy / rho0 + (1.0 / rfy - 1.0 / rho0) * ghy)
+    w = wstar - dt * (gpz / rho0 + (1.0 / rfz - 1.0 / rho0) * ghz)
+    return u, v, w, p
+
+
+def extend(u, v, w, src, g: Grid, q=None):
+    """Liquid-velocity extension and interface velocity (section 3.6).
+
+    phi solves L_h phi = s (the Stefan potential, s = mdot (1/rho2 - 1/rho1)|grad C|),
+    u_1^e = u - G phi and, when q = (mdot/rho1) n on faces is given,
+    u_Gamma = u_1^e - q.  Returns (ue, ve, we, ug, vg, wg, phi); the u_Gamma
+    entries are None without q.
+    """
+    phi = solve(src, g)
+    gx, gy, gz = grad(phi, g)
+    ue, ve, we = u - gx, v - gy, w - gz
+    if q is None:
+        return ue, ve, we, None, None, None, phi
+    return ue, ve, we, ue - q[0], ve - q[1], we - q[2], phi
