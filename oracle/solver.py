@@ -20,6 +20,13 @@ definition computed in the most transparent way available:
    right-hand side before, and from the solution after, so that a large
    constant offset cannot leak through the numerically computed null vector.
 4. Inverse transforms.
+5. One step of iterative refinement: the residual of the discrete equation,
+   f - mean_W(f) - L_h p, is evaluated in extended precision (numpy
+   longdouble) and its solution added.  The eigenvector route alone loses
+   accuracy on long, strongly stretched z lines (relative errors up to ~1e-11
+   at nz = 600-1024, where the condition number of the z operator is ~1e5-1e6);
+   one refinement step brings it to the accuracy of the discrete solution
+   (a second step changes it by ~1e-17).
 """
 from __future__ import annotations
 
@@ -28,7 +35,7 @@ import scipy.fft as sfft
 import scipy.linalg as sla
 
 from .grid import Grid
-from .stencils import grad, div, face_density
+from .stencils import grad, div, lap, face_density
 
 
 def eigenvalues_1d(n: int, h: float, letter: str) -> np.ndarray:
@@ -74,14 +81,9 @@ def _inv(a, axis, letter):
     return sfft.idct(a, type=2, norm="ortho", axis=axis)
 
 
-def solve(f, g: Grid, return_mean: bool = False):
-    """p with L_h p = f - mean_W(f) and sum(dV p) = 0 (FP64, any bc in P/N)."""
-    f = np.asarray(f, dtype=np.float64)
-    if f.shape != g.shape:
-        raise ValueError(f"rhs shape {f.shape} != grid {g.shape}")
-    # the definition: right-hand side minus its volume-weighted mean
-    fbar = g.weighted_mean(f)
-    F = (f - fbar).astype(np.complex128)
+def _spectral(fc, g: Grid):
+    """Eigen-decomposition solve of L_h p = fc for a compatible fc (steps 1-4)."""
+    F = fc.astype(np.complex128)
     F = _fwd(F, 2, g.bc[0])
     F = _fwd(F, 1, g.bc[1])
     lam = (eigenvalues_1d(g.ny, g.dy, g.bc[1])[:, None]
@@ -106,7 +108,27 @@ def solve(f, g: Grid, return_mean: bool = False):
 
     P = _inv(P, 1, g.bc[1])
     P = _inv(P, 2, g.bc[0])
-    p = P.real.copy()
+    return P.real.copy()
+
+
+def _lap_extended(p, g: Grid):
+    """L_h p evaluated in numpy longdouble (the same stencil, wider arithmetic)."""
+    return lap(np.asarray(p, dtype=np.longdouble), g)
+
+
+def solve(f, g: Grid, return_mean: bool = False):
+    """p with L_h p = f - mean_W(f) and sum(dV p) = 0 (FP64, any bc in P/N)."""
+    f = np.asarray(f, dtype=np.float64)
+    if f.shape != g.shape:
+        raise ValueError(f"rhs shape {f.shape} != grid {g.shape}")
+    # the definition: right-hand side minus its volume-weighted mean
+    fbar = g.weighted_mean(f)
+    fc = f - fbar
+    p = _spectral(fc, g)
+    # step 5: one refinement step with an extended-precision residual
+    r = (fc.astype(np.longdouble) - _lap_extended(p, g)).astype(np.float64)
+    r -= g.weighted_mean(r)
+    p = p + _spectral(r, g)
     # the gauge: zero volume-weighted mean (removes only round-off here)
     p -= g.weighted_mean(p)
     if return_mean:

@@ -191,6 +191,45 @@ def test_second_order_convergence():
 # ----------------------------------------------------------------------------
 # library special cases
 # ----------------------------------------------------------------------------
+def ld_pinned_thomas(fz, dzf, periodic):
+    """Textbook Thomas sweep in numpy longdouble on the pinned 1-D problem
+    (p0 = 0, rows 1..nz-1, then the weighted mean removed)."""
+    L = np.longdouble
+    nz = len(fz)
+    dzf_l = dzf.astype(L)
+    fc = fz.astype(L) - (fz.astype(L) * dzf_l).sum() / dzf_l.sum()
+    dzc = (dzf_l + np.roll(dzf_l, -1)) / 2
+    lo = np.zeros(nz, L); up = np.zeros(nz, L)
+    for k in range(nz):
+        if k + 1 < nz or periodic:
+            up[k] = 1 / (dzf_l[k] * dzc[k])
+        if k > 0 or periodic:
+            lo[k] = 1 / (dzf_l[k] * dzc[k - 1])
+    di = -(lo + up)
+    cp = np.zeros(nz, L); dp = np.zeros(nz, L); x = np.zeros(nz, L)
+    for k in range(1, nz):
+        den = di[k] - (lo[k] * cp[k - 1] if k > 1 else 0)
+        cp[k] = up[k] / den
+        dp[k] = (fc[k] - (lo[k] * dp[k - 1] if k > 1 else 0)) / den
+    x[nz - 1] = dp[nz - 1]
+    for k in range(nz - 2, 0, -1):
+        x[k] = dp[k] - cp[k] * x[k + 1]
+    x -= (x * dzf_l).sum() / dzf_l.sum()
+    return x.astype(np.float64)
+
+
+@pytest.mark.parametrize("zbc", ["N", "P"])
+@pytest.mark.parametrize("nz", [600, 1024])
+def test_z_only_rhs_long_lines(zbc, nz):
+    """Long, ill-conditioned z lines against an extended-precision sweep."""
+    dzf = vofsynth.stretched_dz(nz, 1.0, 1.5) if zbc == "N" else np.full(nz, 1.0 / nz)
+    g = oracle.Grid(4, 4, nz, 0.25, 0.25, dzf, "PP" + zbc)
+    fz = np.random.default_rng(nz).standard_normal(nz)
+    p = oracle.solve(np.broadcast_to(fz[:, None, None], g.shape).copy(), g)
+    ref = ld_pinned_thomas(fz, dzf, zbc == "P")
+    assert np.abs(p[:, 0, 0] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("zbc", ["N", "P"])
 def test_z_only_rhs_solve_banded(zbc):
     nx, ny, nz = 4, 4, 40
