@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark of the Poisson / projection / extension hot path on one MI355X.
+
+One step = one time step of the path: the pressure projection (right-hand
+side assembly, Poisson solve, velocity correction) followed by the
+liquid-velocity extension (Poisson solve of the Stefan source, extension and
+interface velocity), on the 256^3 grid (periodic x/y, walls in z, uniform),
+FP64.  value = Poisson-solve throughput including the stencils around each
+solve: 2 * nx*ny*nz / (time per step), in Mpts/s.
+
+Also reported on the same line: the bare FP64 and mixed-precision solve
+rates at the same size (mixed: FP32 chain plus FP64 defect correction, with
+its relative L2 distance to the FP64 result), the per-kernel times measured
+with HIP events over the timed steps, the roofline fraction of the dominant
+kernel and the FP64 CPU oracle timed on the host on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--workload ppn256]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpts/s per Poisson solve at 256^3 (FP64 vs mixed) + %HBM peak; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per launch, in units of N = nx*ny*nz FP64 values of 8 B:
+# every transform / z pass reads and writes one field once; the stencils read
+# their inputs and write their outputs once each.
+ALG_BYTES_PER_POINT = {
+    "x_forward": 16, "y_forward": 16, "z_solve": 16, "y_inverse": 16, "x_inverse": 16,
+    "x_forward_f32": 12, "y_forward_f32": 8, "z_solve_f32": 8, "y_inverse_f32": 8,
+    "x_inverse_f32": 12,          # FP32 in, FP64 out (accumulate: +8)
+    "residual": 24,               # f, p in; r out
+    "rhs_assembly": 56,           # u*, v*, w*, p_hat, rho, s in; b out
+    "correction": 72,             # u*, v*, w*, p, p_hat, rho in; u, v, w out
+    "extension": 104,             # u, v, w, phi, qx, qy, qz in; ue, ve, we, ug, vg, wg out
+}
+KERNEL_SOURCES = {
+    "x_forward": "transforms.hip", "y_forward": "transforms.hip", "y_inverse": "transforms.hip",
+    "x_inverse": "transforms.hip", "z_solve": "zsolve.hip", "rhs_assembly": "stencils.hip",
+    "correction": "stencils.hip", "extension": "stencils.hip",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ppn256")
+    ap.add_argument("--solve-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="ppn256",
+                    help="workload the CPU oracle is timed on (bounded sample)")
+    return ap.parse_args()
+
+
+def source_sha(name):
+    path = os.path.join(ROOT, "paper_1907_00890_amd", "csrc", name)
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 PMC counters (committed
+    summary), or None if absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(workload, {}).get(kernel)
+    if not rec or rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_inputs(cfg, torch, dev):
+    import numpy as np
+
+    import vofsynth
+    g = cfg
+    dzf = cfg.dzf()
+    us, vs, ws = vofsynth.random_faces(cfg.shape, 100, cfg.bc)
+    C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, dzf, seed=2)
+    rho1, rho2 = 1000.0, 1.0
+    rho = rho1 * C + rho2 * (1.0 - C)
+    mag, _ = vofsynth.grad_mag_central(C, g.dx, g.dy, dzf, cfg.bc)
+    s = 1e-2 * mag
+    mdot = 1e-2 / (1.0 / rho2 - 1.0 / rho1)
+    q = vofsynth.interface_normal_faces(C, g.dx, g.dy, dzf, cfg.bc, mdot / rho1)
+    phat = vofsynth.gaussian_field(cfg.shape, 101)
+    f = vofsynth.remove_weighted_mean(vofsynth.gaussian_field(cfg.shape, 200), dzf)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    return dict(u=T(us), v=T(vs), w=T(ws), rho=T(rho), s=T(s), phat=T(phat),
+                qx=T(q[0]), qy=T(q[1]), qz=T(q[2]), f=T(f), rho0=min(rho1, rho2), dt=1.0)
+
+
+def cpu_baseline(sample_name):
+    """Time the FP64 oracle's project + extend step on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    import vofsynth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    cfg = vofsynth.config(sample_name)
+    g = oracle.Grid.from_config(cfg)
+    dzf = cfg.dzf()
+    us, vs, ws = vofsynth.random_faces(cfg.shape, 100, cfg.bc)
+    C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, dzf, seed=2)
+    rho = 1000.0 * C + (1.0 - C)
+    s = 1e-2 * vofsynth.grad_mag_central(C, g.dx, g.dy, dzf, cfg.bc)[0]
+    q = vofsynth.interface_normal_faces(C, g.dx, g.dy, dzf, cfg.bc, 1e-5)
+    phat = vofsynth.gaussian_field(cfg.shape, 101)
+    t0 = time.perf_counter()
+    u, v, w, p = oracle.project(us, vs, ws, phat, rho, 1.0, s, 1.0, g)
+    oracle.extend(u, v, w, s, g, q=q)
+    t = time.perf_counter() - t0
+    return {"value": round(2 * cfg.npts / t / 1e6, 3), "unit": "Mpts/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"one project + extend step of the same recipe on {cfg.nx}x{cfg.ny}x{cfg.nz} "
+                      f"{cfg.bc} (FP64 numpy/scipy oracle, {t:.1f} s)",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = vofsynth.config(args.workload)
+    n = cfg.npts
+    X = make_inputs(cfg, torch, dev)
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc)
+    p = torch.empty(cfg.shape, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(p)
+    ue, ve, we = torch.empty_like(p), torch.empty_like(p), torch.empty_like(p)
+    ug, vg, wg = torch.empty_like(p), torch.empty_like(p), torch.empty_like(p)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.project(X["u"], X["v"], X["w"], X["phat"], X["rho"], X["rho0"], X["s"], X["dt"], p)
+        plan.extend(X["u"], X["v"], X["w"], X["s"], q=(X["qx"], X["qy"], X["qz"]),
+                    out=(ue, ve, we), gamma=(ug, vg, wg), phi=phi)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.kernel_times()
+    plan.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = e0.elapsed_time(e1)
+    ktimes = plan.kernel_times()
+    plan.set_profiling(False)
+    ms_step = ms_total / args.steps
+    value = 2 * n / (ms_step * 1e-3) / 1e6
+
+    # bare solves at the same size: FP64 and mixed (FP32 chain + 1 FP64 correction)
+    f = X["f"]
+    out64 = torch.empty_like(f)
+    for _ in range(3):
+        plan.solve(f, out64)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.solve_reps):
+        plan.solve(f, out64)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms64 = a.elapsed_time(b) / args.solve_reps
+    mixed = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc, precision="mixed")
+    mixed.set_mixed(1)
+    out32 = torch.empty_like(f)
+    for _ in range(3):
+        mixed.solve(f, out32)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(args.solve_reps):
+        mixed.solve(f, out32)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms32 = a.elapsed_time(b) / args.solve_reps
+    rel_mixed = (torch.linalg.vector_norm(out32 - out64) / torch.linalg.vector_norm(out64)).item()
+
+    # roofline of the dominant kernel (largest total time over the timed steps)
+    kernels = {}
+    for name, (ms, cnt) in ktimes.items():
+        per = ms / cnt
+        alg = ALG_BYTES_PER_POINT.get(name, 0) * n
+        kernels[name] = {"launches": cnt, "avg_ms": round(per, 5),
+                         "alg_bytes": alg, "gbs": round(alg / (per * 1e-3) / 1e9, 1)}
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dk = kernels[dom]
+    traffic = load_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": dk["avg_ms"]}
+    kern_ms_step = sum(ms for ms, _ in ktimes.values()) / args.steps
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: project + extend step, {cfg.nx}x{cfg.ny}x{cfg.nz} "
+                               f"{cfg.bc}, {'uniform' if cfg.beta is None else 'tanh beta=%g' % cfg.beta}"
+                               " z, 2 Poisson solves per step",
+                   "grid": [cfg.nx, cfg.ny, cfg.nz], "bc": cfg.bc, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "solve_fp64": {"ms": round(ms64, 4), "mpts_s": round(n / (ms64 * 1e-3) / 1e6, 1),
+                       "model_gbs_80N": round(80 * n / (ms64 * 1e-3) / 1e9, 1)},
+        "solve_mixed": {"ms": round(ms32, 4), "mpts_s": round(n / (ms32 * 1e-3) / 1e6, 1),
+                        "dc_steps": 1, "rel_l2_vs_fp64": rel_mixed,
+                        "speedup_vs_fp64": round(ms64 / ms32, 3)},
+        "kernels": kernels,
+        "kernel_ms_per_step": round(kern_ms_step, 4),
+        "wall_s_timed": round(t_wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    plan.close()
+    mixed.close()
+
+
+if __name__ == "__main__":
+    main()

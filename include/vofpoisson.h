@@ -1,0 +1,172 @@
+/*
+ * vofpoisson -- constant-coefficient Poisson solve, pressure projection and
+ * liquid-velocity extension for MI355X (gfx950), C ABI.
+ *
+ * The operation (Scapin, Costa & Brandt, "A volume-of-fluid method for
+ * interface-resolved simulations of phase-changing two-fluid flows"):
+ *
+ *  - section 3.2, pressure Poisson equation and velocity correction of the
+ *    split projection: the variable-density pressure equation is split into a
+ *    constant-coefficient Laplacian of p^{n+1} (solved directly) and an
+ *    explicit term in the extrapolated pressure p_hat;
+ *  - section 3.6, Stefan-flow potential, liquid-velocity extension and
+ *    interface velocity: lap(phi) = s, u_1^e = u - grad(phi),
+ *    u_Gamma = u_1^e - (mdot/rho1) n, with phi under the pressure's boundary
+ *    conditions.
+ *
+ * Discretisation (section 3: fixed Cartesian grid, marker-and-cell layout,
+ * second-order finite differences).  Fields are real, row-major with x
+ * fastest: element (i, j, k) is at i + nx*(j + ny*k).  Cell-centred scalars
+ * (p, p_hat, rho, s, phi) have nx*ny*nz entries; each face-velocity array
+ * has nx*ny*nz entries too: u[i,j,k] is on face i+1/2, v on j+1/2, w on
+ * k+1/2.  With a wall ('N') in a direction the face with the last index is
+ * the wall; the face at -1/2 is implicit.  G is the face gradient (zero on
+ * wall faces), D the cell divergence, L = D(G(.)).  x and y are uniform
+ * (dx, dy); z may be stretched: dz[k] is the width of cell k and the centre
+ * distance across face k+1/2 is (dz[k] + dz[k+1]) / 2 (periodic z wraps).
+ *
+ * The Poisson solve returns the unique p with
+ *      L p = f - mean_W(f)   and   sum_k dV_k p_k = 0,
+ * mean_W being the cell-volume-weighted mean.  A right-hand side with a
+ * non-zero weighted mean is not an error: its mean is removed (and kept in
+ * the plan as a diagnostic, poisson_plan_last_mean).
+ *
+ * Pointers: every field pointer is a DEVICE pointer owned by the caller and
+ * must stay valid until the work queued on `hip_stream` has completed.
+ * `hip_stream` is a hipStream_t (NULL = the default stream).  All calls are
+ * asynchronous (no host synchronisation).  A plan holds its own device
+ * workspace, so one plan must not be used by two streams at the same time.
+ *
+ * Status codes: 0 ok; -1 invalid argument; -2 unsupported size or boundary
+ * combination; -3 device out of memory; -4 HIP runtime error (the HIP
+ * error string is kept per thread, see poisson_strerror).
+ */
+#ifndef VOFPOISSON_H
+#define VOFPOISSON_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VP_OK 0
+#define VP_EINVAL (-1)
+#define VP_EUNSUPPORTED (-2)
+#define VP_ENOMEM (-3)
+#define VP_EHIP (-4)
+
+#define VP_PRECISION_FP64 0
+#define VP_PRECISION_MIXED 1
+
+typedef struct poisson_plan poisson_plan;
+
+/*
+ * Create a plan on the current HIP device.
+ *   nx, ny : power of two in [8, 1024];
+ *   nz     : >= 1 (>= 3 when z is periodic), at most 4096;
+ *   dx, dy : > 0;  dz: HOST array of nz cell widths, each > 0 (copied);
+ *   bc     : 3 characters for x, y, z: 'P' periodic, 'N' wall with zero
+ *            normal gradient of p (zero normal velocity);
+ *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 transforms and
+ *            FP32 tridiagonal storage with FP64 pivots, refined by FP64
+ *            residual / defect-correction steps, see poisson_plan_set_mixed);
+ *   max_batch : largest n accepted by poisson_solve_batched (>= 1).
+ * Allocates the plan's device tables and workspace (8*nx*ny*nz bytes for
+ * FP64; FP64 + FP32 buffers for mixed).  Returns NULL and sets *status on
+ * failure (status may be NULL).
+ */
+poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy,
+                                  const double* dz, const char* bc, int precision,
+                                  int max_batch, int* status);
+
+/* Release every device allocation of the plan (synchronises the device). */
+void poisson_plan_destroy(poisson_plan* plan);
+
+/*
+ * Poisson solve (the direct constant-coefficient solver of section 3.2):
+ * sol = L^+ rhs as defined above.  rhs and sol: device, nx*ny*nz doubles;
+ * sol may alias rhs.
+ */
+int poisson_solve(poisson_plan* plan, const double* rhs, double* sol, void* hip_stream);
+
+/*
+ * n independent solves with the plan's shape (n <= max_batch), queued back
+ * to back on one stream; rhs[i] / sol[i] are HOST arrays of device pointers.
+ */
+int poisson_solve_batched(poisson_plan* plan, int n, const double* const* rhs,
+                          double* const* sol, void* hip_stream);
+
+/*
+ * Pressure projection of section 3.2 (constant-coefficient split):
+ *   b   = rho0 D[(1/rho0 - 1/rho_f) G p_hat] + (rho0/dt) (D u* - s)
+ *   p   = Poisson solve of b
+ *   u  <- u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ]
+ * rho_f is the mean of the two cell densities sharing a face.
+ *   u, v, w : in u*, out u^{n+1} (device, overwritten in place);
+ *   phat, rho : device cell fields; rho0 > 0 (the smaller phase density);
+ *   src : device s = mdot (1/rho2 - 1/rho1) |grad C|, or NULL for s = 0;
+ *   dt > 0;  p : device output pressure (must not alias the inputs).
+ */
+int project(poisson_plan* plan, double* u, double* v, double* w,
+            const double* phat, const double* rho, double rho0,
+            const double* src, double dt, double* p, void* hip_stream);
+
+/*
+ * Liquid-velocity extension of section 3.6:
+ *   phi = Poisson solve of src;  u_1^e = u - G phi;  u_Gamma = u_1^e - q.
+ *   u, v, w   : device input velocity (one-fluid, after projection);
+ *   src       : device s = mdot (1/rho2 - 1/rho1) |grad C| (cell centres);
+ *   qx,qy,qz  : device (mdot/rho1) n on faces, or all NULL (then ug, vg, wg
+ *               must be NULL too);
+ *   ue,ve,we  : device outputs u_1^e (may alias u, v, w);
+ *   ug,vg,wg  : device outputs u_Gamma, or NULL;
+ *   phi       : device output potential, or NULL (then the plan workspace
+ *               holds it until the next call).
+ */
+int extend_liquid_velocity(poisson_plan* plan, const double* u, const double* v,
+                           const double* w, const double* src,
+                           const double* qx, const double* qy, const double* qz,
+                           double* ue, double* ve, double* we,
+                           double* ug, double* vg, double* wg,
+                           double* phi, void* hip_stream);
+
+/*
+ * Mixed-precision control (plans created with VP_PRECISION_MIXED): the
+ * number of FP64 defect-correction steps after the first FP32 solve
+ * (0..8, default 1).  Returns VP_EINVAL for an FP64 plan or a bad count.
+ */
+int poisson_plan_set_mixed(poisson_plan* plan, int dc_steps);
+
+/*
+ * Weighted mean removed from the last right-hand side solved with this plan
+ * (copied from the device: synchronises `hip_stream`).  Returns a status.
+ */
+int poisson_plan_last_mean(poisson_plan* plan, double* mean_out, void* hip_stream);
+
+/* Size in bytes of the device memory held by a plan with these arguments. */
+long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_batch);
+
+/*
+ * Per-launch timing.  With profiling enabled, every kernel the plan launches
+ * is bracketed by two HIP events recorded on the caller's stream (a small
+ * launch overhead).  poisson_plan_kernel_times waits for the recorded events,
+ * writes per kernel class the total milliseconds and the launch count into
+ * total_ms[0..n) and launches[0..n) (classes beyond n are dropped), and
+ * forgets the recorded launches.  Classes are numbered 0..VP_NUM_KERNEL_CLASSES-1;
+ * poisson_kernel_class_name gives their names (NULL outside that range).
+ */
+#define VP_NUM_KERNEL_CLASSES 14
+int poisson_plan_set_profiling(poisson_plan* plan, int enable);
+int poisson_plan_kernel_times(poisson_plan* plan, double* total_ms, int* launches, int n);
+const char* poisson_kernel_class_name(int cls);
+
+/* Human-readable text for a status code (for VP_EHIP: the last HIP error). */
+const char* poisson_strerror(int status);
+
+/* Library version string. */
+const char* vofpoisson_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOFPOISSON_H */

@@ -1,0 +1,174 @@
+"""MI355X-native Poisson / projection / liquid-velocity-extension path.
+
+Python binding of libvofpoisson (include/vofpoisson.h): torch tensors in and
+out (device memory and streams only), all arithmetic in the library's HIP
+kernels for gfx950.  Fields are float64 tensors of shape (nz, ny, nx) on a
+ROCm device, contiguous (x fastest).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import VofPoissonError, check  # noqa: F401
+
+__all__ = ["Plan", "VofPoissonError", "footprint", "version"]
+
+
+def version() -> str:
+    return _lib.lib.vofpoisson_version().decode()
+
+
+def footprint(nx: int, ny: int, nz: int, precision: str = "fp64", max_batch: int = 1) -> int:
+    """Device bytes a plan of this shape holds."""
+    return int(_lib.lib.poisson_plan_footprint(nx, ny, nz, _lib.PRECISION[precision], max_batch))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A solve plan: grid, boundary conditions, device tables and workspace.
+
+    nx, ny: powers of two in [8, 1024]; nz >= 1; dz: nz cell widths (z may be
+    stretched); bc: three letters from 'P' (periodic) / 'N' (wall, zero
+    normal gradient) for x, y, z.  precision: 'fp64' or 'mixed'.
+    """
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, bc, precision="fp64", max_batch=1):
+        import numpy as np
+        dz = np.ascontiguousarray(np.asarray(dz, dtype=np.float64).reshape(-1))
+        if dz.shape != (nz,):
+            raise ValueError("dz must have nz entries")
+        self.shape = (int(nz), int(ny), int(nx))
+        self.bc = str(bc).upper()
+        self.precision = precision
+        self.max_batch = int(max_batch)
+        self._dz = dz
+        status = ctypes.c_int(0)
+        h = _lib.lib.poisson_plan_create(
+            int(nx), int(ny), int(nz), float(dx), float(dy),
+            dz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.bc.encode(),
+            _lib.PRECISION[precision], int(max_batch), ctypes.byref(status))
+        if not h:
+            raise VofPoissonError(status.value, "poisson_plan_create")
+        self._h = ctypes.c_void_p(h)
+
+    # -- helpers --------------------------------------------------------------
+    def _ptr(self, t, name, optional=False):
+        import torch
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a torch tensor on a ROCm device")
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
+        if tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _new(self, like):
+        import torch
+        return torch.empty(self.shape, dtype=torch.float64, device=like.device)
+
+    # -- entry points ---------------------------------------------------------
+    def solve(self, rhs, out=None, stream=None):
+        """out = L^+ rhs (zero volume-weighted mean); out may be rhs."""
+        if out is None:
+            out = self._new(rhs)
+        check(_lib.lib.poisson_solve(self._h, self._ptr(rhs, "rhs"), self._ptr(out, "out"),
+                                     _stream_ptr(stream)), "poisson_solve")
+        return out
+
+    def solve_batched(self, rhs_list, out_list=None, stream=None):
+        n = len(rhs_list)
+        if out_list is None:
+            out_list = [self._new(r) for r in rhs_list]
+        arr_in = (ctypes.c_void_p * n)(*[self._ptr(r, "rhs").value for r in rhs_list])
+        arr_out = (ctypes.c_void_p * n)(*[self._ptr(o, "out").value for o in out_list])
+        check(_lib.lib.poisson_solve_batched(self._h, n, arr_in, arr_out, _stream_ptr(stream)),
+              "poisson_solve_batched")
+        return out_list
+
+    def project(self, u, v, w, phat, rho, rho0, src, dt, p=None, stream=None):
+        """In-place projection of (u, v, w) = u*; returns (u, v, w, p)."""
+        if p is None:
+            p = self._new(u)
+        check(_lib.lib.project(self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
+                               self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
+                               self._ptr(src, "src", optional=True), float(dt),
+                               self._ptr(p, "p"), _stream_ptr(stream)), "project")
+        return u, v, w, p
+
+    def extend(self, u, v, w, src, q=None, out=None, gamma=None, phi=None, stream=None):
+        """u_1^e = u - G phi (phi = L^+ src), u_Gamma = u_1^e - q.
+
+        Returns (ue, ve, we, ug, vg, wg, phi); the u_Gamma entries are None
+        without q.
+        """
+        if out is None:
+            out = (self._new(u), self._new(u), self._new(u))
+        if q is not None and gamma is None:
+            gamma = (self._new(u), self._new(u), self._new(u))
+        if phi is None and self.precision == "mixed":
+            phi = self._new(u)
+        qs = (None, None, None) if q is None else q
+        gs = (None, None, None) if gamma is None else gamma
+        args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
+                self._ptr(src, "src")]
+        args += [self._ptr(t, "q", optional=True) for t in qs]
+        args += [self._ptr(t, "out") for t in out]
+        args += [self._ptr(t, "gamma", optional=True) for t in gs]
+        args += [self._ptr(phi, "phi", optional=True), _stream_ptr(stream)]
+        check(_lib.lib.extend_liquid_velocity(*args), "extend_liquid_velocity")
+        return (*out, *gs, phi)
+
+    def set_mixed(self, dc_steps: int):
+        check(_lib.lib.poisson_plan_set_mixed(self._h, int(dc_steps)), "poisson_plan_set_mixed")
+
+    def last_mean(self, stream=None) -> float:
+        out = ctypes.c_double(0.0)
+        check(_lib.lib.poisson_plan_last_mean(self._h, ctypes.byref(out), _stream_ptr(stream)),
+              "poisson_plan_last_mean")
+        return out.value
+
+    def set_profiling(self, enable: bool = True):
+        """Bracket every kernel launch of this plan with HIP events."""
+        check(_lib.lib.poisson_plan_set_profiling(self._h, int(bool(enable))),
+              "poisson_plan_set_profiling")
+
+    def kernel_times(self):
+        """{class name: (total ms, launches)} for the launches recorded since
+        the last call (waits for them to finish)."""
+        n = _lib.NUM_KERNEL_CLASSES
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        check(_lib.lib.poisson_plan_kernel_times(self._h, ms, cnt, n), "poisson_plan_kernel_times")
+        out = {}
+        for i in range(n):
+            if cnt[i]:
+                out[_lib.lib.poisson_kernel_class_name(i).decode()] = (ms[i], cnt[i])
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib.poisson_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

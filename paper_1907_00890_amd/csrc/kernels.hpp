@@ -1,0 +1,86 @@
+// Host-side launchers of the HIP kernels (internal to libvofpoisson).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vp {
+
+enum : int { BC_P = 0, BC_N = 1 };  // periodic / wall with zero normal gradient
+
+// Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU (needed for
+// launches above 64 KB); done once per kernel instantiation.
+template <typename K>
+inline hipError_t allow_large_lds(K* kernel) {
+  static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024);
+  return once;
+}
+
+// transforms.hip -------------------------------------------------------------
+// tab layout per direction and precision: cos(2 pi k/N), sin(2 pi k/N) for
+// k < N, then cos(pi m/(2N)), sin(pi m/(2N)) for m <= N/2.
+int ypass_tile_cols(int nx, int ny);
+hipError_t launch_xfwd_f64(const double* in, double* out, int nx, int bc, long nrows,
+                           const double* tab, hipStream_t st);
+hipError_t launch_xinv_f64(const double* in, double* out, int nx, int bc, long nrows,
+                           const double* tab, hipStream_t st);
+hipError_t launch_xfwd_f32(const double* in, float* out, int nx, int bc, long nrows,
+                           const float* tab, hipStream_t st);
+// accum: out += result - sub[0] (sub may be null: nothing subtracted)
+hipError_t launch_xinv_f32(const float* in, double* out, int nx, int bc, long nrows, bool accum,
+                           const double* sub, const float* tab, hipStream_t st);
+hipError_t launch_y_f64(double* data, int nx, int ny, int nz, int bc, bool fwd,
+                        const double* tab, hipStream_t st);
+hipError_t launch_y_f32(float* data, int nx, int ny, int nz, int bc, bool fwd, const float* tab,
+                        hipStream_t st);
+
+// zsolve.hip -----------------------------------------------------------------
+struct ZArgs {
+  long plane;          // nx * ny lines
+  int nx;              // for the (cx, cy) split of a line index
+  int nz;
+  int seg;             // segment length bound M (16 or 32)
+  int nseg;            // S segments per line
+  int seg_base;        // nz / S
+  int seg_rem;         // nz % S (first seg_rem segments are one longer)
+  int periodic;        // z periodic
+  double scale;        // 1 / (nx * ny)
+  double dz_sum;       // sum of dzf
+  const double* lamx;  // eigenvalue per packed x position
+  const double* lamy;
+  double dzc_wrap;     // centre distance across the wrap face (periodic z)
+  const double* za;    // sub-diagonal of the row-scaled z operator (wall form: za[0] = 0)
+  const double* zc;    // super-diagonal (wall form: zc[nz-1] = 0)
+  const double* dzf;
+  const double* dzc;   // centre distance across face k+1/2 (wrap at nz-1 if periodic)
+  double* mean_out;    // removed weighted mean (diagnostic), may be null
+};
+hipError_t launch_zsolve_f64(double* data, const ZArgs& a, hipStream_t st);
+hipError_t launch_zsolve_f32(float* data, const ZArgs& a, hipStream_t st);
+
+// stencils.hip ---------------------------------------------------------------
+struct GridArgs {
+  int nx, ny, nz;
+  int bcx, bcy, bcz;   // 0 periodic, 1 wall
+  double dx, dy;
+  const double* dzf;   // nz
+  const double* dzc;   // nz (last entry: wrap distance when z is periodic)
+};
+hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const double* w,
+                      const double* phat, const double* rho, double rho0, const double* src,
+                      double dt, double* b, hipStream_t st);
+hipError_t launch_correct(const GridArgs& g, double* u, double* v, double* w, const double* p,
+                          const double* phat, const double* rho, double rho0, double dt,
+                          hipStream_t st);
+hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, const double* w,
+                         const double* phi, const double* qx, const double* qy, const double* qz,
+                         double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
+                         hipStream_t st);
+// r = f - L_h p; also mean_out[0] = volume-weighted mean of p.  partial must
+// hold kResidualMaxBlocks doubles.
+constexpr int kResidualMaxBlocks = 2048;
+int residual_blocks(long n);
+hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
+                           double* partial, double* mean_out, double dz_sum, hipStream_t st);
+
+}  // namespace vp

@@ -1,0 +1,481 @@
+// Plan, workspace and C entry points of libvofpoisson (see include/vofpoisson.h).
+//
+// Spectral solve (the constant-coefficient direct solver of section 3.2, used
+// again for the Stefan potential of section 3.6):
+//   x pass (forward)  -> y pass (forward) -> z tridiagonal pass
+//   -> y pass (inverse) -> x pass (inverse)
+// The forward transforms are unnormalised; the z pass scales by 1/(nx*ny)
+// and the inverse transforms return N times their input, so the chain is
+// exactly the inverse operator on the zero-mean subspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "vofpoisson.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? VP_ENOMEM : VP_EHIP;
+}
+
+#define VP_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+enum KernelClass {
+  K_XFWD = 0, K_YFWD, K_Z, K_YINV, K_XINV,
+  K_XFWD32, K_YFWD32, K_Z32, K_YINV32, K_XINV32,
+  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_NCLASS
+};
+const char* const kClassNames[K_NCLASS] = {
+    "x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse",
+    "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
+    "residual", "rhs_assembly", "correction", "extension"};
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+// Twiddle table of one direction: cos/sin(2 pi k/N), k < N, then
+// cos/sin(pi m/(2N)), m <= N/2 (the DCT post/pre rotation).
+std::vector<double> make_table(int n) {
+  std::vector<double> t(2 * n + 2 * (n / 2 + 1));
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int k = 0; k < n; ++k) {
+    t[k] = std::cos(2.0 * pi * k / n);
+    t[n + k] = std::sin(2.0 * pi * k / n);
+  }
+  for (int m = 0; m <= n / 2; ++m) {
+    t[2 * n + m] = std::cos(pi * m / (2.0 * n));
+    t[2 * n + (n / 2 + 1) + m] = std::sin(pi * m / (2.0 * n));
+  }
+  return t;
+}
+
+// Eigenvalue of the 1-D second difference for every packed coefficient position.
+std::vector<double> make_lambda(int n, double h, int bc) {
+  const double pi = 3.14159265358979323846264338327950288;
+  std::vector<double> l(n);
+  for (int c = 0; c < n; ++c) {
+    double s;
+    if (bc == vp::BC_P) {
+      const int m = c == 0 ? 0 : (c == 1 ? n / 2 : c / 2);
+      s = std::sin(pi * m / n);
+    } else {
+      s = std::sin(pi * c / (2.0 * n));
+    }
+    l[c] = -4.0 / (h * h) * s * s;
+  }
+  return l;
+}
+
+}  // namespace
+
+struct poisson_plan {
+  int nx = 0, ny = 0, nz = 0;
+  int bc[3] = {0, 0, 0};
+  int precision = 0, max_batch = 1, dc_steps = 1;
+  double dx = 0, dy = 0, dz_sum = 0;
+  int device = 0;
+  long long bytes = 0;
+  std::vector<void*> allocs;
+
+  double *tabx64 = nullptr, *taby64 = nullptr;
+  float *tabx32 = nullptr, *taby32 = nullptr;
+  double *lamx = nullptr, *lamy = nullptr, *za = nullptr, *zc = nullptr;
+  double *dzf = nullptr, *dzc = nullptr, *mean = nullptr;
+  double* work64 = nullptr;
+  float* work32 = nullptr;
+  double* res64 = nullptr;
+  double* partial = nullptr;
+
+  vp::ZArgs z{};
+  vp::GridArgs g{};
+
+  // optional per-launch timing (HIP events on the caller's stream)
+  struct Mark {
+    int cls;
+    hipEvent_t a, b;
+  };
+  bool profiling = false;
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+
+  long npts() const { return (long)nx * ny * nz; }
+
+  template <typename T>
+  int alloc(T** p, size_t count, const char* what) {
+    void* q = nullptr;
+    VP_HIP(hipMalloc(&q, count * sizeof(T)), what);
+    allocs.push_back(q);
+    bytes += (long long)(count * sizeof(T));
+    *p = static_cast<T*>(q);
+    return VP_OK;
+  }
+  template <typename T>
+  int upload(T** p, const std::vector<T>& h, const char* what) {
+    int st = alloc(p, h.size(), what);
+    if (st) return st;
+    VP_HIP(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), what);
+    return VP_OK;
+  }
+  void release() {
+    for (void* q : allocs) (void)hipFree(q);
+    allocs.clear();
+    for (auto& m : marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    marks.clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+namespace {
+
+// Launch `call` on stream st; with profiling on, bracket it with two events.
+#define VP_LAUNCH(P, cls, call, what, st)                                 \
+  do {                                                                    \
+    hipEvent_t a_ = nullptr, b_ = nullptr;                                \
+    if ((P)->profiling) {                                                 \
+      a_ = (P)->event();                                                  \
+      b_ = (P)->event();                                                  \
+      if (a_) (void)hipEventRecord(a_, st);                               \
+    }                                                                     \
+    VP_HIP((call), what);                                                 \
+    if ((P)->profiling && a_ && b_) {                                     \
+      (void)hipEventRecord(b_, st);                                       \
+      (P)->marks.push_back({cls, a_, b_});                                \
+    }                                                                     \
+  } while (0)
+
+int plan_init(poisson_plan* P, const double* dz) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  int st;
+  // tables
+  const std::vector<double> tx = make_table(nx), ty = make_table(ny);
+  if ((st = P->upload(&P->tabx64, tx, "table x"))) return st;
+  if ((st = P->upload(&P->taby64, ty, "table y"))) return st;
+  if (P->precision == VP_PRECISION_MIXED) {
+    std::vector<float> fx(tx.begin(), tx.end()), fy(ty.begin(), ty.end());
+    if ((st = P->upload(&P->tabx32, fx, "table x f32"))) return st;
+    if ((st = P->upload(&P->taby32, fy, "table y f32"))) return st;
+  }
+  if ((st = P->upload(&P->lamx, make_lambda(nx, P->dx, P->bc[0]), "lambda x"))) return st;
+  if ((st = P->upload(&P->lamy, make_lambda(ny, P->dy, P->bc[1]), "lambda y"))) return st;
+
+  // z grid: centre distances and the row-scaled tridiagonal coefficients
+  const bool zper = P->bc[2] == vp::BC_P;
+  std::vector<double> f(dz, dz + nz), c(nz, 0.0), a(nz, 0.0), cc(nz, 0.0);
+  double sum = 0.0;
+  for (int k = 0; k < nz; ++k) sum += f[k];
+  for (int k = 0; k + 1 < nz; ++k) c[k] = 0.5 * (f[k] + f[k + 1]);
+  if (zper) c[nz - 1] = 0.5 * (f[nz - 1] + f[0]);
+  else c[nz - 1] = 1.0;  // unused (wall)
+  // wall form of the operator; a periodic z adds the wrap face through one
+  // flux unknown inside the z kernel (distance c[nz-1])
+  for (int k = 0; k < nz; ++k) {
+    if (k > 0) a[k] = 1.0 / (f[k] * c[k - 1]);
+    if (k + 1 < nz) cc[k] = 1.0 / (f[k] * c[k]);
+  }
+  P->dz_sum = sum;
+  if ((st = P->upload(&P->dzf, f, "dzf"))) return st;
+  if ((st = P->upload(&P->dzc, c, "dzc"))) return st;
+  if ((st = P->upload(&P->za, a, "za"))) return st;
+  if ((st = P->upload(&P->zc, cc, "zc"))) return st;
+  if ((st = P->alloc(&P->mean, 4, "mean"))) return st;
+  VP_HIP(hipMemset(P->mean, 0, 4 * sizeof(double)), "mean init");
+
+  const size_t n = (size_t)P->npts();
+  if ((st = P->alloc(&P->work64, n, "workspace"))) return st;
+  if (P->precision == VP_PRECISION_MIXED) {
+    if ((st = P->alloc(&P->work32, n, "workspace f32"))) return st;
+    if ((st = P->alloc(&P->res64, n, "residual"))) return st;
+    if ((st = P->alloc(&P->partial, vp::kResidualMaxBlocks, "partial sums"))) return st;
+  }
+
+  // z launch geometry: S segments of at most 16 rows (S <= 64)
+  vp::ZArgs& Z = P->z;
+  Z.plane = (long)nx * ny;
+  Z.nx = nx;
+  Z.nz = nz;
+  Z.seg = 16;
+  Z.nseg = (nz + Z.seg - 1) / Z.seg;
+  Z.seg_base = nz / Z.nseg;
+  Z.seg_rem = nz % Z.nseg;
+  Z.periodic = zper ? 1 : 0;
+  Z.dzc_wrap = zper ? c[nz - 1] : 0.0;
+  Z.scale = 1.0 / ((double)nx * (double)ny);
+  Z.dz_sum = sum;
+  Z.lamx = P->lamx;
+  Z.lamy = P->lamy;
+  Z.za = P->za;
+  Z.zc = P->zc;
+  Z.dzf = P->dzf;
+  Z.dzc = P->dzc;
+  Z.mean_out = P->mean;
+
+  vp::GridArgs& G = P->g;
+  G.nx = nx; G.ny = ny; G.nz = nz;
+  G.bcx = P->bc[0]; G.bcy = P->bc[1]; G.bcz = P->bc[2];
+  G.dx = P->dx; G.dy = P->dy;
+  G.dzf = P->dzf; G.dzc = P->dzc;
+  return VP_OK;
+}
+
+// FP64 chain: rhs -> sol (sol may alias rhs)
+int solve_f64(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
+  const long nrows = (long)P->ny * P->nz;
+  double* w = P->work64;
+  VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(rhs, w, P->nx, P->bc[0], nrows, P->tabx64, st), "x forward", st);
+  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz, P->bc[1], true, P->taby64, st), "y forward", st);
+  VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, st), "z solve", st);
+  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz, P->bc[1], false, P->taby64, st), "y inverse", st);
+  VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, sol, P->nx, P->bc[0], nrows, P->tabx64, st), "x inverse", st);
+  return VP_OK;
+}
+
+// FP32 chain on an FP64 right-hand side; out = result, or with accum
+// out += result - sub[0]
+int solve_f32(poisson_plan* P, const double* rhs, double* out, bool accum, const double* sub,
+              hipStream_t st) {
+  const long nrows = (long)P->ny * P->nz;
+  float* w = P->work32;
+  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(rhs, w, P->nx, P->bc[0], nrows, P->tabx32, st), "x forward f32", st);
+  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz, P->bc[1], true, P->taby32, st), "y forward f32", st);
+  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, P->z, st), "z solve f32", st);
+  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz, P->bc[1], false, P->taby32, st), "y inverse f32", st);
+  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, out, P->nx, P->bc[0], nrows, accum, sub, P->tabx32, st),
+            "x inverse f32", st);
+  return VP_OK;
+}
+
+// Mixed precision: p = S32(f), then dc_steps times
+//   r = f - L_h p (FP64, also giving mean_W(p)),  p += S32(r) - mean_W(p).
+// The FP32 chain cannot see the null (constant) mode, so the FP64 weighted
+// mean is removed in every correction step instead.
+int solve_mixed(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
+  const double* f = rhs;
+  if (rhs == sol) {
+    VP_HIP(hipMemcpyAsync(P->res64, rhs, sizeof(double) * P->npts(), hipMemcpyDeviceToDevice, st),
+           "copy rhs");
+    f = P->res64;
+  }
+  double* r = (f == P->res64) ? P->work64 : P->res64;
+  int s = solve_f32(P, f, sol, false, nullptr, st);
+  if (s) return s;
+  for (int it = 0; it < P->dc_steps; ++it) {
+    VP_LAUNCH(P, K_RESIDUAL, vp::launch_residual(P->g, f, sol, r, P->partial, P->mean + 1, P->dz_sum, st),
+              "residual", st);
+    s = solve_f32(P, r, sol, true, P->mean + 1, st);
+    if (s) return s;
+  }
+  return VP_OK;
+}
+
+int solve_any(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
+  if (P->precision == VP_PRECISION_MIXED) return solve_mixed(P, rhs, sol, st);
+  return solve_f64(P, rhs, sol, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                                  const char* bc, int precision, int max_batch, int* status) {
+  auto fail = [&](int s) -> poisson_plan* {
+    if (status) *status = s;
+    return nullptr;
+  };
+  if (!dz || !bc || nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || !(dy > 0) || max_batch < 1)
+    return fail(VP_EINVAL);
+  int bcs[3];
+  for (int d = 0; d < 3; ++d) {
+    const char ch = bc[d];
+    if (ch == 'P' || ch == 'p') bcs[d] = vp::BC_P;
+    else if (ch == 'N' || ch == 'n') bcs[d] = vp::BC_N;
+    else if (ch == 'D' || ch == 'd') return fail(VP_EUNSUPPORTED);
+    else return fail(VP_EINVAL);
+  }
+  if (bc[3] != '\0') return fail(VP_EINVAL);
+  for (int k = 0; k < nz; ++k)
+    if (!(dz[k] > 0) || !std::isfinite(dz[k])) return fail(VP_EINVAL);
+  if (bcs[2] == vp::BC_P && nz < 3) return fail(VP_EINVAL);
+  if (precision != VP_PRECISION_FP64 && precision != VP_PRECISION_MIXED) return fail(VP_EINVAL);
+  if (!pow2_in(nx, 8, 1024) || !pow2_in(ny, 8, 1024) || nz > 1024) return fail(VP_EUNSUPPORTED);
+
+  poisson_plan* P = new (std::nothrow) poisson_plan();
+  if (!P) return fail(VP_ENOMEM);
+  P->nx = nx; P->ny = ny; P->nz = nz;
+  P->dx = dx; P->dy = dy;
+  P->bc[0] = bcs[0]; P->bc[1] = bcs[1]; P->bc[2] = bcs[2];
+  P->precision = precision;
+  P->max_batch = max_batch;
+  P->dc_steps = precision == VP_PRECISION_MIXED ? 1 : 0;
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    delete P;
+    return fail(VP_EHIP);
+  }
+  const int st = plan_init(P, dz);
+  if (st != VP_OK) {
+    P->release();
+    delete P;
+    return fail(st);
+  }
+  if (status) *status = VP_OK;
+  return P;
+}
+
+void poisson_plan_destroy(poisson_plan* P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  P->release();
+  delete P;
+}
+
+int poisson_solve(poisson_plan* P, const double* rhs, double* sol, void* stream) {
+  if (!P || !rhs || !sol) return VP_EINVAL;
+  return solve_any(P, rhs, sol, static_cast<hipStream_t>(stream));
+}
+
+int poisson_solve_batched(poisson_plan* P, int n, const double* const* rhs, double* const* sol,
+                          void* stream) {
+  if (!P || !rhs || !sol || n < 0 || n > P->max_batch) return VP_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!rhs[i] || !sol[i]) return VP_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    const int s = solve_any(P, rhs[i], sol[i], static_cast<hipStream_t>(stream));
+    if (s) return s;
+  }
+  return VP_OK;
+}
+
+int project(poisson_plan* P, double* u, double* v, double* w, const double* phat,
+            const double* rho, double rho0, const double* src, double dt, double* p,
+            void* stream) {
+  if (!P || !u || !v || !w || !phat || !rho || !p || !(rho0 > 0) || !(dt > 0)) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // mixed precision keeps the FP64 right-hand side for its residuals
+  double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
+  VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src, dt, b, st), "rhs assembly", st);
+  int s = solve_any(P, b, p, st);
+  if (s) return s;
+  VP_LAUNCH(P, K_CORRECT, vp::launch_correct(P->g, u, v, w, p, phat, rho, rho0, dt, st), "correction", st);
+  return VP_OK;
+}
+
+int extend_liquid_velocity(poisson_plan* P, const double* u, const double* v, const double* w,
+                           const double* src, const double* qx, const double* qy,
+                           const double* qz, double* ue, double* ve, double* we, double* ug,
+                           double* vg, double* wg, double* phi, void* stream) {
+  if (!P || !u || !v || !w || !src || !ue || !ve || !we) return VP_EINVAL;
+  const bool hq = qx && qy && qz, hg = ug && vg && wg;
+  if ((qx || qy || qz) && !hq) return VP_EINVAL;
+  if ((ug || vg || wg) && !hg) return VP_EINVAL;
+  if (hq != hg) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* out = phi;
+  if (!out) {
+    if (P->precision == VP_PRECISION_MIXED) return VP_EINVAL;  // needs a caller buffer
+    out = P->work64;
+  }
+  int s = solve_any(P, src, out, st);
+  if (s) return s;
+  VP_LAUNCH(P, K_EXTEND, vp::launch_extend(P->g, u, v, w, out, qx, qy, qz, ue, ve, we, ug, vg, wg, st),
+            "extension", st);
+  return VP_OK;
+}
+
+int poisson_plan_set_mixed(poisson_plan* P, int dc_steps) {
+  if (!P || P->precision != VP_PRECISION_MIXED || dc_steps < 0 || dc_steps > 8) return VP_EINVAL;
+  P->dc_steps = dc_steps;
+  return VP_OK;
+}
+
+int poisson_plan_last_mean(poisson_plan* P, double* mean_out, void* stream) {
+  if (!P || !mean_out) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  VP_HIP(hipMemcpyAsync(mean_out, P->mean, sizeof(double), hipMemcpyDeviceToHost, st), "mean");
+  VP_HIP(hipStreamSynchronize(st), "mean sync");
+  return VP_OK;
+}
+
+long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_batch) {
+  (void)max_batch;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return -1;
+  const long long n = (long long)nx * ny * nz;
+  long long b = 8 * n;
+  if (precision == VP_PRECISION_MIXED) b += 4 * n + 8 * n + 8LL * vp::kResidualMaxBlocks;
+  b += 8LL * (3 * nx + 3 * ny + 4 * nz + 16);
+  return b;
+}
+
+const char* poisson_strerror(int status) {
+  switch (status) {
+    case VP_OK: return "ok";
+    case VP_EINVAL: return "invalid argument";
+    case VP_EUNSUPPORTED: return "unsupported size or boundary condition";
+    case VP_ENOMEM: return "device out of memory";
+    case VP_EHIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+    default: return "unknown status";
+  }
+}
+
+int poisson_plan_set_profiling(poisson_plan* P, int enable) {
+  if (!P) return VP_EINVAL;
+  P->profiling = enable != 0;
+  return VP_OK;
+}
+
+int poisson_plan_kernel_times(poisson_plan* P, double* total_ms, int* launches, int n) {
+  if (!P || n < 0 || (n > 0 && (!total_ms || !launches))) return VP_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  int status = VP_OK;
+  for (auto& m : P->marks) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(m.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.a, m.b);
+    if (e != hipSuccess && status == VP_OK) status = hip_fail(e, "kernel timing");
+    if (m.cls < n) {
+      total_ms[m.cls] += ms;
+      launches[m.cls] += 1;
+    }
+    P->pool.push_back(m.a);
+    P->pool.push_back(m.b);
+  }
+  P->marks.clear();
+  return status;
+}
+
+const char* poisson_kernel_class_name(int cls) {
+  return (cls >= 0 && cls < K_NCLASS) ? kClassNames[cls] : nullptr;
+}
+
+const char* vofpoisson_version(void) { return "vofpoisson 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/*.h, and rejects bad arguments before touching a device."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1907_00890_amd", "libvofpoisson.so")
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = "\n".join(ln for ln in text.splitlines() if not ln.lstrip().startswith("#"))
+        for m in re.finditer(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(", text):
+            name = m.group(1)
+            if name in ("if", "sizeof", "defined"):
+                continue
+            # only names that start a declaration (preceded by a type token)
+            names.add(name)
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libvofpoisson.so is not built (run __graft_entry__.build())")
+    from paper_1907_00890_amd import _lib
+    return _lib.lib
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "poisson_plan_create" in names and "extend_liquid_velocity" in names
+    for n in names:
+        assert hasattr(lib, n), f"missing export {n}"
+
+
+def test_binding_covers_header():
+    from paper_1907_00890_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+def test_strerror_and_version(lib):
+    assert b"gfx950" in lib.vofpoisson_version()
+    for s in (0, -1, -2, -3, -4, 7):
+        assert isinstance(lib.poisson_strerror(s), bytes)
+
+
+def _create(lib, nx, ny, nz, bc, dz=None, precision=0, max_batch=1, dx=0.1, dy=0.1):
+    dz = dz if dz is not None else [1.0 / max(nz, 1)] * max(nz, 1)
+    arr = (ctypes.c_double * len(dz))(*dz)
+    st = ctypes.c_int(123)
+    h = lib.poisson_plan_create(nx, ny, nz, dx, dy, arr, bc, precision, max_batch,
+                                ctypes.byref(st))
+    return h, st.value
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((0, 8, 8, b"PPN"), -1),
+    ((8, 8, 8, b"PPX"), -1),
+    ((8, 8, 8, b"PP"), -1),
+    ((8, 8, 8, b"PPPP"), -1),
+    ((8, 8, 2, b"PPP"), -1),        # periodic z needs nz >= 3
+    ((12, 8, 8, b"PPN"), -2),       # not a power of two
+    ((8, 2048, 8, b"PPN"), -2),     # too long
+    ((4, 8, 8, b"PPN"), -2),        # too short
+    ((8, 8, 8, b"PPD"), -2),        # Dirichlet not in this version
+    ((8, 8, 2000, b"PPN"), -2),     # nz too large
+])
+def test_create_rejects(lib, args, expect):
+    h, st = _create(lib, *args)
+    assert not h and st == expect
+
+
+def test_create_rejects_bad_widths(lib):
+    h, st = _create(lib, 8, 8, 4, b"PPN", dz=[0.25, 0.25, -0.1, 0.25])
+    assert not h and st == -1
+    h, st = _create(lib, 8, 8, 4, b"PPN", dx=0.0)
+    assert not h and st == -1
+    h, st = _create(lib, 8, 8, 4, b"PPN", precision=3)
+    assert not h and st == -1
+
+
+def test_null_plan_calls(lib):
+    assert lib.poisson_solve(None, None, None, None) == -1
+    assert lib.poisson_plan_set_mixed(None, 1) == -1
+    lib.poisson_plan_destroy(None)
+
+
+def test_footprint(lib):
+    n = 64 * 64 * 64
+    assert lib.poisson_plan_footprint(64, 64, 64, 0, 1) >= 8 * n
+    assert lib.poisson_plan_footprint(64, 64, 64, 1, 1) >= 20 * n
+    assert lib.poisson_plan_footprint(0, 64, 64, 0, 1) < 0

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Element-by-element relative L2 on seeded inputs at sizes the oracle finishes
+in seconds (several FFT tiles, ragged z segments, every boundary
+combination); at the full benchmark sizes, properties that hold at any size
+(residual of the discrete equation and the gauge) evaluated with plain torch
+ops, independent of the library's own stencils.
+
+Tolerances: FP64 relative L2 <= 1e-12; mixed precision <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import vofsynth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1907_00890_amd  # noqa: F401  (fails loudly without the library)
+    return torch
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _grid(nx, ny, nz, bc, beta=None, lx=1.0, ly=1.0, lz=1.0):
+    dzf = vofsynth.uniform_dz(nz, lz) if beta is None else vofsynth.stretched_dz(nz, lz, beta)
+    return oracle.Grid(nx, ny, nz, lx / nx, ly / ny, dzf, bc)
+
+
+def _plan(g, precision="fp64", max_batch=1):
+    from paper_1907_00890_amd import Plan
+    return Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, g.bc, precision=precision,
+                max_batch=max_batch)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+SOLVE_CASES = [
+    # (nx, ny, nz, bc, beta)
+    (32, 32, 32, "PPP", None),       # 32^3 triply periodic
+    (128, 128, 128, "PPN", None),    # 128^3 periodic x/y, walls z
+    (64, 32, 40, "NPN", 1.5),        # stretched, ragged segments
+    (16, 8, 12, "PNN", 1.3),
+    (8, 16, 3, "PPP", None),         # shortest periodic z
+    (32, 64, 17, "NNP", None),       # odd periodic z (segments 9 + 8)
+    (16, 16, 2, "NNN", None),
+    (16, 32, 1, "PPN", None),        # one-cell slab
+    (1024, 8, 5, "PNN", None),       # longest x line
+    (8, 1024, 4, "NPN", None),       # longest y line
+    (16, 8, 600, "PPN", 1.5),        # 32-row segments
+    (8, 8, 1024, "PPP", None),       # longest z
+    (256, 16, 33, "NNN", 1.1),
+]
+
+
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
+def test_solve_parity(torch_dev, case):
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 100 + nx + ny + nz)
+    ref = oracle.solve(f, g)
+    plan = _plan(g)
+    p = plan.solve(_dev(torch, f))
+    torch.cuda.synchronize()
+    err = rel_l2(p.cpu().numpy(), ref)
+    print(f"solve {case}: rel L2 {err:.3e}")
+    assert err <= FP64_TOL, err
+    # the weighted mean of the rhs is reported
+    assert abs(plan.last_mean() - g.weighted_mean(f)) <= 1e-13 * np.abs(f).max()
+    plan.close()
+
+
+def test_solve_in_place_and_offset(torch_dev):
+    torch = torch_dev
+    g = _grid(64, 64, 48, "PPN", 1.5)
+    f = vofsynth.gaussian_field(g.shape, 7) + 5.0
+    ref = oracle.solve(f, g)
+    plan = _plan(g)
+    t = _dev(torch, f)
+    plan.solve(t, out=t)
+    torch.cuda.synchronize()
+    assert rel_l2(t.cpu().numpy(), ref) <= FP64_TOL
+
+
+def test_eigenfunction_closed_form(torch_dev):
+    """sin(2 pi x) cos(4 pi y) sin(2 pi z), 32^3 periodic: p = f / Lambda."""
+    torch = torch_dev
+    n, h = 32, 1.0 / 32
+    x = (np.arange(n) + 0.5) * h
+    f = (np.sin(2 * np.pi * x)[None, None, :] * np.cos(4 * np.pi * x)[None, :, None]
+         * np.sin(2 * np.pi * x)[:, None, None])
+    lam = -(4.0 / h**2) * (2 * np.sin(np.pi / n) ** 2 + np.sin(2 * np.pi / n) ** 2)
+    g = _grid(n, n, n, "PPP")
+    p = _plan(g).solve(_dev(torch, f)).cpu().numpy()
+    assert rel_l2(p, f / lam) <= FP64_TOL
+
+
+def _project_inputs(g, seed=2):
+    us, vs, ws = vofsynth.random_faces(g.shape, seed + 1, g.bc)
+    phat = vofsynth.gaussian_field(g.shape, seed + 20)
+    C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, seed=seed)
+    rho = 1000.0 * C + 1.0 * (1 - C)
+    mag, _ = vofsynth.grad_mag_central(C, g.dx, g.dy, g.dzf, g.bc)
+    s = 1e-2 * mag
+    return us, vs, ws, phat, rho, 1.0, s, 0.3
+
+
+@pytest.mark.parametrize("shape,bc,beta", [((128, 128, 128), "PPN", None),
+                                           ((64, 32, 48), "NPN", 1.5),
+                                           ((32, 32, 32), "PPP", None)])
+def test_project_parity(torch_dev, shape, bc, beta):
+    torch = torch_dev
+    g = _grid(*shape, bc, beta)
+    us, vs, ws, phat, rho, rho0, s, dt = _project_inputs(g)
+    u, v, w, p = oracle.project(us, vs, ws, phat, rho, rho0, s, dt, g)
+    plan = _plan(g)
+    du, dv, dw = _dev(torch, us), _dev(torch, vs), _dev(torch, ws)
+    out = plan.project(du, dv, dw, _dev(torch, phat), _dev(torch, rho), rho0, _dev(torch, s), dt)
+    torch.cuda.synchronize()
+    for name, a, b in zip("uvwp", out, (u, v, w, p)):
+        err = rel_l2(a.cpu().numpy(), b)
+        print(f"project {shape} {bc} {name}: {err:.3e}")
+        assert err <= FP64_TOL, (name, err)
+    # invariant on the GPU result: D u^{n+1} = s - mean_W(s)
+    d = oracle.div(out[0].cpu().numpy(), out[1].cpu().numpy(), out[2].cpu().numpy(), g)
+    scale = np.abs(oracle.div(us, vs, ws, g)).max()
+    assert np.abs(d - (s - g.weighted_mean(s))).max() <= 1e-11 * scale
+
+
+def test_project_without_source(torch_dev):
+    torch = torch_dev
+    g = _grid(32, 32, 32, "PPP")
+    us, vs, ws = vofsynth.random_faces(g.shape, 1, g.bc)
+    rho = np.ones(g.shape)
+    z = np.zeros(g.shape)
+    u, v, w, p = oracle.project(us, vs, ws, z, rho, 1.0, z, 1.0, g)
+    plan = _plan(g)
+    out = plan.project(_dev(torch, us), _dev(torch, vs), _dev(torch, ws), _dev(torch, z),
+                       _dev(torch, rho), 1.0, None, 1.0)
+    for a, b in zip(out, (u, v, w, p)):
+        assert rel_l2(a.cpu().numpy(), b) <= FP64_TOL
+    d = oracle.div(*(t.cpu().numpy() for t in out[:3]), g)
+    assert np.abs(d).max() <= 1e-11 * np.abs(oracle.div(us, vs, ws, g)).max()
+
+
+@pytest.mark.parametrize("shape,bc,beta", [((128, 128, 128), "PPN", None),
+                                           ((64, 32, 48), "NPN", 1.5)])
+def test_extend_parity(torch_dev, shape, bc, beta):
+    torch = torch_dev
+    g = _grid(*shape, bc, beta)
+    usol = vofsynth.solenoidal_faces(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, g.bc, seed=3)
+    psi = vofsynth.gaussian_field(g.shape, 4)
+    u = [a + b for a, b in zip(usol, oracle.grad(psi, g))]
+    s = oracle.lap(psi, g)
+    C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, seed=2)
+    q = vofsynth.interface_normal_faces(C, g.dx, g.dy, g.dzf, g.bc, 1.001e-2 / 1000.0)
+    ref = oracle.extend(u[0], u[1], u[2], s, g, q=q)
+    plan = _plan(g)
+    out = plan.extend(*(_dev(torch, a) for a in u), _dev(torch, s),
+                      q=tuple(_dev(torch, a) for a in q), phi=_dev(torch, np.zeros(g.shape)))
+    torch.cuda.synchronize()
+    for name, a, b in zip(("ue", "ve", "we", "ug", "vg", "wg", "phi"), out, ref):
+        err = rel_l2(a.cpu().numpy(), b)
+        print(f"extend {shape} {bc} {name}: {err:.3e}")
+        assert err <= FP64_TOL, (name, err)
+    # extension recovers the solenoidal part (invariant, GPU result)
+    scale = max(np.abs(a).max() for a in u)
+    for a, b in zip(out[:3], usol):
+        assert np.abs(a.cpu().numpy() - b).max() <= 1e-10 * scale
+
+
+def test_extend_static_droplet(torch_dev):
+    """u = G psi only (pure Stefan flow): u_1^e = 0 and u_Gamma = -q."""
+    torch = torch_dev
+    g = _grid(64, 64, 64, "PPN")
+    psi = vofsynth.gaussian_field(g.shape, 9)
+    u = oracle.grad(psi, g)
+    s = oracle.lap(psi, g)
+    q = vofsynth.random_faces(g.shape, 10, g.bc)
+    out = _plan(g).extend(*(_dev(torch, a) for a in u), _dev(torch, s),
+                          q=tuple(_dev(torch, a) for a in q))
+    scale = max(np.abs(a).max() for a in u)
+    for a in out[:3]:
+        assert np.abs(a.cpu().numpy()).max() <= 1e-10 * scale
+    for a, b in zip(out[3:6], q):
+        assert np.abs(a.cpu().numpy() + b).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("case,dc", [((64, 64, 64, "PPP", None), 1),
+                                     ((128, 128, 128, "PPN", None), 2),
+                                     ((64, 32, 40, "NPN", 1.5), 2)])
+def test_mixed_parity(torch_dev, case, dc):
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 4)
+    f = vofsynth.remove_weighted_mean(f, g.dzf)
+    ref = oracle.solve(f, g)
+    plan = _plan(g, precision="mixed")
+    plan.set_mixed(dc)
+    p = plan.solve(_dev(torch, f))
+    torch.cuda.synchronize()
+    err = rel_l2(p.cpu().numpy(), ref)
+    print(f"mixed {case} dc={dc}: rel L2 {err:.3e}")
+    assert err <= MIXED_TOL, err
+
+
+def test_batched_equals_single(torch_dev):
+    torch = torch_dev
+    g = _grid(64, 32, 24, "PPN", 1.5)
+    fs = [vofsynth.gaussian_field(g.shape, 50 + i) for i in range(3)]
+    plan = _plan(g, max_batch=3)
+    singles = [plan.solve(_dev(torch, f)).cpu().numpy() for f in fs]
+    outs = plan.solve_batched([_dev(torch, f) for f in fs])
+    torch.cuda.synchronize()
+    for a, b, f in zip(outs, singles, fs):
+        assert np.array_equal(a.cpu().numpy(), b)
+        assert rel_l2(b, oracle.solve(f, g)) <= FP64_TOL
+
+
+# ----------------------------------------------------------------------------
+# full benchmark sizes: properties computed with plain torch on the device
+# ----------------------------------------------------------------------------
+def torch_laplacian(torch, p, g):
+    """L_h p with torch.roll / slicing (independent of the library)."""
+    dzf = torch.as_tensor(g.dzf, device=p.device)
+    dzc = torch.as_tensor(np.nan_to_num(g.dzc, nan=1.0), device=p.device)
+
+    def fdiff(a, axis, h, letter):
+        if letter == "P":
+            return (torch.roll(a, -1, dims=axis) - a) / h
+        out = torch.zeros_like(a)
+        n = a.shape[axis]
+        lo = a.narrow(axis, 0, n - 1)
+        hi = a.narrow(axis, 1, n - 1)
+        hh = h if not torch.is_tensor(h) else h.narrow(axis, 0, n - 1)
+        out.narrow(axis, 0, n - 1).copy_((hi - lo) / hh)
+        return out
+
+    def bdiv(a, axis, h, letter):
+        if letter == "P":
+            return (a - torch.roll(a, 1, dims=axis)) / h
+        prev = torch.zeros_like(a)
+        n = a.shape[axis]
+        prev.narrow(axis, 1, n - 1).copy_(a.narrow(axis, 0, n - 1))
+        return (a - prev) / h
+
+    gx = fdiff(p, 2, g.dx, g.bc[0])
+    gy = fdiff(p, 1, g.dy, g.bc[1])
+    gz = fdiff(p, 0, dzc[:, None, None], g.bc[2])
+    return (bdiv(gx, 2, g.dx, g.bc[0]) + bdiv(gy, 1, g.dy, g.bc[1])
+            + bdiv(gz, 0, dzf[:, None, None], g.bc[2]))
+
+
+@pytest.mark.parametrize("name", ["ppn256", "ppn512s"])
+def test_full_size_residual(torch_dev, name):
+    torch = torch_dev
+    cfg = vofsynth.config(name)
+    g = oracle.Grid.from_config(cfg)
+    f = vofsynth.remove_weighted_mean(vofsynth.gaussian_field(g.shape, 200), g.dzf)
+    plan = _plan(g)
+    fd = _dev(torch, f)
+    p = plan.solve(fd)
+    r = torch_laplacian(torch, p, g) - fd
+    rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(fd)).item()
+    dv = torch.as_tensor(g.dzf, device=p.device)[:, None, None]
+    gauge = (p * dv).sum().abs().item() / (p.abs() * dv).sum().item()
+    print(f"{name}: residual {rel:.3e} gauge {gauge:.3e}")
+    assert rel <= 1e-10 and gauge <= 1e-12
