@@ -146,6 +146,16 @@ int poisson_plan_last_mean(poisson_plan* plan, double* mean_out, void* hip_strea
 long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_batch);
 
 /*
+ * Launch-shape tuning (results do not change, only speed):
+ *   "z_lines"   : lines per block of the z pass, 8, 16 (default) or 32
+ *                 (capped so that lines * segments <= 512);
+ *   "xcd_remap" : 1 maps consecutive rows of cells of the stencil
+ *                 kernels to one XCD so their neighbours share its L2; 0 (default) off.
+ * Returns VP_EINVAL for an unknown key or value.
+ */
+int poisson_plan_tune(poisson_plan* plan, const char* key, int value);
+
+/*
  * Per-launch timing.  With profiling enabled, every kernel the plan launches
  * is bracketed by two HIP events recorded on the caller's stream (a small
  * launch overhead).  poisson_plan_kernel_times waits for the recorded events,

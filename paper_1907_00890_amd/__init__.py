@@ -138,6 +138,10 @@ class Plan:
               "poisson_plan_last_mean")
         return out.value
 
+    def tune(self, key: str, value: int):
+        """Launch-shape knob (see poisson_plan_tune); results do not change."""
+        check(_lib.lib.poisson_plan_tune(self._h, key.encode(), int(value)), "poisson_plan_tune")
+
     def set_profiling(self, enable: bool = True):
         """Bracket every kernel launch of this plan with HIP events."""
         check(_lib.lib.poisson_plan_set_profiling(self._h, int(bool(enable))),

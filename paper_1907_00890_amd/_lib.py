@@ -35,6 +35,7 @@ SIGNATURES = {
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_last_mean": (_i, [_p, ctypes.POINTER(_d), _p]),
     "poisson_plan_footprint": (ctypes.c_longlong, [_i, _i, _i, _i, _i]),
+    "poisson_plan_tune": (_i, [_p, ctypes.c_char_p, _i]),
     "poisson_plan_set_profiling": (_i, [_p, _i]),
     "poisson_plan_kernel_times": (_i, [_p, ctypes.POINTER(_d), ctypes.POINTER(_i), _i]),
     "poisson_kernel_class_name": (ctypes.c_char_p, [_i]),

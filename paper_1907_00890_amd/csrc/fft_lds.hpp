@@ -1,17 +1,22 @@
-// Radix-8/4/2 Stockham FFT on lines held in LDS, plus the pre/post steps that
-// turn one complex transform into two real transforms (periodic: real DFT in
-// packed form; walls: DCT-II / DCT-III by the even/odd reordering of
-// J. Makhoul, "A fast cosine transform in one and two dimensions", IEEE
-// TASSP 28(1), 1980).
+// Building blocks of the x and y transforms of the spectral Poisson solve
+// (the constant-coefficient direct solver of section 3.2 diagonalises the
+// 1-D second difference of the staggered grid in x and y).
 //
-// These transforms diagonalise the 1-D second difference of the staggered
-// grid (the constant-coefficient Poisson operator of section 3.2) in x and y.
-//
-// Packed spectrum of one real line of length N (coefficient position c):
-//   periodic:  c=0 -> Re X_0, c=1 -> Re X_{N/2}, c=2m -> Re X_m, c=2m+1 -> Im X_m
-//              (X_m = sum_j x_j e^{-2 pi i j m / N}), eigenvalue index m
-//   walls:     c=m -> X_m = sum_j x_j cos(pi m (2j+1) / (2N)), eigenvalue index m
-// The inverse routines return N times the original line (no 1/N scaling).
+// * Small DFTs in registers (radix 2, 4, 8, 16; radix 16 as 4 x 4).
+// * Stockham passes of radix 16 first, then the remainder (plan<N>):
+//   N = 256 -> 16 x 16, 512 -> 16 x 16 x 2, 1024 -> 16 x 16 x 4.  Each of the
+//   N/16 threads of a line holds 16 complex values; pass p reads positions
+//   j + r N/R and writes (j / NS) NS R + j % NS + r NS (NS = product of the
+//   earlier radices).
+// * Two real lines per complex transform.  Periodic lines use a real DFT in
+//   packed form, wall lines a DCT-II / DCT-III computed through the even/odd
+//   reordering of J. Makhoul ("A fast cosine transform in one and two
+//   dimensions", IEEE TASSP 28(1), 1980).  Packed spectrum of a real line of
+//   length N, coefficient position c:
+//     periodic: c=0 Re X_0, c=1 Re X_{N/2}, c=2m Re X_m, c=2m+1 Im X_m
+//               (X_m = sum_j x_j e^{-2 pi i j m / N}), eigenvalue index m;
+//     walls:    c=m X_m = sum_j x_j cos(pi m (2j+1) / (2N)), eigenvalue index m.
+//   Inverse transforms return N times the line (no 1/N).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -19,12 +24,15 @@
 
 namespace vp {
 
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 // ---------------------------------------------------------------------------
 // small DFTs in registers; SIGN = -1 forward (e^{-i...}), +1 inverse
 // ---------------------------------------------------------------------------
 template <int SIGN, typename T>
-__device__ __forceinline__ void mul_pm_i(T& r, T& i) {
-  // (r + i I) * (SIGN I)
+__device__ __forceinline__ void mul_pm_i(T& r, T& i) {  // (r + i I) * (SIGN I)
   const T tr = r;
   if constexpr (SIGN < 0) { r = i; i = -tr; }
   else { r = -i; i = tr; }
@@ -58,10 +66,10 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   dft4<SIGN>(orr, oi);
   const T h = T(0.70710678118654752440084436210485);
   // w^1 = (1 + SIGN i)/sqrt2, w^2 = SIGN i, w^3 = (-1 + SIGN i)/sqrt2
-  T t1r = (orr[1] - T(SIGN) * oi[1]) * h, t1i = (T(SIGN) * orr[1] + oi[1]) * h;
+  const T t1r = (orr[1] - T(SIGN) * oi[1]) * h, t1i = (T(SIGN) * orr[1] + oi[1]) * h;
   T t2r = orr[2], t2i = oi[2];
   mul_pm_i<SIGN>(t2r, t2i);
-  T t3r = (-orr[3] - T(SIGN) * oi[3]) * h, t3i = (T(SIGN) * orr[3] - oi[3]) * h;
+  const T t3r = (-orr[3] - T(SIGN) * oi[3]) * h, t3i = (T(SIGN) * orr[3] - oi[3]) * h;
   r[0] = er[0] + orr[0]; i[0] = ei[0] + oi[0];
   r[4] = er[0] - orr[0]; i[4] = ei[0] - oi[0];
   r[1] = er[1] + t1r; i[1] = ei[1] + t1i;
@@ -72,9 +80,54 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   r[7] = er[3] - t3r; i[7] = ei[3] - t3i;
 }
 
+// radix 16 as 4 x 4: DFT4 over n1 of x[4 n1 + n2] (index k1), twiddle
+// w16^{n2 k1}, DFT4 over n2; output X[k1 + 4 k2]
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft16(T* r, T* i) {
+  T yr[4][4], yi[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+      yr[n2][n1] = r[4 * n1 + n2];
+      yi[n2][n1] = i[4 * n1 + n2];
+    }
+    dft4<SIGN>(yr[n2], yi[n2]);
+  }
+  const T c1 = T(0.92387953251128675612818318939678828682);   // cos(pi/8)
+  const T s1 = T(0.38268343236508977172845998403039886676);   // sin(pi/8)
+  const T h = T(0.70710678118654752440084436210484903928);    // cos(pi/4)
+  // w16^m = cos(2 pi m/16) + SIGN i sin(2 pi m/16) for m = n2 k1 in 1..9
+  const T wc[10] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1};
+  const T ws[10] = {T(0), s1, h, c1, T(1), c1, h, s1, T(0), -s1};
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      const int m = n2 * k1;
+      const T c = wc[m], s = T(SIGN) * ws[m];
+      const T xr = yr[n2][k1], xi = yi[n2][k1];
+      yr[n2][k1] = xr * c - xi * s;
+      yi[n2][k1] = xr * s + xi * c;
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T zr[4] = {yr[0][k1], yr[1][k1], yr[2][k1], yr[3][k1]};
+    T zi[4] = {yi[0][k1], yi[1][k1], yi[2][k1], yi[3][k1]};
+    dft4<SIGN>(zr, zi);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      r[k1 + 4 * k2] = zr[k2];
+      i[k1 + 4 * k2] = zi[k2];
+    }
+  }
+}
+
 template <int R, int SIGN, typename T>
 __device__ __forceinline__ void dftR(T* r, T* i) {
-  if constexpr (R == 8) dft8<SIGN>(r, i);
+  if constexpr (R == 16) dft16<SIGN>(r, i);
+  else if constexpr (R == 8) dft8<SIGN>(r, i);
   else if constexpr (R == 4) dft4<SIGN>(r, i);
   else dft2<SIGN>(r, i);
 }
@@ -86,179 +139,110 @@ __device__ __forceinline__ int dct_perm(int p) {
 }
 
 // ---------------------------------------------------------------------------
-// Stockham passes.  Each of the TPL threads of a line performs (N/R)/TPL
-// radix-R butterflies per pass; lines are read and written in place in LDS
-// (element e of a line at re[e*es], im[e*es]) with a block barrier between the
-// reads and the writes of every pass.  twc[k] = cos(2 pi k / N) and
-// tws[k] = sin(2 pi k / N) for k in [0, N).
-// PERM_IN permutes the reads of the first pass, PERM_OUT the writes of the
-// last one (the DCT reordering and its inverse).
+// pass bookkeeping
 // ---------------------------------------------------------------------------
-template <typename T, int N, int TPL, int SIGN, bool PERM_IN, bool PERM_OUT, int NS>
-__device__ __forceinline__ void stockham(T* __restrict__ re, T* __restrict__ im, int es, int t,
-                                         const T* __restrict__ twc, const T* __restrict__ tws) {
-  constexpr int REM = N / NS;
-  if constexpr (REM > 1) {
-    constexpr int R = REM >= 8 ? 8 : REM;
-    constexpr int NB = N / R;
-    constexpr int BPT = NB / TPL;
-    static_assert(BPT >= 1 && BPT * TPL == NB, "threads per line must divide N/R");
-    constexpr bool FIRST = (NS == 1);
-    constexpr bool LAST = (NS * R == N);
-    T vr[BPT][R], vi[BPT][R];
+template <int N>
+struct FftShape {
+  static constexpr int PT = N >= 16 ? 16 : N;  // complex values per thread
+  static constexpr int TPL = N / PT;           // threads per line
+};
+template <int N, int NS>
+struct PassRadix {
+  static constexpr int REM = N / NS;
+  static constexpr int R = REM >= 16 ? 16 : REM;
+};
+
+// Twiddles of one pass for this thread: w_N^{(j % NS) r N/(NS R)}, r = 1..R-1,
+// for each of its PT/R butterflies j = t + TPL b.  tab holds cos(2 pi k/N) at
+// [k] and sin(2 pi k/N) at [N + k].
+template <typename T, int N, int NS, int SIGN>
+__device__ __forceinline__ void load_twiddles(const T* __restrict__ tab, int t, T* wr, T* wi) {
+  constexpr int R = PassRadix<N, NS>::R;
+  constexpr int PT = FftShape<N>::PT, TPL = FftShape<N>::TPL;
+  constexpr int B = PT / R;
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int j = t + TPL * b;
+  for (int b = 0; b < B; ++b) {
+    const int k = (t + TPL * b) % NS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int src = j + r * NB;
-        if constexpr (PERM_IN && FIRST) src = dct_perm<N>(src);
-        vr[b][r] = re[src * es];
-        vi[b][r] = im[src * es];
-      }
+    for (int r = 1; r < R; ++r) {
+      const int ti = k * r * (N / (NS * R));
+      wr[b * R + r] = tab[ti];
+      wi[b * R + r] = T(SIGN) * tab[N + ti];
     }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      const int j = t + TPL * b;
-      const int k = j % NS;
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const int ti = k * r * (N / (NS * R));
-          const T wr = twc[ti], wi = T(SIGN) * tws[ti];
-          const T xr = vr[b][r], xi = vi[b][r];
-          vr[b][r] = xr * wr - xi * wi;
-          vi[b][r] = xr * wi + xi * wr;
-        }
-      }
-      dftR<R, SIGN>(vr[b], vi[b]);
-      const int base = (j / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int dst = base + r * NS;
-        if constexpr (PERM_OUT && LAST) dst = dct_perm<N>(dst);
-        re[dst * es] = vr[b][r];
-        im[dst * es] = vi[b][r];
-      }
-    }
-    __syncthreads();
-    stockham<T, N, TPL, SIGN, PERM_IN, PERM_OUT, NS * R>(re, im, es, t, twc, tws);
   }
 }
 
-// ---------------------------------------------------------------------------
-// Forward: two real lines a, b -> their packed spectra (in place).
-// The caller has stored a in the "re" slots and b in the "im" slots; on
-// return the re slots hold a's packed spectrum and the im slots b's.
-// pc[m] = cos(pi m / (2N)), ps[m] = sin(pi m / (2N)) for m in [0, N/2].
-// ---------------------------------------------------------------------------
-template <typename T, int N, int BC, int TPL>
-__device__ __forceinline__ void real_pair_forward(T* __restrict__ a, T* __restrict__ b, int es, int t,
-                                                  const T* __restrict__ twc, const T* __restrict__ tws,
-                                                  const T* __restrict__ pc, const T* __restrict__ ps) {
-  stockham<T, N, TPL, -1, BC == BC_N, false, 1>(a, b, es, t, twc, tws);
-  constexpr int MPT = (N / 2) / TPL;  // modes per thread, m in [0, N/2)
-  static_assert(MPT * TPL == N / 2, "bad TPL");
-  T zr[MPT], zi[MPT], wr[MPT], wi[MPT];
-  T hr = T(0), hi = T(0);  // Z[N/2], read by thread 0
+// twiddle + DFT of the thread's PT/R butterflies of one pass
+template <typename T, int N, int NS, int SIGN>
+__device__ __forceinline__ void pass_compute(T* vr, T* vi, const T* wr, const T* wi) {
+  constexpr int R = PassRadix<N, NS>::R;
+  constexpr int B = FftShape<N>::PT / R;
 #pragma unroll
-  for (int u = 0; u < MPT; ++u) {
-    const int m = t + TPL * u;
-    const int mm = (N - m) & (N - 1);
-    zr[u] = a[m * es]; zi[u] = b[m * es];
-    wr[u] = a[mm * es]; wi[u] = b[mm * es];
-  }
-  if (t == 0) { hr = a[(N / 2) * es]; hi = b[(N / 2) * es]; }
-  __syncthreads();
+  for (int b = 0; b < B; ++b) {
+    if constexpr (NS > 1) {
 #pragma unroll
-  for (int u = 0; u < MPT; ++u) {
-    const int m = t + TPL * u;
-    // A = (Z_m + conj Z_{N-m}) / 2,  B = (Z_m - conj Z_{N-m}) / (2i)
-    const T Ar = T(0.5) * (zr[u] + wr[u]), Ai = T(0.5) * (zi[u] - wi[u]);
-    const T Br = T(0.5) * (zi[u] + wi[u]), Bi = T(0.5) * (wr[u] - zr[u]);
-    if constexpr (BC == BC_P) {
-      if (m == 0) {
-        a[0] = zr[u]; b[0] = zi[u];
-        a[es] = hr; b[es] = hi;
-      } else {
-        a[(2 * m) * es] = Ar; a[(2 * m + 1) * es] = Ai;
-        b[(2 * m) * es] = Br; b[(2 * m + 1) * es] = Bi;
-      }
-    } else {
-      if (m == 0) {
-        const T h = T(0.70710678118654752440084436210485);
-        a[0] = zr[u]; b[0] = zi[u];
-        a[(N / 2) * es] = h * hr; b[(N / 2) * es] = h * hi;
-      } else {
-        // Y = e^{-i pi m/(2N)} V_m;  X_m = Re Y, X_{N-m} = -Im Y
-        const T c = pc[m], s = ps[m];
-        const T yAr = c * Ar + s * Ai, yAi = c * Ai - s * Ar;
-        const T yBr = c * Br + s * Bi, yBi = c * Bi - s * Br;
-        a[m * es] = yAr; a[(N - m) * es] = -yAi;
-        b[m * es] = yBr; b[(N - m) * es] = -yBi;
+      for (int r = 1; r < R; ++r) {
+        const T xr = vr[b * R + r], xi = vi[b * R + r];
+        const T c = wr[b * R + r], s = wi[b * R + r];
+        vr[b * R + r] = xr * c - xi * s;
+        vi[b * R + r] = xr * s + xi * c;
       }
     }
+    dftR<R, SIGN>(vr + b * R, vi + b * R);
   }
-  __syncthreads();
+}
+
+// input position of value (b, r) of a pass, and output position
+template <int N, int NS>
+__device__ __forceinline__ int pass_in(int t, int b, int r) {
+  constexpr int R = PassRadix<N, NS>::R;
+  return t + FftShape<N>::TPL * b + r * (N / R);
+}
+template <int N, int NS>
+__device__ __forceinline__ int pass_out(int t, int b, int r) {
+  constexpr int R = PassRadix<N, NS>::R;
+  const int j = t + FftShape<N>::TPL * b;
+  return (j / NS) * NS * R + (j % NS) + r * NS;
 }
 
 // ---------------------------------------------------------------------------
-// Inverse: two packed spectra (re slots: line a, im slots: line b) -> N times
-// the two real lines, in place.
+// two real lines <-> one complex line: per-mode pre/post steps.
+// For mode m in [1, N/2) the two spectra A_m, B_m of the real lines a, b
+// follow from Z_m and Z_{N-m} of Z = FFT(a + i b):
+//   A = (Z_m + conj Z_{N-m}) / 2,  B = (Z_m - conj Z_{N-m}) / (2i).
+// pc[m] = cos(pi m/(2N)), ps[m] = sin(pi m/(2N)) (the DCT rotation).
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC, int TPL>
-__device__ __forceinline__ void real_pair_inverse(T* __restrict__ a, T* __restrict__ b, int es, int t,
-                                                  const T* __restrict__ twc, const T* __restrict__ tws,
-                                                  const T* __restrict__ pc, const T* __restrict__ ps) {
-  constexpr int MPT = (N / 2) / TPL;
-  T z0r[MPT], z0i[MPT], z1r[MPT], z1i[MPT];
-  T hr = T(0), hi = T(0);
-#pragma unroll
-  for (int u = 0; u < MPT; ++u) {
-    const int m = t + TPL * u;
+template <typename T, int N, int BC>
+struct RealPair {
+  // forward: Z_m, Z_{N-m} -> outputs: periodic (a[2m], a[2m+1], b[2m], b[2m+1]);
+  // walls (a[m], a[N-m], b[m], b[N-m])
+  static __device__ __forceinline__ void post(T zr, T zi, T wr, T wi, T c, T s, T* oa, T* ob) {
+    const T Ar = T(0.5) * (zr + wr), Ai = T(0.5) * (zi - wi);
+    const T Br = T(0.5) * (zi + wi), Bi = T(0.5) * (wr - zr);
     if constexpr (BC == BC_P) {
-      if (m == 0) {
-        z0r[u] = a[0]; z0i[u] = b[0];
-        hr = a[es]; hi = b[es];
-        z1r[u] = T(0); z1i[u] = T(0);
-      } else {
-        const T Ar = a[(2 * m) * es], Ai = a[(2 * m + 1) * es];
-        const T Br = b[(2 * m) * es], Bi = b[(2 * m + 1) * es];
-        z0r[u] = Ar - Bi; z0i[u] = Ai + Br;   // Z_m = A + iB
-        z1r[u] = Ar + Bi; z1i[u] = Br - Ai;   // Z_{N-m} = conj A + i conj B
-      }
+      oa[0] = Ar; oa[1] = Ai;
+      ob[0] = Br; ob[1] = Bi;
     } else {
-      if (m == 0) {
-        const T r2 = T(1.4142135623730950488016887242097);
-        z0r[u] = a[0]; z0i[u] = b[0];
-        hr = r2 * a[(N / 2) * es]; hi = r2 * b[(N / 2) * es];
-        z1r[u] = T(0); z1i[u] = T(0);
-      } else {
-        // V_m = e^{+i pi m/(2N)} (X_m - i X_{N-m})
-        const T c = pc[m], s = ps[m];
-        const T xa = a[m * es], xan = a[(N - m) * es];
-        const T xb = b[m * es], xbn = b[(N - m) * es];
-        const T vAr = c * xa + s * xan, vAi = s * xa - c * xan;
-        const T vBr = c * xb + s * xbn, vBi = s * xb - c * xbn;
-        z0r[u] = vAr - vBi; z0i[u] = vAi + vBr;
-        z1r[u] = vAr + vBi; z1i[u] = vBr - vAi;
-      }
+      // Y = e^{-i pi m/(2N)} V_m;  X_m = Re Y, X_{N-m} = -Im Y
+      oa[0] = c * Ar + s * Ai; oa[1] = -(c * Ai - s * Ar);
+      ob[0] = c * Br + s * Bi; ob[1] = -(c * Bi - s * Br);
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < MPT; ++u) {
-    const int m = t + TPL * u;
-    a[m * es] = z0r[u]; b[m * es] = z0i[u];
-    if (m == 0) {
-      a[(N / 2) * es] = hr; b[(N / 2) * es] = hi;
+  // inverse: packed inputs of mode m -> Z_m, Z_{N-m}
+  static __device__ __forceinline__ void pre(const T* ia, const T* ib, T c, T s, T& z0r, T& z0i,
+                                             T& z1r, T& z1i) {
+    if constexpr (BC == BC_P) {
+      const T Ar = ia[0], Ai = ia[1], Br = ib[0], Bi = ib[1];
+      z0r = Ar - Bi; z0i = Ai + Br;   // A + iB
+      z1r = Ar + Bi; z1i = Br - Ai;   // conj A + i conj B
     } else {
-      a[(N - m) * es] = z1r[u]; b[(N - m) * es] = z1i[u];
+      // V_m = e^{+i pi m/(2N)} (X_m - i X_{N-m}); ia = (X_m, X_{N-m})
+      const T vAr = c * ia[0] + s * ia[1], vAi = s * ia[0] - c * ia[1];
+      const T vBr = c * ib[0] + s * ib[1], vBi = s * ib[0] - c * ib[1];
+      z0r = vAr - vBi; z0i = vAi + vBr;
+      z1r = vAr + vBi; z1i = vBr - vAi;
     }
   }
-  __syncthreads();
-  stockham<T, N, TPL, +1, false, BC == BC_N, 1>(a, b, es, t, twc, tws);
-}
+};
 
 }  // namespace vp

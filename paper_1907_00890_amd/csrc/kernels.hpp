@@ -39,7 +39,8 @@ struct ZArgs {
   long plane;          // nx * ny lines
   int nx;              // for the (cx, cy) split of a line index
   int nz;
-  int seg;             // segment length bound M (16 or 32)
+  int seg;             // segment length bound M (16)
+  int lines;           // lines per block (8, 16 or 32; capped so lines * nseg <= 512)
   int nseg;            // S segments per line
   int seg_base;        // nz / S
   int seg_rem;         // nz % S (first seg_rem segments are one longer)
@@ -61,6 +62,8 @@ hipError_t launch_zsolve_f32(float* data, const ZArgs& a, hipStream_t st);
 // stencils.hip ---------------------------------------------------------------
 struct GridArgs {
   int nx, ny, nz;
+  int lx, ly;          // log2(nx), log2(ny): nx and ny are powers of two
+  int xcd_remap;       // map consecutive rows of cells to one XCD (L2 reuse of y/z neighbours)
   int bcx, bcy, bcz;   // 0 periodic, 1 wall
   double dx, dy;
   const double* dzf;   // nz

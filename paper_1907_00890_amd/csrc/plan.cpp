@@ -221,6 +221,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.nx = nx;
   Z.nz = nz;
   Z.seg = 16;
+  Z.lines = 16;
   Z.nseg = (nz + Z.seg - 1) / Z.seg;
   Z.seg_base = nz / Z.nseg;
   Z.seg_rem = nz % Z.nseg;
@@ -238,9 +239,14 @@ int plan_init(poisson_plan* P, const double* dz) {
 
   vp::GridArgs& G = P->g;
   G.nx = nx; G.ny = ny; G.nz = nz;
+  G.lx = 0;
+  while ((1 << G.lx) < nx) ++G.lx;
+  G.ly = 0;
+  while ((1 << G.ly) < ny) ++G.ly;
   G.bcx = P->bc[0]; G.bcy = P->bc[1]; G.bcz = P->bc[2];
   G.dx = P->dx; G.dy = P->dy;
   G.dzf = P->dzf; G.dzc = P->dzc;
+  G.xcd_remap = 0;
   return VP_OK;
 }
 
@@ -441,6 +447,22 @@ const char* poisson_strerror(int status) {
     case VP_EHIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
     default: return "unknown status";
   }
+}
+
+int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
+  if (!P || !key) return VP_EINVAL;
+  const std::string k(key);
+  if (k == "z_lines") {
+    if (value != 8 && value != 16 && value != 32) return VP_EINVAL;
+    P->z.lines = value;
+    return VP_OK;
+  }
+  if (k == "xcd_remap") {
+    if (value != 0 && value != 1) return VP_EINVAL;
+    P->g.xcd_remap = value;
+    return VP_OK;
+  }
+  return VP_EINVAL;
 }
 
 int poisson_plan_set_profiling(poisson_plan* P, int enable) {

@@ -20,9 +20,9 @@ struct Nb {
 
 __device__ __forceinline__ Nb neighbours(const GridArgs& g, long idx) {
   const long plane = (long)g.nx * g.ny;
-  const int i = (int)(idx % g.nx);
-  const int j = (int)((idx / g.nx) % g.ny);
-  const int k = (int)(idx / plane);
+  const int i = (int)(idx & (g.nx - 1));
+  const int j = (int)((idx >> g.lx) & (g.ny - 1));
+  const int k = (int)(idx >> (g.lx + g.ly));
   Nb n;
   n.c = idx;
   n.k = k;
@@ -33,6 +33,18 @@ __device__ __forceinline__ Nb neighbours(const GridArgs& g, long idx) {
   n.zp = k + 1 < g.nz ? idx + plane : (g.bcz == 0 ? idx - (long)(g.nz - 1) * plane : -1);
   n.zm = k > 0 ? idx - plane : (g.bcz == 0 ? idx + (long)(g.nz - 1) * plane : -1);
   return n;
+}
+
+// Logical block index.  Workgroups are dealt to the 8 XCDs of the chip in
+// turn, each XCD with its own L2; with the remap, XCD x runs a contiguous
+// range of blocks, so the rows above and below a block (its y and z
+// neighbours) are mostly read by the same XCD and come from its L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long logical_block(const GridArgs& g, long nblocks) {
+  const long b = blockIdx.x;
+  if (!g.xcd_remap) return b;
+  const long per = (nblocks + kXcds - 1) / kXcds;
+  return (b % kXcds) * per + b / kXcds;
 }
 
 // inverse of the face density 1 / ((rho_a + rho_b) / 2)
@@ -46,7 +58,7 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
                                               const double* __restrict__ rho, double rho0,
                                               const double* __restrict__ src, double dt,
                                               double* __restrict__ b, long n) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
   if (idx >= n) return;
   const Nb nb = neighbours(g, idx);
   const double ir0 = 1.0 / rho0;
@@ -81,7 +93,7 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
                                                   const double* __restrict__ ph,
                                                   const double* __restrict__ rho, double rho0,
                                                   double dt, long n) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
   if (idx >= n) return;
   const Nb nb = neighbours(g, idx);
   const double ir0 = 1.0 / rho0;
@@ -113,7 +125,7 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
                                                  double* __restrict__ we, double* __restrict__ ug,
                                                  double* __restrict__ vg, double* __restrict__ wg,
                                                  long n) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
   if (idx >= n) return;
   const Nb nb = neighbours(g, idx);
   const double f0 = phi[idx];
@@ -181,7 +193,12 @@ __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = red[0] / denom;
 }
 
-static inline dim3 grid_for(long n) { return dim3((unsigned)((n + 255) / 256)); }
+// grid of 256-thread blocks, rounded up to a multiple of the XCD count so
+// that the remapped logical blocks cover [0, nblocks)
+static inline dim3 grid_for(long n) {
+  const long nb = (n + 255) / 256;
+  return dim3((unsigned)((nb + kXcds - 1) / kXcds * kXcds));
+}
 
 hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const double* w,
                       const double* phat, const double* rho, double rho0, const double* src,

@@ -1,12 +1,16 @@
 // x and y passes of the spectral Poisson solve: real-to-real transforms of
-// every x-line (contiguous rows) and every y-line (columns of a z-plane).
+// every x-line (contiguous rows) and every y-line (columns of a z-plane), two
+// real lines per complex FFT (see fft_lds.hpp for the packed spectra).
 //
-// x pass: a block owns RPB = 4096/N consecutive rows (one contiguous chunk
-// of 4096 values), pairs them as (re, im) lines and transforms 2 real rows
-// with one complex FFT.  y pass: a block owns a tile of C consecutive columns
-// of one z-plane, pairs neighbouring columns the same way; each row of the
-// tile is one C-wide contiguous chunk in memory.  Both passes stage the
-// block's data in LDS, so global loads and stores stay coalesced.
+// Data path of a forward pass: the first Stockham pass loads straight from
+// HBM into registers (a line's N/16 threads read consecutive addresses), the
+// intermediate passes exchange through LDS, and the real-pair step reads the
+// last pass from LDS and writes the packed spectrum straight to HBM.  The
+// inverse mirrors it: the real-pair step loads from HBM into LDS and the last
+// Stockham pass stores to HBM.  One block owns 2*LPB whole rows (x) or a
+// tile of 2*LINES columns of one z-plane (y), so every HBM access is a
+// contiguous chunk.  LDS rows are padded by one slot every 16 values, which
+// spreads the strided writes of the first pass over the banks.
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.hpp"
@@ -14,178 +18,432 @@
 
 namespace vp {
 
-// ---------------------------------------------------------------------------
-// x pass
-// ---------------------------------------------------------------------------
-template <typename TI, typename T, typename TO, int N, int BC, bool FWD, bool ACCUM>
-__global__ __launch_bounds__(256) void k_xpass(const TI* __restrict__ in, TO* __restrict__ out,
-                                                long nrows, const T* __restrict__ tab,
-                                                const double* __restrict__ sub) {
-  constexpr int TPL = N / 8;
-  constexpr int LPB = 256 / TPL;  // complex lines per block
-  constexpr int RPB = 2 * LPB;    // real rows per block
-  constexpr int LD = N + 1;       // padded LDS row stride
-  __shared__ T lds[RPB * LD];
-  const int tid = threadIdx.x;
-  const long row0 = (long)blockIdx.x * RPB;
-  const long nval = (nrows - row0 < RPB ? nrows - row0 : RPB) * (long)N;
-  const long g0 = row0 * N;
+__device__ __forceinline__ int lds_pos(int e) { return e + (e >> 4); }
+template <int N>
+constexpr int lds_len() {
+  return N + N / 16 + 1;
+}
 
-#pragma unroll 4
-  for (int e = tid; e < RPB * N; e += 256) {
-    const int r = e / N, c = e % N;
-    lds[r * LD + c] = e < nval ? T(in[g0 + e]) : T(0);
+// ---------------------------------------------------------------------------
+// LDS access policies: x lines as separate re/im rows, y lines interleaved
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+struct XLds {
+  T* re;
+  T* im;
+  __device__ XLds(T* base, int q, int lpb) {
+    re = base + q * lds_len<N>();
+    im = base + (lpb + q) * lds_len<N>();
   }
-  __syncthreads();
+  __device__ void put(int e, T r, T i) {
+    re[lds_pos(e)] = r;
+    im[lds_pos(e)] = i;
+  }
+  __device__ void get(int e, T& r, T& i) const {
+    r = re[lds_pos(e)];
+    i = im[lds_pos(e)];
+  }
+};
 
-  const int q = tid / TPL, t = tid % TPL;
-  T* a = lds + (2 * q) * LD;
-  T* b = lds + (2 * q + 1) * LD;
-  const T* twc = tab;
-  const T* tws = tab + N;
+template <typename T, int N>
+struct YLds {
+  using T2 = typename Vec2<T>::type;
+  T2* base;
+  int lp;
+  __device__ YLds(T2* b, int q, int lines) : base(b + q), lp(lines + 1) {}
+  __device__ void put(int e, T r, T i) {
+    T2 v;
+    v.x = r;
+    v.y = i;
+    base[lds_pos(e) * lp] = v;
+  }
+  __device__ void get(int e, T& r, T& i) const {
+    const T2 v = base[lds_pos(e) * lp];
+    r = v.x;
+    i = v.y;
+  }
+};
+
+// Stockham passes after the first one, through LDS (in place).  With
+// LAST_IN_REGS the last pass stays in registers (the caller stores it);
+// otherwise it is written back to LDS.  Twiddle loads are issued before the
+// barrier they wait on.
+template <typename T, int N, int NS, int SIGN, bool LAST_IN_REGS, typename L>
+__device__ __forceinline__ void later_passes(L& lds, int t, const T* __restrict__ tab, T* vr,
+                                             T* vi) {
+  if constexpr (NS < N) {
+    constexpr int R = PassRadix<N, NS>::R;
+    constexpr int B = FftShape<N>::PT / R;
+    constexpr bool LAST = (NS * R == N);
+    T wr[FftShape<N>::PT], wi[FftShape<N>::PT];
+    if constexpr (NS > 1) load_twiddles<T, N, NS, SIGN>(tab, t, wr, wi);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds.get(pass_in<N, NS>(t, b, r), vr[b * R + r], vi[b * R + r]);
+    __syncthreads();
+    pass_compute<T, N, NS, SIGN>(vr, vi, wr, wi);
+    if constexpr (!(LAST && LAST_IN_REGS)) {
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds.put(pass_out<N, NS>(t, b, r), vr[b * R + r], vi[b * R + r]);
+    }
+    later_passes<T, N, NS * R, SIGN, LAST_IN_REGS>(lds, t, tab, vr, vi);
+  }
+}
+
+// stride NS of the last pass of the plan for length N
+template <int N, int NS = 1>
+constexpr int last_ns() {
+  if constexpr (NS * PassRadix<N, NS>::R == N) return NS;
+  else return last_ns<N, NS * PassRadix<N, NS>::R>();
+}
+
+// ---------------------------------------------------------------------------
+// forward pass body shared by x and y: `load(e, re, im)` gives element e of
+// lines a and b; `store(c0, a0, b0, c1, a1, b1)` writes packed coefficients
+// c0 and c1 of both lines
+// ---------------------------------------------------------------------------
+template <typename T, int N, int BC, typename L, typename Load, typename Store>
+__device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict__ tab, Load load,
+                                             Store store) {
+  using S = FftShape<N>;
+  constexpr int PT = S::PT, TPL = S::TPL;
+  constexpr int R1 = PassRadix<N, 1>::R;
+  T vr[PT], vi[PT];
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    int e = t + r * TPL;
+    if constexpr (BC == BC_N) e = dct_perm<N>(e);
+    load(e, vr[r], vi[r]);
+  }
+  {
+    T wr[PT], wi[PT];
+    pass_compute<T, N, 1, -1>(vr, vi, wr, wi);
+  }
+#pragma unroll
+  for (int b = 0; b < PT / R1; ++b)
+#pragma unroll
+    for (int r = 0; r < R1; ++r) lds.put(pass_out<N, 1>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
+  later_passes<T, N, R1, -1, false>(lds, t, tab, vr, vi);
+  __syncthreads();
   const T* pc = tab + 2 * N;
   const T* ps = tab + 2 * N + (N / 2 + 1);
-  if constexpr (FWD)
-    real_pair_forward<T, N, BC, TPL>(a, b, 1, t, twc, tws, pc, ps);
-  else
-    real_pair_inverse<T, N, BC, TPL>(a, b, 1, t, twc, tws, pc, ps);
-
-  TO shift = TO(0);
-  if constexpr (ACCUM) {
-    if (sub) shift = TO(sub[0]);
-  }
-#pragma unroll 4
-  for (int e = tid; e < RPB * N; e += 256) {
-    if (e < nval) {
-      const int r = e / N, c = e % N;
-      if constexpr (ACCUM)
-        out[g0 + e] += TO(lds[r * LD + c]) - shift;
+#pragma unroll
+  for (int u = 0; u < PT / 2; ++u) {
+    const int m = t + TPL * u;
+    T zr, zi;
+    lds.get(m, zr, zi);
+    if (m == 0) {
+      T hr, hi;
+      lds.get(N / 2, hr, hi);
+      if constexpr (BC == BC_P) {
+        store(0, zr, zi, 1, hr, hi);
+      } else {
+        const T h = T(0.70710678118654752440084436210485);
+        store(0, zr, zi, N / 2, h * hr, h * hi);
+      }
+    } else {
+      T wr, wi;
+      lds.get(N - m, wr, wi);
+      T oa[2], ob[2];
+      RealPair<T, N, BC>::post(zr, zi, wr, wi, pc[m], ps[m], oa, ob);
+      if constexpr (BC == BC_P)
+        store(2 * m, oa[0], ob[0], 2 * m + 1, oa[1], ob[1]);
       else
-        out[g0 + e] = TO(lds[r * LD + c]);
+        store(m, oa[0], ob[0], N - m, oa[1], ob[1]);
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// y pass: block (tile, plane); tile = C columns x N rows, threads = (C/2)*(N/8)
-// ---------------------------------------------------------------------------
-template <typename T, int N, int BC, bool FWD>
-__global__ __launch_bounds__(1024) void k_ypass(T* __restrict__ data, int nx, long plane, int C,
-                                                 const T* __restrict__ tab) {
-  constexpr int TPL = N / 8;
-  extern __shared__ unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
-  const int CS = C + 1;  // padded tile row stride
-  const int nthr = (C / 2) * TPL;
-  const int tid = threadIdx.x;
-  const long base = (long)blockIdx.y * plane + (long)blockIdx.x * C;
-
-  for (int e = tid; e < N * C; e += nthr) {
-    const int j = e / C, c = e % C;
-    tile[j * CS + c] = data[base + (long)j * nx + c];
-  }
-  __syncthreads();
-
-  const int p = tid % (C / 2), t = tid / (C / 2);
-  T* a = tile + 2 * p;
-  T* b = tile + 2 * p + 1;
-  const T* twc = tab;
-  const T* tws = tab + N;
+// inverse body: `load2(c0, c1, a0, b0, a1, b1)` reads packed coefficients c0
+// and c1 of both lines; `store(e, re, im)` writes element e of lines a and b
+template <typename T, int N, int BC, typename L, typename Load2, typename Store>
+__device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict__ tab, Load2 load2,
+                                             Store store) {
+  using S = FftShape<N>;
+  constexpr int PT = S::PT, TPL = S::TPL;
   const T* pc = tab + 2 * N;
   const T* ps = tab + 2 * N + (N / 2 + 1);
-  if constexpr (FWD)
-    real_pair_forward<T, N, BC, TPL>(a, b, CS, t, twc, tws, pc, ps);
-  else
-    real_pair_inverse<T, N, BC, TPL>(a, b, CS, t, twc, tws, pc, ps);
-
-  for (int e = tid; e < N * C; e += nthr) {
-    const int j = e / C, c = e % C;
-    data[base + (long)j * nx + c] = tile[j * CS + c];
+#pragma unroll
+  for (int u = 0; u < PT / 2; ++u) {
+    const int m = t + TPL * u;
+    if (m == 0) {
+      T a0, b0, a1, b1;
+      if constexpr (BC == BC_P) {
+        load2(0, 1, a0, b0, a1, b1);
+      } else {
+        load2(0, N / 2, a0, b0, a1, b1);
+        const T r2 = T(1.4142135623730950488016887242097);
+        a1 *= r2;
+        b1 *= r2;
+      }
+      lds.put(0, a0, b0);
+      lds.put(N / 2, a1, b1);
+    } else {
+      T ia[2], ib[2];
+      if constexpr (BC == BC_P)
+        load2(2 * m, 2 * m + 1, ia[0], ib[0], ia[1], ib[1]);
+      else
+        load2(m, N - m, ia[0], ib[0], ia[1], ib[1]);
+      T z0r, z0i, z1r, z1i;
+      RealPair<T, N, BC>::pre(ia, ib, pc[m], ps[m], z0r, z0i, z1r, z1i);
+      lds.put(m, z0r, z0i);
+      lds.put(N - m, z1r, z1i);
+    }
   }
+  T vr[PT], vi[PT];
+  later_passes<T, N, 1, +1, true>(lds, t, tab, vr, vi);
+  // the last pass is in registers: store to HBM
+  constexpr int NSL = last_ns<N>();
+  constexpr int RL = PassRadix<N, NSL>::R;
+#pragma unroll
+  for (int b = 0; b < PT / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int e = pass_out<N, NSL>(t, b, r);
+      if constexpr (BC == BC_N) e = dct_perm<N>(e);
+      store(e, vr[b * RL + r], vi[b * RL + r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x kernels: a block owns 2*LPB consecutive rows (nrows is even)
+// ---------------------------------------------------------------------------
+template <typename TI, typename T, int N, int BC>
+__global__ __launch_bounds__(256) void k_xfwd(const TI* __restrict__ in, T* __restrict__ out,
+                                               long nrows, const T* __restrict__ tab) {
+  constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
+  __shared__ T lds_mem[2 * LPB * lds_len<N>()];
+  const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
+  const bool ok = ra < nrows;
+  const TI* ga = in + ra * N;
+  const TI* gb = ga + N;
+  T* oa = out + ra * N;
+  T* ob = oa + N;
+  XLds<T, N> lds(lds_mem, q, LPB);
+  forward_body<T, N, BC>(
+      lds, t, tab,
+      [&](int e, T& r, T& i) {
+        r = ok ? T(ga[e]) : T(0);
+        i = ok ? T(gb[e]) : T(0);
+      },
+      [&](int c0, T a0, T b0, int c1, T a1, T b1) {
+        if (!ok) return;
+        oa[c0] = a0;
+        ob[c0] = b0;
+        oa[c1] = a1;
+        ob[c1] = b1;
+      });
+}
+
+template <typename T, typename TO, int N, int BC, bool ACCUM>
+__global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, TO* __restrict__ out,
+                                               long nrows, const T* __restrict__ tab,
+                                               const double* __restrict__ sub) {
+  constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
+  __shared__ T lds_mem[2 * LPB * lds_len<N>()];
+  const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
+  const bool ok = ra < nrows;
+  const T* ia = in + ra * N;
+  const T* ib = ia + N;
+  TO* oa = out + ra * N;
+  TO* ob = oa + N;
+  TO shift = TO(0);
+  if constexpr (ACCUM) {
+    if (sub) shift = TO(sub[0]);
+  }
+  XLds<T, N> lds(lds_mem, q, LPB);
+  inverse_body<T, N, BC>(
+      lds, t, tab,
+      [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
+        a0 = ok ? ia[c0] : T(0);
+        b0 = ok ? ib[c0] : T(0);
+        a1 = ok ? ia[c1] : T(0);
+        b1 = ok ? ib[c1] : T(0);
+      },
+      [&](int e, T r, T i) {
+        if (!ok) return;
+        if constexpr (ACCUM) {
+          oa[e] += TO(r) - shift;
+          ob[e] += TO(i) - shift;
+        } else {
+          oa[e] = TO(r);
+          ob[e] = TO(i);
+        }
+      });
+}
+
+// ---------------------------------------------------------------------------
+// y kernels: block (tile, plane); tile = 2*lines columns x N rows; thread
+// (q, t) with q fastest, so a wavefront reads 2*lines consecutive columns
+// ---------------------------------------------------------------------------
+template <typename T, int N, int BC>
+__global__ __launch_bounds__(256) void k_yfwd(T* __restrict__ data, int nx, long plane, int llines,
+                                               const T* __restrict__ tab) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int lines = 1 << llines;
+  const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
+  T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
+                                  2 * q);
+  const int nx2 = nx >> 1;  // row stride in T2 units
+  YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
+  forward_body<T, N, BC>(
+      lds, t, tab,
+      [&](int e, T& r, T& i) {
+        const T2 v = col[(long)e * nx2];
+        r = v.x;
+        i = v.y;
+      },
+      [&](int c0, T a0, T b0, int c1, T a1, T b1) {
+        T2 v0, v1;
+        v0.x = a0;
+        v0.y = b0;
+        v1.x = a1;
+        v1.y = b1;
+        col[(long)c0 * nx2] = v0;
+        col[(long)c1 * nx2] = v1;
+      });
+}
+
+template <typename T, int N, int BC>
+__global__ __launch_bounds__(256) void k_yinv(T* __restrict__ data, int nx, long plane, int llines,
+                                               const T* __restrict__ tab) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int lines = 1 << llines;
+  const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
+  T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
+                                  2 * q);
+  const int nx2 = nx >> 1;
+  YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
+  inverse_body<T, N, BC>(
+      lds, t, tab,
+      [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
+        const T2 v0 = col[(long)c0 * nx2], v1 = col[(long)c1 * nx2];
+        a0 = v0.x;
+        b0 = v0.y;
+        a1 = v1.x;
+        b1 = v1.y;
+      },
+      [&](int e, T r, T i) {
+        T2 v;
+        v.x = r;
+        v.y = i;
+        col[(long)e * nx2] = v;
+      });
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-template <typename TI, typename T, typename TO, int BC, bool FWD, bool ACCUM>
-static hipError_t launch_x_bc(const void* in, void* out, int n, long nrows, const void* tab,
-                              const double* sub, hipStream_t st) {
-  const long rpb = 2 * (256 / (n / 8));
-  const dim3 grid((unsigned)((nrows + rpb - 1) / rpb));
-  const TI* i = static_cast<const TI*>(in);
-  TO* o = static_cast<TO*>(out);
-  const T* tb = static_cast<const T*>(tab);
-#define VP_XCASE(NN)                                                                     \
-  case NN:                                                                               \
-    hipLaunchKernelGGL((k_xpass<TI, T, TO, NN, BC, FWD, ACCUM>), grid, dim3(256), 0, st, \
-                       i, o, nrows, tb, sub);                                            \
-    break;
+#define VP_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename TI, typename T, int BC>
+static hipError_t launch_xfwd_bc(const TI* in, T* out, int n, long nrows, const T* tab,
+                                 hipStream_t st) {
+#define VP_XF(NN)                                                                          \
+  case NN: {                                                                               \
+    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                        \
+    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC>), dim3((unsigned)((nrows + rpb - 1) / rpb)), \
+                       dim3(256), 0, st, in, out, nrows, tab);                             \
+    break;                                                                                 \
+  }
   switch (n) {
-    VP_XCASE(8) VP_XCASE(16) VP_XCASE(32) VP_XCASE(64) VP_XCASE(128) VP_XCASE(256)
-    VP_XCASE(512) VP_XCASE(1024)
+    VP_SIZES(VP_XF)
     default: return hipErrorInvalidValue;
   }
-#undef VP_XCASE
+#undef VP_XF
   return hipGetLastError();
 }
 
-template <typename TI, typename T, typename TO, bool FWD, bool ACCUM>
-static hipError_t launch_x(const void* in, void* out, int n, int bc, long nrows, const void* tab,
-                           hipStream_t st, const double* sub = nullptr) {
-  return bc == BC_P ? launch_x_bc<TI, T, TO, BC_P, FWD, ACCUM>(in, out, n, nrows, tab, sub, st)
-                    : launch_x_bc<TI, T, TO, BC_N, FWD, ACCUM>(in, out, n, nrows, tab, sub, st);
-}
-
-int ypass_tile_cols(int nx, int ny) {
-  int c = 4096 / ny;
-  if (c < 16) c = 16;
-  if (c > nx) c = nx;
-  return c;
-}
-
-template <typename T, int BC, bool FWD>
-static hipError_t launch_y_bc(void* data, int nx, int ny, int nz, const void* tab, hipStream_t st) {
-  const int C = ypass_tile_cols(nx, ny);
-  const int nthr = (C / 2) * (ny / 8);
-  const size_t shm = sizeof(T) * (size_t)ny * (C + 1);
-  const dim3 grid((unsigned)(nx / C), (unsigned)nz);
-  T* d = static_cast<T*>(data);
-  const T* tb = static_cast<const T*>(tab);
-  const long plane = (long)nx * ny;
-#define VP_YCASE(NN)                                                                        \
-  case NN:                                                                                  \
-    if (shm > 65536) {                                                                      \
-      const hipError_t e = allow_large_lds(&k_ypass<T, NN, BC, FWD>);                       \
-      if (e != hipSuccess) return e;                                                        \
-    }                                                                                       \
-    hipLaunchKernelGGL((k_ypass<T, NN, BC, FWD>), grid, dim3(nthr), shm, st, d, nx, plane, C, \
-                       tb);                                                                 \
-    break;
-  switch (ny) {
-    VP_YCASE(8) VP_YCASE(16) VP_YCASE(32) VP_YCASE(64) VP_YCASE(128) VP_YCASE(256)
-    VP_YCASE(512) VP_YCASE(1024)
+template <typename T, typename TO, int BC, bool ACCUM>
+static hipError_t launch_xinv_bc(const T* in, TO* out, int n, long nrows, const T* tab,
+                                 const double* sub, hipStream_t st) {
+#define VP_XI(NN)                                                                          \
+  case NN: {                                                                               \
+    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                        \
+    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM>),                                     \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb)), dim3(256), 0, st, in, out, \
+                       nrows, tab, sub);                                                   \
+    break;                                                                                 \
+  }
+  switch (n) {
+    VP_SIZES(VP_XI)
     default: return hipErrorInvalidValue;
   }
-#undef VP_YCASE
+#undef VP_XI
+  return hipGetLastError();
+}
+
+// y tile: `lines` column pairs per block, 256 threads when the plane is wide
+// enough; 2*lines columns divide nx (both powers of two)
+static int ypass_lines(int nx, int ny) {
+  const int tpl = ny >= 16 ? ny / 16 : 1;
+  int lines = 256 / tpl;
+  if (lines < 1) lines = 1;
+  if (lines > nx / 2) lines = nx / 2;
+  return lines;
+}
+
+int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
+
+template <typename T, int BC, bool FWD>
+static hipError_t launch_y_bc(T* data, int nx, int ny, int nz, const T* tab, hipStream_t st) {
+  using T2 = typename Vec2<T>::type;
+  const int lines = ypass_lines(nx, ny);
+  int ll = 0;
+  while ((1 << ll) < lines) ++ll;
+  const long plane = (long)nx * ny;
+  const dim3 grid((unsigned)(nx / (2 * lines)), (unsigned)nz);
+#define VP_Y(NN)                                                                   \
+  case NN: {                                                                       \
+    const int nthr = lines * FftShape<NN>::TPL;                                    \
+    const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);           \
+    auto kern = FWD ? &k_yfwd<T, NN, BC> : &k_yinv<T, NN, BC>;                     \
+    if (shm > 65536) {                                                             \
+      const hipError_t e = allow_large_lds(kern);                                  \
+      if (e != hipSuccess) return e;                                               \
+    }                                                                              \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, ll, tab); \
+    break;                                                                         \
+  }
+  switch (ny) {
+    VP_SIZES(VP_Y)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_Y
   return hipGetLastError();
 }
 
 hipError_t launch_xfwd_f64(const double* in, double* out, int nx, int bc, long nrows,
                            const double* tab, hipStream_t st) {
-  return launch_x<double, double, double, true, false>(in, out, nx, bc, nrows, tab, st);
+  return bc == BC_P ? launch_xfwd_bc<double, double, BC_P>(in, out, nx, nrows, tab, st)
+                    : launch_xfwd_bc<double, double, BC_N>(in, out, nx, nrows, tab, st);
 }
 hipError_t launch_xinv_f64(const double* in, double* out, int nx, int bc, long nrows,
                            const double* tab, hipStream_t st) {
-  return launch_x<double, double, double, false, false>(in, out, nx, bc, nrows, tab, st);
+  return bc == BC_P
+             ? launch_xinv_bc<double, double, BC_P, false>(in, out, nx, nrows, tab, nullptr, st)
+             : launch_xinv_bc<double, double, BC_N, false>(in, out, nx, nrows, tab, nullptr, st);
 }
 hipError_t launch_xfwd_f32(const double* in, float* out, int nx, int bc, long nrows,
                            const float* tab, hipStream_t st) {
-  return launch_x<double, float, float, true, false>(in, out, nx, bc, nrows, tab, st);
+  return bc == BC_P ? launch_xfwd_bc<double, float, BC_P>(in, out, nx, nrows, tab, st)
+                    : launch_xfwd_bc<double, float, BC_N>(in, out, nx, nrows, tab, st);
 }
 hipError_t launch_xinv_f32(const float* in, double* out, int nx, int bc, long nrows, bool accum,
                            const double* sub, const float* tab, hipStream_t st) {
-  return accum ? launch_x<float, float, double, false, true>(in, out, nx, bc, nrows, tab, st, sub)
-               : launch_x<float, float, double, false, false>(in, out, nx, bc, nrows, tab, st);
+  if (bc == BC_P)
+    return accum ? launch_xinv_bc<float, double, BC_P, true>(in, out, nx, nrows, tab, sub, st)
+                 : launch_xinv_bc<float, double, BC_P, false>(in, out, nx, nrows, tab, sub, st);
+  return accum ? launch_xinv_bc<float, double, BC_N, true>(in, out, nx, nrows, tab, sub, st)
+               : launch_xinv_bc<float, double, BC_N, false>(in, out, nx, nrows, tab, sub, st);
 }
 hipError_t launch_y_f64(double* data, int nx, int ny, int nz, int bc, bool fwd, const double* tab,
                         hipStream_t st) {

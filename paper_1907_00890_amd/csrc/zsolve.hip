@@ -46,31 +46,59 @@
 
 namespace vp {
 
+// 1/x for a positive normal x: hardware reciprocal estimate refined by two
+// Newton-Raphson steps (r <- r + r (1 - x r)), accurate to about one ulp.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // Reduced system of line l (rows r*LB + l) in M-matrix form: B u = R with
 // off-diagonal magnitudes lo, up and row sums rho; one or two right-hand
 // sides (R1, and R2 when `two`).  Solutions overwrite R1 / R2.
 template <int LB>
 __device__ __forceinline__ void red_solve(const double* lo, double* up, const double* rho,
                                           double* R1, double* R2, bool two, int nr, int l) {
+  // forward sweep; the next row's coefficients are read ahead of the
+  // dependent pivot chain
   double ratio = 0.0, y1 = 0.0, y2 = 0.0;
+  double nlo = lo[l], nup = up[l], nrho = rho[l], nR1 = R1[l], nR2 = two ? R2[l] : 0.0;
   for (int r = 0; r < nr; ++r) {
     const int o = r * LB + l;
-    const double lr = lo[o];
-    const double sig = rho[o] + lr * ratio;
-    const double iu = 1.0 / (up[o] + sig);
+    const double lr = nlo, ur = nup, rr = nrho, b1 = nR1, b2 = nR2;
+    if (r + 1 < nr) {
+      const int o1 = o + LB;
+      nlo = lo[o1];
+      nup = up[o1];
+      nrho = rho[o1];
+      nR1 = R1[o1];
+      if (two) nR2 = R2[o1];
+    }
+    const double sig = rr + lr * ratio;
+    const double iu = rcp64(ur + sig);
     ratio = sig * iu;
-    y1 = (R1[o] + lr * y1) * iu;
+    y1 = (b1 + lr * y1) * iu;
     R1[o] = y1;
     if (two) {
-      y2 = (R2[o] + lr * y2) * iu;
+      y2 = (b2 + lr * y2) * iu;
       R2[o] = y2;
     }
-    up[o] *= iu;
+    up[o] = ur * iu;
   }
+  // backward sweep
+  double x1 = y1, x2 = y2;
   for (int r = nr - 2; r >= 0; --r) {
-    const int o = r * LB + l, o1 = (r + 1) * LB + l;
-    R1[o] += up[o] * R1[o1];
-    if (two) R2[o] += up[o] * R2[o1];
+    const int o = r * LB + l;
+    const double f = up[o];
+    x1 = R1[o] + f * x1;
+    R1[o] = x1;
+    if (two) {
+      x2 = R2[o] + f * x2;
+      R2[o] = x2;
+    }
   }
 }
 
@@ -207,7 +235,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
         const int k = k0 + i;
         const double a = A.za[k], c = A.zc[k];
         const double sig = ell + a * ratio;
-        const double iu = 1.0 / (c + sig);
+        const double iu = rcp64(c + sig);
         ratio = sig * iu;
         ya = (a * ya - al[i]) * iu;  // right-hand side of B is -r
         yb = (i == 1 ? a : a * yb) * iu;
@@ -337,9 +365,12 @@ static hipError_t launch_z(T* data, const ZArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_z1<T>), grid, dim3(256), 0, st, data, a);
     return hipGetLastError();
   }
-  // LB lines x S segments per block, at most 512 lanes
-  if (a.nseg <= 16) return launch_z_lb<T, 32>(data, a, st);
-  if (a.nseg <= 32) return launch_z_lb<T, 16>(data, a, st);
+  // LB lines x S segments per block, at most 512 lanes; a.lines picks LB
+  int lb = a.lines;
+  while (lb > 8 && lb * a.nseg > 512) lb /= 2;
+  if (lb >= 32) return launch_z_lb<T, 32>(data, a, st);
+  if (lb == 16) return launch_z_lb<T, 16>(data, a, st);
+  if (lb * a.nseg > 512) return hipErrorInvalidValue;
   return launch_z_lb<T, 8>(data, a, st);
 }
 
