@@ -37,7 +37,8 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nz, int bc, bool fwd, c
 // zsolve.hip -----------------------------------------------------------------
 struct ZArgs {
   long plane;          // nx * ny lines
-  int nx;              // for the (cx, cy) split of a line index
+  int nx;              // for the (cx, cy) split of a line index (a power of two)
+  int lx;              // log2(nx)
   int nz;
   int seg;             // segment length bound M (16)
   int lines;           // lines per block (8, 16 or 32; capped so lines * nseg <= 512)
@@ -50,6 +51,8 @@ struct ZArgs {
   const double* lamx;  // eigenvalue per packed x position
   const double* lamy;
   double dzc_wrap;     // centre distance across the wrap face (periodic z)
+  int uniform_z;       // all dzf equal: interior coefficients are hz2
+  double hz2;          // 1 / dz^2 of a uniform z grid
   const double* za;    // sub-diagonal of the row-scaled z operator (wall form: za[0] = 0)
   const double* zc;    // super-diagonal (wall form: zc[nz-1] = 0)
   const double* dzf;

@@ -219,6 +219,8 @@ int plan_init(poisson_plan* P, const double* dz) {
   vp::ZArgs& Z = P->z;
   Z.plane = (long)nx * ny;
   Z.nx = nx;
+  Z.lx = 0;
+  while ((1 << Z.lx) < nx) ++Z.lx;
   Z.nz = nz;
   Z.seg = 16;
   Z.lines = 16;
@@ -227,6 +229,16 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.seg_rem = nz % Z.nseg;
   Z.periodic = zper ? 1 : 0;
   Z.dzc_wrap = zper ? c[nz - 1] : 0.0;
+  // a uniform grid (bitwise equal widths) lets the z kernel use one constant
+  // coefficient; za / zc hold exactly that value in the interior
+  Z.uniform_z = 1;
+  for (int k = 1; k < nz; ++k)
+    if (f[k] != f[0]) Z.uniform_z = 0;
+  Z.hz2 = nz > 1 ? cc[0] : 0.0;
+  if (Z.uniform_z) {
+    for (int k = 1; k + 1 < nz; ++k)
+      if (a[k] != Z.hz2 || cc[k] != Z.hz2) Z.uniform_z = 0;
+  }
   Z.scale = 1.0 / ((double)nx * (double)ny);
   Z.dz_sum = sum;
   Z.lamx = P->lamx;

@@ -11,9 +11,13 @@
 // segments; a lane owns one segment in registers and eliminates its interior
 // rows for the data and for the two couplings to the segment's end values
 // (x_i = alpha_i + beta_i x_first + gamma_i x_last).  The end values of all
-// segments then satisfy a tridiagonal system of 2S unknowns, which one lane
-// per line solves in LDS; each lane finally rebuilds its interior.  Lines run
-// on consecutive lanes, so every load and store of a z-plane row is coalesced.
+// segments then satisfy a tridiagonal system of 2S unknowns, which two lanes
+// per line solve in LDS from both ends (a twisted factorisation that meets in
+// the middle); each lane finally rebuilds its interior.  Lines run on
+// consecutive lanes, so every load and store of a z-plane row is coalesced.
+// When every segment has exactly M rows and/or the z grid is uniform, the
+// kernel is specialised at compile time (no per-row guards, constant
+// coefficients).
 //
 // Accuracy.  B = -(A + lambda I) is an M-matrix whose rows all sum to
 // ell = -lambda > 0 (walls and periodic ends alike: A annihilates constants).
@@ -56,53 +60,108 @@ __device__ __forceinline__ double rcp64(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// Reduced system of line l (rows r*LB + l) in M-matrix form: B u = R with
-// off-diagonal magnitudes lo, up and row sums rho; one or two right-hand
-// sides (R1, and R2 when `two`).  Solutions overwrite R1 / R2.
+// Reduced system of line l (rows r*LB + l) in M-matrix form,
+//   -lo_r u_{r-1} + (rho_r + lo_r + up_r) u_r - up_r u_{r+1} = R_r,
+// with one or two right-hand sides (R1, and R2 when `two`); solutions
+// overwrite R1 / R2.  Twisted factorisation: the lane with half == 0
+// eliminates rows 0..h-1 downwards, the lane with half == 1 rows nr-1..h+1
+// upwards, both in row-sum form; row h then has the pivot
+//   rho_h + lo_h ratio_top + up_h ratio_bottom
+// (a sum of positive terms) and each lane substitutes back over its half.
+// ex: 6 * LB doubles of LDS for the exchange at row h.  All lanes of the
+// block call this (it contains barriers); `act` marks the two working lanes.
 template <int LB>
-__device__ __forceinline__ void red_solve(const double* lo, double* up, const double* rho,
-                                          double* R1, double* R2, bool two, int nr, int l) {
-  // forward sweep; the next row's coefficients are read ahead of the
-  // dependent pivot chain
-  double ratio = 0.0, y1 = 0.0, y2 = 0.0;
-  double nlo = lo[l], nup = up[l], nrho = rho[l], nR1 = R1[l], nR2 = two ? R2[l] : 0.0;
-  for (int r = 0; r < nr; ++r) {
-    const int o = r * LB + l;
-    const double lr = nlo, ur = nup, rr = nrho, b1 = nR1, b2 = nR2;
-    if (r + 1 < nr) {
-      const int o1 = o + LB;
-      nlo = lo[o1];
-      nup = up[o1];
-      nrho = rho[o1];
-      nR1 = R1[o1];
-      if (two) nR2 = R2[o1];
+__device__ __forceinline__ void red_twisted(double* lo, double* up, const double* rho, double* R1,
+                                            double* R2, double* ex, bool two, int nr, int l,
+                                            bool act, int half) {
+  const int h = nr / 2;
+  if (act && half == 0) {
+    double ratio = 0.0, y1 = 0.0, y2 = 0.0;
+    for (int r = 0; r < h; ++r) {
+      const int o = r * LB + l;
+      const double lr = lo[o], ur = up[o];
+      const double sig = rho[o] + lr * ratio;
+      const double iu = rcp64(ur + sig);
+      ratio = sig * iu;
+      y1 = (R1[o] + lr * y1) * iu;
+      R1[o] = y1;
+      if (two) {
+        y2 = (R2[o] + lr * y2) * iu;
+        R2[o] = y2;
+      }
+      up[o] = ur * iu;
     }
-    const double sig = rr + lr * ratio;
-    const double iu = rcp64(ur + sig);
-    ratio = sig * iu;
-    y1 = (b1 + lr * y1) * iu;
-    R1[o] = y1;
-    if (two) {
-      y2 = (b2 + lr * y2) * iu;
-      R2[o] = y2;
+    ex[0 * LB + l] = ratio;
+    ex[1 * LB + l] = y1;
+    ex[2 * LB + l] = y2;
+    if (nr == 2) {  // one segment: no lane below row h
+      ex[3 * LB + l] = 0.0;
+      ex[4 * LB + l] = 0.0;
+      ex[5 * LB + l] = 0.0;
     }
-    up[o] = ur * iu;
+  } else if (act && half == 1) {
+    double ratio = 0.0, z1 = 0.0, z2 = 0.0;
+    for (int r = nr - 1; r > h; --r) {
+      const int o = r * LB + l;
+      const double lr = lo[o], ur = up[o];
+      const double sig = rho[o] + ur * ratio;
+      const double iv = rcp64(lr + sig);
+      ratio = sig * iv;
+      z1 = (R1[o] + ur * z1) * iv;
+      R1[o] = z1;
+      if (two) {
+        z2 = (R2[o] + ur * z2) * iv;
+        R2[o] = z2;
+      }
+      lo[o] = lr * iv;
+    }
+    ex[3 * LB + l] = ratio;
+    ex[4 * LB + l] = z1;
+    ex[5 * LB + l] = z2;
   }
-  // backward sweep
-  double x1 = y1, x2 = y2;
-  for (int r = nr - 2; r >= 0; --r) {
-    const int o = r * LB + l;
-    const double f = up[o];
-    x1 = R1[o] + f * x1;
-    R1[o] = x1;
-    if (two) {
-      x2 = R2[o] + f * x2;
-      R2[o] = x2;
+  __syncthreads();
+  if (act) {
+    const int o = h * LB + l;
+    const double lr = lo[o], ur = up[o];
+    const double rt = ex[0 * LB + l], yt1 = ex[1 * LB + l], yt2 = ex[2 * LB + l];
+    const double rb = ex[3 * LB + l], zb1 = ex[4 * LB + l], zb2 = ex[5 * LB + l];
+    const double ip = rcp64(rho[o] + lr * rt + ur * rb);
+    double x1 = (R1[o] + lr * yt1 + ur * zb1) * ip;
+    double x2 = two ? (R2[o] + lr * yt2 + ur * zb2) * ip : 0.0;
+    const double xh1 = x1, xh2 = x2;
+    if (half == 0) {
+      for (int r = h - 1; r >= 0; --r) {
+        const int q = r * LB + l;
+        x1 = R1[q] + up[q] * x1;
+        R1[q] = x1;
+        if (two) {
+          x2 = R2[q] + up[q] * x2;
+          R2[q] = x2;
+        }
+      }
+      if (nr == 2) {  // one segment: this lane also owns row h
+        R1[o] = xh1;
+        if (two) R2[o] = xh2;
+      }
+    } else {
+      for (int r = h + 1; r < nr; ++r) {
+        const int q = r * LB + l;
+        x1 = R1[q] + lo[q] * x1;
+        R1[q] = x1;
+        if (two) {
+          x2 = R2[q] + lo[q] * x2;
+          R2[q] = x2;
+        }
+      }
+      R1[o] = xh1;
+      if (two) R2[o] = xh2;
     }
   }
 }
 
-template <typename T, int M, int LB>
+// US: every segment has exactly M rows.  UZ: uniform z spacing (interior
+// coefficients a = c = A.hz2).
+template <typename T, int M, int LB, bool US, bool UZ>
 __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A) {
   extern __shared__ double zsm[];
   const int S = A.nseg, nr = 2 * S;
@@ -111,7 +170,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   double* rho = up + nr * LB;
   double* R1 = rho + nr * LB;
   double* R2 = R1 + nr * LB;
-  double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line)
+  double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line), then the twisted exchange
 
   const int l = threadIdx.x % LB, s = threadIdx.x / LB;
   const long line = (long)blockIdx.x * LB + l;
@@ -122,25 +181,30 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   const bool per = A.periodic != 0;
   const long P = A.plane;
   double lam = 0.0;
-  if (valid) lam = A.lamx[line % A.nx] + A.lamy[line / A.nx];
+  if (valid) lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx];
   const double ell = -lam;
-  const int k0 = s * A.seg_base + (s < A.seg_rem ? s : A.seg_rem);
-  const int m = A.seg_base + (s < A.seg_rem ? 1 : 0);
+  const int k0 = US ? s * M : s * A.seg_base + (s < A.seg_rem ? s : A.seg_rem);
+  const int m = US ? M : A.seg_base + (s < A.seg_rem ? 1 : 0);
   const int k1 = k0 + m - 1;
+  T* xs = x + (long)k0 * P + line;
 
   double al[M], be[M], cg[M], ta[M];
-  double rfirst = 0.0, rlast = 0.0;
+  double rlast = 0.0;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     double v = 0.0;
-    if (i < m && valid) v = double(x[(long)(k0 + i) * P + line]) * A.scale;
+    if ((US || i < m) && valid) v = double(xs[(long)i * P]) * A.scale;
     al[i] = v;
     be[i] = 0.0;
     cg[i] = 0.0;
     ta[i] = 0.0;
-    if (i == m - 1) rlast = v;
+    if (US) {
+      if (i == M - 1) rlast = v;
+    } else if (i == m - 1) {
+      rlast = v;
+    }
   }
-  rfirst = al[0];
+  const double rfirst = al[0];
 
   // ---- singular line (block 0, lanes l == 0): segmented running sums ----
   if (blk0) {
@@ -220,7 +284,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     if (sing) {
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        if (i < m) x[(long)(k0 + i) * P] = T(cg[i] - pm);
+        if (i < m) xs[(long)i * P] = T(cg[i] - pm);
     }
   }
 
@@ -231,9 +295,15 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     double ratio = 1.0, ya = 0.0, yb = 0.0, yt = 0.0;
 #pragma unroll
     for (int i = 1; i < M - 1; ++i) {
-      if (i < m - 1) {
-        const int k = k0 + i;
-        const double a = A.za[k], c = A.zc[k];
+      if (US || i < m - 1) {
+        double a, c;
+        if (UZ) {
+          a = A.hz2;
+          c = A.hz2;
+        } else {
+          a = A.za[k0 + i];
+          c = A.zc[k0 + i];
+        }
         const double sig = ell + a * ratio;
         const double iu = rcp64(c + sig);
         ratio = sig * iu;
@@ -249,10 +319,10 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     double an = 0.0, bn = 0.0, gn = 0.0, tn = 0.0;
 #pragma unroll
     for (int i = M - 2; i >= 1; --i) {
-      if (i <= m - 2) {
+      if (US || i <= m - 2) {
         const double f = cg[i];
         double gc;
-        if (i == m - 2) {
+        if ((US && i == M - 2) || (!US && i == m - 2)) {
           gc = f;
           aL = al[i];
           bL = be[i];
@@ -271,7 +341,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
         tn = ta[i];
       }
     }
-    if (m >= 3) {
+    if (US ? (M >= 3) : (m >= 3)) {
       a1 = al[1];
       b1 = be[1];
       g1 = cg[1];
@@ -283,7 +353,18 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   {
     const int oF = (2 * s) * LB + l, oE = (2 * s + 1) * LB + l;
     if (gen) {
-      const double a0 = A.za[k0], c0 = A.zc[k0], aE = A.za[k1], cE = A.zc[k1];
+      double a0, c0, aE, cE;
+      if (UZ) {
+        a0 = k0 == 0 ? 0.0 : A.hz2;
+        c0 = A.hz2;
+        aE = A.hz2;
+        cE = k1 == A.nz - 1 ? 0.0 : A.hz2;
+      } else {
+        a0 = A.za[k0];
+        c0 = A.zc[k0];
+        aE = A.za[k1];
+        cE = A.zc[k1];
+      }
       lo[oF] = a0;
       up[oF] = c0 * g1;
       rho[oF] = ell * (1.0 + c0 * t1);
@@ -301,7 +382,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     }
   }
   __syncthreads();
-  if (s == 0 && gen) red_solve<LB>(lo, up, rho, R1, R2, per, nr, l);
+  red_twisted<LB>(lo, up, rho, R1, R2, red, per, nr, l, gen && s < 2, s);
   __syncthreads();
 
   if (gen) {
@@ -316,15 +397,15 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      if (i < m) {
+      if (US || i < m) {
         double v;
         if (i == 0)
           v = Ft;
-        else if (i == m - 1)
+        else if ((US && i == M - 1) || (!US && i == m - 1))
           v = Et;
         else
           v = al[i] + be[i] * Ft + cg[i] * Et;
-        x[(long)(k0 + i) * P + line] = T(v);
+        xs[(long)i * P] = T(v);
       }
     }
   }
@@ -340,22 +421,32 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
     if (A.mean_out) A.mean_out[0] = r;
     x[0] = T(0);
   } else {
-    const double lam = A.lamx[line % A.nx] + A.lamy[line / A.nx];
+    const double lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx];
     x[line] = T(r / lam);
   }
 }
 
-template <typename T, int LB>
-static hipError_t launch_z_lb(T* data, const ZArgs& a, hipStream_t st) {
+template <typename T, int LB, bool US, bool UZ>
+static hipError_t launch_z_shape(T* data, const ZArgs& a, hipStream_t st) {
   const int nr = 2 * a.nseg;
-  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)a.nseg * LB);
+  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)(a.nseg > 6 ? a.nseg : 6) * LB);
   const dim3 grid((unsigned)((a.plane + LB - 1) / LB));
   const dim3 block((unsigned)(LB * a.nseg));
   if (a.seg != 16 || LB * a.nseg > 512) return hipErrorInvalidValue;
-  if (shm > 65536 && allow_large_lds(&k_zsolve<T, 16, LB>) != hipSuccess)
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_zsolve<T, 16, LB>), grid, block, shm, st, data, a);
+  auto kern = &k_zsolve<T, 16, LB, US, UZ>;
+  if (shm > 65536 && allow_large_lds(kern) != hipSuccess) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, grid, block, shm, st, data, a);
   return hipGetLastError();
+}
+
+template <typename T, int LB>
+static hipError_t launch_z_lb(T* data, const ZArgs& a, hipStream_t st) {
+  const bool us = a.seg_rem == 0 && a.seg_base == a.seg;
+  if (us)
+    return a.uniform_z ? launch_z_shape<T, LB, true, true>(data, a, st)
+                       : launch_z_shape<T, LB, true, false>(data, a, st);
+  return a.uniform_z ? launch_z_shape<T, LB, false, true>(data, a, st)
+                     : launch_z_shape<T, LB, false, false>(data, a, st);
 }
 
 template <typename T>
