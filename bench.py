@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="ppn256",
                     help="workload the CPU oracle is timed on (bounded sample)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain device copies of one field (a known byte "
+                         "count for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -247,6 +250,13 @@ def main():
         "kernel_ms_per_step": round(kern_ms_step, 4),
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.copy_calibration:
+        src = torch.randn(cfg.shape, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = int(src.numel() * 8)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(line), flush=True)

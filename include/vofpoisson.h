@@ -149,8 +149,8 @@ long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_
  * Launch-shape tuning (results do not change, only speed):
  *   "z_lines"   : lines per block of the z pass, 8, 16 (default) or 32
  *                 (capped so that lines * segments <= 512);
- *   "xcd_remap" : 1 maps consecutive rows of cells of the stencil
- *                 kernels to one XCD so their neighbours share its L2; 0 (default) off.
+ *   "stencil_planes" : z-planes marched by one block of the right-hand-side
+ *                 and residual kernels (1..nz; default chosen for ~16k blocks).
  * Returns VP_EINVAL for an unknown key or value.
  */
 int poisson_plan_tune(poisson_plan* plan, const char* key, int value);

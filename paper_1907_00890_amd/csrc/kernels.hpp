@@ -66,7 +66,7 @@ hipError_t launch_zsolve_f32(float* data, const ZArgs& a, hipStream_t st);
 struct GridArgs {
   int nx, ny, nz;
   int lx, ly;          // log2(nx), log2(ny): nx and ny are powers of two
-  int xcd_remap;       // map consecutive rows of cells to one XCD (L2 reuse of y/z neighbours)
+  int kc;              // z-planes marched by one stencil block
   int bcx, bcy, bcz;   // 0 periodic, 1 wall
   double dx, dy;
   const double* dzf;   // nz
@@ -84,8 +84,9 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          hipStream_t st);
 // r = f - L_h p; also mean_out[0] = volume-weighted mean of p.  partial must
 // hold kResidualMaxBlocks doubles.
-constexpr int kResidualMaxBlocks = 2048;
-int residual_blocks(long n);
+constexpr int kResidualMaxBlocks = 16384;
+int stencil_blocks(const GridArgs& g);
+int stencil_default_planes(int nx, int ny, int nz);
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
                            double* partial, double* mean_out, double dz_sum, hipStream_t st);
 

@@ -258,7 +258,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   G.bcx = P->bc[0]; G.bcy = P->bc[1]; G.bcz = P->bc[2];
   G.dx = P->dx; G.dy = P->dy;
   G.dzf = P->dzf; G.dzc = P->dzc;
-  G.xcd_remap = 0;
+  G.kc = vp::stencil_default_planes(nx, ny, nz);
   return VP_OK;
 }
 
@@ -469,9 +469,12 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     P->z.lines = value;
     return VP_OK;
   }
-  if (k == "xcd_remap") {
-    if (value != 0 && value != 1) return VP_EINVAL;
-    P->g.xcd_remap = value;
+  if (k == "stencil_planes") {
+    if (value < 1 || value > P->nz) return VP_EINVAL;
+    vp::GridArgs g = P->g;
+    g.kc = value;
+    if (vp::stencil_blocks(g) > vp::kResidualMaxBlocks) return VP_EINVAL;
+    P->g.kc = value;
     return VP_OK;
   }
   return VP_EINVAL;

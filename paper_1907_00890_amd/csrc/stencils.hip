@@ -2,49 +2,58 @@
 // side of the split pressure equation and the velocity correction; section
 // 3.6: the liquid-velocity extension and the interface velocity).
 //
-// One thread per cell (x fastest, so a wavefront reads 64 consecutive values
-// of every array).  Neighbour values in x, y, z come through the L1/L2
-// caches; each array is read from HBM about once.  Faces: u on i+1/2, v on
-// j+1/2, w on k+1/2; a wall face (last index) has zero gradient, the face at
-// -1/2 of a wall direction is implicit and zero.
+// Faces: u on i+1/2, v on j+1/2, w on k+1/2; a wall face (last index) has
+// zero gradient, the face at -1/2 of a wall direction is implicit and zero.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 
 namespace vp {
 
-struct Nb {
-  long c, xp, xm, yp, ym, zp, zm;  // neighbour offsets (-1: wall)
-  int k;
+// ---------------------------------------------------------------------------
+// Launch geometry shared by the stencils: a block is a TX x TY tile of one
+// z-plane (TX = min(nx, 64), 256 threads) and marches through `kc`
+// consecutive planes, keeping the values at k-1, k, k+1 of the fields that
+// are read at z-neighbours in registers.  x and y neighbours are re-read
+// through L1 (they are loaded by the same block, except the tile's halo).
+// The 7-point kernels (right-hand side, residual) march a few planes; the
+// streaming ones (correction, extension) take one plane per block.
+// ---------------------------------------------------------------------------
+struct Tile {
+  int i, j, kb, ke;
+  bool ok;
+  long c0;     // offset of (i, j, 0)
+  long xp, xm, yp, ym;  // in-plane neighbour offsets, 0 with `has` false
+  bool hxp, hxm, hyp, hym;
 };
 
-__device__ __forceinline__ Nb neighbours(const GridArgs& g, long idx) {
-  const long plane = (long)g.nx * g.ny;
-  const int i = (int)(idx & (g.nx - 1));
-  const int j = (int)((idx >> g.lx) & (g.ny - 1));
-  const int k = (int)(idx >> (g.lx + g.ly));
-  Nb n;
-  n.c = idx;
-  n.k = k;
-  n.xp = i + 1 < g.nx ? idx + 1 : (g.bcx == 0 ? idx - (g.nx - 1) : -1);
-  n.xm = i > 0 ? idx - 1 : (g.bcx == 0 ? idx + (g.nx - 1) : -1);
-  n.yp = j + 1 < g.ny ? idx + g.nx : (g.bcy == 0 ? idx - (long)(g.ny - 1) * g.nx : -1);
-  n.ym = j > 0 ? idx - g.nx : (g.bcy == 0 ? idx + (long)(g.ny - 1) * g.nx : -1);
-  n.zp = k + 1 < g.nz ? idx + plane : (g.bcz == 0 ? idx - (long)(g.nz - 1) * plane : -1);
-  n.zm = k > 0 ? idx - plane : (g.bcz == 0 ? idx + (long)(g.nz - 1) * plane : -1);
-  return n;
+__device__ __forceinline__ Tile tile_of(const GridArgs& g) {
+  Tile t;
+  const int tx = g.nx < 64 ? g.nx : 64;
+  const int ltx = g.lx < 6 ? g.lx : 6;
+  t.i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
+  t.j = blockIdx.y * (256 / tx) + (threadIdx.x >> ltx);
+  t.kb = blockIdx.z * g.kc;
+  t.ke = t.kb + g.kc < g.nz ? t.kb + g.kc : g.nz;
+  t.ok = t.j < g.ny;
+  t.c0 = (long)t.j * g.nx + t.i;
+  t.hxp = t.i + 1 < g.nx || g.bcx == 0;
+  t.hxm = t.i > 0 || g.bcx == 0;
+  t.hyp = t.j + 1 < g.ny || g.bcy == 0;
+  t.hym = t.j > 0 || g.bcy == 0;
+  t.xp = t.i + 1 < g.nx ? 1 : -(long)(g.nx - 1);
+  t.xm = t.i > 0 ? -1 : (long)(g.nx - 1);
+  t.yp = t.j + 1 < g.ny ? (long)g.nx : -(long)(g.ny - 1) * g.nx;
+  t.ym = t.j > 0 ? -(long)g.nx : (long)(g.ny - 1) * g.nx;
+  return t;
 }
 
-// Logical block index.  Workgroups are dealt to the 8 XCDs of the chip in
-// turn, each XCD with its own L2; with the remap, XCD x runs a contiguous
-// range of blocks, so the rows above and below a block (its y and z
-// neighbours) are mostly read by the same XCD and come from its L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ long logical_block(const GridArgs& g, long nblocks) {
-  const long b = blockIdx.x;
-  if (!g.xcd_remap) return b;
-  const long per = (nblocks + kXcds - 1) / kXcds;
-  return (b % kXcds) * per + b / kXcds;
+// plane index of the z-neighbours of plane k; -1 at a wall
+__device__ __forceinline__ int kplus(const GridArgs& g, int k) {
+  return k + 1 < g.nz ? k + 1 : (g.bcz == 0 ? 0 : -1);
+}
+__device__ __forceinline__ int kminus(const GridArgs& g, int k) {
+  return k > 0 ? k - 1 : (g.bcz == 0 ? g.nz - 1 : -1);
 }
 
 // inverse of the face density 1 / ((rho_a + rho_b) / 2)
@@ -57,32 +66,47 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
                                               const double* __restrict__ ph,
                                               const double* __restrict__ rho, double rho0,
                                               const double* __restrict__ src, double dt,
-                                              double* __restrict__ b, long n) {
-  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
-  if (idx >= n) return;
-  const Nb nb = neighbours(g, idx);
-  const double ir0 = 1.0 / rho0;
-  const double p0 = ph[idx], r0 = rho[idx];
-  const double idx_ = 1.0 / g.dx, idy = 1.0 / g.dy;
-  const double dzf = g.dzf[nb.k];
-  // flux (1/rho0 - 1/rho_f) G p_hat on the six faces of the cell
-  double fxp = 0.0, fxm = 0.0, fyp = 0.0, fym = 0.0, fzp = 0.0, fzm = 0.0;
-  if (nb.xp >= 0) fxp = (ir0 - inv_face_rho(r0, rho[nb.xp])) * (ph[nb.xp] - p0) * idx_;
-  if (nb.xm >= 0) fxm = (ir0 - inv_face_rho(rho[nb.xm], r0)) * (p0 - ph[nb.xm]) * idx_;
-  if (nb.yp >= 0) fyp = (ir0 - inv_face_rho(r0, rho[nb.yp])) * (ph[nb.yp] - p0) * idy;
-  if (nb.ym >= 0) fym = (ir0 - inv_face_rho(rho[nb.ym], r0)) * (p0 - ph[nb.ym]) * idy;
-  if (nb.zp >= 0) fzp = (ir0 - inv_face_rho(r0, rho[nb.zp])) * (ph[nb.zp] - p0) / g.dzc[nb.k];
-  if (nb.zm >= 0) {
-    const int km = nb.k > 0 ? nb.k - 1 : g.nz - 1;
-    fzm = (ir0 - inv_face_rho(rho[nb.zm], r0)) * (p0 - ph[nb.zm]) / g.dzc[km];
+                                              double* __restrict__ b) {
+  const Tile t = tile_of(g);
+  if (!t.ok) return;
+  const long P = (long)g.nx * g.ny;
+  const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, r0dt = rho0 / dt;
+  int km = kminus(g, t.kb);
+  double phm = 0.0, rhm = 0.0, wm = 0.0;
+  if (km >= 0) {
+    phm = ph[km * P + t.c0];
+    rhm = rho[km * P + t.c0];
+    wm = w[km * P + t.c0];
   }
-  const double divf = (fxp - fxm) * idx_ + (fyp - fym) * idy + (fzp - fzm) / dzf;
-  const double um = nb.xm >= 0 ? u[nb.xm] : 0.0;
-  const double vm = nb.ym >= 0 ? v[nb.ym] : 0.0;
-  const double wm = nb.zm >= 0 ? w[nb.zm] : 0.0;
-  const double divu = (u[idx] - um) * idx_ + (v[idx] - vm) * idy + (w[idx] - wm) / dzf;
-  const double s = src ? src[idx] : 0.0;
-  b[idx] = rho0 * divf + (rho0 / dt) * (divu - s);
+  double phc = ph[t.kb * P + t.c0], rhc = rho[t.kb * P + t.c0];
+  for (int k = t.kb; k < t.ke; ++k) {
+    const long c = k * P + t.c0;
+    const int kp = kplus(g, k);
+    double php = 0.0, rhp = 0.0;
+    if (kp >= 0) {
+      php = ph[kp * P + t.c0];
+      rhp = rho[kp * P + t.c0];
+    }
+    const double dzf = g.dzf[k];
+    double fxp = 0.0, fxm = 0.0, fyp = 0.0, fym = 0.0, fzp = 0.0, fzm = 0.0;
+    if (t.hxp) fxp = (ir0 - inv_face_rho(rhc, rho[c + t.xp])) * (ph[c + t.xp] - phc) * idx;
+    if (t.hxm) fxm = (ir0 - inv_face_rho(rho[c + t.xm], rhc)) * (phc - ph[c + t.xm]) * idx;
+    if (t.hyp) fyp = (ir0 - inv_face_rho(rhc, rho[c + t.yp])) * (ph[c + t.yp] - phc) * idy;
+    if (t.hym) fym = (ir0 - inv_face_rho(rho[c + t.ym], rhc)) * (phc - ph[c + t.ym]) * idy;
+    if (kp >= 0) fzp = (ir0 - inv_face_rho(rhc, rhp)) * (php - phc) / g.dzc[k];
+    if (km >= 0) fzm = (ir0 - inv_face_rho(rhm, rhc)) * (phc - phm) / g.dzc[km];
+    const double divf = (fxp - fxm) * idx + (fyp - fym) * idy + (fzp - fzm) / dzf;
+    const double wc = w[c];
+    const double um = t.hxm ? u[c + t.xm] : 0.0;
+    const double vm = t.hym ? v[c + t.ym] : 0.0;
+    const double divu = (u[c] - um) * idx + (v[c] - vm) * idy + (wc - (km >= 0 ? wm : 0.0)) / dzf;
+    const double sv = src ? src[c] : 0.0;
+    b[c] = rho0 * divf + r0dt * (divu - sv);
+    phm = phc; phc = php;
+    rhm = rhc; rhc = rhp;
+    wm = wc;
+    km = k;
+  }
 }
 
 // u <- u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ] on the cell's
@@ -92,24 +116,37 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
                                                   const double* __restrict__ p,
                                                   const double* __restrict__ ph,
                                                   const double* __restrict__ rho, double rho0,
-                                                  double dt, long n) {
-  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
-  if (idx >= n) return;
-  const Nb nb = neighbours(g, idx);
-  const double ir0 = 1.0 / rho0;
-  const double p0 = p[idx], h0 = ph[idx], r0 = rho[idx];
-  if (nb.xp >= 0) {
-    const double gp = (p[nb.xp] - p0) / g.dx, gh = (ph[nb.xp] - h0) / g.dx;
-    u[idx] -= dt * (ir0 * gp + (inv_face_rho(r0, rho[nb.xp]) - ir0) * gh);
-  }
-  if (nb.yp >= 0) {
-    const double gp = (p[nb.yp] - p0) / g.dy, gh = (ph[nb.yp] - h0) / g.dy;
-    v[idx] -= dt * (ir0 * gp + (inv_face_rho(r0, rho[nb.yp]) - ir0) * gh);
-  }
-  if (nb.zp >= 0) {
-    const double h = g.dzc[nb.k];
-    const double gp = (p[nb.zp] - p0) / h, gh = (ph[nb.zp] - h0) / h;
-    w[idx] -= dt * (ir0 * gp + (inv_face_rho(r0, rho[nb.zp]) - ir0) * gh);
+                                                  double dt) {
+  const Tile t = tile_of(g);
+  if (!t.ok) return;
+  const long P = (long)g.nx * g.ny;
+  const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+  double pc = p[t.kb * P + t.c0], hc = ph[t.kb * P + t.c0], rc = rho[t.kb * P + t.c0];
+  for (int k = t.kb; k < t.ke; ++k) {
+    const long c = k * P + t.c0;
+    const int kp = kplus(g, k);
+    double pp = 0.0, hp = 0.0, rp = 0.0;
+    if (kp >= 0) {
+      pp = p[kp * P + t.c0];
+      hp = ph[kp * P + t.c0];
+      rp = rho[kp * P + t.c0];
+    }
+    if (t.hxp) {
+      const double gp = (p[c + t.xp] - pc) * idx, gh = (ph[c + t.xp] - hc) * idx;
+      u[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rho[c + t.xp]) - ir0) * gh);
+    }
+    if (t.hyp) {
+      const double gp = (p[c + t.yp] - pc) * idy, gh = (ph[c + t.yp] - hc) * idy;
+      v[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rho[c + t.yp]) - ir0) * gh);
+    }
+    if (kp >= 0) {
+      const double h = g.dzc[k];
+      const double gp = (pp - pc) / h, gh = (hp - hc) / h;
+      w[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rp) - ir0) * gh);
+    }
+    pc = pp;
+    hc = hp;
+    rc = rp;
   }
 }
 
@@ -123,59 +160,74 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
                                                  const double* __restrict__ qz,
                                                  double* __restrict__ ue, double* __restrict__ ve,
                                                  double* __restrict__ we, double* __restrict__ ug,
-                                                 double* __restrict__ vg, double* __restrict__ wg,
-                                                 long n) {
-  const long idx = logical_block(g, (n + 255) / 256) * 256 + threadIdx.x;
-  if (idx >= n) return;
-  const Nb nb = neighbours(g, idx);
-  const double f0 = phi[idx];
-  const double gx = nb.xp >= 0 ? (phi[nb.xp] - f0) / g.dx : 0.0;
-  const double gy = nb.yp >= 0 ? (phi[nb.yp] - f0) / g.dy : 0.0;
-  const double gz = nb.zp >= 0 ? (phi[nb.zp] - f0) / g.dzc[nb.k] : 0.0;
-  const double a = u[idx] - gx, b = v[idx] - gy, c = w[idx] - gz;
-  ue[idx] = a;
-  ve[idx] = b;
-  we[idx] = c;
-  if (ug) {
-    ug[idx] = a - qx[idx];
-    vg[idx] = b - qy[idx];
-    wg[idx] = c - qz[idx];
+                                                 double* __restrict__ vg, double* __restrict__ wg) {
+  const Tile t = tile_of(g);
+  if (!t.ok) return;
+  const long P = (long)g.nx * g.ny;
+  const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+  double fc = phi[t.kb * P + t.c0];
+  for (int k = t.kb; k < t.ke; ++k) {
+    const long c = k * P + t.c0;
+    const int kp = kplus(g, k);
+    const double fp = kp >= 0 ? phi[kp * P + t.c0] : 0.0;
+    const double gx = t.hxp ? (phi[c + t.xp] - fc) * idx : 0.0;
+    const double gy = t.hyp ? (phi[c + t.yp] - fc) * idy : 0.0;
+    const double gz = kp >= 0 ? (fp - fc) / g.dzc[k] : 0.0;
+    const double a = u[c] - gx, bb = v[c] - gy, cc = w[c] - gz;
+    ue[c] = a;
+    ve[c] = bb;
+    we[c] = cc;
+    if (ug) {
+      ug[c] = a - qx[c];
+      vg[c] = bb - qy[c];
+      wg[c] = cc - qz[c];
+    }
+    fc = fp;
   }
 }
 
 // r = f - L_h p (FP64 residual of the defect-correction steps).  Each block
-// also sums dzf[k] * p over the cells it visits (fixed order, no atomics), so
-// that the weighted mean of p is known without another pass over memory.
+// also sums dzf[k] * p over its cells (fixed order, no atomics) into
+// partial[block], so the weighted mean of p costs no extra pass.
 __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double* __restrict__ f,
                                                    const double* __restrict__ p,
                                                    double* __restrict__ r,
-                                                   double* __restrict__ partial, long n) {
+                                                   double* __restrict__ partial) {
   __shared__ double red[256];
-  const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
+  const Tile t = tile_of(g);
   double acc = 0.0;
-  for (long idx = (long)blockIdx.x * 256 + threadIdx.x; idx < n; idx += (long)gridDim.x * 256) {
-    const Nb nb = neighbours(g, idx);
-    const double p0 = p[idx];
-    double lx = 0.0, ly = 0.0, lz = 0.0;
-    if (nb.xp >= 0) lx += (p[nb.xp] - p0);
-    if (nb.xm >= 0) lx -= (p0 - p[nb.xm]);
-    if (nb.yp >= 0) ly += (p[nb.yp] - p0);
-    if (nb.ym >= 0) ly -= (p0 - p[nb.ym]);
-    if (nb.zp >= 0) lz += (p[nb.zp] - p0) / g.dzc[nb.k];
-    if (nb.zm >= 0) {
-      const int km = nb.k > 0 ? nb.k - 1 : g.nz - 1;
-      lz -= (p0 - p[nb.zm]) / g.dzc[km];
+  if (t.ok) {
+    const long P = (long)g.nx * g.ny;
+    const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
+    int km = kminus(g, t.kb);
+    double pm = km >= 0 ? p[km * P + t.c0] : 0.0;
+    double pc = p[t.kb * P + t.c0];
+    for (int k = t.kb; k < t.ke; ++k) {
+      const long c = k * P + t.c0;
+      const int kp = kplus(g, k);
+      const double pp = kp >= 0 ? p[kp * P + t.c0] : 0.0;
+      double lx = 0.0, ly = 0.0, lz = 0.0;
+      if (t.hxp) lx += p[c + t.xp] - pc;
+      if (t.hxm) lx -= pc - p[c + t.xm];
+      if (t.hyp) ly += p[c + t.yp] - pc;
+      if (t.hym) ly -= pc - p[c + t.ym];
+      if (kp >= 0) lz += (pp - pc) / g.dzc[k];
+      if (km >= 0) lz -= (pc - pm) / g.dzc[km];
+      r[c] = f[c] - (lx * idx2 + ly * idy2 + lz / g.dzf[k]);
+      acc += g.dzf[k] * pc;
+      pm = pc;
+      pc = pp;
+      km = k;
     }
-    r[idx] = f[idx] - (lx * idx2 + ly * idy2 + lz / g.dzf[nb.k]);
-    acc += g.dzf[nb.k] * p0;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0)
+    partial[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
 
 // out[0] = (sum of the partial sums) / denom, one block, fixed order
@@ -193,28 +245,44 @@ __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = red[0] / denom;
 }
 
-// grid of 256-thread blocks, rounded up to a multiple of the XCD count so
-// that the remapped logical blocks cover [0, nblocks)
-static inline dim3 grid_for(long n) {
-  const long nb = (n + 255) / 256;
-  return dim3((unsigned)((nb + kXcds - 1) / kXcds * kXcds));
+static inline dim3 tile_grid(const GridArgs& g) {
+  const int tx = g.nx < 64 ? g.nx : 64;
+  const int ty = 256 / tx;
+  return dim3((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
+              (unsigned)((g.nz + g.kc - 1) / g.kc));
+}
+
+int stencil_blocks(const GridArgs& g) {
+  const dim3 d = tile_grid(g);
+  return (int)(d.x * d.y * d.z);
+}
+
+int stencil_default_planes(int nx, int ny, int nz) {
+  const int tx = nx < 64 ? nx : 64;
+  const long tiles = (long)(nx / tx) * ((ny + 256 / tx - 1) / (256 / tx));
+  long kc = (nz * tiles + 16383) / 16384;
+  if (kc < 1) kc = 1;
+  if (kc > nz) kc = nz;
+  return (int)kc;
 }
 
 hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const double* w,
                       const double* phat, const double* rho, double rho0, const double* src,
                       double dt, double* b, hipStream_t st) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL(k_rhs, grid_for(n), dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src, dt,
-                     b, n);
+  hipLaunchKernelGGL(k_rhs, tile_grid(g), dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src, dt,
+                     b);
   return hipGetLastError();
 }
 
+// the streaming stencils (correction, extension) run one plane per block:
+// more independent loads in flight than a march
 hipError_t launch_correct(const GridArgs& g, double* u, double* v, double* w, const double* p,
                           const double* phat, const double* rho, double rho0, double dt,
                           hipStream_t st) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL(k_correct, grid_for(n), dim3(256), 0, st, g, u, v, w, p, phat, rho, rho0,
-                     dt, n);
+  GridArgs g1 = g;
+  g1.kc = 1;
+  hipLaunchKernelGGL(k_correct, tile_grid(g1), dim3(256), 0, st, g1, u, v, w, p, phat, rho, rho0,
+                     dt);
   return hipGetLastError();
 }
 
@@ -222,22 +290,18 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          const double* phi, const double* qx, const double* qy, const double* qz,
                          double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
                          hipStream_t st) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  hipLaunchKernelGGL(k_extend, grid_for(n), dim3(256), 0, st, g, u, v, w, phi, qx, qy, qz, ue, ve,
-                     we, ug, vg, wg, n);
+  GridArgs g1 = g;
+  g1.kc = 1;
+  hipLaunchKernelGGL(k_extend, tile_grid(g1), dim3(256), 0, st, g1, u, v, w, phi, qx, qy, qz, ue,
+                     ve, we, ug, vg, wg);
   return hipGetLastError();
-}
-
-int residual_blocks(long n) {
-  const long b = (n + 255) / 256;
-  return (int)(b < kResidualMaxBlocks ? b : kResidualMaxBlocks);
 }
 
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
                            double* partial, double* mean_out, double dz_sum, hipStream_t st) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  const int nb = residual_blocks(n);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, g, f, p, r, partial, n);
+  const int nb = stencil_blocks(g);
+  if (nb > kResidualMaxBlocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, r, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double denom = (double)g.nx * (double)g.ny * dz_sum;
