@@ -130,6 +130,26 @@ int extend_liquid_velocity(poisson_plan* plan, const double* u, const double* v,
                            double* phi, void* hip_stream);
 
 /*
+ * One time step of the path: the projection of section 3.2 followed by the
+ * extension of section 3.6 applied to the projected velocity.  Equivalent to
+ * project(plan, u, v, w, phat, rho, rho0, src_p, dt, p) followed by
+ * extend_liquid_velocity(plan, u, v, w, src_ext, q, ue, ug, phi), with the
+ * correction and extension stencils fused into one pass over the faces.
+ *   u, v, w    : in u*, out u^{n+1} (device, in place);
+ *   src_p      : source of the pressure equation, or NULL (s = 0);
+ *   src_ext    : source of the Stefan potential (required; in the paper the
+ *                same field mdot (1/rho2 - 1/rho1) |grad C| as src_p);
+ *   p, phi     : device outputs (distinct buffers);
+ *   ue,ve,we   : device outputs u_1^e, or all NULL;
+ *   qx..wg     : as in extend_liquid_velocity.
+ */
+int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* phat,
+             const double* rho, double rho0, const double* src_p, double dt, double* p,
+             const double* src_ext, const double* qx, const double* qy, const double* qz,
+             double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
+             double* phi, void* hip_stream);
+
+/*
  * Mixed-precision control (plans created with VP_PRECISION_MIXED): the
  * number of FP64 defect-correction steps after the first FP32 solve
  * (0..8, default 1).  Returns VP_EINVAL for an FP64 plan or a bad count.
@@ -156,16 +176,16 @@ long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_
 int poisson_plan_tune(poisson_plan* plan, const char* key, int value);
 
 /*
- * Per-launch timing.  With profiling enabled, every kernel the plan launches
- * is bracketed by two HIP events recorded on the caller's stream (a small
- * launch overhead).  poisson_plan_kernel_times waits for the recorded events,
+ * Per-launch timing.  class_mask selects kernel classes (bit c for class c;
+ * -1 for all, 0 to stop): every launch of a selected class is bracketed by
+ * two HIP events recorded on the caller's stream (a small launch overhead).  poisson_plan_kernel_times waits for the recorded events,
  * writes per kernel class the total milliseconds and the launch count into
  * total_ms[0..n) and launches[0..n) (classes beyond n are dropped), and
  * forgets the recorded launches.  Classes are numbered 0..VP_NUM_KERNEL_CLASSES-1;
  * poisson_kernel_class_name gives their names (NULL outside that range).
  */
-#define VP_NUM_KERNEL_CLASSES 14
-int poisson_plan_set_profiling(poisson_plan* plan, int enable);
+#define VP_NUM_KERNEL_CLASSES 15
+int poisson_plan_set_profiling(poisson_plan* plan, int class_mask);
 int poisson_plan_kernel_times(poisson_plan* plan, double* total_ms, int* launches, int n);
 const char* poisson_kernel_class_name(int cls);
 

@@ -24,6 +24,10 @@ def footprint(nx: int, ny: int, nz: int, precision: str = "fp64", max_batch: int
     return int(_lib.lib.poisson_plan_footprint(nx, ny, nz, _lib.PRECISION[precision], max_batch))
 
 
+def kernel_class_names():
+    return [_lib.lib.poisson_kernel_class_name(i).decode() for i in range(_lib.NUM_KERNEL_CLASSES)]
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -129,6 +133,31 @@ class Plan:
         check(_lib.lib.extend_liquid_velocity(*args), "extend_liquid_velocity")
         return (*out, *gs, phi)
 
+    def step(self, u, v, w, phat, rho, rho0, src_p, dt, src_ext, p=None, phi=None, q=None,
+             out=None, gamma=None, stream=None):
+        """One time step: projection of (u, v, w) = u* (in place) and extension of the
+        projected velocity.  Returns (u, v, w, p, phi, ue, ve, we, ug, vg, wg); ue.. are
+        None unless `out` is given, ug.. None without q."""
+        if p is None:
+            p = self._new(u)
+        if phi is None:
+            phi = self._new(u)
+        if q is not None and gamma is None:
+            gamma = (self._new(u), self._new(u), self._new(u))
+        qs = (None, None, None) if q is None else q
+        es = (None, None, None) if out is None else out
+        gs = (None, None, None) if gamma is None else gamma
+        args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
+                self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
+                self._ptr(src_p, "src_p", optional=True), float(dt), self._ptr(p, "p"),
+                self._ptr(src_ext, "src_ext")]
+        args += [self._ptr(t, "q", optional=True) for t in qs]
+        args += [self._ptr(t, "out", optional=True) for t in es]
+        args += [self._ptr(t, "gamma", optional=True) for t in gs]
+        args += [self._ptr(phi, "phi"), _stream_ptr(stream)]
+        check(_lib.lib.vof_step(*args), "vof_step")
+        return (u, v, w, p, phi, *es, *gs)
+
     def set_mixed(self, dc_steps: int):
         check(_lib.lib.poisson_plan_set_mixed(self._h, int(dc_steps)), "poisson_plan_set_mixed")
 
@@ -142,9 +171,19 @@ class Plan:
         """Launch-shape knob (see poisson_plan_tune); results do not change."""
         check(_lib.lib.poisson_plan_tune(self._h, key.encode(), int(value)), "poisson_plan_tune")
 
-    def set_profiling(self, enable: bool = True):
-        """Bracket every kernel launch of this plan with HIP events."""
-        check(_lib.lib.poisson_plan_set_profiling(self._h, int(bool(enable))),
+    def set_profiling(self, enable=True, classes=None):
+        """Bracket kernel launches of this plan with HIP events: every class when
+        `classes` is None, else only the named classes (see kernel_class_names)."""
+        if not enable:
+            mask = 0
+        elif classes is None:
+            mask = -1
+        else:
+            names = kernel_class_names()
+            mask = 0
+            for c in classes:
+                mask |= 1 << names.index(c)
+        check(_lib.lib.poisson_plan_set_profiling(self._h, int(mask)),
               "poisson_plan_set_profiling")
 
     def kernel_times(self):

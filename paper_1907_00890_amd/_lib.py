@@ -32,6 +32,7 @@ SIGNATURES = {
     "poisson_solve_batched": (_i, [_p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p]),
     "project": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p]),
     "extend_liquid_velocity": (_i, [_p] + [_p] * 14 + [_p]),
+    "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_last_mean": (_i, [_p, ctypes.POINTER(_d), _p]),
     "poisson_plan_footprint": (ctypes.c_longlong, [_i, _i, _i, _i, _i]),
@@ -49,7 +50,7 @@ for _name, (_res, _args) in SIGNATURES.items():
     _f.argtypes = _args
 
 VP_OK, VP_EINVAL, VP_EUNSUPPORTED, VP_ENOMEM, VP_EHIP = 0, -1, -2, -3, -4
-NUM_KERNEL_CLASSES = 14
+NUM_KERNEL_CLASSES = 15
 PRECISION = {"fp64": 0, "mixed": 1}
 
 

@@ -82,6 +82,11 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          const double* phi, const double* qx, const double* qy, const double* qz,
                          double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
                          hipStream_t st);
+hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double* w, const double* p,
+                                const double* phat, const double* rho, double rho0, double dt,
+                                const double* phi, const double* qx, const double* qy,
+                                const double* qz, double* ue, double* ve, double* we, double* ug,
+                                double* vg, double* wg, hipStream_t st);
 // r = f - L_h p; also mean_out[0] = volume-weighted mean of p.  partial must
 // hold kResidualMaxBlocks doubles.
 constexpr int kResidualMaxBlocks = 16384;

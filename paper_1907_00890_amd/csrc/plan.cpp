@@ -37,12 +37,12 @@ int hip_fail(hipError_t e, const char* what) {
 enum KernelClass {
   K_XFWD = 0, K_YFWD, K_Z, K_YINV, K_XINV,
   K_XFWD32, K_YFWD32, K_Z32, K_YINV32, K_XINV32,
-  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_NCLASS
+  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_EPILOGUE, K_NCLASS
 };
 const char* const kClassNames[K_NCLASS] = {
     "x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse",
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
-    "residual", "rhs_assembly", "correction", "extension"};
+    "residual", "rhs_assembly", "correction", "extension", "step_epilogue"};
 
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
@@ -107,7 +107,7 @@ struct poisson_plan {
     int cls;
     hipEvent_t a, b;
   };
-  bool profiling = false;
+  unsigned profiling = 0;  // bit c: bracket launches of kernel class c
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   hipEvent_t event() {
@@ -158,13 +158,14 @@ namespace {
 #define VP_LAUNCH(P, cls, call, what, st)                                 \
   do {                                                                    \
     hipEvent_t a_ = nullptr, b_ = nullptr;                                \
-    if ((P)->profiling) {                                                 \
+    const bool prof_ = ((P)->profiling >> (cls)) & 1u;                    \
+    if (prof_) {                                                          \
       a_ = (P)->event();                                                  \
       b_ = (P)->event();                                                  \
       if (a_) (void)hipEventRecord(a_, st);                               \
     }                                                                     \
     VP_HIP((call), what);                                                 \
-    if ((P)->profiling && a_ && b_) {                                     \
+    if (prof_ && a_ && b_) {                                              \
       (void)hipEventRecord(b_, st);                                       \
       (P)->marks.push_back({cls, a_, b_});                                \
     }                                                                     \
@@ -426,6 +427,34 @@ int extend_liquid_velocity(poisson_plan* P, const double* u, const double* v, co
   return VP_OK;
 }
 
+int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* phat,
+             const double* rho, double rho0, const double* src_p, double dt, double* p,
+             const double* src_ext, const double* qx, const double* qy, const double* qz,
+             double* ue, double* ve, double* we, double* ug, double* vg, double* wg, double* phi,
+             void* stream) {
+  if (!P || !u || !v || !w || !phat || !rho || !p || !src_ext || !phi || !(rho0 > 0) || !(dt > 0))
+    return VP_EINVAL;
+  const bool hq = qx && qy && qz, hg = ug && vg && wg, he = ue && ve && we;
+  if ((qx || qy || qz) && !hq) return VP_EINVAL;
+  if ((ug || vg || wg) && !hg) return VP_EINVAL;
+  if ((ue || ve || we) && !he) return VP_EINVAL;
+  if (hq != hg) return VP_EINVAL;
+  if (phi == p) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
+  VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),
+            "rhs assembly", st);
+  int s = solve_any(P, b, p, st);
+  if (s) return s;
+  s = solve_any(P, src_ext, phi, st);
+  if (s) return s;
+  VP_LAUNCH(P, K_EPILOGUE,
+            vp::launch_step_epilogue(P->g, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
+                                     ve, we, ug, vg, wg, st),
+            "step epilogue", st);
+  return VP_OK;
+}
+
 int poisson_plan_set_mixed(poisson_plan* P, int dc_steps) {
   if (!P || P->precision != VP_PRECISION_MIXED || dc_steps < 0 || dc_steps > 8) return VP_EINVAL;
   P->dc_steps = dc_steps;
@@ -480,9 +509,9 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
   return VP_EINVAL;
 }
 
-int poisson_plan_set_profiling(poisson_plan* P, int enable) {
+int poisson_plan_set_profiling(poisson_plan* P, int class_mask) {
   if (!P) return VP_EINVAL;
-  P->profiling = enable != 0;
+  P->profiling = (unsigned)class_mask;
   return VP_OK;
 }
 

@@ -27,10 +27,14 @@ struct Tile {
   bool hxp, hxm, hyp, hym;
 };
 
+// TXMAX: 64 for the marching 7-point kernels (taller tiles, fewer halo
+// rows), 256 for the streaming ones (whole rows)
+template <int TXMAX>
 __device__ __forceinline__ Tile tile_of(const GridArgs& g) {
+  constexpr int LTXMAX = TXMAX == 256 ? 8 : 6;
   Tile t;
-  const int tx = g.nx < 64 ? g.nx : 64;
-  const int ltx = g.lx < 6 ? g.lx : 6;
+  const int tx = g.nx < TXMAX ? g.nx : TXMAX;
+  const int ltx = g.lx < LTXMAX ? g.lx : LTXMAX;
   t.i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
   t.j = blockIdx.y * (256 / tx) + (threadIdx.x >> ltx);
   t.kb = blockIdx.z * g.kc;
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
                                               const double* __restrict__ rho, double rho0,
                                               const double* __restrict__ src, double dt,
                                               double* __restrict__ b) {
-  const Tile t = tile_of(g);
+  const Tile t = tile_of<64>(g);
   if (!t.ok) return;
   const long P = (long)g.nx * g.ny;
   const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, r0dt = rho0 / dt;
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
                                                   const double* __restrict__ ph,
                                                   const double* __restrict__ rho, double rho0,
                                                   double dt) {
-  const Tile t = tile_of(g);
+  const Tile t = tile_of<256>(g);
   if (!t.ok) return;
   const long P = (long)g.nx * g.ny;
   const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
                                                  double* __restrict__ ue, double* __restrict__ ve,
                                                  double* __restrict__ we, double* __restrict__ ug,
                                                  double* __restrict__ vg, double* __restrict__ wg) {
-  const Tile t = tile_of(g);
+  const Tile t = tile_of<256>(g);
   if (!t.ok) return;
   const long P = (long)g.nx * g.ny;
   const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
@@ -186,6 +190,59 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
   }
 }
 
+// One time step's two stencils after the solves, fused: on each of the
+// cell's "+" faces
+//   u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ]  (in place)
+//   u_1^e   = u^{n+1} - G phi,   u_Gamma = u_1^e - q
+__global__ __launch_bounds__(256) void k_step_epilogue(
+    const GridArgs g, double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
+    const double* __restrict__ p, const double* __restrict__ ph, const double* __restrict__ rho,
+    double rho0, double dt, const double* __restrict__ phi, const double* __restrict__ qx,
+    const double* __restrict__ qy, const double* __restrict__ qz, double* __restrict__ ue,
+    double* __restrict__ ve, double* __restrict__ we, double* __restrict__ ug,
+    double* __restrict__ vg, double* __restrict__ wg) {
+  const Tile t = tile_of<256>(g);
+  if (!t.ok) return;
+  const long P = (long)g.nx * g.ny;
+  const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+  const int k = t.kb;
+  const long c = k * P + t.c0;
+  const int kp = kplus(g, k);
+  const double pc = p[c], hc = ph[c], rc = rho[c], fc = phi[c];
+  double un = u[c], vn = v[c], wn = w[c];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (t.hxp) {
+    const long n = c + t.xp;
+    un -= dt * (ir0 * (p[n] - pc) * idx + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idx);
+    gx = (phi[n] - fc) * idx;
+  }
+  if (t.hyp) {
+    const long n = c + t.yp;
+    vn -= dt * (ir0 * (p[n] - pc) * idy + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idy);
+    gy = (phi[n] - fc) * idy;
+  }
+  if (kp >= 0) {
+    const long n = kp * P + t.c0;
+    const double h = g.dzc[k];
+    wn -= dt * (ir0 * (p[n] - pc) / h + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) / h);
+    gz = (phi[n] - fc) / h;
+  }
+  u[c] = un;
+  v[c] = vn;
+  w[c] = wn;
+  const double ex = un - gx, ey = vn - gy, ez = wn - gz;
+  if (ue) {
+    ue[c] = ex;
+    ve[c] = ey;
+    we[c] = ez;
+  }
+  if (ug) {
+    ug[c] = ex - qx[c];
+    vg[c] = ey - qy[c];
+    wg[c] = ez - qz[c];
+  }
+}
+
 // r = f - L_h p (FP64 residual of the defect-correction steps).  Each block
 // also sums dzf[k] * p over its cells (fixed order, no atomics) into
 // partial[block], so the weighted mean of p costs no extra pass.
@@ -194,7 +251,7 @@ __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double
                                                    double* __restrict__ r,
                                                    double* __restrict__ partial) {
   __shared__ double red[256];
-  const Tile t = tile_of(g);
+  const Tile t = tile_of<64>(g);
   double acc = 0.0;
   if (t.ok) {
     const long P = (long)g.nx * g.ny;
@@ -245,8 +302,9 @@ __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = red[0] / denom;
 }
 
+template <int TXMAX = 64>
 static inline dim3 tile_grid(const GridArgs& g) {
-  const int tx = g.nx < 64 ? g.nx : 64;
+  const int tx = g.nx < TXMAX ? g.nx : TXMAX;
   const int ty = 256 / tx;
   return dim3((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
               (unsigned)((g.nz + g.kc - 1) / g.kc));
@@ -281,8 +339,8 @@ hipError_t launch_correct(const GridArgs& g, double* u, double* v, double* w, co
                           hipStream_t st) {
   GridArgs g1 = g;
   g1.kc = 1;
-  hipLaunchKernelGGL(k_correct, tile_grid(g1), dim3(256), 0, st, g1, u, v, w, p, phat, rho, rho0,
-                     dt);
+  hipLaunchKernelGGL(k_correct, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, p, phat, rho,
+                     rho0, dt);
   return hipGetLastError();
 }
 
@@ -292,8 +350,20 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          hipStream_t st) {
   GridArgs g1 = g;
   g1.kc = 1;
-  hipLaunchKernelGGL(k_extend, tile_grid(g1), dim3(256), 0, st, g1, u, v, w, phi, qx, qy, qz, ue,
-                     ve, we, ug, vg, wg);
+  hipLaunchKernelGGL(k_extend, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, phi, qx, qy, qz,
+                     ue, ve, we, ug, vg, wg);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double* w, const double* p,
+                                const double* phat, const double* rho, double rho0, double dt,
+                                const double* phi, const double* qx, const double* qy,
+                                const double* qz, double* ue, double* ve, double* we, double* ug,
+                                double* vg, double* wg, hipStream_t st) {
+  GridArgs g1 = g;
+  g1.kc = 1;
+  hipLaunchKernelGGL(k_step_epilogue, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, p, phat,
+                     rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
   return hipGetLastError();
 }
 
