@@ -63,6 +63,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="ppn256",
                     help="workload the CPU oracle is timed on (bounded sample)")
+    ap.add_argument("--serve-rates", default="1000",
+                    help="comma-separated request rates (req/s) of the serving mix; "
+                         "'sweep' for 50,100,200,500,1000,2000; 'none' to skip")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain device copies of one field (a known byte "
                          "count for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -108,6 +114,155 @@ def make_inputs(cfg, torch, dev):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     return dict(u=T(us), v=T(vs), w=T(ws), rho=T(rho), s=T(s), phat=T(phat),
                 qx=T(q[0]), qy=T(q[1]), qz=T(q[2]), f=T(f), rho0=min(rho1, rho2), dt=1.0)
+
+
+# ---------------------------------------------------------------------------
+# serving mix: Poisson arrivals of solves and extensions of mixed grids
+# ---------------------------------------------------------------------------
+SERVE_CLASSES = [
+    # name, nx, ny, nz, Lz, beta (tanh clustering of z; None = uniform)
+    ("64^3", 64, 64, 64, 1.0, None),
+    ("128^3", 128, 128, 128, 1.0, None),
+    ("256^3", 256, 256, 256, 1.0, None),
+    ("128x128x256s", 128, 128, 256, 1.0, 1.5),
+    ("1024^2 slab", 1024, 1024, 1, 1.0 / 1024, None),
+]
+
+
+class ServeMix:
+    """Device-resident inputs and output slots for the serving mix.
+
+    Per class: a bank of two seeded zero-mean N(0,1) right-hand sides and
+    velocity fields (inputs resident in HBM before timing), and `slots`
+    output sets reused round-robin; a slot still in use by an unfinished
+    request is waited for before reuse (client back-pressure, inside the
+    measured latency).
+    """
+
+    def __init__(self, torch, dev, slots=12):
+        import numpy as np
+
+        import vofsynth
+        from paper_1907_00890_amd.serve import Grid
+        self.torch = torch
+        self.cls = []
+        for k, (name, nx, ny, nz, lz, beta) in enumerate(SERVE_CLASSES):
+            dzf = vofsynth.uniform_dz(nz, lz) if beta is None else vofsynth.stretched_dz(nz, lz, beta)
+            g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, dzf, "PPN")
+            bank = []
+            for b in range(2):
+                f = vofsynth.remove_weighted_mean(
+                    vofsynth.gaussian_field(g.shape, 1_000_000 + 10 * k + b), dzf)
+                u = vofsynth.random_faces(g.shape, 2_000_000 + 10 * k + b, "PPN")
+                T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+                bank.append({"f": T(f), "u": [T(a) for a in u]})
+            outs = []
+            for _ in range(slots):
+                e = lambda: torch.empty(g.shape, dtype=torch.float64, device=dev)  # noqa: E731
+                outs.append({"sol": e(), "out": (e(), e(), e()), "phi": e(), "ticket": None})
+            self.cls.append({"name": name, "grid": g, "bank": bank, "outs": outs, "next": 0,
+                             "npts": nx * ny * nz})
+
+    def submit(self, srv, ci, kind, precision, bank_i, early_results):
+        c = self.cls[ci]
+        slot = c["outs"][c["next"]]
+        c["next"] = (c["next"] + 1) % len(c["outs"])
+        if slot["ticket"] is not None:  # back-pressure: the slot is still in use
+            early_results[slot["ticket"]] = srv.wait(slot["ticket"], -1)
+        b = c["bank"][bank_i]
+        if kind == "solve":
+            t = srv.submit_solve(c["grid"], b["f"], slot["sol"], precision=precision)
+        else:
+            u, v, w = b["u"]
+            t = srv.submit_extend(c["grid"], u, v, w, b["f"], slot["out"], phi=slot["phi"],
+                                  precision=precision)
+        slot["ticket"] = t
+        return t
+
+
+def serve_run(srv, mix, rate, n, seed):
+    """Poisson arrivals at `rate` req/s; returns latency statistics (ms)."""
+    import numpy as np
+
+    from paper_1907_00890_amd.serve import now_us
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1e6 / rate, size=n)
+    ci = rng.integers(0, len(mix.cls), size=n)
+    kinds = np.where(rng.random(n) < 0.5, "solve", "extend")
+    precs = np.where(rng.random(n) < 0.5, "fp64", "mixed")
+    banks = rng.integers(0, 2, size=n)
+    early = {}
+    tickets, t_arr = [], []
+    t0 = now_us() + 2000.0
+    arrival = t0
+    for i in range(n):
+        arrival += gaps[i]
+        while True:
+            d = arrival - now_us()
+            if d <= 0:
+                break
+            if d > 300:
+                time.sleep((d - 200) * 1e-6)
+        tickets.append(mix.submit(srv, int(ci[i]), kinds[i], precs[i], int(banks[i]), early))
+        t_arr.append(arrival)
+    res = []
+    for t in tickets:
+        r = early.pop(t, None) or srv.wait(t, -1)
+        res.append(r)
+    for c in mix.cls:
+        for s in c["outs"]:
+            s["ticket"] = None
+    ok = [r["status"] == 0 for r in res]
+    lat = np.array([(r["t_done_us"] - a) * 1e-3 for r, a in zip(res, t_arr)])
+    qwait = np.array([(r["t_dispatch_us"] - a) * 1e-3 for r, a in zip(res, t_arr)])
+    t_end = max(r["t_done_us"] for r in res)
+    pts = sum(mix.cls[int(c)]["npts"] for c in ci)
+    per_class = {}
+    for k, c in enumerate(mix.cls):
+        m = ci == k
+        if m.any():
+            per_class[c["name"]] = {"n": int(m.sum()),
+                                    "p50_ms": round(float(np.percentile(lat[m], 50)), 3),
+                                    "p99_ms": round(float(np.percentile(lat[m], 99)), 3)}
+    return {"rate_req_s": rate, "requests": n, "completed": int(sum(ok)),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "queue_wait_p99_ms": round(float(np.percentile(qwait, 99)), 3),
+            "throughput_req_s": round(n / ((t_end - t0) * 1e-6), 1),
+            "throughput_mpts_s": round(pts / ((t_end - t0) * 1e-6) / 1e6, 1),
+            "mean_batch": round(float(np.mean([r["batch"] for r in res])), 2),
+            "per_class": per_class}
+
+
+def serve_bench(torch, dev, rates, n, lanes, max_batch):
+    from paper_1907_00890_amd.serve import Server
+    mix = ServeMix(torch, dev)
+    out = []
+    with Server(96 << 30, lanes=lanes, max_batch=max_batch, max_pending=1 << 20) as srv:
+        # warm every class / kind / precision once: plans resident before timing
+        warm = []
+        early = {}
+        for k in range(len(mix.cls)):
+            for kind in ("solve", "extend"):
+                for prec in ("fp64", "mixed"):
+                    warm.append(mix.submit(srv, k, kind, prec, 0, early))
+        for t in warm:
+            early.pop(t, None) or srv.wait(t, -1)
+        for c in mix.cls:
+            for s in c["outs"]:
+                s["ticket"] = None
+        for rate in rates:
+            r = serve_run(srv, mix, rate, n, seed=5)
+            print(f"[serve] rate {rate} req/s: p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms, "
+                  f"{r['throughput_req_s']} req/s, mean batch {r['mean_batch']}",
+                  file=sys.stderr, flush=True)
+            out.append(r)
+        st = srv.stats()
+    return out, {"lanes": lanes, "max_batch": max_batch, "hbm_budget_gib": 96,
+                 "plans_resident": st["plans_resident"],
+                 "bytes_resident_gib": round(st["bytes_resident"] / 2**30, 2),
+                 "failed": st["failed"], "rejected": st["rejected"]}
 
 
 def cpu_baseline(sample_name):
@@ -294,6 +449,19 @@ def main():
         "kernel_ms_per_step": round(kern_ms_step, 4),
         "wall_s_timed": round(t_wall, 3),
     }
+    rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
+        args.serve_rates, None)
+    if rates is None:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+    if rates:
+        runs, setup = serve_bench(torch, dev, rates, args.serve_requests, args.serve_lanes,
+                                  args.serve_batch)
+        line["serving"] = {"mix": "Poisson arrivals (seed 5), classes uniform over "
+                                  + ", ".join(c[0] for c in SERVE_CLASSES)
+                                  + " (PPN; 128x128x256 tanh beta=1.5), solve/extend 50/50, "
+                                  "FP64/mixed 50/50, device-resident seeded inputs",
+                           "latency": "arrival to completion observed by the server",
+                           "setup": setup, "runs": runs}
     if args.copy_calibration:
         src = torch.randn(cfg.shape, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -57,26 +57,39 @@ extern "C" {
 #define VP_PRECISION_FP64 0
 #define VP_PRECISION_MIXED 1
 
+#define VP_MAX_BATCH 16 /* fields per batched call */
+
 typedef struct poisson_plan poisson_plan;
 
 /*
  * Create a plan on the current HIP device.
  *   nx, ny : power of two in [8, 1024];
- *   nz     : >= 1 (>= 3 when z is periodic), at most 4096;
+ *   nz     : >= 1 (>= 3 when z is periodic), at most 1024;
  *   dx, dy : > 0;  dz: HOST array of nz cell widths, each > 0 (copied);
  *   bc     : 3 characters for x, y, z: 'P' periodic, 'N' wall with zero
  *            normal gradient of p (zero normal velocity);
  *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 transforms and
  *            FP32 tridiagonal storage with FP64 pivots, refined by FP64
  *            residual / defect-correction steps, see poisson_plan_set_mixed);
- *   max_batch : largest n accepted by poisson_solve_batched (>= 1).
- * Allocates the plan's device tables and workspace (8*nx*ny*nz bytes for
- * FP64; FP64 + FP32 buffers for mixed).  Returns NULL and sets *status on
- * failure (status may be NULL).
+ *   max_batch : largest n accepted by the batched calls, 1..VP_MAX_BATCH.
+ * Allocates the plan's device tables and workspace: one spectrum slot of
+ * 8*nx*ny*nz bytes per batch member for FP64, plus FP32 spectra and FP64
+ * residuals for mixed (poisson_plan_footprint gives the exact total).
+ * Returns NULL and sets *status on failure (status may be NULL):
+ * VP_EINVAL for bad arguments, VP_EUNSUPPORTED for sizes or boundary
+ * conditions outside the limits above.
  */
 poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy,
                                   const double* dz, const char* bc, int precision,
                                   int max_batch, int* status);
+
+/*
+ * Check the arguments of poisson_plan_create without touching the device:
+ * VP_OK, VP_EINVAL or VP_EUNSUPPORTED, exactly as poisson_plan_create would
+ * return them.
+ */
+int poisson_plan_check(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                       const char* bc, int precision, int max_batch);
 
 /* Release every device allocation of the plan (synchronises the device). */
 void poisson_plan_destroy(poisson_plan* plan);
@@ -89,8 +102,10 @@ void poisson_plan_destroy(poisson_plan* plan);
 int poisson_solve(poisson_plan* plan, const double* rhs, double* sol, void* hip_stream);
 
 /*
- * n independent solves with the plan's shape (n <= max_batch), queued back
- * to back on one stream; rhs[i] / sol[i] are HOST arrays of device pointers.
+ * n independent solves with the plan's shape (0 <= n <= max_batch) in one
+ * launch per pass: rhs and sol are HOST arrays of n device pointers.  Each
+ * result equals that of poisson_solve on the same input, bit for bit (no
+ * arithmetic depends on the other members).  sol[i] may alias rhs[i].
  */
 int poisson_solve_batched(poisson_plan* plan, int n, const double* const* rhs,
                           double* const* sol, void* hip_stream);
@@ -129,6 +144,22 @@ int extend_liquid_velocity(poisson_plan* plan, const double* u, const double* v,
                            double* ug, double* vg, double* wg,
                            double* phi, void* hip_stream);
 
+/* The device fields of one extension (same meaning as the arguments above). */
+typedef struct vp_extend_fields {
+  const double *u, *v, *w, *src, *qx, *qy, *qz;
+  double *ue, *ve, *we, *ug, *vg, *wg, *phi;
+} vp_extend_fields;
+
+/*
+ * n extensions with the plan's shape (0 <= n <= max_batch): the n Poisson
+ * solves share one launch per pass, then the extension stencil runs per
+ * member.  fields: HOST array of n structs.  With phi NULL (FP64 plans only)
+ * member i's potential stays in workspace slot i.  Results equal those of
+ * extend_liquid_velocity member by member, bit for bit.
+ */
+int extend_liquid_velocity_batched(poisson_plan* plan, int n, const vp_extend_fields* fields,
+                                   void* hip_stream);
+
 /*
  * One time step of the path: the projection of section 3.2 followed by the
  * extension of section 3.6 applied to the projected velocity.  Equivalent to
@@ -162,8 +193,13 @@ int poisson_plan_set_mixed(poisson_plan* plan, int dc_steps);
  */
 int poisson_plan_last_mean(poisson_plan* plan, double* mean_out, void* hip_stream);
 
-/* Size in bytes of the device memory held by a plan with these arguments. */
+/*
+ * Size in bytes of the device memory a plan with these arguments holds
+ * (-1 for invalid arguments); poisson_plan_device_bytes gives it for an
+ * existing plan.
+ */
 long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_batch);
+long long poisson_plan_device_bytes(const poisson_plan* plan);
 
 /*
  * Launch-shape tuning (results do not change, only speed):

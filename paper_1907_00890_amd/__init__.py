@@ -100,6 +100,42 @@ class Plan:
               "poisson_solve_batched")
         return out_list
 
+    def extend_batched(self, items, stream=None):
+        """Batched extension: items is a list of dicts with keys u, v, w, src and
+        optionally q (3 tensors), out (3), gamma (3), phi.  Missing outputs are
+        allocated; returns a list of (ue, ve, we, ug, vg, wg, phi) per item."""
+        n = len(items)
+        arr = (_lib.ExtendFields * max(n, 1))()
+        results = []
+        for k, it in enumerate(items):
+            u = it["u"]
+            out = it.get("out") or (self._new(u), self._new(u), self._new(u))
+            q = it.get("q")
+            gamma = it.get("gamma")
+            if q is not None and gamma is None:
+                gamma = (self._new(u), self._new(u), self._new(u))
+            phi = it.get("phi")
+            if phi is None and self.precision == "mixed":
+                phi = self._new(u)
+            qs = (None, None, None) if q is None else q
+            gs = (None, None, None) if gamma is None else gamma
+            f = arr[k]
+            f.u, f.v, f.w = (self._ptr(it[c], c).value for c in ("u", "v", "w"))
+            f.src = self._ptr(it["src"], "src").value
+            f.qx, f.qy, f.qz = (getattr(self._ptr(t, "q", optional=True), "value", None)
+                                for t in qs)
+            f.ue, f.ve, f.we = (self._ptr(t, "out").value for t in out)
+            f.ug, f.vg, f.wg = (getattr(self._ptr(t, "gamma", optional=True), "value", None)
+                                for t in gs)
+            f.phi = getattr(self._ptr(phi, "phi", optional=True), "value", None)
+            results.append((*out, *gs, phi))
+        check(_lib.lib.extend_liquid_velocity_batched(self._h, n, arr, _stream_ptr(stream)),
+              "extend_liquid_velocity_batched")
+        return results
+
+    def device_bytes(self) -> int:
+        return int(_lib.lib.poisson_plan_device_bytes(self._h))
+
     def project(self, u, v, w, phat, rho, rho0, src, dt, p=None, stream=None):
         """In-place projection of (u, v, w) = u*; returns (u, v, w, p)."""
         if p is None:

@@ -23,19 +23,30 @@ _p = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
 
+
+class ExtendFields(ctypes.Structure):
+    """vp_extend_fields: device pointers of one extension."""
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("u", "v", "w", "src", "qx", "qy", "qz", "ue", "ve", "we", "ug", "vg", "wg",
+                 "phi")]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "poisson_plan_create": (_p, [_i, _i, _i, _d, _d, ctypes.POINTER(_d), ctypes.c_char_p, _i, _i,
                                  ctypes.POINTER(_i)]),
+    "poisson_plan_check": (_i, [_i, _i, _i, _d, _d, ctypes.POINTER(_d), ctypes.c_char_p, _i, _i]),
     "poisson_plan_destroy": (None, [_p]),
     "poisson_solve": (_i, [_p, _p, _p, _p]),
     "poisson_solve_batched": (_i, [_p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p]),
     "project": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p]),
     "extend_liquid_velocity": (_i, [_p] + [_p] * 14 + [_p]),
+    "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_last_mean": (_i, [_p, ctypes.POINTER(_d), _p]),
     "poisson_plan_footprint": (ctypes.c_longlong, [_i, _i, _i, _i, _i]),
+    "poisson_plan_device_bytes": (ctypes.c_longlong, [_p]),
     "poisson_plan_tune": (_i, [_p, ctypes.c_char_p, _i]),
     "poisson_plan_set_profiling": (_i, [_p, _i]),
     "poisson_plan_kernel_times": (_i, [_p, ctypes.POINTER(_d), ctypes.POINTER(_i), _i]),
@@ -51,6 +62,7 @@ for _name, (_res, _args) in SIGNATURES.items():
 
 VP_OK, VP_EINVAL, VP_EUNSUPPORTED, VP_ENOMEM, VP_EHIP = 0, -1, -2, -3, -4
 NUM_KERNEL_CLASSES = 15
+MAX_BATCH = 16
 PRECISION = {"fp64": 0, "mixed": 1}
 
 

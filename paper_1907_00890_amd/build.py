@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvofpoisson.so")
 
-SOURCES = ["plan.cpp", "transforms.hip", "zsolve.hip", "stencils.hip"]
+SOURCES = ["plan.cpp", "plan_check.cpp", "serve.cpp", "transforms.hip", "zsolve.hip", "stencils.hip"]
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -37,7 +37,7 @@ def common_flags():
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-Wno-unused-function",
+        "-Wall", "-Wno-unused-function", "-pthread",
         "-I", INCLUDE, "-I", CSRC,
     ]
 
@@ -60,7 +60,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "limits.hpp"
+
 namespace vp {
 
 enum : int { BC_P = 0, BC_N = 1 };  // periodic / wall with zero normal gradient
@@ -16,23 +18,45 @@ inline hipError_t allow_large_lds(K* kernel) {
   return once;
 }
 
+// Up to kMaxBatch independent fields go through one launch of each pass: the
+// batch member is blockIdx.y (x and z passes) or folded into the plane index
+// (y pass, the spectra of a batch are consecutive).  Caller-owned fields are
+// passed as a table of pointers, by value in the kernel arguments.
+template <typename T>
+struct Batch {
+  T* p[kMaxBatch];
+};
+template <typename T>
+inline Batch<T> batch_of(T* const* ptrs, int n) {
+  Batch<T> b{};
+  for (int i = 0; i < n && i < kMaxBatch; ++i) b.p[i] = ptrs[i];
+  return b;
+}
+
 // transforms.hip -------------------------------------------------------------
 // tab layout per direction and precision: cos(2 pi k/N), sin(2 pi k/N) for
 // k < N, then cos(pi m/(2N)), sin(pi m/(2N)) for m <= N/2.
 int ypass_tile_cols(int nx, int ny);
-hipError_t launch_xfwd_f64(const double* in, double* out, int nx, int bc, long nrows,
-                           const double* tab, hipStream_t st);
-hipError_t launch_xinv_f64(const double* in, double* out, int nx, int bc, long nrows,
-                           const double* tab, hipStream_t st);
-hipError_t launch_xfwd_f32(const double* in, float* out, int nx, int bc, long nrows,
+// x passes: `in`/`out` hold nb caller fields; the spectra of batch member b
+// start at b * stride of the workspace
+hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
+                           int nx, int bc, long nrows, const double* tab, hipStream_t st);
+hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
+                           int nx, int bc, long nrows, const double* tab, hipStream_t st);
+// sub (may be null): member b's input is read as in[b] - sub[b] (in FP64,
+// before the conversion to FP32)
+hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
+                           int nx, int bc, long nrows, const double* sub, const float* tab,
+                           hipStream_t st);
+// accum: out += result - sub[b] for batch member b (sub may be null: nothing subtracted)
+hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
+                           int nx, int bc, long nrows, bool accum, const double* sub,
                            const float* tab, hipStream_t st);
-// accum: out += result - sub[0] (sub may be null: nothing subtracted)
-hipError_t launch_xinv_f32(const float* in, double* out, int nx, int bc, long nrows, bool accum,
-                           const double* sub, const float* tab, hipStream_t st);
-hipError_t launch_y_f64(double* data, int nx, int ny, int nz, int bc, bool fwd,
+// y passes over nplanes consecutive z-planes (nz * batch)
+hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const double* tab, hipStream_t st);
-hipError_t launch_y_f32(float* data, int nx, int ny, int nz, int bc, bool fwd, const float* tab,
-                        hipStream_t st);
+hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
+                        const float* tab, hipStream_t st);
 
 // zsolve.hip -----------------------------------------------------------------
 struct ZArgs {
@@ -57,10 +81,11 @@ struct ZArgs {
   const double* zc;    // super-diagonal (wall form: zc[nz-1] = 0)
   const double* dzf;
   const double* dzc;   // centre distance across face k+1/2 (wrap at nz-1 if periodic)
-  double* mean_out;    // removed weighted mean (diagnostic), may be null
+  double* mean_out;    // removed weighted mean of batch member b at [b] (diagnostic), may be null
+  long batch_stride;   // elements between the spectra of consecutive batch members
 };
-hipError_t launch_zsolve_f64(double* data, const ZArgs& a, hipStream_t st);
-hipError_t launch_zsolve_f32(float* data, const ZArgs& a, hipStream_t st);
+hipError_t launch_zsolve_f64(double* data, const ZArgs& a, int nb, hipStream_t st);
+hipError_t launch_zsolve_f32(float* data, const ZArgs& a, int nb, hipStream_t st);
 
 // stencils.hip ---------------------------------------------------------------
 struct GridArgs {
@@ -87,12 +112,12 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
                                 const double* phi, const double* qx, const double* qy,
                                 const double* qz, double* ue, double* ve, double* we, double* ug,
                                 double* vg, double* wg, hipStream_t st);
-// r = f - L_h p; also mean_out[0] = volume-weighted mean of p.  partial must
-// hold kResidualMaxBlocks doubles.
-constexpr int kResidualMaxBlocks = 16384;
+// r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
+// r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);
 int stencil_default_planes(int nx, int ny, int nz);
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
-                           double* partial, double* mean_out, double dz_sum, hipStream_t st);
+                           double* partial, double* mean_p, double* mean_r, double dz_sum,
+                           hipStream_t st);
 
 }  // namespace vp

@@ -44,8 +44,6 @@ const char* const kClassNames[K_NCLASS] = {
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
     "residual", "rhs_assembly", "correction", "extension", "step_epilogue"};
 
-bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
-
 // Twiddle table of one direction: cos/sin(2 pi k/N), k < N, then
 // cos/sin(pi m/(2N)), m <= N/2 (the DCT post/pre rotation).
 std::vector<double> make_table(int n) {
@@ -205,15 +203,17 @@ int plan_init(poisson_plan* P, const double* dz) {
   if ((st = P->upload(&P->dzc, c, "dzc"))) return st;
   if ((st = P->upload(&P->za, a, "za"))) return st;
   if ((st = P->upload(&P->zc, cc, "zc"))) return st;
-  if ((st = P->alloc(&P->mean, 4, "mean"))) return st;
-  VP_HIP(hipMemset(P->mean, 0, 4 * sizeof(double)), "mean init");
+  if ((st = P->alloc(&P->mean, 3 * vp::kMaxBatch, "mean"))) return st;
+  VP_HIP(hipMemset(P->mean, 0, 3 * vp::kMaxBatch * sizeof(double)), "mean init");
 
-  const size_t n = (size_t)P->npts();
+  // one spectrum slot per batch member
+  const size_t n = (size_t)P->npts() * P->max_batch;
   if ((st = P->alloc(&P->work64, n, "workspace"))) return st;
   if (P->precision == VP_PRECISION_MIXED) {
     if ((st = P->alloc(&P->work32, n, "workspace f32"))) return st;
     if ((st = P->alloc(&P->res64, n, "residual"))) return st;
-    if ((st = P->alloc(&P->partial, vp::kResidualMaxBlocks, "partial sums"))) return st;
+    if ((st = P->alloc(&P->partial, (size_t)2 * vp::kResidualMaxBlocks * P->max_batch, "partial sums")))
+      return st;
   }
 
   // z launch geometry: S segments of at most 16 rows (S <= 64)
@@ -249,6 +249,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.dzf = P->dzf;
   Z.dzc = P->dzc;
   Z.mean_out = P->mean;
+  Z.batch_stride = P->npts();
 
   vp::GridArgs& G = P->g;
   G.nx = nx; G.ny = ny; G.nz = nz;
@@ -263,59 +264,88 @@ int plan_init(poisson_plan* P, const double* dz) {
   return VP_OK;
 }
 
-// FP64 chain: rhs -> sol (sol may alias rhs)
-int solve_f64(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
-  const long nrows = (long)P->ny * P->nz;
+// FP64 chain over nb fields: rhs[b] -> sol[b] (sol[b] may alias rhs[b])
+int solve_f64(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
+              hipStream_t st) {
+  const long nrows = (long)P->ny * P->nz, N = P->npts();
   double* w = P->work64;
-  VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(rhs, w, P->nx, P->bc[0], nrows, P->tabx64, st), "x forward", st);
-  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz, P->bc[1], true, P->taby64, st), "y forward", st);
-  VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, st), "z solve", st);
-  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz, P->bc[1], false, P->taby64, st), "y inverse", st);
-  VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, sol, P->nx, P->bc[0], nrows, P->tabx64, st), "x inverse", st);
+  const vp::Batch<const double> in = vp::batch_of(rhs, nb);
+  const vp::Batch<double> out = vp::batch_of(sol, nb);
+  VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, st), "x forward", st);
+  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, st), "y forward", st);
+  VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, nb, st), "z solve", st);
+  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, st), "y inverse", st);
+  VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, N, out, nb, P->nx, P->bc[0], nrows, P->tabx64, st), "x inverse", st);
   return VP_OK;
 }
 
-// FP32 chain on an FP64 right-hand side; out = result, or with accum
-// out += result - sub[0]
-int solve_f32(poisson_plan* P, const double* rhs, double* out, bool accum, const double* sub,
-              hipStream_t st) {
-  const long nrows = (long)P->ny * P->nz;
+// FP32 chain on FP64 right-hand sides rhs[b] - rsub[b] (rsub may be null);
+// out[b] = result, or with accum out[b] += result - sub[b]
+int solve_f32(poisson_plan* P, int nb, const double* const* rhs, const double* rsub,
+              double* const* out, bool accum, const double* sub, hipStream_t st) {
+  const long nrows = (long)P->ny * P->nz, N = P->npts();
   float* w = P->work32;
-  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(rhs, w, P->nx, P->bc[0], nrows, P->tabx32, st), "x forward f32", st);
-  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz, P->bc[1], true, P->taby32, st), "y forward f32", st);
-  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, P->z, st), "z solve f32", st);
-  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz, P->bc[1], false, P->taby32, st), "y inverse f32", st);
-  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, out, P->nx, P->bc[0], nrows, accum, sub, P->tabx32, st),
+  const vp::Batch<const double> in = vp::batch_of(rhs, nb);
+  const vp::Batch<double> o = vp::batch_of(out, nb);
+  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, rsub, P->tabx32, st), "x forward f32", st);
+  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby32, st), "y forward f32", st);
+  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, P->z, nb, st), "z solve f32", st);
+  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby32, st), "y inverse f32", st);
+  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, o, nb, P->nx, P->bc[0], nrows, accum, sub, P->tabx32, st),
             "x inverse f32", st);
   return VP_OK;
 }
 
 // Mixed precision: p = S32(f), then dc_steps times
-//   r = f - L_h p (FP64, also giving mean_W(p)),  p += S32(r) - mean_W(p).
+//   r = f - L_h p (FP64, also giving mean_W(p) and mean_W(r)),
+//   p += S32(r - mean_W(r)) - mean_W(p).
 // The FP32 chain cannot see the null (constant) mode, so the FP64 weighted
-// mean is removed in every correction step instead.
-int solve_mixed(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
-  const double* f = rhs;
-  if (rhs == sol) {
-    VP_HIP(hipMemcpyAsync(P->res64, rhs, sizeof(double) * P->npts(), hipMemcpyDeviceToDevice, st),
-           "copy rhs");
-    f = P->res64;
+// means are removed in every correction step instead: mean_W(r) equals
+// mean_W(f), which would otherwise dominate r and swamp its FP32 copy.
+// Batch member b keeps f in place, or in work64 slot b when an output
+// overwrites it, and its residual in res64 slot b (work64 slot b when f
+// itself lies in res64 slot b).
+int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
+                hipStream_t st) {
+  const long N = P->npts();
+  const double* f[vp::kMaxBatch];
+  double* r[vp::kMaxBatch];
+  for (int b = 0; b < nb; ++b) {
+    f[b] = rhs[b];
+    bool clobbered = false;
+    for (int c = 0; c < nb; ++c) clobbered = clobbered || sol[c] == rhs[b];
+    if (clobbered) {
+      VP_HIP(hipMemcpyAsync(P->work64 + b * N, rhs[b], sizeof(double) * N, hipMemcpyDeviceToDevice, st),
+             "copy rhs");
+      f[b] = P->work64 + b * N;
+    }
+    r[b] = (f[b] == P->res64 + b * N) ? P->work64 + b * N : P->res64 + b * N;
   }
-  double* r = (f == P->res64) ? P->work64 : P->res64;
-  int s = solve_f32(P, f, sol, false, nullptr, st);
+  double* const pmeans = P->mean + vp::kMaxBatch;      // FP64 weighted mean of p per member
+  double* const rmeans = P->mean + 2 * vp::kMaxBatch;  // and of the residual
+  int s = solve_f32(P, nb, f, nullptr, sol, false, nullptr, st);
   if (s) return s;
   for (int it = 0; it < P->dc_steps; ++it) {
-    VP_LAUNCH(P, K_RESIDUAL, vp::launch_residual(P->g, f, sol, r, P->partial, P->mean + 1, P->dz_sum, st),
-              "residual", st);
-    s = solve_f32(P, r, sol, true, P->mean + 1, st);
+    for (int b = 0; b < nb; ++b)
+      VP_LAUNCH(P, K_RESIDUAL,
+                vp::launch_residual(P->g, f[b], sol[b], r[b],
+                                    P->partial + 2L * b * vp::kResidualMaxBlocks, pmeans + b,
+                                    rmeans + b, P->dz_sum, st),
+                "residual", st);
+    s = solve_f32(P, nb, r, rmeans, sol, true, pmeans, st);
     if (s) return s;
   }
   return VP_OK;
 }
 
-int solve_any(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
-  if (P->precision == VP_PRECISION_MIXED) return solve_mixed(P, rhs, sol, st);
-  return solve_f64(P, rhs, sol, st);
+int solve_any(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
+              hipStream_t st) {
+  if (P->precision == VP_PRECISION_MIXED) return solve_mixed(P, nb, rhs, sol, st);
+  return solve_f64(P, nb, rhs, sol, st);
+}
+
+int solve_one(poisson_plan* P, const double* rhs, double* sol, hipStream_t st) {
+  return solve_any(P, 1, &rhs, &sol, st);
 }
 
 }  // namespace
@@ -328,22 +358,10 @@ poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, 
     if (status) *status = s;
     return nullptr;
   };
-  if (!dz || !bc || nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || !(dy > 0) || max_batch < 1)
-    return fail(VP_EINVAL);
+  const int chk = poisson_plan_check(nx, ny, nz, dx, dy, dz, bc, precision, max_batch);
+  if (chk != VP_OK) return fail(chk);
   int bcs[3];
-  for (int d = 0; d < 3; ++d) {
-    const char ch = bc[d];
-    if (ch == 'P' || ch == 'p') bcs[d] = vp::BC_P;
-    else if (ch == 'N' || ch == 'n') bcs[d] = vp::BC_N;
-    else if (ch == 'D' || ch == 'd') return fail(VP_EUNSUPPORTED);
-    else return fail(VP_EINVAL);
-  }
-  if (bc[3] != '\0') return fail(VP_EINVAL);
-  for (int k = 0; k < nz; ++k)
-    if (!(dz[k] > 0) || !std::isfinite(dz[k])) return fail(VP_EINVAL);
-  if (bcs[2] == vp::BC_P && nz < 3) return fail(VP_EINVAL);
-  if (precision != VP_PRECISION_FP64 && precision != VP_PRECISION_MIXED) return fail(VP_EINVAL);
-  if (!pow2_in(nx, 8, 1024) || !pow2_in(ny, 8, 1024) || nz > 1024) return fail(VP_EUNSUPPORTED);
+  for (int d = 0; d < 3; ++d) bcs[d] = (bc[d] == 'P' || bc[d] == 'p') ? vp::BC_P : vp::BC_N;
 
   poisson_plan* P = new (std::nothrow) poisson_plan();
   if (!P) return fail(VP_ENOMEM);
@@ -376,7 +394,7 @@ void poisson_plan_destroy(poisson_plan* P) {
 
 int poisson_solve(poisson_plan* P, const double* rhs, double* sol, void* stream) {
   if (!P || !rhs || !sol) return VP_EINVAL;
-  return solve_any(P, rhs, sol, static_cast<hipStream_t>(stream));
+  return solve_one(P, rhs, sol, static_cast<hipStream_t>(stream));
 }
 
 int poisson_solve_batched(poisson_plan* P, int n, const double* const* rhs, double* const* sol,
@@ -384,11 +402,8 @@ int poisson_solve_batched(poisson_plan* P, int n, const double* const* rhs, doub
   if (!P || !rhs || !sol || n < 0 || n > P->max_batch) return VP_EINVAL;
   for (int i = 0; i < n; ++i)
     if (!rhs[i] || !sol[i]) return VP_EINVAL;
-  for (int i = 0; i < n; ++i) {
-    const int s = solve_any(P, rhs[i], sol[i], static_cast<hipStream_t>(stream));
-    if (s) return s;
-  }
-  return VP_OK;
+  if (n == 0) return VP_OK;
+  return solve_any(P, n, rhs, sol, static_cast<hipStream_t>(stream));
 }
 
 int project(poisson_plan* P, double* u, double* v, double* w, const double* phat,
@@ -399,9 +414,47 @@ int project(poisson_plan* P, double* u, double* v, double* w, const double* phat
   // mixed precision keeps the FP64 right-hand side for its residuals
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src, dt, b, st), "rhs assembly", st);
-  int s = solve_any(P, b, p, st);
+  int s = solve_one(P, b, p, st);
   if (s) return s;
   VP_LAUNCH(P, K_CORRECT, vp::launch_correct(P->g, u, v, w, p, phat, rho, rho0, dt, st), "correction", st);
+  return VP_OK;
+}
+
+namespace {
+int check_extend(const vp_extend_fields& a) {
+  if (!a.u || !a.v || !a.w || !a.src || !a.ue || !a.ve || !a.we) return VP_EINVAL;
+  const bool hq = a.qx && a.qy && a.qz, hg = a.ug && a.vg && a.wg;
+  if ((a.qx || a.qy || a.qz) && !hq) return VP_EINVAL;
+  if ((a.ug || a.vg || a.wg) && !hg) return VP_EINVAL;
+  if (hq != hg) return VP_EINVAL;
+  return VP_OK;
+}
+}  // namespace
+
+int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_fields* a,
+                                   void* stream) {
+  if (!P || !a || n < 0 || n > P->max_batch) return VP_EINVAL;
+  const long N = P->npts();
+  const double* rhs[vp::kMaxBatch];
+  double* phi[vp::kMaxBatch];
+  for (int b = 0; b < n; ++b) {
+    if (check_extend(a[b])) return VP_EINVAL;
+    rhs[b] = a[b].src;
+    phi[b] = a[b].phi;
+    if (!phi[b]) {
+      if (P->precision == VP_PRECISION_MIXED) return VP_EINVAL;  // needs a caller buffer
+      phi[b] = P->work64 + b * N;  // the x pass writes its own slot in place
+    }
+  }
+  if (n == 0) return VP_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int s = solve_any(P, n, rhs, phi, st);
+  if (s) return s;
+  for (int b = 0; b < n; ++b)
+    VP_LAUNCH(P, K_EXTEND,
+              vp::launch_extend(P->g, a[b].u, a[b].v, a[b].w, phi[b], a[b].qx, a[b].qy, a[b].qz,
+                                a[b].ue, a[b].ve, a[b].we, a[b].ug, a[b].vg, a[b].wg, st),
+              "extension", st);
   return VP_OK;
 }
 
@@ -409,22 +462,9 @@ int extend_liquid_velocity(poisson_plan* P, const double* u, const double* v, co
                            const double* src, const double* qx, const double* qy,
                            const double* qz, double* ue, double* ve, double* we, double* ug,
                            double* vg, double* wg, double* phi, void* stream) {
-  if (!P || !u || !v || !w || !src || !ue || !ve || !we) return VP_EINVAL;
-  const bool hq = qx && qy && qz, hg = ug && vg && wg;
-  if ((qx || qy || qz) && !hq) return VP_EINVAL;
-  if ((ug || vg || wg) && !hg) return VP_EINVAL;
-  if (hq != hg) return VP_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  double* out = phi;
-  if (!out) {
-    if (P->precision == VP_PRECISION_MIXED) return VP_EINVAL;  // needs a caller buffer
-    out = P->work64;
-  }
-  int s = solve_any(P, src, out, st);
-  if (s) return s;
-  VP_LAUNCH(P, K_EXTEND, vp::launch_extend(P->g, u, v, w, out, qx, qy, qz, ue, ve, we, ug, vg, wg, st),
-            "extension", st);
-  return VP_OK;
+  if (!P) return VP_EINVAL;
+  const vp_extend_fields a = {u, v, w, src, qx, qy, qz, ue, ve, we, ug, vg, wg, phi};
+  return extend_liquid_velocity_batched(P, 1, &a, stream);
 }
 
 int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* phat,
@@ -444,9 +484,9 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),
             "rhs assembly", st);
-  int s = solve_any(P, b, p, st);
+  int s = solve_one(P, b, p, st);
   if (s) return s;
-  s = solve_any(P, src_ext, phi, st);
+  s = solve_one(P, src_ext, phi, st);
   if (s) return s;
   VP_LAUNCH(P, K_EPILOGUE,
             vp::launch_step_epilogue(P->g, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
@@ -469,15 +509,7 @@ int poisson_plan_last_mean(poisson_plan* P, double* mean_out, void* stream) {
   return VP_OK;
 }
 
-long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_batch) {
-  (void)max_batch;
-  if (nx <= 0 || ny <= 0 || nz <= 0) return -1;
-  const long long n = (long long)nx * ny * nz;
-  long long b = 8 * n;
-  if (precision == VP_PRECISION_MIXED) b += 4 * n + 8 * n + 8LL * vp::kResidualMaxBlocks;
-  b += 8LL * (3 * nx + 3 * ny + 4 * nz + 16);
-  return b;
-}
+long long poisson_plan_device_bytes(const poisson_plan* P) { return P ? P->bytes : -1; }
 
 const char* poisson_strerror(int status) {
   switch (status) {

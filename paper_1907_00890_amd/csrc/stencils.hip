@@ -244,15 +244,16 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
 }
 
 // r = f - L_h p (FP64 residual of the defect-correction steps).  Each block
-// also sums dzf[k] * p over its cells (fixed order, no atomics) into
-// partial[block], so the weighted mean of p costs no extra pass.
+// also sums dzf[k] * p and dzf[k] * r over its cells (fixed order, no
+// atomics) into partial[block] and partial[kResidualMaxBlocks + block], so
+// the weighted means of p and r cost no extra pass.
 __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double* __restrict__ f,
                                                    const double* __restrict__ p,
                                                    double* __restrict__ r,
                                                    double* __restrict__ partial) {
-  __shared__ double red[256];
+  __shared__ double red[2][256];
   const Tile t = tile_of<64>(g);
-  double acc = 0.0;
+  double acc = 0.0, accr = 0.0;
   if (t.ok) {
     const long P = (long)g.nx * g.ny;
     const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
@@ -270,36 +271,57 @@ __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double
       if (t.hym) ly -= pc - p[c + t.ym];
       if (kp >= 0) lz += (pp - pc) / g.dzc[k];
       if (km >= 0) lz -= (pc - pm) / g.dzc[km];
-      r[c] = f[c] - (lx * idx2 + ly * idy2 + lz / g.dzf[k]);
+      const double rc = f[c] - (lx * idx2 + ly * idy2 + lz / g.dzf[k]);
+      r[c] = rc;
       acc += g.dzf[k] * pc;
+      accr += g.dzf[k] * rc;
       pm = pc;
       pc = pp;
       km = k;
     }
   }
-  red[threadIdx.x] = acc;
+  red[0][threadIdx.x] = acc;
+  red[1][threadIdx.x] = accr;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0)
-    partial[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partial[b] = red[0][0];
+    partial[kResidualMaxBlocks + b] = red[1][0];
+  }
 }
 
-// out[0] = (sum of the partial sums) / denom, one block, fixed order
+// out_p[0], out_r[0] = (sums of the two partial-sum rows) / denom, one
+// block, fixed order
 __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ partial, int nb,
-                                                      double denom, double* __restrict__ out) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) acc += partial[i];
-  red[threadIdx.x] = acc;
+                                                      double denom, double* __restrict__ out_p,
+                                                      double* __restrict__ out_r) {
+  __shared__ double red[2][256];
+  double acc = 0.0, accr = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    acc += partial[i];
+    accr += partial[kResidualMaxBlocks + i];
+  }
+  red[0][threadIdx.x] = acc;
+  red[1][threadIdx.x] = accr;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0] / denom;
+  if (threadIdx.x == 0) {
+    out_p[0] = red[0][0] / denom;
+    out_r[0] = red[1][0] / denom;
+  }
 }
 
 template <int TXMAX = 64>
@@ -368,14 +390,15 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 }
 
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
-                           double* partial, double* mean_out, double dz_sum, hipStream_t st) {
+                           double* partial, double* mean_p, double* mean_r, double dz_sum,
+                           hipStream_t st) {
   const int nb = stencil_blocks(g);
   if (nb > kResidualMaxBlocks) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, r, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double denom = (double)g.nx * (double)g.ny * dz_sum;
-  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, st, partial, nb, denom, mean_out);
+  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, st, partial, nb, denom, mean_p, mean_r);
   return hipGetLastError();
 }
 

@@ -212,24 +212,35 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
 // ---------------------------------------------------------------------------
 // x kernels: a block owns 2*LPB consecutive rows (nrows is even)
 // ---------------------------------------------------------------------------
-template <typename TI, typename T, int N, int BC>
-__global__ __launch_bounds__(256) void k_xfwd(const TI* __restrict__ in, T* __restrict__ out,
-                                               long nrows, const T* __restrict__ tab) {
+// SUB: member b's input is read as in[b] - sub[b] (FP64, before any
+// conversion to T); without it the kernel reads its input unchanged.
+template <typename TI, typename T, int N, int BC, bool SUB>
+__global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __restrict__ out,
+                                               long ostride, long nrows,
+                                               const T* __restrict__ tab,
+                                               const double* __restrict__ sub) {
   constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
   const bool ok = ra < nrows;
-  const TI* ga = in + ra * N;
+  const TI* ga = in.p[blockIdx.y] + ra * N;
   const TI* gb = ga + N;
-  T* oa = out + ra * N;
+  T* oa = out + blockIdx.y * ostride + ra * N;
   T* ob = oa + N;
+  TI shift = TI(0);
+  if constexpr (SUB) shift = TI(sub[blockIdx.y]);
   XLds<T, N> lds(lds_mem, q, LPB);
   forward_body<T, N, BC>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
-        r = ok ? T(ga[e]) : T(0);
-        i = ok ? T(gb[e]) : T(0);
+        if constexpr (SUB) {
+          r = ok ? T(ga[e] - shift) : T(0);
+          i = ok ? T(gb[e] - shift) : T(0);
+        } else {
+          r = ok ? T(ga[e]) : T(0);
+          i = ok ? T(gb[e]) : T(0);
+        }
       },
       [&](int c0, T a0, T b0, int c1, T a1, T b1) {
         if (!ok) return;
@@ -241,21 +252,22 @@ __global__ __launch_bounds__(256) void k_xfwd(const TI* __restrict__ in, T* __re
 }
 
 template <typename T, typename TO, int N, int BC, bool ACCUM>
-__global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, TO* __restrict__ out,
-                                               long nrows, const T* __restrict__ tab,
+__global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long istride,
+                                               const Batch<TO> out, long nrows,
+                                               const T* __restrict__ tab,
                                                const double* __restrict__ sub) {
   constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
   const bool ok = ra < nrows;
-  const T* ia = in + ra * N;
+  const T* ia = in + blockIdx.y * istride + ra * N;
   const T* ib = ia + N;
-  TO* oa = out + ra * N;
+  TO* oa = out.p[blockIdx.y] + ra * N;
   TO* ob = oa + N;
   TO shift = TO(0);
   if constexpr (ACCUM) {
-    if (sub) shift = TO(sub[0]);
+    if (sub) shift = TO(sub[blockIdx.y]);
   }
   XLds<T, N> lds(lds_mem, q, LPB);
   inverse_body<T, N, BC>(
@@ -344,16 +356,18 @@ __global__ __launch_bounds__(256) void k_yinv(T* __restrict__ data, int nx, long
 // ---------------------------------------------------------------------------
 #define VP_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
-template <typename TI, typename T, int BC>
-static hipError_t launch_xfwd_bc(const TI* in, T* out, int n, long nrows, const T* tab,
-                                 hipStream_t st) {
-#define VP_XF(NN)                                                                          \
-  case NN: {                                                                               \
-    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                        \
-    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC>), dim3((unsigned)((nrows + rpb - 1) / rpb)), \
-                       dim3(256), 0, st, in, out, nrows, tab);                             \
-    break;                                                                                 \
+template <typename TI, typename T, int BC, bool SUB>
+static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
+                                 long nrows, const double* sub, const T* tab, hipStream_t st) {
+#define VP_XF(NN)                                                                           \
+  case NN: {                                                                                \
+    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                         \
+    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB>),                                        \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       st, in, out, ostride, nrows, tab, sub);                              \
+    break;                                                                                  \
   }
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
   switch (n) {
     VP_SIZES(VP_XF)
     default: return hipErrorInvalidValue;
@@ -363,16 +377,17 @@ static hipError_t launch_xfwd_bc(const TI* in, T* out, int n, long nrows, const 
 }
 
 template <typename T, typename TO, int BC, bool ACCUM>
-static hipError_t launch_xinv_bc(const T* in, TO* out, int n, long nrows, const T* tab,
-                                 const double* sub, hipStream_t st) {
-#define VP_XI(NN)                                                                          \
-  case NN: {                                                                               \
-    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                        \
-    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM>),                                     \
-                       dim3((unsigned)((nrows + rpb - 1) / rpb)), dim3(256), 0, st, in, out, \
-                       nrows, tab, sub);                                                   \
-    break;                                                                                 \
+static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out, int nb, int n,
+                                 long nrows, const T* tab, const double* sub, hipStream_t st) {
+#define VP_XI(NN)                                                                           \
+  case NN: {                                                                                \
+    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                         \
+    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM>),                                      \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       st, in, istride, out, nrows, tab, sub);                              \
+    break;                                                                                  \
   }
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
   switch (n) {
     VP_SIZES(VP_XI)
     default: return hipErrorInvalidValue;
@@ -421,29 +436,45 @@ static hipError_t launch_y_bc(T* data, int nx, int ny, int nz, const T* tab, hip
   return hipGetLastError();
 }
 
-hipError_t launch_xfwd_f64(const double* in, double* out, int nx, int bc, long nrows,
-                           const double* tab, hipStream_t st) {
-  return bc == BC_P ? launch_xfwd_bc<double, double, BC_P>(in, out, nx, nrows, tab, st)
-                    : launch_xfwd_bc<double, double, BC_N>(in, out, nx, nrows, tab, st);
+hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
+                           int nx, int bc, long nrows, const double* tab, hipStream_t st) {
+  return bc == BC_P ? launch_xfwd_bc<double, double, BC_P, false>(in, nb, out, ostride, nx, nrows,
+                                                                  nullptr, tab, st)
+                    : launch_xfwd_bc<double, double, BC_N, false>(in, nb, out, ostride, nx, nrows,
+                                                                  nullptr, tab, st);
 }
-hipError_t launch_xinv_f64(const double* in, double* out, int nx, int bc, long nrows,
-                           const double* tab, hipStream_t st) {
-  return bc == BC_P
-             ? launch_xinv_bc<double, double, BC_P, false>(in, out, nx, nrows, tab, nullptr, st)
-             : launch_xinv_bc<double, double, BC_N, false>(in, out, nx, nrows, tab, nullptr, st);
+hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
+                           int nx, int bc, long nrows, const double* tab, hipStream_t st) {
+  return bc == BC_P ? launch_xinv_bc<double, double, BC_P, false>(in, istride, out, nb, nx, nrows,
+                                                                  tab, nullptr, st)
+                    : launch_xinv_bc<double, double, BC_N, false>(in, istride, out, nb, nx, nrows,
+                                                                  tab, nullptr, st);
 }
-hipError_t launch_xfwd_f32(const double* in, float* out, int nx, int bc, long nrows,
+hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
+                           int nx, int bc, long nrows, const double* sub, const float* tab,
+                           hipStream_t st) {
+  if (sub)
+    return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, true>(in, nb, out, ostride, nx, nrows,
+                                                                  sub, tab, st)
+                      : launch_xfwd_bc<double, float, BC_N, true>(in, nb, out, ostride, nx, nrows,
+                                                                  sub, tab, st);
+  return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, false>(in, nb, out, ostride, nx, nrows,
+                                                                 nullptr, tab, st)
+                    : launch_xfwd_bc<double, float, BC_N, false>(in, nb, out, ostride, nx, nrows,
+                                                                 nullptr, tab, st);
+}
+hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
+                           int nx, int bc, long nrows, bool accum, const double* sub,
                            const float* tab, hipStream_t st) {
-  return bc == BC_P ? launch_xfwd_bc<double, float, BC_P>(in, out, nx, nrows, tab, st)
-                    : launch_xfwd_bc<double, float, BC_N>(in, out, nx, nrows, tab, st);
-}
-hipError_t launch_xinv_f32(const float* in, double* out, int nx, int bc, long nrows, bool accum,
-                           const double* sub, const float* tab, hipStream_t st) {
   if (bc == BC_P)
-    return accum ? launch_xinv_bc<float, double, BC_P, true>(in, out, nx, nrows, tab, sub, st)
-                 : launch_xinv_bc<float, double, BC_P, false>(in, out, nx, nrows, tab, sub, st);
-  return accum ? launch_xinv_bc<float, double, BC_N, true>(in, out, nx, nrows, tab, sub, st)
-               : launch_xinv_bc<float, double, BC_N, false>(in, out, nx, nrows, tab, sub, st);
+    return accum ? launch_xinv_bc<float, double, BC_P, true>(in, istride, out, nb, nx, nrows, tab,
+                                                             sub, st)
+                 : launch_xinv_bc<float, double, BC_P, false>(in, istride, out, nb, nx, nrows,
+                                                              tab, sub, st);
+  return accum ? launch_xinv_bc<float, double, BC_N, true>(in, istride, out, nb, nx, nrows, tab,
+                                                           sub, st)
+               : launch_xinv_bc<float, double, BC_N, false>(in, istride, out, nb, nx, nrows, tab,
+                                                            sub, st);
 }
 hipError_t launch_y_f64(double* data, int nx, int ny, int nz, int bc, bool fwd, const double* tab,
                         hipStream_t st) {

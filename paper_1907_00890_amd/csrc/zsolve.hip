@@ -174,6 +174,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
 
   const int l = threadIdx.x % LB, s = threadIdx.x / LB;
   const long line = (long)blockIdx.x * LB + l;
+  x += blockIdx.y * A.batch_stride;
   const bool valid = line < A.plane;
   const bool blk0 = blockIdx.x == 0;
   const bool sing = blk0 && l == 0;  // line 0: lambda_x + lambda_y == 0
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
         if (i < m) acc += A.dzf[k0 + i] * al[i];
     }
     const double rbar = line_sum(acc) / A.dz_sum;
-    if (sing && s == 0 && A.mean_out) A.mean_out[0] = rbar;
+    if (sing && s == 0 && A.mean_out) A.mean_out[blockIdx.y] = rbar;
     double run = 0.0;
     if (sing) {
 #pragma unroll
@@ -416,9 +417,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
   const long line = (long)blockIdx.x * 256 + threadIdx.x;
   if (line >= A.plane) return;
+  x += blockIdx.y * A.batch_stride;
   const double r = double(x[line]) * A.scale;
   if (line == 0) {
-    if (A.mean_out) A.mean_out[0] = r;
+    if (A.mean_out) A.mean_out[blockIdx.y] = r;
     x[0] = T(0);
   } else {
     const double lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx];
@@ -427,10 +429,10 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
 }
 
 template <typename T, int LB, bool US, bool UZ>
-static hipError_t launch_z_shape(T* data, const ZArgs& a, hipStream_t st) {
+static hipError_t launch_z_shape(T* data, const ZArgs& a, int nb, hipStream_t st) {
   const int nr = 2 * a.nseg;
   const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)(a.nseg > 6 ? a.nseg : 6) * LB);
-  const dim3 grid((unsigned)((a.plane + LB - 1) / LB));
+  const dim3 grid((unsigned)((a.plane + LB - 1) / LB), (unsigned)nb);
   const dim3 block((unsigned)(LB * a.nseg));
   if (a.seg != 16 || LB * a.nseg > 512) return hipErrorInvalidValue;
   auto kern = &k_zsolve<T, 16, LB, US, UZ>;
@@ -440,36 +442,37 @@ static hipError_t launch_z_shape(T* data, const ZArgs& a, hipStream_t st) {
 }
 
 template <typename T, int LB>
-static hipError_t launch_z_lb(T* data, const ZArgs& a, hipStream_t st) {
+static hipError_t launch_z_lb(T* data, const ZArgs& a, int nb, hipStream_t st) {
   const bool us = a.seg_rem == 0 && a.seg_base == a.seg;
   if (us)
-    return a.uniform_z ? launch_z_shape<T, LB, true, true>(data, a, st)
-                       : launch_z_shape<T, LB, true, false>(data, a, st);
-  return a.uniform_z ? launch_z_shape<T, LB, false, true>(data, a, st)
-                     : launch_z_shape<T, LB, false, false>(data, a, st);
+    return a.uniform_z ? launch_z_shape<T, LB, true, true>(data, a, nb, st)
+                       : launch_z_shape<T, LB, true, false>(data, a, nb, st);
+  return a.uniform_z ? launch_z_shape<T, LB, false, true>(data, a, nb, st)
+                     : launch_z_shape<T, LB, false, false>(data, a, nb, st);
 }
 
 template <typename T>
-static hipError_t launch_z(T* data, const ZArgs& a, hipStream_t st) {
+static hipError_t launch_z(T* data, const ZArgs& a, int nb, hipStream_t st) {
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
   if (a.nz == 1) {
-    const dim3 grid((unsigned)((a.plane + 255) / 256));
+    const dim3 grid((unsigned)((a.plane + 255) / 256), (unsigned)nb);
     hipLaunchKernelGGL((k_z1<T>), grid, dim3(256), 0, st, data, a);
     return hipGetLastError();
   }
   // LB lines x S segments per block, at most 512 lanes; a.lines picks LB
   int lb = a.lines;
   while (lb > 8 && lb * a.nseg > 512) lb /= 2;
-  if (lb >= 32) return launch_z_lb<T, 32>(data, a, st);
-  if (lb == 16) return launch_z_lb<T, 16>(data, a, st);
+  if (lb >= 32) return launch_z_lb<T, 32>(data, a, nb, st);
+  if (lb == 16) return launch_z_lb<T, 16>(data, a, nb, st);
   if (lb * a.nseg > 512) return hipErrorInvalidValue;
-  return launch_z_lb<T, 8>(data, a, st);
+  return launch_z_lb<T, 8>(data, a, nb, st);
 }
 
-hipError_t launch_zsolve_f64(double* data, const ZArgs& a, hipStream_t st) {
-  return launch_z<double>(data, a, st);
+hipError_t launch_zsolve_f64(double* data, const ZArgs& a, int nb, hipStream_t st) {
+  return launch_z<double>(data, a, nb, st);
 }
-hipError_t launch_zsolve_f32(float* data, const ZArgs& a, hipStream_t st) {
-  return launch_z<float>(data, a, st);
+hipError_t launch_zsolve_f32(float* data, const ZArgs& a, int nb, hipStream_t st) {
+  return launch_z<float>(data, a, nb, st);
 }
 
 }  // namespace vp

@@ -42,8 +42,17 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_binding_covers_header():
-    from paper_1907_00890_amd import _lib
-    assert set(declared_functions()) == set(_lib.SIGNATURES)
+    from paper_1907_00890_amd import _lib, serve
+    assert set(declared_functions()) == set(_lib.SIGNATURES) | set(serve.SIGNATURES)
+
+
+def test_plan_check_matches_create(lib):
+    dz = (ctypes.c_double * 8)(*([0.125] * 8))
+    assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == 0
+    assert lib.poisson_plan_check(12, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == -2
+    assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, b"PPD", 0, 1) == -2
+    assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, b"PPQ", 0, 1) == -1
+    assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 17) == -1
 
 
 def test_strerror_and_version(lib):
@@ -85,10 +94,13 @@ def test_create_rejects_bad_widths(lib):
     assert not h and st == -1
     h, st = _create(lib, 8, 8, 4, b"PPN", precision=3)
     assert not h and st == -1
+    h, st = _create(lib, 8, 8, 4, b"PPN", max_batch=17)
+    assert not h and st == -1
 
 
 def test_null_plan_calls(lib):
     assert lib.poisson_solve(None, None, None, None) == -1
+    assert lib.extend_liquid_velocity_batched(None, 1, None, None) == -1
     assert lib.poisson_plan_set_mixed(None, 1) == -1
     lib.poisson_plan_destroy(None)
 
@@ -98,3 +110,8 @@ def test_footprint(lib):
     assert lib.poisson_plan_footprint(64, 64, 64, 0, 1) >= 8 * n
     assert lib.poisson_plan_footprint(64, 64, 64, 1, 1) >= 20 * n
     assert lib.poisson_plan_footprint(0, 64, 64, 0, 1) < 0
+    # one workspace slot per batch member
+    one = lib.poisson_plan_footprint(64, 64, 64, 0, 1)
+    assert lib.poisson_plan_footprint(64, 64, 64, 0, 4) - one == 3 * 8 * n
+    assert lib.poisson_plan_footprint(64, 64, 64, 0, 17) < 0
+    assert lib.poisson_plan_device_bytes(None) < 0

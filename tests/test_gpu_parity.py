@@ -220,17 +220,79 @@ def test_mixed_parity(torch_dev, case, dc):
     assert err <= MIXED_TOL, err
 
 
-def test_batched_equals_single(torch_dev):
+BATCH_CASES = [
+    # (nx, ny, nz, bc, beta, precision, n)
+    (64, 32, 24, "PPN", 1.5, "fp64", 3),
+    (32, 32, 32, "PPP", None, "mixed", 4),
+    (16, 8, 1, "NPN", None, "fp64", 16),      # slab, the largest batch
+    (8, 16, 40, "NNP", None, "mixed", 2),
+]
+
+
+@pytest.mark.parametrize("case", BATCH_CASES,
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}-{c[5]}-b{c[6]}")
+def test_batched_equals_single(torch_dev, case):
+    """One launch per pass for the whole batch gives each member's single result
+    bit for bit (the arithmetic of a member never depends on the others)."""
     torch = torch_dev
-    g = _grid(64, 32, 24, "PPN", 1.5)
-    fs = [vofsynth.gaussian_field(g.shape, 50 + i) for i in range(3)]
-    plan = _plan(g, max_batch=3)
+    nx, ny, nz, bc, beta, prec, n = case
+    g = _grid(nx, ny, nz, bc, beta)
+    fs = [vofsynth.gaussian_field(g.shape, 50 + i) for i in range(n)]
+    plan = _plan(g, precision=prec, max_batch=n)
     singles = [plan.solve(_dev(torch, f)).cpu().numpy() for f in fs]
     outs = plan.solve_batched([_dev(torch, f) for f in fs])
+    # in place: every member's output overwrites its own input
+    ins = [_dev(torch, f) for f in fs]
+    plan.solve_batched(ins, ins)
+    # a smaller batch after a larger one on the same plan
+    part = plan.solve_batched([_dev(torch, f) for f in fs[: max(1, n // 2)]])
     torch.cuda.synchronize()
-    for a, b, f in zip(outs, singles, fs):
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    for k, (a, b, c, f) in enumerate(zip(outs, singles, ins, fs)):
+        assert np.array_equal(a.cpu().numpy(), b), k
+        assert np.array_equal(c.cpu().numpy(), b), k
+        assert rel_l2(b, oracle.solve(f, g)) <= tol
+    for a, b in zip(part, singles):
         assert np.array_equal(a.cpu().numpy(), b)
-        assert rel_l2(b, oracle.solve(f, g)) <= FP64_TOL
+
+
+def test_extend_batched_equals_single(torch_dev):
+    torch = torch_dev
+    g = _grid(32, 16, 20, "PPN", 1.5)
+    n = 3
+    items, singles = [], []
+    plan = _plan(g, max_batch=n)
+    for k in range(n):
+        u, v, w = vofsynth.random_faces(g.shape, 300 + k, g.bc)
+        s = vofsynth.remove_weighted_mean(vofsynth.gaussian_field(g.shape, 310 + k), g.dzf)
+        q = vofsynth.random_faces(g.shape, 320 + k, g.bc)
+        d = [_dev(torch, a) for a in (u, v, w, s)]
+        dq = tuple(_dev(torch, a) for a in q)
+        items.append({"u": d[0], "v": d[1], "w": d[2], "src": d[3], "q": dq,
+                      "phi": torch.empty_like(d[0])})
+        out = plan.extend(*d, q=dq, phi=torch.empty_like(d[0]))
+        singles.append([t.cpu().numpy() for t in out])
+    res = plan.extend_batched(items)
+    # phi left in the workspace slots (no caller buffer)
+    res2 = plan.extend_batched([{k2: it[k2] for k2 in ("u", "v", "w", "src")} for it in items])
+    torch.cuda.synchronize()
+    for k in range(n):
+        got = [t.cpu().numpy() for t in res[k]]
+        for a, b in zip(got, singles[k]):
+            assert np.array_equal(a, b), k
+        for a, b in zip(res2[k][:3], singles[k][:3]):
+            assert np.array_equal(a.cpu().numpy(), b), k
+        ref = oracle.extend(items[k]["u"].cpu().numpy(), items[k]["v"].cpu().numpy(),
+                            items[k]["w"].cpu().numpy(), items[k]["src"].cpu().numpy(), g)
+        assert rel_l2(got[0], ref[0]) <= FP64_TOL
+
+
+def test_footprint_matches_allocation(torch_dev):
+    from paper_1907_00890_amd import footprint
+    for prec, b in (("fp64", 1), ("fp64", 5), ("mixed", 3)):
+        g = _grid(32, 16, 12, "PNN")
+        plan = _plan(g, precision=prec, max_batch=b)
+        assert plan.device_bytes() == footprint(32, 16, 12, prec, b)
 
 
 # ----------------------------------------------------------------------------
