@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--workload", default="ppn256")
     ap.add_argument("--solve-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of autotuning the plans")
     ap.add_argument("--cpu-sample", default="ppn256",
                     help="workload the CPU oracle is timed on (bounded sample)")
     ap.add_argument("--serve-rates", default="1000",
@@ -134,12 +136,12 @@ class ServeMix:
 
     Per class: a bank of two seeded zero-mean N(0,1) right-hand sides and
     velocity fields (inputs resident in HBM before timing), and `slots`
-    output sets reused round-robin; a slot still in use by an unfinished
-    request is waited for before reuse (client back-pressure, inside the
-    measured latency).
+    output sets per request kind reused round-robin; a slot still in use by
+    an unfinished request is waited for before reuse (client back-pressure,
+    inside the measured latency).
     """
 
-    def __init__(self, torch, dev, slots=12):
+    def __init__(self, torch, dev, slots=32):
         import numpy as np
 
         import vofsynth
@@ -156,17 +158,18 @@ class ServeMix:
                 u = vofsynth.random_faces(g.shape, 2_000_000 + 10 * k + b, "PPN")
                 T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
                 bank.append({"f": T(f), "u": [T(a) for a in u]})
-            outs = []
-            for _ in range(slots):
-                e = lambda: torch.empty(g.shape, dtype=torch.float64, device=dev)  # noqa: E731
-                outs.append({"sol": e(), "out": (e(), e(), e()), "phi": e(), "ticket": None})
-            self.cls.append({"name": name, "grid": g, "bank": bank, "outs": outs, "next": 0,
-                             "npts": nx * ny * nz})
+            e = lambda: torch.empty(g.shape, dtype=torch.float64, device=dev)  # noqa: E731
+            outs = {"solve": [{"sol": e(), "ticket": None} for _ in range(slots)],
+                    "extend": [{"out": (e(), e(), e()), "phi": e(), "ticket": None}
+                               for _ in range(slots)]}
+            self.cls.append({"name": name, "grid": g, "bank": bank, "outs": outs,
+                             "next": {"solve": 0, "extend": 0}, "npts": nx * ny * nz})
 
     def submit(self, srv, ci, kind, precision, bank_i, early_results):
         c = self.cls[ci]
-        slot = c["outs"][c["next"]]
-        c["next"] = (c["next"] + 1) % len(c["outs"])
+        pool = c["outs"][kind]
+        slot = pool[c["next"][kind]]
+        c["next"][kind] = (c["next"][kind] + 1) % len(pool)
         if slot["ticket"] is not None:  # back-pressure: the slot is still in use
             early_results[slot["ticket"]] = srv.wait(slot["ticket"], -1)
         b = c["bank"][bank_i]
@@ -178,6 +181,12 @@ class ServeMix:
                                   precision=precision)
         slot["ticket"] = t
         return t
+
+    def release(self):
+        for c in self.cls:
+            for pool in c["outs"].values():
+                for s in pool:
+                    s["ticket"] = None
 
 
 def serve_run(srv, mix, rate, n, seed):
@@ -209,9 +218,7 @@ def serve_run(srv, mix, rate, n, seed):
     for t in tickets:
         r = early.pop(t, None) or srv.wait(t, -1)
         res.append(r)
-    for c in mix.cls:
-        for s in c["outs"]:
-            s["ticket"] = None
+    mix.release()
     ok = [r["status"] == 0 for r in res]
     lat = np.array([(r["t_done_us"] - a) * 1e-3 for r, a in zip(res, t_arr)])
     qwait = np.array([(r["t_dispatch_us"] - a) * 1e-3 for r, a in zip(res, t_arr)])
@@ -240,7 +247,12 @@ def serve_bench(torch, dev, rates, n, lanes, max_batch):
     mix = ServeMix(torch, dev)
     out = []
     with Server(96 << 30, lanes=lanes, max_batch=max_batch, max_pending=1 << 20) as srv:
-        # warm every class / kind / precision once: plans resident before timing
+        # plans resident before timing: one instance per lane of every class and
+        # precision, then one request of every class / kind / precision (first
+        # launches of every kernel)
+        for c in mix.cls:
+            for prec in ("fp64", "mixed"):
+                srv.prewarm(c["grid"], prec, instances=lanes)
         warm = []
         early = {}
         for k in range(len(mix.cls)):
@@ -249,9 +261,7 @@ def serve_bench(torch, dev, rates, n, lanes, max_batch):
                     warm.append(mix.submit(srv, k, kind, prec, 0, early))
         for t in warm:
             early.pop(t, None) or srv.wait(t, -1)
-        for c in mix.cls:
-            for s in c["outs"]:
-                s["ticket"] = None
+        mix.release()
         for rate in rates:
             r = serve_run(srv, mix, rate, n, seed=5)
             print(f"[serve] rate {rate} req/s: p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms, "
@@ -322,6 +332,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     q = (X["qx"], X["qy"], X["qz"])
+    # launch shapes and radix schedules picked by the autotuner (before timing)
+    tuned = plan.autotune(batch=1) if not args.no_autotune else plan.tuning()
 
     def step():
         # one time step through the fused entry point (all outputs written)
@@ -398,8 +410,10 @@ def main():
     b.record(stream)
     torch.cuda.synchronize()
     ms64 = a.elapsed_time(b) / args.solve_reps
+    # mixed: FP32 chain + FP64 defect correction, up to 3 steps, stopping on the
+    # device once the estimated error is at most 1e-11 (the library default)
     mixed = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc, precision="mixed")
-    mixed.set_mixed(1)
+    tuned_mixed = mixed.autotune(batch=1) if not args.no_autotune else mixed.tuning()
     out32 = torch.empty_like(f)
     for _ in range(3):
         mixed.solve(f, out32)
@@ -411,6 +425,7 @@ def main():
     torch.cuda.synchronize()
     ms32 = a.elapsed_time(b) / args.solve_reps
     rel_mixed = (torch.linalg.vector_norm(out32 - out64) / torch.linalg.vector_norm(out64)).item()
+    (dc_steps, dc_est), = mixed.mixed_report()
 
     # roofline of the dominant kernel, timed over the timed steps; the other
     # kernels' times come from the fully bracketed pass
@@ -440,11 +455,13 @@ def main():
         "solve_fp64": {"ms": round(ms64, 4), "mpts_s": round(n / (ms64 * 1e-3) / 1e6, 1),
                        "model_gbs_80N": round(80 * n / (ms64 * 1e-3) / 1e9, 1)},
         "solve_mixed": {"ms": round(ms32, 4), "mpts_s": round(n / (ms32 * 1e-3) / 1e6, 1),
-                        "dc_steps": 1, "rel_l2_vs_fp64": rel_mixed,
+                        "dc_steps": dc_steps, "dc_error_estimate": dc_est,
+                        "rel_l2_vs_fp64": rel_mixed,
                         "speedup_vs_fp64": round(ms64 / ms32, 3)},
         "step_variants_ms": {"fused_timed_region": round(ms_step, 4), "fused": round(ms_eager, 4),
                              "fused_hip_graph": round(ms_graph, 4),
                              "separate_project_extend": round(ms_separate, 4)},
+        "tuning": {"fp64": tuned, "mixed": tuned_mixed},
         "kernels": kernels,
         "kernel_ms_per_step": round(kern_ms_step, 4),
         "wall_s_timed": round(t_wall, 3),

@@ -181,11 +181,27 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
              double* phi, void* hip_stream);
 
 /*
- * Mixed-precision control (plans created with VP_PRECISION_MIXED): the
- * number of FP64 defect-correction steps after the first FP32 solve
- * (0..8, default 1).  Returns VP_EINVAL for an FP64 plan or a bad count.
+ * Mixed-precision control (plans created with VP_PRECISION_MIXED).  A mixed
+ * solve is p_0 = S32(f) followed by at most dc_steps FP64 defect-correction
+ * steps p_k = p_{k-1} + e_k, e_k = S32(f - L_h p_{k-1}) (FP64 residual and
+ * update, FP32 transforms and storage, FP64 z pivots).  The relative error
+ * left in p_k is bounded by |e_1| / |p_1| after the first step and estimated
+ * as |e_k|^2 / (|e_{k-1}| |p_k|) after later ones (the contraction measured
+ * between consecutive corrections); a member stops, on the device and
+ * without a host synchronisation, once that is at most the tolerance.
+ *   poisson_plan_set_mixed     : the most steps, 0..8 (default 3);
+ *   poisson_plan_set_mixed_tol : the tolerance (default 1e-11); <= 0 runs
+ *                                every step;
+ *   poisson_plan_mixed_report  : steps taken and the last estimate of each of
+ *                                the n members of the last mixed call
+ *                                (host arrays, may be NULL; synchronises
+ *                                hip_stream).
+ * Each returns VP_EINVAL for an FP64 plan or a bad argument.
  */
 int poisson_plan_set_mixed(poisson_plan* plan, int dc_steps);
+int poisson_plan_set_mixed_tol(poisson_plan* plan, double tol);
+int poisson_plan_mixed_report(poisson_plan* plan, int n, int* steps, double* estimate,
+                              void* hip_stream);
 
 /*
  * Weighted mean removed from the last right-hand side solved with this plan
@@ -202,7 +218,11 @@ long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_
 long long poisson_plan_device_bytes(const poisson_plan* plan);
 
 /*
- * Launch-shape tuning (results do not change, only speed):
+ * Launch-shape tuning (results do not change beyond rounding order, only speed):
+ *   "x_radix", "y_radix" : values per thread of the radix schedule of the x
+ *                 and y transform passes, 16 (radix-16 passes, default) or 8
+ *                 (radix-8 passes: fewer registers and LDS per line, more
+ *                 blocks per compute unit);
  *   "z_lines"   : lines per block of the z pass, 8, 16 (default) or 32
  *                 (capped so that lines * segments <= 512);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
@@ -210,6 +230,20 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  * Returns VP_EINVAL for an unknown key or value.
  */
 int poisson_plan_tune(poisson_plan* plan, const char* key, int value);
+
+/* Current value of a tuning key (see poisson_plan_tune). */
+int poisson_plan_get_tuning(poisson_plan* plan, const char* key, int* value);
+
+/*
+ * Autotuner: times every candidate of each knob above on the plan's own
+ * workspace (which it overwrites) for a batch of nb fields, on hip_stream
+ * (synchronising it), median of 5 runs each, one knob after another (x
+ * radix, y radix, z lines, stencil planes; the last only when the
+ * workspace holds a second field: mixed plans or max_batch >= 2), and
+ * leaves each at its fastest value.  chosen (may be NULL) receives the four
+ * values in that order.  Not for use while other calls on the plan run.
+ */
+int poisson_plan_autotune(poisson_plan* plan, int nb, void* hip_stream, int* chosen);
 
 /*
  * Per-launch timing.  class_mask selects kernel classes (bit c for class c;

@@ -93,6 +93,10 @@ typedef struct vp_server_stats {
 double vp_server_now_us(void);
 
 /*
+ * A new plan instance of a class whose plans are all busy is made only when
+ * that class and kind have at least max_batch / 2 queued requests; a smaller
+ * backlog waits for the busy plan's lane.
+ *
  * Start a server on the current HIP device (none touched with dry_run).
  * Returns NULL and sets *status (VP_EINVAL for a bad configuration, VP_EHIP
  * if streams cannot be created).
@@ -106,6 +110,17 @@ vp_server* vp_server_create(const vp_server_config* config, int* status);
  * budget) or VP_EAGAIN (max_pending requests already queued).
  */
 int vp_server_submit(vp_server* server, const vp_request* request, long long* ticket);
+
+/*
+ * Create plans of the request's class (only its grid, dz, bc and precision
+ * are read) until `instances` (1..lanes) exist, so that traffic of that class
+ * finds them resident: a plan made while batches run stalls the scheduler
+ * for the device allocation.  Waits up to timeout_ms (< 0: forever).
+ * VP_OK (*created = plans made, may be NULL), VP_ETOOBIG if that many plans
+ * exceed the budget, VP_EAGAIN on timeout, or the plan-creation status.
+ */
+int vp_server_prewarm(vp_server* server, const vp_request* request, int instances,
+                      double timeout_ms, int* created);
 
 /*
  * Wait up to timeout_ms (0: just look, < 0: forever) for a request to end.

@@ -194,8 +194,21 @@ class Plan:
         check(_lib.lib.vof_step(*args), "vof_step")
         return (u, v, w, p, phi, *es, *gs)
 
-    def set_mixed(self, dc_steps: int):
+    def set_mixed(self, dc_steps: int, tol=None):
+        """Mixed plans: at most dc_steps FP64 defect-correction steps, stopping per
+        member once the estimated error is at most tol (tol <= 0: every step)."""
         check(_lib.lib.poisson_plan_set_mixed(self._h, int(dc_steps)), "poisson_plan_set_mixed")
+        if tol is not None:
+            check(_lib.lib.poisson_plan_set_mixed_tol(self._h, float(tol)),
+                  "poisson_plan_set_mixed_tol")
+
+    def mixed_report(self, n: int = 1, stream=None):
+        """[(steps taken, last error estimate)] of the n members of the last mixed call."""
+        steps = (ctypes.c_int * n)()
+        est = (ctypes.c_double * n)()
+        check(_lib.lib.poisson_plan_mixed_report(self._h, int(n), steps, est, _stream_ptr(stream)),
+              "poisson_plan_mixed_report")
+        return [(steps[i], est[i]) for i in range(n)]
 
     def last_mean(self, stream=None) -> float:
         out = ctypes.c_double(0.0)
@@ -203,9 +216,29 @@ class Plan:
               "poisson_plan_last_mean")
         return out.value
 
+    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes")
+
     def tune(self, key: str, value: int):
         """Launch-shape knob (see poisson_plan_tune); results do not change."""
         check(_lib.lib.poisson_plan_tune(self._h, key.encode(), int(value)), "poisson_plan_tune")
+
+    def tuning(self) -> dict:
+        """Current value of every tuning key."""
+        out = {}
+        for k in self.TUNING_KEYS:
+            v = ctypes.c_int(0)
+            check(_lib.lib.poisson_plan_get_tuning(self._h, k.encode(), ctypes.byref(v)),
+                  "poisson_plan_get_tuning")
+            out[k] = v.value
+        return out
+
+    def autotune(self, batch: int = 1, stream=None) -> dict:
+        """Time every candidate of each tuning key on this plan's workspace and keep
+        the fastest (see poisson_plan_autotune); returns the chosen values."""
+        chosen = (ctypes.c_int * 4)()
+        check(_lib.lib.poisson_plan_autotune(self._h, int(batch), _stream_ptr(stream), chosen),
+              "poisson_plan_autotune")
+        return dict(zip(self.TUNING_KEYS, list(chosen)))
 
     def set_profiling(self, enable=True, classes=None):
         """Bracket kernel launches of this plan with HIP events: every class when

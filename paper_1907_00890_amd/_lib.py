@@ -44,10 +44,14 @@ SIGNATURES = {
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
+    "poisson_plan_set_mixed_tol": (_i, [_p, _d]),
+    "poisson_plan_mixed_report": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), _p]),
     "poisson_plan_last_mean": (_i, [_p, ctypes.POINTER(_d), _p]),
     "poisson_plan_footprint": (ctypes.c_longlong, [_i, _i, _i, _i, _i]),
     "poisson_plan_device_bytes": (ctypes.c_longlong, [_p]),
     "poisson_plan_tune": (_i, [_p, ctypes.c_char_p, _i]),
+    "poisson_plan_get_tuning": (_i, [_p, ctypes.c_char_p, ctypes.POINTER(_i)]),
+    "poisson_plan_autotune": (_i, [_p, _i, _p, ctypes.POINTER(_i)]),
     "poisson_plan_set_profiling": (_i, [_p, _i]),
     "poisson_plan_kernel_times": (_i, [_p, ctypes.POINTER(_d), ctypes.POINTER(_i), _i]),
     "poisson_kernel_class_name": (ctypes.c_char_p, [_i]),

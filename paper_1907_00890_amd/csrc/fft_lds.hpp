@@ -141,24 +141,26 @@ __device__ __forceinline__ int dct_perm(int p) {
 // ---------------------------------------------------------------------------
 // pass bookkeeping
 // ---------------------------------------------------------------------------
-template <int N>
+// PTM: complex values per thread (16: radix-16 passes, 8: radix-8 passes;
+// the radix schedule of a length is greedy, largest radix first)
+template <int N, int PTM = 16>
 struct FftShape {
-  static constexpr int PT = N >= 16 ? 16 : N;  // complex values per thread
-  static constexpr int TPL = N / PT;           // threads per line
+  static constexpr int PT = N >= PTM ? PTM : N;  // complex values per thread
+  static constexpr int TPL = N / PT;             // threads per line
 };
-template <int N, int NS>
+template <int N, int NS, int PTM = 16>
 struct PassRadix {
   static constexpr int REM = N / NS;
-  static constexpr int R = REM >= 16 ? 16 : REM;
+  static constexpr int R = REM >= PTM ? PTM : REM;
 };
 
 // Twiddles of one pass for this thread: w_N^{(j % NS) r N/(NS R)}, r = 1..R-1,
 // for each of its PT/R butterflies j = t + TPL b.  tab holds cos(2 pi k/N) at
 // [k] and sin(2 pi k/N) at [N + k].
-template <typename T, int N, int NS, int SIGN>
+template <typename T, int N, int NS, int SIGN, int PTM>
 __device__ __forceinline__ void load_twiddles(const T* __restrict__ tab, int t, T* wr, T* wi) {
-  constexpr int R = PassRadix<N, NS>::R;
-  constexpr int PT = FftShape<N>::PT, TPL = FftShape<N>::TPL;
+  constexpr int R = PassRadix<N, NS, PTM>::R;
+  constexpr int PT = FftShape<N, PTM>::PT, TPL = FftShape<N, PTM>::TPL;
   constexpr int B = PT / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
@@ -173,10 +175,10 @@ __device__ __forceinline__ void load_twiddles(const T* __restrict__ tab, int t, 
 }
 
 // twiddle + DFT of the thread's PT/R butterflies of one pass
-template <typename T, int N, int NS, int SIGN>
+template <typename T, int N, int NS, int SIGN, int PTM>
 __device__ __forceinline__ void pass_compute(T* vr, T* vi, const T* wr, const T* wi) {
-  constexpr int R = PassRadix<N, NS>::R;
-  constexpr int B = FftShape<N>::PT / R;
+  constexpr int R = PassRadix<N, NS, PTM>::R;
+  constexpr int B = FftShape<N, PTM>::PT / R;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     if constexpr (NS > 1) {
@@ -193,15 +195,15 @@ __device__ __forceinline__ void pass_compute(T* vr, T* vi, const T* wr, const T*
 }
 
 // input position of value (b, r) of a pass, and output position
-template <int N, int NS>
+template <int N, int NS, int PTM>
 __device__ __forceinline__ int pass_in(int t, int b, int r) {
-  constexpr int R = PassRadix<N, NS>::R;
-  return t + FftShape<N>::TPL * b + r * (N / R);
+  constexpr int R = PassRadix<N, NS, PTM>::R;
+  return t + FftShape<N, PTM>::TPL * b + r * (N / R);
 }
-template <int N, int NS>
+template <int N, int NS, int PTM>
 __device__ __forceinline__ int pass_out(int t, int b, int r) {
-  constexpr int R = PassRadix<N, NS>::R;
-  const int j = t + FftShape<N>::TPL * b;
+  constexpr int R = PassRadix<N, NS, PTM>::R;
+  const int j = t + FftShape<N, PTM>::TPL * b;
   return (j / NS) * NS * R + (j % NS) + r * NS;
 }
 

@@ -37,26 +37,43 @@ inline Batch<T> batch_of(T* const* ptrs, int n) {
 // tab layout per direction and precision: cos(2 pi k/N), sin(2 pi k/N) for
 // k < N, then cos(pi m/(2N)), sin(pi m/(2N)) for m <= N/2.
 int ypass_tile_cols(int nx, int ny);
+// Options of the FP32 passes of the mixed-precision chain:
+//   sub   : x forward reads member b as in[b] - sub[b] (FP64, before the
+//           conversion to FP32); null: unchanged;
+//   skip  : per-member flags; a member whose flag is set is left untouched
+//           (its blocks return at once); null: every member runs;
+//   norms : x inverse writes per-block sums of e^2 and p^2 (see k_xinv);
+//   nzm   : z-planes per member (y passes: member = plane / nzm).
+struct PassOpts {
+  const double* sub = nullptr;
+  const int* skip = nullptr;
+  double* norms = nullptr;
+  int nzm = 0;
+};
+
 // x passes: `in`/`out` hold nb caller fields; the spectra of batch member b
-// start at b * stride of the workspace
+// start at b * stride of the workspace.  pt: values per thread of the radix
+// schedule of every transform pass (16: radix-16 passes, 8: radix-8).
 hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
-                           int nx, int bc, long nrows, const double* tab, hipStream_t st);
-hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, const double* tab, hipStream_t st);
-// sub (may be null): member b's input is read as in[b] - sub[b] (in FP64,
-// before the conversion to FP32)
-hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
-                           int nx, int bc, long nrows, const double* sub, const float* tab,
+                           int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st);
-// accum: out += result - sub[b] for batch member b (sub may be null: nothing subtracted)
+hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
+                           int nx, int bc, long nrows, const double* tab, int pt,
+                           hipStream_t st);
+hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
+                           int nx, int bc, long nrows, const float* tab, int pt,
+                           const PassOpts& o, hipStream_t st);
+// accum: out += result - o.sub[b] for batch member b (o.sub may be null)
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, bool accum, const double* sub,
-                           const float* tab, hipStream_t st);
+                           int nx, int bc, long nrows, bool accum, const float* tab, int pt,
+                           const PassOpts& o, hipStream_t st);
+// blocks per member of an x pass (the norms partial sums of k_xinv)
+long xpass_blocks(int nx, int pt, long nrows);
 // y passes over nplanes consecutive z-planes (nz * batch)
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const double* tab, hipStream_t st);
+                        const double* tab, int pt, hipStream_t st);
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const float* tab, hipStream_t st);
+                        const float* tab, int pt, const PassOpts& o, hipStream_t st);
 
 // zsolve.hip -----------------------------------------------------------------
 struct ZArgs {
@@ -83,6 +100,7 @@ struct ZArgs {
   const double* dzc;   // centre distance across face k+1/2 (wrap at nz-1 if periodic)
   double* mean_out;    // removed weighted mean of batch member b at [b] (diagnostic), may be null
   long batch_stride;   // elements between the spectra of consecutive batch members
+  const int* skip;     // per-member flags: set = leave the member untouched (may be null)
 };
 hipError_t launch_zsolve_f64(double* data, const ZArgs& a, int nb, hipStream_t st);
 hipError_t launch_zsolve_f32(float* data, const ZArgs& a, int nb, hipStream_t st);
@@ -116,8 +134,18 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 // r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);
 int stencil_default_planes(int nx, int ny, int nz);
+// skip (may be null): a set flag skips the launch's work (device-side)
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
                            double* partial, double* mean_p, double* mean_r, double dz_sum,
-                           hipStream_t st);
+                           const int* skip, hipStream_t st);
+// Defect-correction control of the mixed chain, per member b of a batch of
+// nb (state: 4 doubles per member, flags: one int per member).
+// dc_reset clears flags and state; dc_update reduces the x-inverse norms of
+// step `step` (0 = the first FP32 solve) and sets flag[b] once the error
+// estimate (|e_1| / |p_1| after the first step, |e_k|^2 / (|e_{k-1}| |p_k|)
+// after later ones) is at most tol (tol <= 0: never).
+hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st);
+hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
+                            double* state, int* flags, hipStream_t st);
 
 }  // namespace vp

@@ -9,6 +9,7 @@
 // exactly the inverse operator on the zero-mean subspace.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -83,6 +84,7 @@ struct poisson_plan {
   int nx = 0, ny = 0, nz = 0;
   int bc[3] = {0, 0, 0};
   int precision = 0, max_batch = 1, dc_steps = 1;
+  int x_pt = 16, y_pt = 16;  // radix schedules of the x and y passes (tuning knobs)
   double dx = 0, dy = 0, dz_sum = 0;
   int device = 0;
   long long bytes = 0;
@@ -96,6 +98,12 @@ struct poisson_plan {
   float* work32 = nullptr;
   double* res64 = nullptr;
   double* partial = nullptr;
+  // mixed-precision correction control: per-member state, flags, and the
+  // x-inverse norm partial sums
+  double* dc_state = nullptr;
+  int* dc_flags = nullptr;
+  double* dc_norms = nullptr;
+  double dc_tol = 1e-11;
 
   vp::ZArgs z{};
   vp::GridArgs g{};
@@ -214,6 +222,10 @@ int plan_init(poisson_plan* P, const double* dz) {
     if ((st = P->alloc(&P->res64, n, "residual"))) return st;
     if ((st = P->alloc(&P->partial, (size_t)2 * vp::kResidualMaxBlocks * P->max_batch, "partial sums")))
       return st;
+    if ((st = P->alloc(&P->dc_state, 4 * vp::kMaxBatch, "dc state"))) return st;
+    if ((st = P->alloc(&P->dc_flags, vp::kMaxBatch, "dc flags"))) return st;
+    // an x block owns at least two rows: at most ny*nz/2 blocks per member
+    if ((st = P->alloc(&P->dc_norms, (size_t)P->ny * P->nz * P->max_batch, "dc norms"))) return st;
   }
 
   // z launch geometry: S segments of at most 16 rows (S <= 64)
@@ -271,43 +283,58 @@ int solve_f64(poisson_plan* P, int nb, const double* const* rhs, double* const* 
   double* w = P->work64;
   const vp::Batch<const double> in = vp::batch_of(rhs, nb);
   const vp::Batch<double> out = vp::batch_of(sol, nb);
-  VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, st), "x forward", st);
-  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, st), "y forward", st);
+  VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, st), "x forward", st);
+  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, P->y_pt, st), "y forward", st);
   VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, nb, st), "z solve", st);
-  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, st), "y inverse", st);
-  VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, N, out, nb, P->nx, P->bc[0], nrows, P->tabx64, st), "x inverse", st);
+  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, P->y_pt, st), "y inverse", st);
+  VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, N, out, nb, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, st), "x inverse", st);
   return VP_OK;
 }
 
-// FP32 chain on FP64 right-hand sides rhs[b] - rsub[b] (rsub may be null);
-// out[b] = result, or with accum out[b] += result - sub[b]
-int solve_f32(poisson_plan* P, int nb, const double* const* rhs, const double* rsub,
-              double* const* out, bool accum, const double* sub, hipStream_t st) {
+// FP32 chain on FP64 right-hand sides rhs[b] - o.sub[b] (o.sub may be
+// null); out[b] = result, or with accum out[b] += result - asub[b].  o.skip
+// and o.norms as in vp::PassOpts.
+int solve_f32(poisson_plan* P, int nb, const double* const* rhs, double* const* out, bool accum,
+              const double* asub, vp::PassOpts o, hipStream_t st) {
   const long nrows = (long)P->ny * P->nz, N = P->npts();
   float* w = P->work32;
   const vp::Batch<const double> in = vp::batch_of(rhs, nb);
-  const vp::Batch<double> o = vp::batch_of(out, nb);
-  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, rsub, P->tabx32, st), "x forward f32", st);
-  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby32, st), "y forward f32", st);
-  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, P->z, nb, st), "z solve f32", st);
-  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby32, st), "y inverse f32", st);
-  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, o, nb, P->nx, P->bc[0], nrows, accum, sub, P->tabx32, st),
+  const vp::Batch<double> ob = vp::batch_of(out, nb);
+  vp::ZArgs z = P->z;
+  z.skip = o.skip;
+  o.nzm = P->nz;
+  vp::PassOpts fo = o, io = o;
+  fo.norms = nullptr;
+  io.sub = asub;
+  vp::PassOpts mo = o;  // y passes: flags only
+  mo.sub = nullptr;
+  mo.norms = nullptr;
+  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx32, P->x_pt, fo, st), "x forward f32", st);
+  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby32, P->y_pt, mo, st), "y forward f32", st);
+  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, z, nb, st), "z solve f32", st);
+  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby32, P->y_pt, mo, st), "y inverse f32", st);
+  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, ob, nb, P->nx, P->bc[0], nrows, accum, P->tabx32, P->x_pt, io, st),
             "x inverse f32", st);
   return VP_OK;
 }
 
-// Mixed precision: p = S32(f), then dc_steps times
+// Mixed precision: p_0 = S32(f), then up to dc_steps times
 //   r = f - L_h p (FP64, also giving mean_W(p) and mean_W(r)),
-//   p += S32(r - mean_W(r)) - mean_W(p).
+//   e = S32(r - mean_W(r)) - mean_W(p),  p += e.
 // The FP32 chain cannot see the null (constant) mode, so the FP64 weighted
 // means are removed in every correction step instead: mean_W(r) equals
 // mean_W(f), which would otherwise dominate r and swamp its FP32 copy.
+// Stopping, per member and on the device: the error left in p_k is bounded
+// by |e_1| after the first step and estimated as |e_k|^2 / |e_{k-1}| after
+// later ones, from norms the x-inverse pass reduces; once that is at most
+// dc_tol relative to |p| the member's flag is set and its later steps return
+// at once (no host synchronisation).
 // Batch member b keeps f in place, or in work64 slot b when an output
 // overwrites it, and its residual in res64 slot b (work64 slot b when f
 // itself lies in res64 slot b).
 int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
                 hipStream_t st) {
-  const long N = P->npts();
+  const long N = P->npts(), nrows = (long)P->ny * P->nz;
   const double* f[vp::kMaxBatch];
   double* r[vp::kMaxBatch];
   for (int b = 0; b < nb; ++b) {
@@ -323,17 +350,27 @@ int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const
   }
   double* const pmeans = P->mean + vp::kMaxBatch;      // FP64 weighted mean of p per member
   double* const rmeans = P->mean + 2 * vp::kMaxBatch;  // and of the residual
-  int s = solve_f32(P, nb, f, nullptr, sol, false, nullptr, st);
+  const long nblk = vp::xpass_blocks(P->nx, P->x_pt, nrows);
+  VP_HIP(vp::launch_dc_reset(P->dc_state, P->dc_flags, nb, st), "dc reset");
+  vp::PassOpts o;
+  o.norms = P->dc_norms;
+  int s = solve_f32(P, nb, f, sol, false, nullptr, o, st);
   if (s) return s;
-  for (int it = 0; it < P->dc_steps; ++it) {
+  VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, 0, P->dc_tol, P->dc_state, P->dc_flags, st),
+         "dc update");
+  o.sub = rmeans;
+  o.skip = P->dc_flags;
+  for (int it = 1; it <= P->dc_steps; ++it) {
     for (int b = 0; b < nb; ++b)
       VP_LAUNCH(P, K_RESIDUAL,
                 vp::launch_residual(P->g, f[b], sol[b], r[b],
                                     P->partial + 2L * b * vp::kResidualMaxBlocks, pmeans + b,
-                                    rmeans + b, P->dz_sum, st),
+                                    rmeans + b, P->dz_sum, P->dc_flags + b, st),
                 "residual", st);
-    s = solve_f32(P, nb, r, rmeans, sol, true, pmeans, st);
+    s = solve_f32(P, nb, r, sol, true, pmeans, o, st);
     if (s) return s;
+    VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, it, P->dc_tol, P->dc_state, P->dc_flags, st),
+           "dc update");
   }
   return VP_OK;
 }
@@ -370,7 +407,7 @@ poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, 
   P->bc[0] = bcs[0]; P->bc[1] = bcs[1]; P->bc[2] = bcs[2];
   P->precision = precision;
   P->max_batch = max_batch;
-  P->dc_steps = precision == VP_PRECISION_MIXED ? 1 : 0;
+  P->dc_steps = precision == VP_PRECISION_MIXED ? 3 : 0;
   if (hipGetDevice(&P->device) != hipSuccess) {
     delete P;
     return fail(VP_EHIP);
@@ -501,6 +538,27 @@ int poisson_plan_set_mixed(poisson_plan* P, int dc_steps) {
   return VP_OK;
 }
 
+int poisson_plan_set_mixed_tol(poisson_plan* P, double tol) {
+  if (!P || P->precision != VP_PRECISION_MIXED || !(tol == tol)) return VP_EINVAL;
+  P->dc_tol = tol;
+  return VP_OK;
+}
+
+int poisson_plan_mixed_report(poisson_plan* P, int n, int* steps, double* estimate,
+                              void* stream) {
+  if (!P || P->precision != VP_PRECISION_MIXED || n < 1 || n > P->max_batch) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double h[4 * vp::kMaxBatch];
+  VP_HIP(hipMemcpyAsync(h, P->dc_state, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, st),
+         "dc report");
+  VP_HIP(hipStreamSynchronize(st), "dc report sync");
+  for (int b = 0; b < n; ++b) {
+    if (steps) steps[b] = (int)h[4 * b + 2];
+    if (estimate) estimate[b] = h[4 * b + 1];
+  }
+  return VP_OK;
+}
+
 int poisson_plan_last_mean(poisson_plan* P, double* mean_out, void* stream) {
   if (!P || !mean_out) return VP_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -530,6 +588,11 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     P->z.lines = value;
     return VP_OK;
   }
+  if (k == "x_radix" || k == "y_radix") {
+    if (value != 8 && value != 16) return VP_EINVAL;
+    (k == "x_radix" ? P->x_pt : P->y_pt) = value;
+    return VP_OK;
+  }
   if (k == "stencil_planes") {
     if (value < 1 || value > P->nz) return VP_EINVAL;
     vp::GridArgs g = P->g;
@@ -539,6 +602,156 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     return VP_OK;
   }
   return VP_EINVAL;
+}
+
+}  // extern "C"
+
+namespace {
+
+// median time in ms of `reps` runs of launch(), after one untimed run
+template <typename F>
+int time_ms(hipStream_t st, int reps, F launch, float* out) {
+  int s = launch();
+  if (s) return s;
+  std::vector<float> t;
+  hipEvent_t a = nullptr, b = nullptr;
+  VP_HIP(hipEventCreate(&a), "tune event");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(hipErrorOutOfMemory, "tune event");
+  }
+  for (int r = 0; r < reps && s == VP_OK; ++r) {
+    (void)hipEventRecord(a, st);
+    s = launch();
+    (void)hipEventRecord(b, st);
+    float ms = 0.f;
+    if (s == VP_OK && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&ms, a, b) == hipSuccess)
+      t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s) return s;
+  if (t.empty()) return hip_fail(hipErrorUnknown, "tune timing");
+  std::sort(t.begin(), t.end());
+  *out = t[t.size() / 2];
+  return VP_OK;
+}
+
+// pick the candidate of `knob` (an int of the plan) with the smallest median
+// time of `launch`; the knob is left at the winner
+template <typename F>
+int pick(hipStream_t st, int* knob, const std::vector<int>& cands, F launch, int* chosen) {
+  float best = 0.f;
+  int arg = *knob;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    *knob = cands[i];
+    float ms = 0.f;
+    const int s = time_ms(st, 5, launch, &ms);
+    if (s) return s;
+    if (i == 0 || ms < best) {
+      best = ms;
+      arg = cands[i];
+    }
+  }
+  *knob = arg;
+  if (chosen) *chosen = arg;
+  return VP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
+  if (!P || nb < 1 || nb > P->max_batch) return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long N = P->npts(), nrows = (long)P->ny * P->nz;
+  const bool mixed = P->precision == VP_PRECISION_MIXED;
+  // the passes run in place on the zeroed workspace (each block owns the
+  // rows or columns it rewrites); the result is discarded
+  VP_HIP(hipMemsetAsync(P->work64, 0, sizeof(double) * N * P->max_batch, st), "tune clear");
+  if (mixed) VP_HIP(hipMemsetAsync(P->work32, 0, sizeof(float) * N * P->max_batch, st), "tune clear");
+  const double* in64[vp::kMaxBatch];
+  double* out64[vp::kMaxBatch];
+  for (int b = 0; b < nb; ++b) {
+    in64[b] = P->work64 + b * N;
+    out64[b] = P->work64 + b * N;
+  }
+  const vp::Batch<const double> bin = vp::batch_of(in64, nb);
+  const vp::Batch<double> bout = vp::batch_of(out64, nb);
+  int res[4] = {P->x_pt, P->y_pt, P->z.lines, P->g.kc};
+  int s;
+  auto hs = [](hipError_t e) { return e == hipSuccess ? VP_OK : hip_fail(e, "tune launch"); };
+  // x passes: forward + inverse
+  s = pick(st, &P->x_pt, {16, 8}, [&]() -> int {
+    if (mixed) {
+      const vp::PassOpts none{};
+      int e = hs(vp::launch_xfwd_f32(bin, nb, P->work32, N, P->nx, P->bc[0], nrows, P->tabx32,
+                                     P->x_pt, none, st));
+      if (e) return e;
+      return hs(vp::launch_xinv_f32(P->work32, N, bout, nb, P->nx, P->bc[0], nrows, false,
+                                    P->tabx32, P->x_pt, none, st));
+    }
+    int e = hs(vp::launch_xfwd_f64(bin, nb, P->work64, N, P->nx, P->bc[0], nrows, P->tabx64,
+                                   P->x_pt, st));
+    if (e) return e;
+    return hs(vp::launch_xinv_f64(P->work64, N, bout, nb, P->nx, P->bc[0], nrows, P->tabx64,
+                                  P->x_pt, st));
+  }, &res[0]);
+  if (s) return s;
+  // y passes: forward + inverse
+  s = pick(st, &P->y_pt, {16, 8}, [&]() -> int {
+    for (int fwd = 1; fwd >= 0; --fwd) {
+      const int e = mixed ? hs(vp::launch_y_f32(P->work32, P->nx, P->ny, P->nz * nb, P->bc[1],
+                                                fwd != 0, P->taby32, P->y_pt, vp::PassOpts{}, st))
+                          : hs(vp::launch_y_f64(P->work64, P->nx, P->ny, P->nz * nb, P->bc[1],
+                                                fwd != 0, P->taby64, P->y_pt, st));
+      if (e) return e;
+    }
+    return VP_OK;
+  }, &res[1]);
+  if (s) return s;
+  // z pass: lines per block
+  if (P->nz > 1) {
+    s = pick(st, &P->z.lines, {8, 16, 32}, [&]() -> int {
+      return mixed ? hs(vp::launch_zsolve_f32(P->work32, P->z, nb, st))
+                   : hs(vp::launch_zsolve_f64(P->work64, P->z, nb, st));
+    }, &res[2]);
+    if (s) return s;
+  }
+  // marching stencils: planes per block of the right-hand-side kernel, when
+  // the workspace has a second field to write to
+  double* second = mixed ? P->res64 : (P->max_batch > 1 ? P->work64 + N : nullptr);
+  if (second) {
+    std::vector<int> cands;
+    for (int kc : {1, 2, 4, 8, 16, 32, vp::stencil_default_planes(P->nx, P->ny, P->nz)}) {
+      vp::GridArgs g = P->g;
+      g.kc = kc;
+      if (kc <= P->nz && vp::stencil_blocks(g) <= vp::kResidualMaxBlocks &&
+          std::find(cands.begin(), cands.end(), kc) == cands.end())
+        cands.push_back(kc);
+    }
+    const double* f = P->work64;
+    s = pick(st, &P->g.kc, cands, [&]() -> int {
+      return hs(vp::launch_rhs(P->g, f, f, f, f, f, 1.0, f, 1.0, second, st));
+    }, &res[3]);
+    if (s) return s;
+  }
+  if (chosen)
+    for (int i = 0; i < 4; ++i) chosen[i] = res[i];
+  return VP_OK;
+}
+
+int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
+  if (!P || !key || !value) return VP_EINVAL;
+  const std::string k(key);
+  if (k == "x_radix") *value = P->x_pt;
+  else if (k == "y_radix") *value = P->y_pt;
+  else if (k == "z_lines") *value = P->z.lines;
+  else if (k == "stencil_planes") *value = P->g.kc;
+  else return VP_EINVAL;
+  return VP_OK;
 }
 
 int poisson_plan_set_profiling(poisson_plan* P, int class_mask) {

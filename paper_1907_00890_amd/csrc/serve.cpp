@@ -90,6 +90,16 @@ struct BatchRun {
   double t_ready = 0;  // dry run: completion time
 };
 
+// a request to create plans ahead of traffic (vp_server_prewarm)
+struct Warm {
+  ClassKey key;
+  int instances = 0;
+  int created = 0;
+  int status = VP_OK;
+  bool done = false;
+  bool abandoned = false;  // the caller stopped waiting: the scheduler frees it
+};
+
 struct Lane {
   hipStream_t stream = nullptr;
   int inflight = 0;
@@ -107,6 +117,7 @@ struct vp_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> incoming;
+  std::deque<Warm*> warm_incoming;
   std::vector<long long> cancels;
   std::map<long long, Req*> finished;
   std::set<long long> live;  // submitted, result not yet taken
@@ -127,7 +138,8 @@ struct vp_server {
   void finish(std::vector<Req*>& done);
   void publish();
   bool poll_running(std::vector<Req*>& done);
-  PlanEntry* acquire(const ClassKey& key, int lane, int* status);
+  PlanEntry* acquire(const ClassKey& key, int lane, bool may_create, int* status);
+  void prewarm(Warm* w);
   bool dispatch(std::vector<Req*>& done);
   void launch(BatchRun* b, std::vector<Req*>& done);
   void run();
@@ -137,6 +149,20 @@ struct vp_server {
 namespace {
 
 bool is_p(char c) { return c == 'P' || c == 'p'; }
+
+ClassKey key_of(const vp_request& r) {
+  ClassKey k;
+  k.nx = r.nx;
+  k.ny = r.ny;
+  k.nz = r.nz;
+  k.precision = r.precision;
+  k.dx = r.dx;
+  k.dy = r.dy;
+  for (int d = 0; d < 3; ++d) k.bc[d] = is_p(r.bc[d]) ? 'P' : 'N';
+  k.bc[3] = '\0';
+  k.dz.assign(r.dz, r.dz + r.nz);
+  return k;
+}
 
 long long footprint_of(const ClassKey& k, int max_batch) {
   return poisson_plan_footprint(k.nx, k.ny, k.nz, k.precision, max_batch);
@@ -215,15 +241,17 @@ bool vp_server::poll_running(std::vector<Req*>& done) {
 }
 
 // A plan of class `key` usable on `lane`: one the lane already owns, an idle
-// one, or a new one within the budget (evicting idle plans, least recently
-// used first).  nullptr with *status VP_OK means "not now" (memory held by
-// running batches); another status is a hard failure for the class.
-PlanEntry* vp_server::acquire(const ClassKey& key, int lane, int* status) {
+// one, or (if may_create) a new one within the budget (evicting idle plans,
+// least recently used first).  nullptr with *status VP_OK means "not now"
+// (memory held by running batches, or no new instance wanted); another
+// status is a hard failure for the class.
+PlanEntry* vp_server::acquire(const ClassKey& key, int lane, bool may_create, int* status) {
   *status = VP_OK;
   for (PlanEntry* pe : plans)
     if (pe->owner == lane && pe->key == key) return pe;
   for (PlanEntry* pe : plans)
     if (pe->owner == -1 && pe->key == key) return pe;
+  if (!may_create) return nullptr;
   const long long need = footprint_of(key, cfg.max_batch);
   long long busy = 0;  // bytes of plans with batches in flight
   for (PlanEntry* pe : plans)
@@ -390,10 +418,19 @@ bool vp_server::dispatch(std::vector<Req*>& done) {
         if (oa != ob) return oa > ob;
         return lanes[a].inflight < lanes[b].inflight;
       });
-      // (beyond its own plans, acquire does not depend on the lane: one try)
+      // Another instance of a class whose plans are all busy on full lanes
+      // costs a device allocation on this thread (stalling every lane), so
+      // one is made only for a backlog of half a batch or more; otherwise the
+      // group waits for its plan's lane.  Beyond its own plans, acquire does
+      // not depend on the lane: one try.
+      bool exists = false;
+      for (PlanEntry* pe : plans) exists = exists || pe->key == head->key;
+      int backlog = 0;
+      for (Req* q : pending) backlog += q->key == head->key && q->r.kind == head->r.kind;
+      const bool may_create = !exists || 2 * backlog >= cfg.max_batch;
       const int lane = order[0];
       int status = VP_OK;
-      PlanEntry* pe = acquire(head->key, lane, &status);
+      PlanEntry* pe = acquire(head->key, lane, may_create, &status);
       if (!pe && status != VP_OK) {
         // the class cannot get a plan: end its pending requests
         for (auto it = pending.begin(); it != pending.end();) {
@@ -429,15 +466,46 @@ bool vp_server::dispatch(std::vector<Req*>& done) {
   }
 }
 
+// create idle plans of one class until `instances` exist (scheduler thread)
+void vp_server::prewarm(Warm* w) {
+  // hold the class's idle plans (and each new one) aside while creating, so
+  // acquire neither returns nor evicts them
+  std::vector<PlanEntry*> held;
+  int have = 0;
+  for (PlanEntry* pe : plans) {
+    if (!(pe->key == w->key)) continue;
+    ++have;
+    if (pe->owner == -1) {
+      pe->owner = -2;
+      held.push_back(pe);
+    }
+  }
+  while (have < w->instances) {
+    int status = VP_OK;
+    PlanEntry* pe = acquire(w->key, -3, true, &status);
+    if (!pe) {
+      w->status = status != VP_OK ? status : VP_ENOMEM;
+      break;
+    }
+    pe->owner = -2;
+    held.push_back(pe);
+    ++have;
+    ++w->created;
+  }
+  for (PlanEntry* pe : held) pe->owner = -1;
+}
+
 void vp_server::run() {
   if (!cfg.dry_run) (void)hipSetDevice(device);
   std::vector<Req*> done;
   for (;;) {
     std::vector<long long> cx;
+    std::vector<Warm*> warms;
     bool stop;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (running.empty() && incoming.empty() && cancels.empty() && !stopping) {
+      if (running.empty() && incoming.empty() && cancels.empty() && warm_incoming.empty() &&
+          !stopping) {
         // idle, or waiting only for queue timeouts / plan memory
         if (pending.empty()) cv_work.wait(lk);
         else cv_work.wait_until(lk, deadline_in(0.2));
@@ -447,6 +515,10 @@ void vp_server::run() {
         incoming.pop_front();
       }
       cx.swap(cancels);
+      while (!warm_incoming.empty()) {
+        warms.push_back(warm_incoming.front());
+        warm_incoming.pop_front();
+      }
       stop = stopping;
       st.pending = (long long)pending.size();
     }
@@ -463,13 +535,24 @@ void vp_server::run() {
         ++it;
       }
     }
+    if (!warms.empty()) {
+      for (Warm* w : warms) prewarm(w);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (Warm* w : warms) {
+          if (w->abandoned) delete w;
+          else w->done = true;
+        }
+      }
+      publish();
+    }
     const bool retired = poll_running(done);
     const bool launched = dispatch(done);
     finish(done);
     if (retired || launched || !cx.empty()) publish();
     if (stop && pending.empty() && running.empty()) {
       std::lock_guard<std::mutex> lk(mu);
-      if (incoming.empty()) break;
+      if (incoming.empty() && warm_incoming.empty()) break;
     }
     if (!running.empty() && !retired && !launched) std::this_thread::yield();
   }
@@ -491,6 +574,8 @@ void vp_server::release_all() {
   finished.clear();
   for (Req* q : incoming) delete q;
   incoming.clear();
+  for (Warm* w : warm_incoming) delete w;
+  warm_incoming.clear();
   for (Req* q : pending) delete q;
   pending.clear();
 }
@@ -556,16 +641,7 @@ int vp_server_submit(vp_server* S, const vp_request* r, long long* ticket) {
   q->r = *r;
   q->r.dz = nullptr;
   q->r.bc = nullptr;
-  ClassKey& k = q->key;
-  k.nx = r->nx;
-  k.ny = r->ny;
-  k.nz = r->nz;
-  k.precision = r->precision;
-  k.dx = r->dx;
-  k.dy = r->dy;
-  for (int d = 0; d < 3; ++d) k.bc[d] = is_p(r->bc[d]) ? 'P' : 'N';
-  k.bc[3] = '\0';
-  k.dz.assign(r->dz, r->dz + r->nz);
+  const ClassKey& k = q->key = key_of(*r);
   if (footprint_of(k, S->cfg.max_batch) > S->cfg.hbm_budget) {
     delete q;
     return reject(VP_ETOOBIG);
@@ -588,6 +664,41 @@ int vp_server_submit(vp_server* S, const vp_request* r, long long* ticket) {
   }
   S->cv_work.notify_one();
   return VP_OK;
+}
+
+int vp_server_prewarm(vp_server* S, const vp_request* r, int instances, double timeout_ms,
+                      int* created) {
+  if (!S || !r || instances < 1 || instances > S->cfg.lanes) return VP_EINVAL;
+  const int chk = poisson_plan_check(r->nx, r->ny, r->nz, r->dx, r->dy, r->dz, r->bc,
+                                     r->precision, S->cfg.max_batch);
+  if (chk != VP_OK) return chk;
+  Warm* w = new (std::nothrow) Warm();
+  if (!w) return VP_ENOMEM;
+  w->key = key_of(*r);
+  w->instances = instances;
+  if ((long long)instances * footprint_of(w->key, S->cfg.max_batch) > S->cfg.hbm_budget) {
+    delete w;
+    return VP_ETOOBIG;
+  }
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->stopping) {
+    delete w;
+    return VP_EAGAIN;
+  }
+  S->warm_incoming.push_back(w);
+  S->cv_work.notify_one();
+  auto ready = [&] { return w->done; };
+  bool ok = true;
+  if (timeout_ms < 0) S->cv_done.wait(lk, ready);
+  else ok = S->cv_done.wait_until(lk, deadline_in(timeout_ms), ready);
+  if (!ok) {
+    w->abandoned = true;  // the scheduler frees it when it gets to it
+    return VP_EAGAIN;
+  }
+  const int st = w->status;
+  if (created) *created = w->created;
+  delete w;
+  return st;
 }
 
 int vp_server_wait(vp_server* S, long long ticket, double timeout_ms, vp_result* res) {

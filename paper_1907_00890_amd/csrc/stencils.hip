@@ -250,8 +250,10 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
 __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double* __restrict__ f,
                                                    const double* __restrict__ p,
                                                    double* __restrict__ r,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial,
+                                                   const int* __restrict__ skip) {
   __shared__ double red[2][256];
+  if (skip && skip[0]) return;
   const Tile t = tile_of<64>(g);
   double acc = 0.0, accr = 0.0;
   if (t.ok) {
@@ -301,8 +303,10 @@ __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double
 // block, fixed order
 __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ partial, int nb,
                                                       double denom, double* __restrict__ out_p,
-                                                      double* __restrict__ out_r) {
+                                                      double* __restrict__ out_r,
+                                                      const int* __restrict__ skip) {
   __shared__ double red[2][256];
+  if (skip && skip[0]) return;
   double acc = 0.0, accr = 0.0;
   for (int i = threadIdx.x; i < nb; i += 256) {
     acc += partial[i];
@@ -391,14 +395,88 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
                            double* partial, double* mean_p, double* mean_r, double dz_sum,
-                           hipStream_t st) {
+                           const int* skip, hipStream_t st) {
   const int nb = stencil_blocks(g);
   if (nb > kResidualMaxBlocks) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, r, partial);
+  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, r, partial, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double denom = (double)g.nx * (double)g.ny * dz_sum;
-  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, st, partial, nb, denom, mean_p, mean_r);
+  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, st, partial, nb, denom, mean_p, mean_r,
+                     skip);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// defect-correction control (mixed precision)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_dc_reset(double* __restrict__ state,
+                                                  int* __restrict__ flags, int nb) {
+  const int b = threadIdx.x;
+  if (b < nb) {
+    flags[b] = 0;
+    for (int i = 0; i < 4; ++i) state[4 * b + i] = 0.0;
+  }
+}
+
+// block b: member b.  state[4b + 0] = |e| of the previous step (|p_0| after
+// the first solve), [1] = last error estimate, [2] = corrections applied.
+__global__ __launch_bounds__(256) void k_dc_update(const double* __restrict__ norms, long nblk,
+                                                   int step, double tol,
+                                                   double* __restrict__ state,
+                                                   int* __restrict__ flags) {
+  __shared__ double red[2][256];
+  const int b = blockIdx.x;
+  if (flags[b]) return;
+  double ee = 0.0, pp = 0.0;
+  for (long i = threadIdx.x; i < nblk; i += 256) {
+    ee += norms[2 * (b * nblk + i)];
+    pp += norms[2 * (b * nblk + i) + 1];
+  }
+  red[0][threadIdx.x] = ee;
+  red[1][threadIdx.x] = pp;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double en = sqrt(red[0][0]), pn = sqrt(red[1][0]);
+  double* s = state + 4 * b;
+  if (step == 0) {
+    s[0] = en;  // e_0 is p_0 itself
+    s[1] = 1.0;
+    s[2] = 0.0;
+    return;
+  }
+  // Error left in p_k, relative to |p_k|.  After the first step only the
+  // bound |e_1| is safe (while the iteration contracts): p_0's error is
+  // smooth, the residual is not, and the FP32 chain is far less accurate on
+  // rough right-hand sides, so |e_1| / |p_0| says nothing about the
+  // contraction.  From the second step on the contraction is measured as
+  // |e_k| / |e_{k-1}|, so the error left is about |e_k|^2 / |e_{k-1}|.
+  double est = 0.0;
+  if (pn > 0.0) est = step == 1 ? en / pn : (s[0] > 0.0 ? en * en / (s[0] * pn) : 0.0);
+  s[0] = en;
+  s[1] = est;
+  s[2] = (double)step;
+  if (tol > 0.0 && est <= tol) flags[b] = 1;
+}
+
+hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st) {
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dc_reset, dim3(1), dim3(64), 0, st, state, flags, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
+                            double* state, int* flags, hipStream_t st) {
+  if (nb < 1 || nb > kMaxBatch || nblk < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dc_update, dim3(nb), dim3(256), 0, st, norms, nblk, step, tol, state,
+                     flags);
   return hipGetLastError();
 }
 

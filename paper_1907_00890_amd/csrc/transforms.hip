@@ -13,6 +13,8 @@
 // spreads the strided writes of the first pass over the banks.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_lds.hpp"
 #include "kernels.hpp"
 
@@ -68,37 +70,37 @@ struct YLds {
 // LAST_IN_REGS the last pass stays in registers (the caller stores it);
 // otherwise it is written back to LDS.  Twiddle loads are issued before the
 // barrier they wait on.
-template <typename T, int N, int NS, int SIGN, bool LAST_IN_REGS, typename L>
+template <typename T, int N, int NS, int SIGN, bool LAST_IN_REGS, int PTM, typename L>
 __device__ __forceinline__ void later_passes(L& lds, int t, const T* __restrict__ tab, T* vr,
                                              T* vi) {
   if constexpr (NS < N) {
-    constexpr int R = PassRadix<N, NS>::R;
-    constexpr int B = FftShape<N>::PT / R;
+    constexpr int R = PassRadix<N, NS, PTM>::R;
+    constexpr int B = FftShape<N, PTM>::PT / R;
     constexpr bool LAST = (NS * R == N);
-    T wr[FftShape<N>::PT], wi[FftShape<N>::PT];
-    if constexpr (NS > 1) load_twiddles<T, N, NS, SIGN>(tab, t, wr, wi);
+    T wr[FftShape<N, PTM>::PT], wi[FftShape<N, PTM>::PT];
+    if constexpr (NS > 1) load_twiddles<T, N, NS, SIGN, PTM>(tab, t, wr, wi);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds.get(pass_in<N, NS>(t, b, r), vr[b * R + r], vi[b * R + r]);
+      for (int r = 0; r < R; ++r) lds.get(pass_in<N, NS, PTM>(t, b, r), vr[b * R + r], vi[b * R + r]);
     __syncthreads();
-    pass_compute<T, N, NS, SIGN>(vr, vi, wr, wi);
+    pass_compute<T, N, NS, SIGN, PTM>(vr, vi, wr, wi);
     if constexpr (!(LAST && LAST_IN_REGS)) {
 #pragma unroll
       for (int b = 0; b < B; ++b)
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds.put(pass_out<N, NS>(t, b, r), vr[b * R + r], vi[b * R + r]);
+        for (int r = 0; r < R; ++r) lds.put(pass_out<N, NS, PTM>(t, b, r), vr[b * R + r], vi[b * R + r]);
     }
-    later_passes<T, N, NS * R, SIGN, LAST_IN_REGS>(lds, t, tab, vr, vi);
+    later_passes<T, N, NS * R, SIGN, LAST_IN_REGS, PTM>(lds, t, tab, vr, vi);
   }
 }
 
 // stride NS of the last pass of the plan for length N
-template <int N, int NS = 1>
+template <int N, int PTM, int NS = 1>
 constexpr int last_ns() {
-  if constexpr (NS * PassRadix<N, NS>::R == N) return NS;
-  else return last_ns<N, NS * PassRadix<N, NS>::R>();
+  if constexpr (NS * PassRadix<N, NS, PTM>::R == N) return NS;
+  else return last_ns<N, PTM, NS * PassRadix<N, NS, PTM>::R>();
 }
 
 // ---------------------------------------------------------------------------
@@ -106,12 +108,12 @@ constexpr int last_ns() {
 // lines a and b; `store(c0, a0, b0, c1, a1, b1)` writes packed coefficients
 // c0 and c1 of both lines
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC, typename L, typename Load, typename Store>
+template <typename T, int N, int BC, int PTM, typename L, typename Load, typename Store>
 __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict__ tab, Load load,
                                              Store store) {
-  using S = FftShape<N>;
+  using S = FftShape<N, PTM>;
   constexpr int PT = S::PT, TPL = S::TPL;
-  constexpr int R1 = PassRadix<N, 1>::R;
+  constexpr int R1 = PassRadix<N, 1, PTM>::R;
   T vr[PT], vi[PT];
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
@@ -121,13 +123,14 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
   }
   {
     T wr[PT], wi[PT];
-    pass_compute<T, N, 1, -1>(vr, vi, wr, wi);
+    pass_compute<T, N, 1, -1, PTM>(vr, vi, wr, wi);
   }
 #pragma unroll
   for (int b = 0; b < PT / R1; ++b)
 #pragma unroll
-    for (int r = 0; r < R1; ++r) lds.put(pass_out<N, 1>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
-  later_passes<T, N, R1, -1, false>(lds, t, tab, vr, vi);
+    for (int r = 0; r < R1; ++r)
+      lds.put(pass_out<N, 1, PTM>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
+  later_passes<T, N, R1, -1, false, PTM>(lds, t, tab, vr, vi);
   __syncthreads();
   const T* pc = tab + 2 * N;
   const T* ps = tab + 2 * N + (N / 2 + 1);
@@ -160,10 +163,10 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
 
 // inverse body: `load2(c0, c1, a0, b0, a1, b1)` reads packed coefficients c0
 // and c1 of both lines; `store(e, re, im)` writes element e of lines a and b
-template <typename T, int N, int BC, typename L, typename Load2, typename Store>
+template <typename T, int N, int BC, int PTM, typename L, typename Load2, typename Store>
 __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict__ tab, Load2 load2,
                                              Store store) {
-  using S = FftShape<N>;
+  using S = FftShape<N, PTM>;
   constexpr int PT = S::PT, TPL = S::TPL;
   const T* pc = tab + 2 * N;
   const T* ps = tab + 2 * N + (N / 2 + 1);
@@ -195,15 +198,15 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
     }
   }
   T vr[PT], vi[PT];
-  later_passes<T, N, 1, +1, true>(lds, t, tab, vr, vi);
+  later_passes<T, N, 1, +1, true, PTM>(lds, t, tab, vr, vi);
   // the last pass is in registers: store to HBM
-  constexpr int NSL = last_ns<N>();
-  constexpr int RL = PassRadix<N, NSL>::R;
+  constexpr int NSL = last_ns<N, PTM>();
+  constexpr int RL = PassRadix<N, NSL, PTM>::R;
 #pragma unroll
   for (int b = 0; b < PT / RL; ++b)
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
-      int e = pass_out<N, NSL>(t, b, r);
+      int e = pass_out<N, NSL, PTM>(t, b, r);
       if constexpr (BC == BC_N) e = dct_perm<N>(e);
       store(e, vr[b * RL + r], vi[b * RL + r]);
     }
@@ -214,13 +217,15 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
 // ---------------------------------------------------------------------------
 // SUB: member b's input is read as in[b] - sub[b] (FP64, before any
 // conversion to T); without it the kernel reads its input unchanged.
-template <typename TI, typename T, int N, int BC, bool SUB>
+template <typename TI, typename T, int N, int BC, bool SUB, int PTM>
 __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __restrict__ out,
                                                long ostride, long nrows,
                                                const T* __restrict__ tab,
-                                               const double* __restrict__ sub) {
-  constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
+                                               const double* __restrict__ sub,
+                                               const int* __restrict__ skip) {
+  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = 256 / TPL;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
+  if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
   const bool ok = ra < nrows;
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __res
   TI shift = TI(0);
   if constexpr (SUB) shift = TI(sub[blockIdx.y]);
   XLds<T, N> lds(lds_mem, q, LPB);
-  forward_body<T, N, BC>(
+  forward_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
         if constexpr (SUB) {
@@ -251,13 +256,21 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __res
       });
 }
 
-template <typename T, typename TO, int N, int BC, bool ACCUM>
+// With FP32 input (the mixed chain) and `norms` set, each block also writes
+// the sums of e^2 and p^2 over its rows to norms[2 * (member * gridDim.x +
+// block) + {0, 1}], where e is the value added (or stored) and p the result.
+template <typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
 __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long istride,
                                                const Batch<TO> out, long nrows,
                                                const T* __restrict__ tab,
-                                               const double* __restrict__ sub) {
-  constexpr int TPL = FftShape<N>::TPL, LPB = 256 / TPL;
+                                               const double* __restrict__ sub,
+                                               const int* __restrict__ skip,
+                                               double* __restrict__ norms) {
+  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = 256 / TPL;
+  constexpr bool NORMS = !std::is_same<T, TO>::value;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
+  if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
+  double ee = 0.0, pp = 0.0;
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
   const bool ok = ra < nrows;
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
     if (sub) shift = TO(sub[blockIdx.y]);
   }
   XLds<T, N> lds(lds_mem, q, LPB);
-  inverse_body<T, N, BC>(
+  inverse_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
         a0 = ok ? ia[c0] : T(0);
@@ -280,32 +293,63 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
       },
       [&](int e, T r, T i) {
         if (!ok) return;
+        const TO da = TO(r) - shift, db = TO(i) - shift;
+        TO pa = da, pb = db;
         if constexpr (ACCUM) {
-          oa[e] += TO(r) - shift;
-          ob[e] += TO(i) - shift;
-        } else {
-          oa[e] = TO(r);
-          ob[e] = TO(i);
+          pa = oa[e] + da;
+          pb = ob[e] + db;
+        }
+        oa[e] = pa;
+        ob[e] = pb;
+        if constexpr (NORMS) {
+          ee += double(da) * double(da) + double(db) * double(db);
+          pp += double(pa) * double(pa) + double(pb) * double(pb);
         }
       });
+  if constexpr (NORMS) {
+    if (norms) {
+      // fixed-order block reduction through the (now free) LDS of the transform
+      double* red = reinterpret_cast<double*>(lds_mem);
+      __syncthreads();
+      red[threadIdx.x] = ee;
+      red[256 + threadIdx.x] = pp;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+          red[threadIdx.x] += red[threadIdx.x + w];
+          red[256 + threadIdx.x] += red[256 + threadIdx.x + w];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+        norms[o] = red[0];
+        norms[o + 1] = red[256];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // y kernels: block (tile, plane); tile = 2*lines columns x N rows; thread
 // (q, t) with q fastest, so a wavefront reads 2*lines consecutive columns
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC>
-__global__ __launch_bounds__(256) void k_yfwd(T* __restrict__ data, int nx, long plane, int llines,
-                                               const T* __restrict__ tab) {
+template <typename T, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yfwd(T* __restrict__ data, int nx,
+                                                               long plane, int llines,
+                                                               const T* __restrict__ tab,
+                                                               int nzm,
+                                                               const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
   T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
                                   2 * q);
   const int nx2 = nx >> 1;  // row stride in T2 units
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
-  forward_body<T, N, BC>(
+  forward_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
         const T2 v = col[(long)e * nx2];
@@ -323,18 +367,22 @@ __global__ __launch_bounds__(256) void k_yfwd(T* __restrict__ data, int nx, long
       });
 }
 
-template <typename T, int N, int BC>
-__global__ __launch_bounds__(256) void k_yinv(T* __restrict__ data, int nx, long plane, int llines,
-                                               const T* __restrict__ tab) {
+template <typename T, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(T* __restrict__ data, int nx,
+                                                               long plane, int llines,
+                                                               const T* __restrict__ tab,
+                                                               int nzm,
+                                                               const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
   T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
                                   2 * q);
   const int nx2 = nx >> 1;
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
-  inverse_body<T, N, BC>(
+  inverse_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
         const T2 v0 = col[(long)c0 * nx2], v1 = col[(long)c1 * nx2];
@@ -356,15 +404,33 @@ __global__ __launch_bounds__(256) void k_yinv(T* __restrict__ data, int nx, long
 // ---------------------------------------------------------------------------
 #define VP_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
-template <typename TI, typename T, int BC, bool SUB>
-static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
-                                 long nrows, const double* sub, const T* tab, hipStream_t st) {
+// pt: values per thread of the radix schedule, 16 or 8 (a tuning knob; the
+// results are the same up to rounding order)
+template <int PTM>
+static long x_rows_per_block(int n) {
+  switch (n) {
+#define VP_RPB(NN) \
+  case NN: return 2L * (256 / FftShape<NN, PTM>::TPL);
+    VP_SIZES(VP_RPB)
+#undef VP_RPB
+    default: return 0;
+  }
+}
+
+long xpass_blocks(int nx, int pt, long nrows) {
+  const long rpb = pt == 8 ? x_rows_per_block<8>(nx) : x_rows_per_block<16>(nx);
+  return rpb > 0 ? (nrows + rpb - 1) / rpb : 0;
+}
+
+template <typename TI, typename T, int BC, bool SUB, int PTM>
+static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
+                                 long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
 #define VP_XF(NN)                                                                           \
   case NN: {                                                                                \
-    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                         \
-    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB>),                                        \
+    const long rpb = 2 * (256 / FftShape<NN, PTM>::TPL);                                    \
+    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB, PTM>),                                   \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
-                       st, in, out, ostride, nrows, tab, sub);                              \
+                       st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -376,15 +442,23 @@ static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long
   return hipGetLastError();
 }
 
-template <typename T, typename TO, int BC, bool ACCUM>
-static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out, int nb, int n,
-                                 long nrows, const T* tab, const double* sub, hipStream_t st) {
+template <typename TI, typename T, int BC, bool SUB>
+static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
+                                 long nrows, const T* tab, int pt, const PassOpts& o,
+                                 hipStream_t st) {
+  return pt == 8 ? launch_xfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
+                 : launch_xfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
+}
+
+template <typename T, typename TO, int BC, bool ACCUM, int PTM>
+static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out, int nb, int n,
+                                 long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
 #define VP_XI(NN)                                                                           \
   case NN: {                                                                                \
-    const long rpb = 2 * (256 / FftShape<NN>::TPL);                                         \
-    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM>),                                      \
+    const long rpb = 2 * (256 / FftShape<NN, PTM>::TPL);                                    \
+    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM, PTM>),                                 \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
-                       st, in, istride, out, nrows, tab, sub);                              \
+                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -396,8 +470,18 @@ static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out
   return hipGetLastError();
 }
 
-// y tile: `lines` column pairs per block, 256 threads when the plane is wide
-// enough; 2*lines columns divide nx (both powers of two)
+template <typename T, typename TO, int BC, bool ACCUM>
+static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out, int nb, int n,
+                                 long nrows, const T* tab, int pt, const PassOpts& o,
+                                 hipStream_t st) {
+  return pt == 8
+             ? launch_xinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
+             : launch_xinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
+}
+
+// y tile: `lines` column pairs per block (the radix-16 thread count of 256
+// when the plane is wide enough, so both schedules read equally wide tiles);
+// 2*lines columns divide nx (both powers of two)
 static int ypass_lines(int nx, int ny) {
   const int tpl = ny >= 16 ? ny / 16 : 1;
   int lines = 256 / tpl;
@@ -408,24 +492,27 @@ static int ypass_lines(int nx, int ny) {
 
 int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
 
-template <typename T, int BC, bool FWD>
-static hipError_t launch_y_bc(T* data, int nx, int ny, int nz, const T* tab, hipStream_t st) {
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
+                              const PassOpts& o, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
   const int lines = ypass_lines(nx, ny);
   int ll = 0;
   while ((1 << ll) < lines) ++ll;
   const long plane = (long)nx * ny;
-  const dim3 grid((unsigned)(nx / (2 * lines)), (unsigned)nz);
+  const dim3 grid((unsigned)(nx / (2 * lines)), (unsigned)nplanes);
+  const int nzm = o.nzm > 0 ? o.nzm : nplanes;
 #define VP_Y(NN)                                                                   \
   case NN: {                                                                       \
-    const int nthr = lines * FftShape<NN>::TPL;                                    \
+    const int nthr = lines * FftShape<NN, PTM>::TPL;                               \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);           \
-    auto kern = FWD ? &k_yfwd<T, NN, BC> : &k_yinv<T, NN, BC>;                     \
+    auto kern = FWD ? &k_yfwd<T, NN, BC, PTM> : &k_yinv<T, NN, BC, PTM>;           \
     if (shm > 65536) {                                                             \
       const hipError_t e = allow_large_lds(kern);                                  \
       if (e != hipSuccess) return e;                                               \
     }                                                                              \
-    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, ll, tab); \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, ll, tab, nzm, \
+                       o.skip);                                                    \
     break;                                                                         \
   }
   switch (ny) {
@@ -436,61 +523,73 @@ static hipError_t launch_y_bc(T* data, int nx, int ny, int nz, const T* tab, hip
   return hipGetLastError();
 }
 
+template <typename T, int BC, bool FWD>
+static hipError_t launch_y_bc(T* data, int nx, int ny, int nplanes, const T* tab, int pt,
+                              const PassOpts& o, hipStream_t st) {
+  return pt == 8 ? launch_y_pt<T, BC, FWD, 8>(data, nx, ny, nplanes, tab, o, st)
+                 : launch_y_pt<T, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
+}
+
 hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
-                           int nx, int bc, long nrows, const double* tab, hipStream_t st) {
+                           int nx, int bc, long nrows, const double* tab, int pt,
+                           hipStream_t st) {
+  const PassOpts o{};
   return bc == BC_P ? launch_xfwd_bc<double, double, BC_P, false>(in, nb, out, ostride, nx, nrows,
-                                                                  nullptr, tab, st)
+                                                                  tab, pt, o, st)
                     : launch_xfwd_bc<double, double, BC_N, false>(in, nb, out, ostride, nx, nrows,
-                                                                  nullptr, tab, st);
+                                                                  tab, pt, o, st);
 }
 hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, const double* tab, hipStream_t st) {
+                           int nx, int bc, long nrows, const double* tab, int pt,
+                           hipStream_t st) {
+  const PassOpts o{};
   return bc == BC_P ? launch_xinv_bc<double, double, BC_P, false>(in, istride, out, nb, nx, nrows,
-                                                                  tab, nullptr, st)
+                                                                  tab, pt, o, st)
                     : launch_xinv_bc<double, double, BC_N, false>(in, istride, out, nb, nx, nrows,
-                                                                  tab, nullptr, st);
+                                                                  tab, pt, o, st);
 }
 hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
-                           int nx, int bc, long nrows, const double* sub, const float* tab,
-                           hipStream_t st) {
-  if (sub)
+                           int nx, int bc, long nrows, const float* tab, int pt,
+                           const PassOpts& o, hipStream_t st) {
+  if (o.sub)
     return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, true>(in, nb, out, ostride, nx, nrows,
-                                                                  sub, tab, st)
+                                                                  tab, pt, o, st)
                       : launch_xfwd_bc<double, float, BC_N, true>(in, nb, out, ostride, nx, nrows,
-                                                                  sub, tab, st);
+                                                                  tab, pt, o, st);
   return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, false>(in, nb, out, ostride, nx, nrows,
-                                                                 nullptr, tab, st)
+                                                                 tab, pt, o, st)
                     : launch_xfwd_bc<double, float, BC_N, false>(in, nb, out, ostride, nx, nrows,
-                                                                 nullptr, tab, st);
+                                                                 tab, pt, o, st);
 }
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, bool accum, const double* sub,
-                           const float* tab, hipStream_t st) {
+                           int nx, int bc, long nrows, bool accum, const float* tab, int pt,
+                           const PassOpts& o, hipStream_t st) {
   if (bc == BC_P)
     return accum ? launch_xinv_bc<float, double, BC_P, true>(in, istride, out, nb, nx, nrows, tab,
-                                                             sub, st)
+                                                             pt, o, st)
                  : launch_xinv_bc<float, double, BC_P, false>(in, istride, out, nb, nx, nrows,
-                                                              tab, sub, st);
+                                                              tab, pt, o, st);
   return accum ? launch_xinv_bc<float, double, BC_N, true>(in, istride, out, nb, nx, nrows, tab,
-                                                           sub, st)
+                                                           pt, o, st)
                : launch_xinv_bc<float, double, BC_N, false>(in, istride, out, nb, nx, nrows, tab,
-                                                            sub, st);
+                                                            pt, o, st);
 }
-hipError_t launch_y_f64(double* data, int nx, int ny, int nz, int bc, bool fwd, const double* tab,
-                        hipStream_t st) {
+hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
+                        const double* tab, int pt, hipStream_t st) {
+  const PassOpts o{};
   if (bc == BC_P)
-    return fwd ? launch_y_bc<double, BC_P, true>(data, nx, ny, nz, tab, st)
-               : launch_y_bc<double, BC_P, false>(data, nx, ny, nz, tab, st);
-  return fwd ? launch_y_bc<double, BC_N, true>(data, nx, ny, nz, tab, st)
-             : launch_y_bc<double, BC_N, false>(data, nx, ny, nz, tab, st);
+    return fwd ? launch_y_bc<double, BC_P, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<double, BC_P, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  return fwd ? launch_y_bc<double, BC_N, true>(data, nx, ny, nplanes, tab, pt, o, st)
+             : launch_y_bc<double, BC_N, false>(data, nx, ny, nplanes, tab, pt, o, st);
 }
-hipError_t launch_y_f32(float* data, int nx, int ny, int nz, int bc, bool fwd, const float* tab,
-                        hipStream_t st) {
+hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
+                        const float* tab, int pt, const PassOpts& o, hipStream_t st) {
   if (bc == BC_P)
-    return fwd ? launch_y_bc<float, BC_P, true>(data, nx, ny, nz, tab, st)
-               : launch_y_bc<float, BC_P, false>(data, nx, ny, nz, tab, st);
-  return fwd ? launch_y_bc<float, BC_N, true>(data, nx, ny, nz, tab, st)
-             : launch_y_bc<float, BC_N, false>(data, nx, ny, nz, tab, st);
+    return fwd ? launch_y_bc<float, BC_P, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<float, BC_P, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  return fwd ? launch_y_bc<float, BC_N, true>(data, nx, ny, nplanes, tab, pt, o, st)
+             : launch_y_bc<float, BC_N, false>(data, nx, ny, nplanes, tab, pt, o, st);
 }
 
 }  // namespace vp

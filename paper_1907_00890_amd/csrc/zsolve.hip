@@ -172,6 +172,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   double* R2 = R1 + nr * LB;
   double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line), then the twisted exchange
 
+  if (A.skip && A.skip[blockIdx.y]) return;  // member already converged (whole block)
   const int l = threadIdx.x % LB, s = threadIdx.x / LB;
   const long line = (long)blockIdx.x * LB + l;
   x += blockIdx.y * A.batch_stride;
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
 template <typename T>
 __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
   const long line = (long)blockIdx.x * 256 + threadIdx.x;
-  if (line >= A.plane) return;
+  if (line >= A.plane || (A.skip && A.skip[blockIdx.y])) return;
   x += blockIdx.y * A.batch_stride;
   const double r = double(x[line]) * A.scale;
   if (line == 0) {

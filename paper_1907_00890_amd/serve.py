@@ -47,6 +47,7 @@ SIGNATURES = {
     "vp_server_now_us": (_d, []),
     "vp_server_create": (_p, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_i)]),
     "vp_server_submit": (_i, [_p, ctypes.POINTER(Request), ctypes.POINTER(_ll)]),
+    "vp_server_prewarm": (_i, [_p, ctypes.POINTER(Request), _i, _d, ctypes.POINTER(_i)]),
     "vp_server_wait": (_i, [_p, _ll, _d, ctypes.POINTER(Result)]),
     "vp_server_cancel": (_i, [_p, _ll]),
     "vp_server_drain": (_i, [_p, _d]),
@@ -166,6 +167,23 @@ class Server:
                 ext[n] = self._ptr(t, sh, n, optional=ts is None)
         return self.submit_raw(EXTEND, grid, precision, ext=ext, timeout_ms=timeout_ms,
                                keep=(u, v, w, src, out, q, gamma, phi))
+
+    def prewarm(self, grid: Grid, precision="fp64", instances=1, timeout_ms=-1.0) -> int:
+        """Make `instances` plans of this class resident before traffic; returns
+        how many were created."""
+        r = Request()
+        r.precision = _lib.PRECISION[precision]
+        r.nx, r.ny, r.nz = grid.nx, grid.ny, grid.nz
+        r.dx, r.dy = grid.dx, grid.dy
+        r.dz = grid.dz.ctypes.data_as(ctypes.POINTER(_d))
+        bc = grid.bc.encode()
+        r.bc = bc
+        made = _i(0)
+        s = _lib_.vp_server_prewarm(self._h, ctypes.byref(r), int(instances), float(timeout_ms),
+                                    ctypes.byref(made))
+        if s != 0:
+            raise ServeError(s, "vp_server_prewarm")
+        return made.value
 
     def wait(self, ticket, timeout_ms=-1.0):
         """The request's result as a dict, or None if it has not ended in time."""

@@ -112,10 +112,19 @@ int main() {
   std::atomic<bool> stop{false};
   std::thread injector([&] {
     int k = 0;
+    std::vector<double> dz(16, 1.0 / 16);
     while (!stop) {
       vp_server_inject(S, (k++ & 1) ? VP_FAULT_LAUNCH : VP_FAULT_PLAN, 1);
       vp_server_stats s{};
       vp_server_get_stats(S, &s);
+      // prewarm requests, some abandoned by a short timeout
+      vp_request w{};
+      w.nx = w.ny = w.nz = 16;
+      w.dx = w.dy = 0.1;
+      w.dz = dz.data();
+      w.bc = "PPN";
+      w.precision = k % 3 == 0 ? VP_PRECISION_MIXED : VP_PRECISION_FP64;
+      vp_server_prewarm(S, &w, 1 + k % 2, (k % 4 == 0) ? 0.001 : 50.0, nullptr);
       std::this_thread::sleep_for(std::chrono::milliseconds(2));
     }
   });

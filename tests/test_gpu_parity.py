@@ -220,6 +220,83 @@ def test_mixed_parity(torch_dev, case, dc):
     assert err <= MIXED_TOL, err
 
 
+RADIX8_CASES = [
+    (256, 16, 33, "NNN", 1.1),
+    (32, 32, 32, "PPP", None),
+    (8, 1024, 4, "NPN", None),
+    (1024, 8, 5, "PNN", None),
+    (16, 512, 24, "PPN", 1.5),
+]
+
+
+@pytest.mark.parametrize("case", RADIX8_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
+def test_radix8_schedule_parity(torch_dev, case):
+    """The radix-8 schedule of the x and y passes (a tuning knob) gives the
+    oracle's result, and the radix-16 result up to rounding order."""
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 7 + nx)
+    ref = oracle.solve(f, g)
+    plan = _plan(g)
+    p16 = plan.solve(_dev(torch, f)).cpu().numpy()
+    plan.tune("x_radix", 8)
+    plan.tune("y_radix", 8)
+    assert plan.tuning()["x_radix"] == 8 and plan.tuning()["y_radix"] == 8
+    p8 = plan.solve(_dev(torch, f)).cpu().numpy()
+    assert rel_l2(p8, ref) <= FP64_TOL
+    assert rel_l2(p8, p16) <= 1e-13
+    mixed = _plan(g, precision="mixed")
+    mixed.tune("x_radix", 8)
+    mixed.tune("y_radix", 8)
+    pm = mixed.solve(_dev(torch, f)).cpu().numpy()
+    assert rel_l2(pm, ref) <= MIXED_TOL
+
+
+@pytest.mark.parametrize("case", [(1024, 8, 5, "PNN", None), (8, 1024, 4, "NPN", None),
+                                  (64, 64, 64, "PPP", None)],
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
+def test_mixed_stops_on_error_estimate(torch_dev, case):
+    """Long FP32 lines need a second correction: the device-side stopping rule
+    takes it where needed and stops after one step where that suffices."""
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 5 + nz)
+    ref = oracle.solve(f, g)
+    plan = _plan(g, precision="mixed")
+    p = plan.solve(_dev(torch, f)).cpu().numpy()
+    (steps, est), = plan.mixed_report()
+    err = rel_l2(p, ref)
+    print(f"mixed {case}: {steps} steps, estimate {est:.2e}, error {err:.2e}")
+    assert err <= MIXED_TOL and 1 <= steps <= 3 and est <= 1e-11
+    # the estimate bounds the error it predicts (within a factor of 10, above
+    # the FP64 parity floor)
+    assert err <= 10 * est + FP64_TOL
+    # fixed single step: the estimate exposes what one step leaves
+    plan.set_mixed(1, tol=0.0)
+    p1 = plan.solve(_dev(torch, f)).cpu().numpy()
+    (s1, e1), = plan.mixed_report()
+    assert s1 == 1
+    err1 = rel_l2(p1, ref)
+    assert err1 <= 10 * e1 + FP64_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_keeps_parity(torch_dev, prec):
+    torch = torch_dev
+    g = _grid(64, 64, 48, "PPN", 1.5)
+    plan = _plan(g, precision=prec, max_batch=2)
+    chosen = plan.autotune(batch=2)
+    assert chosen == plan.tuning()
+    assert chosen["x_radix"] in (8, 16) and chosen["y_radix"] in (8, 16)
+    assert chosen["z_lines"] in (8, 16, 32) and 1 <= chosen["stencil_planes"] <= g.nz
+    f = vofsynth.gaussian_field(g.shape, 77)
+    p = plan.solve(_dev(torch, f)).cpu().numpy()
+    tol = FP64_TOL if prec == "fp64" else MIXED_TOL
+    assert rel_l2(p, oracle.solve(f, g)) <= tol
+
+
 BATCH_CASES = [
     # (nx, ny, nz, bc, beta, precision, n)
     (64, 32, 24, "PPN", 1.5, "fp64", 3),

@@ -221,3 +221,44 @@ def test_bad_configurations():
         args.update(kw)
         with pytest.raises(ServeError):
             Server(args.pop("hbm_budget"), dry_run=True, **args)
+
+
+def test_prewarm_makes_plans_resident():
+    g = grid()
+    with Server(BIG, lanes=3, max_batch=4, dry_run=True, dry_run_us=100) as srv:
+        assert srv.prewarm(g, "fp64", instances=3) == 3
+        assert srv.prewarm(g, "fp64", instances=2) == 0  # already there
+        assert srv.prewarm(g, "mixed", instances=1) == 1
+        st = srv.stats()
+        assert st["plans_created"] == 4 and st["plans_resident"] == 4
+        with pytest.raises(ServeError) as e:
+            srv.prewarm(g, instances=4)  # more than lanes
+        assert e.value.status == -1
+        # traffic finds them: no plan is created while serving
+        wait_all(srv, [solve(srv, g) for _ in range(12)])
+        assert srv.stats()["plans_created"] == 4
+    one = footprint(32, 32, 32, "fp64", 4)
+    with Server(2 * one + one // 2, lanes=3, max_batch=4, dry_run=True) as srv:
+        with pytest.raises(ServeError) as e:
+            srv.prewarm(g, instances=3)
+        assert e.value.status == serve.VP_ETOOBIG
+
+
+def test_new_instance_only_for_a_backlog():
+    """With the class's only plan busy on a full lane, one queued request waits
+    for that lane; half a batch of them gets a second instance on a free lane."""
+    g = grid()
+    with Server(BIG, lanes=2, max_batch=4, dry_run=True, dry_run_us=100000) as srv:
+        ts = [solve(srv, g)]
+        wait_running(srv, 1)
+        ts.append(solve(srv, g))
+        wait_running(srv, 2)  # both on the plan's lane (depth 2)
+        ts.append(solve(srv, g))
+        time.sleep(0.02)
+        st = srv.stats()
+        assert st["plans_created"] == 1 and st["running"] == 2 and st["pending"] == 1
+        ts.append(solve(srv, g))  # backlog of 2 = max_batch / 2
+        wait_running(srv, 3)
+        assert srv.stats()["plans_created"] == 2
+        res = wait_all(srv, ts)
+        assert sorted({r["lane"] for r in res}) == [0, 1]
