@@ -49,7 +49,7 @@ ALG_BYTES_PER_POINT = {
 KERNEL_SOURCES = {
     "x_forward": "transforms.hip", "y_forward": "transforms.hip", "y_inverse": "transforms.hip",
     "x_inverse": "transforms.hip", "z_solve": "zsolve.hip", "rhs_assembly": "stencils.hip",
-    "correction": "stencils.hip", "extension": "stencils.hip",
+    "correction": "stencils.hip", "extension": "stencils.hip", "step_epilogue": "stencils.hip",
 }
 
 

@@ -226,7 +226,9 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *   "z_lines"   : lines per block of the z pass, 8, 16 (default) or 32
  *                 (capped so that lines * segments <= 512);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
- *                 and residual kernels (1..nz; default chosen for ~16k blocks).
+ *                 and residual kernels (1..nz; default chosen for ~16k blocks);
+ *   "stream_planes" : z-planes marched by one block of the correction,
+ *                 extension and step-epilogue kernels (1..nz, default 1).
  * Returns VP_EINVAL for an unknown key or value.
  */
 int poisson_plan_tune(poisson_plan* plan, const char* key, int value);

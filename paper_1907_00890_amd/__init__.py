@@ -216,7 +216,8 @@ class Plan:
               "poisson_plan_last_mean")
         return out.value
 
-    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes")
+    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "stream_planes")
+    AUTOTUNED_KEYS = TUNING_KEYS[:4]
 
     def tune(self, key: str, value: int):
         """Launch-shape knob (see poisson_plan_tune); results do not change."""
@@ -238,7 +239,7 @@ class Plan:
         chosen = (ctypes.c_int * 4)()
         check(_lib.lib.poisson_plan_autotune(self._h, int(batch), _stream_ptr(stream), chosen),
               "poisson_plan_autotune")
-        return dict(zip(self.TUNING_KEYS, list(chosen)))
+        return dict(zip(self.AUTOTUNED_KEYS, list(chosen)))
 
     def set_profiling(self, enable=True, classes=None):
         """Bracket kernel launches of this plan with HIP events: every class when

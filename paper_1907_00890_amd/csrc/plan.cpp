@@ -106,7 +106,8 @@ struct poisson_plan {
   double dc_tol = 1e-11;
 
   vp::ZArgs z{};
-  vp::GridArgs g{};
+  vp::GridArgs g{};   // marching stencils (right-hand side, residual)
+  vp::GridArgs gs{};  // streaming stencils (correction, extension, epilogue)
 
   // optional per-launch timing (HIP events on the caller's stream)
   struct Mark {
@@ -273,6 +274,8 @@ int plan_init(poisson_plan* P, const double* dz) {
   G.dx = P->dx; G.dy = P->dy;
   G.dzf = P->dzf; G.dzc = P->dzc;
   G.kc = vp::stencil_default_planes(nx, ny, nz);
+  P->gs = G;
+  P->gs.kc = 1;
   return VP_OK;
 }
 
@@ -453,7 +456,7 @@ int project(poisson_plan* P, double* u, double* v, double* w, const double* phat
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src, dt, b, st), "rhs assembly", st);
   int s = solve_one(P, b, p, st);
   if (s) return s;
-  VP_LAUNCH(P, K_CORRECT, vp::launch_correct(P->g, u, v, w, p, phat, rho, rho0, dt, st), "correction", st);
+  VP_LAUNCH(P, K_CORRECT, vp::launch_correct(P->gs, u, v, w, p, phat, rho, rho0, dt, st), "correction", st);
   return VP_OK;
 }
 
@@ -489,7 +492,7 @@ int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_field
   if (s) return s;
   for (int b = 0; b < n; ++b)
     VP_LAUNCH(P, K_EXTEND,
-              vp::launch_extend(P->g, a[b].u, a[b].v, a[b].w, phi[b], a[b].qx, a[b].qy, a[b].qz,
+              vp::launch_extend(P->gs, a[b].u, a[b].v, a[b].w, phi[b], a[b].qx, a[b].qy, a[b].qz,
                                 a[b].ue, a[b].ve, a[b].we, a[b].ug, a[b].vg, a[b].wg, st),
               "extension", st);
   return VP_OK;
@@ -526,7 +529,7 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
   s = solve_one(P, src_ext, phi, st);
   if (s) return s;
   VP_LAUNCH(P, K_EPILOGUE,
-            vp::launch_step_epilogue(P->g, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
+            vp::launch_step_epilogue(P->gs, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
                                      ve, we, ug, vg, wg, st),
             "step epilogue", st);
   return VP_OK;
@@ -591,6 +594,11 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
   if (k == "x_radix" || k == "y_radix") {
     if (value != 8 && value != 16) return VP_EINVAL;
     (k == "x_radix" ? P->x_pt : P->y_pt) = value;
+    return VP_OK;
+  }
+  if (k == "stream_planes") {
+    if (value < 1 || value > P->nz) return VP_EINVAL;
+    P->gs.kc = value;
     return VP_OK;
   }
   if (k == "stencil_planes") {
@@ -750,6 +758,7 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "y_radix") *value = P->y_pt;
   else if (k == "z_lines") *value = P->z.lines;
   else if (k == "stencil_planes") *value = P->g.kc;
+  else if (k == "stream_planes") *value = P->gs.kc;
   else return VP_EINVAL;
   return VP_OK;
 }

@@ -205,41 +205,53 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
   if (!t.ok) return;
   const long P = (long)g.nx * g.ny;
   const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
-  const int k = t.kb;
-  const long c = k * P + t.c0;
-  const int kp = kplus(g, k);
-  const double pc = p[c], hc = ph[c], rc = rho[c], fc = phi[c];
-  double un = u[c], vn = v[c], wn = w[c];
-  double gx = 0.0, gy = 0.0, gz = 0.0;
-  if (t.hxp) {
-    const long n = c + t.xp;
-    un -= dt * (ir0 * (p[n] - pc) * idx + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idx);
-    gx = (phi[n] - fc) * idx;
-  }
-  if (t.hyp) {
-    const long n = c + t.yp;
-    vn -= dt * (ir0 * (p[n] - pc) * idy + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idy);
-    gy = (phi[n] - fc) * idy;
-  }
-  if (kp >= 0) {
-    const long n = kp * P + t.c0;
-    const double h = g.dzc[k];
-    wn -= dt * (ir0 * (p[n] - pc) / h + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) / h);
-    gz = (phi[n] - fc) / h;
-  }
-  u[c] = un;
-  v[c] = vn;
-  w[c] = wn;
-  const double ex = un - gx, ey = vn - gy, ez = wn - gz;
-  if (ue) {
-    ue[c] = ex;
-    ve[c] = ey;
-    we[c] = ez;
-  }
-  if (ug) {
-    ug[c] = ex - qx[c];
-    vg[c] = ey - qy[c];
-    wg[c] = ez - qz[c];
+  // the z-neighbour values of plane k become the centre values of plane k+1
+  double pc = p[t.kb * P + t.c0], hc = ph[t.kb * P + t.c0], rc = rho[t.kb * P + t.c0],
+         fc = phi[t.kb * P + t.c0];
+  for (int k = t.kb; k < t.ke; ++k) {
+    const long c = k * P + t.c0;
+    const int kp = kplus(g, k);
+    double un = u[c], vn = v[c], wn = w[c];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (t.hxp) {
+      const long n = c + t.xp;
+      un -= dt * (ir0 * (p[n] - pc) * idx + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idx);
+      gx = (phi[n] - fc) * idx;
+    }
+    if (t.hyp) {
+      const long n = c + t.yp;
+      vn -= dt * (ir0 * (p[n] - pc) * idy + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idy);
+      gy = (phi[n] - fc) * idy;
+    }
+    double pp = 0.0, hp = 0.0, rp = 0.0, fp = 0.0;
+    if (kp >= 0) {
+      const long n = kp * P + t.c0;
+      pp = p[n];
+      hp = ph[n];
+      rp = rho[n];
+      fp = phi[n];
+      const double h = g.dzc[k];
+      wn -= dt * (ir0 * (pp - pc) / h + (inv_face_rho(rc, rp) - ir0) * (hp - hc) / h);
+      gz = (fp - fc) / h;
+    }
+    u[c] = un;
+    v[c] = vn;
+    w[c] = wn;
+    const double ex = un - gx, ey = vn - gy, ez = wn - gz;
+    if (ue) {
+      ue[c] = ex;
+      ve[c] = ey;
+      we[c] = ez;
+    }
+    if (ug) {
+      ug[c] = ex - qx[c];
+      vg[c] = ey - qy[c];
+      wg[c] = ez - qz[c];
+    }
+    pc = pp;
+    hc = hp;
+    rc = rp;
+    fc = fp;
   }
 }
 
@@ -358,14 +370,13 @@ hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const
   return hipGetLastError();
 }
 
-// the streaming stencils (correction, extension) run one plane per block:
-// more independent loads in flight than a march
+// the streaming stencils (correction, extension, step epilogue) take the
+// planes per block from g.kc (the plan passes its own count for them, one
+// plane by default: more independent loads in flight than a march)
 hipError_t launch_correct(const GridArgs& g, double* u, double* v, double* w, const double* p,
                           const double* phat, const double* rho, double rho0, double dt,
                           hipStream_t st) {
-  GridArgs g1 = g;
-  g1.kc = 1;
-  hipLaunchKernelGGL(k_correct, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, p, phat, rho,
+  hipLaunchKernelGGL(k_correct, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, p, phat, rho,
                      rho0, dt);
   return hipGetLastError();
 }
@@ -374,9 +385,7 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          const double* phi, const double* qx, const double* qy, const double* qz,
                          double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
                          hipStream_t st) {
-  GridArgs g1 = g;
-  g1.kc = 1;
-  hipLaunchKernelGGL(k_extend, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, phi, qx, qy, qz,
+  hipLaunchKernelGGL(k_extend, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, phi, qx, qy, qz,
                      ue, ve, we, ug, vg, wg);
   return hipGetLastError();
 }
@@ -386,9 +395,7 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
                                 const double* phi, const double* qx, const double* qy,
                                 const double* qz, double* ue, double* ve, double* we, double* ug,
                                 double* vg, double* wg, hipStream_t st) {
-  GridArgs g1 = g;
-  g1.kc = 1;
-  hipLaunchKernelGGL(k_step_epilogue, tile_grid<256>(g1), dim3(256), 0, st, g1, u, v, w, p, phat,
+  hipLaunchKernelGGL(k_step_epilogue, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, p, phat,
                      rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
   return hipGetLastError();
 }

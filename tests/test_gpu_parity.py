@@ -288,7 +288,7 @@ def test_autotune_keeps_parity(torch_dev, prec):
     g = _grid(64, 64, 48, "PPN", 1.5)
     plan = _plan(g, precision=prec, max_batch=2)
     chosen = plan.autotune(batch=2)
-    assert chosen == plan.tuning()
+    assert chosen == {k: v for k, v in plan.tuning().items() if k in chosen}
     assert chosen["x_radix"] in (8, 16) and chosen["y_radix"] in (8, 16)
     assert chosen["z_lines"] in (8, 16, 32) and 1 <= chosen["stencil_planes"] <= g.nz
     f = vofsynth.gaussian_field(g.shape, 77)
@@ -455,6 +455,14 @@ def test_fused_step_parity(torch_dev, shape, bc, beta):
     # u_1^e is divergence-free (the Stefan source of both solves is the same s)
     dmax = np.abs(oracle.div(ue, ve, we, g)).max()
     assert dmax <= 1e-10 * np.abs(oracle.div(us, vs, ws, g)).max()
+    # marching several planes per block of the streaming stencils (a launch
+    # shape knob) changes no bit of any result
+    plan.tune("stream_planes", 3)
+    out3 = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt, T(s),
+                     q=tuple(T(a) for a in q), out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+    torch.cuda.synchronize()
+    for a, b in zip(out3, (u, v, w, p, phi, ue, ve, we, ug, vg, wg)):
+        assert np.array_equal(a.cpu().numpy(), b)
 
 
 def test_fused_step_graph_replay(torch_dev):
