@@ -227,8 +227,16 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 (capped so that lines * segments <= 512);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
  *                 and residual kernels (1..nz; default chosen for ~16k blocks);
- *   "stream_planes" : z-planes marched by one block of the correction,
- *                 extension and step-epilogue kernels (1..nz, default 1).
+ *   "stream_planes" : z-planes marched by one block of the correction and
+ *                 extension kernels (1..nz, default 1);
+ *   "epilogue_tiled", "epilogue_planes" : the fused epilogue of vof_step on
+ *                 LDS-staged 64 x 8 (or 16) tiles marching that many planes
+ *                 (defaults 8 and 1; tiled 0: plain one-row tiles; results
+ *                 are bit-identical);
+ *   "rhs_tiled" : 8 (default) or 16 assembles the projection's right-hand
+ *                 side on LDS-staged 64 x 8 (x 16) tiles where nx % 64 == 0 and
+ *                 ny divides by the tile height (bit-identical results), 0 on
+ *                 plain 64 x 4 tiles.
  * Returns VP_EINVAL for an unknown key or value.
  */
 int poisson_plan_tune(poisson_plan* plan, const char* key, int value);

@@ -216,7 +216,8 @@ class Plan:
               "poisson_plan_last_mean")
         return out.value
 
-    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "stream_planes")
+    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "stream_planes",
+                   "rhs_tiled", "epilogue_tiled", "epilogue_planes")
     AUTOTUNED_KEYS = TUNING_KEYS[:4]
 
     def tune(self, key: str, value: int):

@@ -110,6 +110,8 @@ struct GridArgs {
   int nx, ny, nz;
   int lx, ly;          // log2(nx), log2(ny): nx and ny are powers of two
   int kc;              // z-planes marched by one stencil block
+  int tiled;           // right-hand side on LDS-staged 64 x tiled tiles (8 or 16 rows) where
+                       // they fit; 0: plain 64 x 4 tiles
   int bcx, bcy, bcz;   // 0 periodic, 1 wall
   double dx, dy;
   const double* dzf;   // nz
@@ -133,6 +135,7 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 // r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
 // r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);
+int rhs_blocks(const GridArgs& g);  // blocks of one launch_rhs
 int stencil_default_planes(int nx, int ny, int nz);
 // skip (may be null): a set flag skips the launch's work (device-side)
 hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,

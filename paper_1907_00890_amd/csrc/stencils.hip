@@ -63,6 +63,33 @@ __device__ __forceinline__ int kminus(const GridArgs& g, int k) {
 // inverse of the face density 1 / ((rho_a + rho_b) / 2)
 __device__ __forceinline__ double inv_face_rho(double ra, double rb) { return 2.0 / (ra + rb); }
 
+// One cell of the split right-hand side from its neighbourhood.  Floating-
+// point contraction is off inside, so every kernel variant that calls it
+// (plain or LDS-staged tiles) produces the same bits.  The neighbour values
+// of a face that does not exist (wall) are not used.
+struct RhsNbr {
+  double ph, rh;  // p_hat and rho across the face
+  bool has;       // the face is not a wall
+};
+__device__ __forceinline__ double rhs_cell(double rho0, double ir0, double idx, double idy,
+                                           double r0dt, double phc, double rhc, RhsNbr xp,
+                                           RhsNbr xm, RhsNbr yp, RhsNbr ym, RhsNbr zp, double dzcp,
+                                           RhsNbr zm, double dzcm, double dzf, double uc,
+                                           double um, double vc, double vm, double wc, double wm,
+                                           double sv) {
+#pragma clang fp contract(off)
+  double fxp = 0.0, fxm = 0.0, fyp = 0.0, fym = 0.0, fzp = 0.0, fzm = 0.0;
+  if (xp.has) fxp = (ir0 - inv_face_rho(rhc, xp.rh)) * (xp.ph - phc) * idx;
+  if (xm.has) fxm = (ir0 - inv_face_rho(xm.rh, rhc)) * (phc - xm.ph) * idx;
+  if (yp.has) fyp = (ir0 - inv_face_rho(rhc, yp.rh)) * (yp.ph - phc) * idy;
+  if (ym.has) fym = (ir0 - inv_face_rho(ym.rh, rhc)) * (phc - ym.ph) * idy;
+  if (zp.has) fzp = (ir0 - inv_face_rho(rhc, zp.rh)) * (zp.ph - phc) / dzcp;
+  if (zm.has) fzm = (ir0 - inv_face_rho(zm.rh, rhc)) * (phc - zm.ph) / dzcm;
+  const double divf = (fxp - fxm) * idx + (fyp - fym) * idy + (fzp - fzm) / dzf;
+  const double divu = (uc - um) * idx + (vc - vm) * idy + (wc - (zm.has ? wm : 0.0)) / dzf;
+  return rho0 * divf + r0dt * (divu - sv);
+}
+
 // b = rho0 D[(1/rho0 - 1/rho_f) G p_hat] + (rho0/dt) (D u* - s)
 __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __restrict__ u,
                                               const double* __restrict__ v,
@@ -91,25 +118,143 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
       php = ph[kp * P + t.c0];
       rhp = rho[kp * P + t.c0];
     }
-    const double dzf = g.dzf[k];
-    double fxp = 0.0, fxm = 0.0, fyp = 0.0, fym = 0.0, fzp = 0.0, fzm = 0.0;
-    if (t.hxp) fxp = (ir0 - inv_face_rho(rhc, rho[c + t.xp])) * (ph[c + t.xp] - phc) * idx;
-    if (t.hxm) fxm = (ir0 - inv_face_rho(rho[c + t.xm], rhc)) * (phc - ph[c + t.xm]) * idx;
-    if (t.hyp) fyp = (ir0 - inv_face_rho(rhc, rho[c + t.yp])) * (ph[c + t.yp] - phc) * idy;
-    if (t.hym) fym = (ir0 - inv_face_rho(rho[c + t.ym], rhc)) * (phc - ph[c + t.ym]) * idy;
-    if (kp >= 0) fzp = (ir0 - inv_face_rho(rhc, rhp)) * (php - phc) / g.dzc[k];
-    if (km >= 0) fzm = (ir0 - inv_face_rho(rhm, rhc)) * (phc - phm) / g.dzc[km];
-    const double divf = (fxp - fxm) * idx + (fyp - fym) * idy + (fzp - fzm) / dzf;
+    const RhsNbr xp{t.hxp ? ph[c + t.xp] : 0.0, t.hxp ? rho[c + t.xp] : 0.0, t.hxp};
+    const RhsNbr xm{t.hxm ? ph[c + t.xm] : 0.0, t.hxm ? rho[c + t.xm] : 0.0, t.hxm};
+    const RhsNbr yp{t.hyp ? ph[c + t.yp] : 0.0, t.hyp ? rho[c + t.yp] : 0.0, t.hyp};
+    const RhsNbr ym{t.hym ? ph[c + t.ym] : 0.0, t.hym ? rho[c + t.ym] : 0.0, t.hym};
+    const RhsNbr zp{php, rhp, kp >= 0}, zm{phm, rhm, km >= 0};
     const double wc = w[c];
     const double um = t.hxm ? u[c + t.xm] : 0.0;
     const double vm = t.hym ? v[c + t.ym] : 0.0;
-    const double divu = (u[c] - um) * idx + (v[c] - vm) * idy + (wc - (km >= 0 ? wm : 0.0)) / dzf;
     const double sv = src ? src[c] : 0.0;
-    b[c] = rho0 * divf + r0dt * (divu - sv);
+    b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc, rhc, xp, xm, yp, ym, zp,
+                    kp >= 0 ? g.dzc[k] : 1.0, zm, km >= 0 ? g.dzc[km] : 1.0, g.dzf[k], u[c], um,
+                    v[c], vm, wc, wm, sv);
     phm = phc; phc = php;
     rhm = rhc; rhc = rhp;
     wm = wc;
     km = k;
+  }
+}
+
+// The same right-hand side on 64 x TY tiles (TY = 8 or 16; nx % 64 == 0,
+// ny % TY == 0):
+// p_hat and rho of the current plane, with their x and y halo, are staged in
+// LDS once per block and plane, and their z-neighbours stay in registers
+// while the block marches through its planes, so every value of the two
+// 7-point fields is read from HBM about once (halo: 2/TY rows, 2/64 columns,
+// 2/kc planes).  A thread owns column tx of rows ty, ty+4, ... of the tile.
+// The per-cell arithmetic is k_rhs's, term for term.
+template <int TY>
+__global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const double* __restrict__ u,
+                                                    const double* __restrict__ v,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ ph,
+                                                    const double* __restrict__ rho, double rho0,
+                                                    const double* __restrict__ src, double dt,
+                                                    double* __restrict__ b) {
+  constexpr int TX = 64, W = TX + 2, RPT = TY / 4;
+  __shared__ double sph[(TY + 2) * W], srh[(TY + 2) * W];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int kb = blockIdx.z * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
+  const int i = i0 + tx;
+  const long P = (long)g.nx * g.ny;
+  const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, r0dt = rho0 / dt;
+  const bool hxp = i + 1 < g.nx || g.bcx == 0, hxm = i > 0 || g.bcx == 0;
+  const long xm = i > 0 ? -1 : (long)(g.nx - 1);
+  // halo cell h of this plane (threads 0 .. 2*TY + 2*TX - 1): LDS slot and
+  // in-plane offset; wrapped when periodic, clamped (and unused) at walls
+  int hslot = -1;
+  long hoff = 0;
+  {
+    const int h = threadIdx.x;
+    int r = 0, c = 0;
+    if (h < 2 * TY) {
+      r = h % TY;
+      c = h < TY ? -1 : TX;
+    } else if (h < 2 * TY + 2 * TX) {
+      c = (h - 2 * TY) % TX;
+      r = h - 2 * TY < TX ? -1 : TY;
+    }
+    if (h < 2 * TY + 2 * TX) {
+      int gi = i0 + c, gj = j0 + r;
+      if (gi < 0) gi = g.bcx == 0 ? g.nx - 1 : 0;
+      if (gi >= g.nx) gi = g.bcx == 0 ? 0 : g.nx - 1;
+      if (gj < 0) gj = g.bcy == 0 ? g.ny - 1 : 0;
+      if (gj >= g.ny) gj = g.bcy == 0 ? 0 : g.ny - 1;
+      hslot = (r + 1) * W + (c + 1);
+      hoff = (long)gj * g.nx + gi;
+    }
+  }
+  long c0[RPT];
+  bool hyp[RPT], hym[RPT];
+  long ymo[RPT];
+  double phm[RPT], phc[RPT], rhm[RPT], rhc[RPT], wm[RPT];
+  int km = kminus(g, kb);
+#pragma unroll
+  for (int m = 0; m < RPT; ++m) {
+    const int j = j0 + ty + 4 * m;
+    c0[m] = (long)j * g.nx + i;
+    hyp[m] = j + 1 < g.ny || g.bcy == 0;
+    hym[m] = j > 0 || g.bcy == 0;
+    ymo[m] = j > 0 ? -(long)g.nx : (long)(g.ny - 1) * g.nx;
+    phm[m] = rhm[m] = wm[m] = 0.0;
+    if (km >= 0) {
+      phm[m] = ph[km * P + c0[m]];
+      rhm[m] = rho[km * P + c0[m]];
+      wm[m] = w[km * P + c0[m]];
+    }
+    phc[m] = ph[kb * P + c0[m]];
+    rhc[m] = rho[kb * P + c0[m]];
+  }
+  for (int k = kb; k < ke; ++k) {
+    const int kp = kplus(g, k);
+    // every global load of this plane is issued before the barrier
+    double php[RPT], rhp[RPT], uc[RPT], um[RPT], vc[RPT], vm[RPT], wcs[RPT], sv[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const long c = k * P + c0[m];
+      php[m] = rhp[m] = 0.0;
+      if (kp >= 0) {
+        php[m] = ph[kp * P + c0[m]];
+        rhp[m] = rho[kp * P + c0[m]];
+      }
+      uc[m] = u[c];
+      um[m] = hxm ? u[c + xm] : 0.0;
+      vc[m] = v[c];
+      vm[m] = hym[m] ? v[c + ymo[m]] : 0.0;
+      wcs[m] = w[c];
+      sv[m] = src ? src[c] : 0.0;
+      const int slot = (ty + 4 * m + 1) * W + tx + 1;
+      sph[slot] = phc[m];
+      srh[slot] = rhc[m];
+    }
+    if (hslot >= 0) {
+      sph[hslot] = ph[k * P + hoff];
+      srh[hslot] = rho[k * P + hoff];
+    }
+    __syncthreads();
+    const double dzf = g.dzf[k];
+    const double dzcp = kp >= 0 ? g.dzc[k] : 1.0, dzcm = km >= 0 ? g.dzc[km] : 1.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const long c = k * P + c0[m];
+      const int sl = (ty + 4 * m + 1) * W + tx + 1;
+      const RhsNbr xp{sph[sl + 1], srh[sl + 1], hxp}, xm{sph[sl - 1], srh[sl - 1], hxm};
+      const RhsNbr yp{sph[sl + W], srh[sl + W], hyp[m]}, ym{sph[sl - W], srh[sl - W], hym[m]};
+      const RhsNbr zp{php[m], rhp[m], kp >= 0}, zm{phm[m], rhm[m], km >= 0};
+      const double wc = wcs[m];
+      b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xm, yp, ym, zp, dzcp, zm,
+                      dzcm, dzf, uc[m], um[m], vc[m], vm[m], wc, wm[m], sv[m]);
+      phm[m] = phc[m];
+      phc[m] = php[m];
+      rhm[m] = rhc[m];
+      rhc[m] = rhp[m];
+      wm[m] = wc;
+    }
+    km = k;
+    __syncthreads();  // the tile is rewritten for the next plane
   }
 }
 
@@ -190,6 +335,51 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
   }
 }
 
+// One "+" face of the fused epilogue: the corrected velocity from u* and the
+// jumps of p, p_hat, rho and phi across the face (inv_h = 1/dx, 1/dy, or
+// z_div = true for a division by the centre distance h), and the gradient of
+// phi through *gphi.  Contraction is off inside: every kernel variant gives
+// the same bits.
+__device__ __forceinline__ double epi_face(double un, double dt, double ir0, double pn, double pc,
+                                           double rn, double rc, double hn, double hc, double fn,
+                                           double fc, double hinv, bool z_div, double h,
+                                           double* gphi) {
+#pragma clang fp contract(off)
+  if (z_div) {
+    *gphi = (fn - fc) / h;
+    return un - dt * (ir0 * (pn - pc) / h + (inv_face_rho(rc, rn) - ir0) * (hn - hc) / h);
+  }
+  *gphi = (fn - fc) * hinv;
+  return un - dt * (ir0 * (pn - pc) * hinv + (inv_face_rho(rc, rn) - ir0) * (hn - hc) * hinv);
+}
+
+__device__ __forceinline__ void epi_store(double un, double vn, double wn, double gx, double gy,
+                                          double gz, long c, double* __restrict__ u,
+                                          double* __restrict__ v, double* __restrict__ w,
+                                          const double* __restrict__ qx,
+                                          const double* __restrict__ qy,
+                                          const double* __restrict__ qz, double qxv, double qyv,
+                                          double qzv, bool have_q, double* __restrict__ ue,
+                                          double* __restrict__ ve, double* __restrict__ we,
+                                          double* __restrict__ ug, double* __restrict__ vg,
+                                          double* __restrict__ wg) {
+#pragma clang fp contract(off)
+  u[c] = un;
+  v[c] = vn;
+  w[c] = wn;
+  const double ex = un - gx, ey = vn - gy, ez = wn - gz;
+  if (ue) {
+    ue[c] = ex;
+    ve[c] = ey;
+    we[c] = ez;
+  }
+  if (ug) {
+    ug[c] = ex - (have_q ? qxv : qx[c]);
+    vg[c] = ey - (have_q ? qyv : qy[c]);
+    wg[c] = ez - (have_q ? qzv : qz[c]);
+  }
+}
+
 // One time step's two stencils after the solves, fused: on each of the
 // cell's "+" faces
 //   u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ]  (in place)
@@ -215,13 +405,11 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
     double gx = 0.0, gy = 0.0, gz = 0.0;
     if (t.hxp) {
       const long n = c + t.xp;
-      un -= dt * (ir0 * (p[n] - pc) * idx + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idx);
-      gx = (phi[n] - fc) * idx;
+      un = epi_face(un, dt, ir0, p[n], pc, rho[n], rc, ph[n], hc, phi[n], fc, idx, false, 0.0, &gx);
     }
     if (t.hyp) {
       const long n = c + t.yp;
-      vn -= dt * (ir0 * (p[n] - pc) * idy + (inv_face_rho(rc, rho[n]) - ir0) * (ph[n] - hc) * idy);
-      gy = (phi[n] - fc) * idy;
+      vn = epi_face(vn, dt, ir0, p[n], pc, rho[n], rc, ph[n], hc, phi[n], fc, idy, false, 0.0, &gy);
     }
     double pp = 0.0, hp = 0.0, rp = 0.0, fp = 0.0;
     if (kp >= 0) {
@@ -230,28 +418,130 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
       hp = ph[n];
       rp = rho[n];
       fp = phi[n];
-      const double h = g.dzc[k];
-      wn -= dt * (ir0 * (pp - pc) / h + (inv_face_rho(rc, rp) - ir0) * (hp - hc) / h);
-      gz = (fp - fc) / h;
+      wn = epi_face(wn, dt, ir0, pp, pc, rp, rc, hp, hc, fp, fc, 0.0, true, g.dzc[k], &gz);
     }
-    u[c] = un;
-    v[c] = vn;
-    w[c] = wn;
-    const double ex = un - gx, ey = vn - gy, ez = wn - gz;
-    if (ue) {
-      ue[c] = ex;
-      ve[c] = ey;
-      we[c] = ez;
-    }
-    if (ug) {
-      ug[c] = ex - qx[c];
-      vg[c] = ey - qy[c];
-      wg[c] = ez - qz[c];
-    }
+    epi_store(un, vn, wn, gx, gy, gz, c, u, v, w, qx, qy, qz, 0.0, 0.0, 0.0, false, ue, ve, we, ug,
+              vg, wg);
     pc = pp;
     hc = hp;
     rc = rp;
     fc = fp;
+  }
+}
+
+// The fused epilogue on 64 x TY tiles (nx % 64 == 0, ny % TY == 0), marching
+// g.kc planes: p, p_hat, rho and phi of the current plane, with their +x and
+// +y halo, are staged in LDS once per block and plane, and their +z values
+// (the next plane's centre values) stay in registers, so each of these four
+// fields is read from HBM about once.  All loads of a plane are issued
+// before its barrier.  The per-face arithmetic is k_step_epilogue's.
+template <int TY>
+__global__ __launch_bounds__(256) void k_step_epilogue_tiled(
+    const GridArgs g, double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
+    const double* __restrict__ p, const double* __restrict__ ph, const double* __restrict__ rho,
+    double rho0, double dt, const double* __restrict__ phi, const double* __restrict__ qx,
+    const double* __restrict__ qy, const double* __restrict__ qz, double* __restrict__ ue,
+    double* __restrict__ ve, double* __restrict__ we, double* __restrict__ ug,
+    double* __restrict__ vg, double* __restrict__ wg) {
+  constexpr int TX = 64, W = TX + 1, RPT = TY / 4, AREA = (TY + 1) * W;
+  __shared__ double sm[4 * AREA];  // p, p_hat, rho, phi
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int kb = blockIdx.z * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
+  const int i = i0 + tx;
+  const long P = (long)g.nx * g.ny;
+  const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+  const bool hxp = i + 1 < g.nx || g.bcx == 0;
+  // halo cell h (threads 0 .. TY + TX - 1): column TX of rows 0..TY-1, then
+  // row TY of columns 0..TX-1; wrapped when periodic, clamped (unused) at walls
+  int hslot = -1;
+  long hoff = 0;
+  if ((int)threadIdx.x < TY + TX) {
+    const int h = threadIdx.x;
+    const int r = h < TY ? h : TY, c = h < TY ? TX : h - TY;
+    int gi = i0 + c, gj = j0 + r;
+    if (gi >= g.nx) gi = g.bcx == 0 ? 0 : g.nx - 1;
+    if (gj >= g.ny) gj = g.bcy == 0 ? 0 : g.ny - 1;
+    hslot = r * W + c;
+    hoff = (long)gj * g.nx + gi;
+  }
+  long c0[RPT];
+  bool hyp[RPT];
+  double pc[RPT], hc[RPT], rc[RPT], fc[RPT];
+#pragma unroll
+  for (int m = 0; m < RPT; ++m) {
+    const int j = j0 + ty + 4 * m;
+    c0[m] = (long)j * g.nx + i;
+    hyp[m] = j + 1 < g.ny || g.bcy == 0;
+    const long c = kb * P + c0[m];
+    pc[m] = p[c];
+    hc[m] = ph[c];
+    rc[m] = rho[c];
+    fc[m] = phi[c];
+  }
+  for (int k = kb; k < ke; ++k) {
+    const int kp = kplus(g, k);
+    double pp[RPT], hp[RPT], rp[RPT], fp[RPT], un[RPT], vn[RPT], wn[RPT];
+    double qxv[RPT] = {}, qyv[RPT] = {}, qzv[RPT] = {};
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const long c = k * P + c0[m];
+      pp[m] = hp[m] = rp[m] = fp[m] = 0.0;
+      if (kp >= 0) {
+        const long n = kp * P + c0[m];
+        pp[m] = p[n];
+        hp[m] = ph[n];
+        rp[m] = rho[n];
+        fp[m] = phi[n];
+      }
+      un[m] = u[c];
+      vn[m] = v[c];
+      wn[m] = w[c];
+      if (ug) {
+        qxv[m] = qx[c];
+        qyv[m] = qy[c];
+        qzv[m] = qz[c];
+      }
+      const int sl = (ty + 4 * m) * W + tx;
+      sm[sl] = pc[m];
+      sm[AREA + sl] = hc[m];
+      sm[2 * AREA + sl] = rc[m];
+      sm[3 * AREA + sl] = fc[m];
+    }
+    if (hslot >= 0) {
+      const long n = k * P + hoff;
+      sm[hslot] = p[n];
+      sm[AREA + hslot] = ph[n];
+      sm[2 * AREA + hslot] = rho[n];
+      sm[3 * AREA + hslot] = phi[n];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+      const long c = k * P + c0[m];
+      const int sl = (ty + 4 * m) * W + tx;
+      double gx = 0.0, gy = 0.0, gz = 0.0;
+      if (hxp) {
+        const int n = sl + 1;
+        un[m] = epi_face(un[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
+                         sm[3 * AREA + n], fc[m], idx, false, 0.0, &gx);
+      }
+      if (hyp[m]) {
+        const int n = sl + W;
+        vn[m] = epi_face(vn[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
+                         sm[3 * AREA + n], fc[m], idy, false, 0.0, &gy);
+      }
+      if (kp >= 0)
+        wn[m] = epi_face(wn[m], dt, ir0, pp[m], pc[m], rp[m], rc[m], hp[m], hc[m], fp[m], fc[m], 0.0,
+                         true, g.dzc[k], &gz);
+      epi_store(un[m], vn[m], wn[m], gx, gy, gz, c, u, v, w, qx, qy, qz, qxv[m], qyv[m], qzv[m],
+                true, ue, ve, we, ug, vg, wg);
+      pc[m] = pp[m];
+      hc[m] = hp[m];
+      rc[m] = rp[m];
+      fc[m] = fp[m];
+    }
+    __syncthreads();  // the tile is rewritten for the next plane
   }
 }
 
@@ -362,9 +652,32 @@ int stencil_default_planes(int nx, int ny, int nz) {
   return (int)kc;
 }
 
+// the tiled kernel needs whole 64 x g.tiled tiles (g.tiled = 8 or 16 rows);
+// g.tiled = 0 keeps the plain one
+static bool rhs_tiles_fit(const GridArgs& g) {
+  return (g.tiled == 8 || g.tiled == 16) && g.nx % 64 == 0 && g.ny % g.tiled == 0;
+}
+
+int rhs_blocks(const GridArgs& g) {
+  if (rhs_tiles_fit(g))
+    return (g.nx / 64) * (g.ny / g.tiled) * ((g.nz + g.kc - 1) / g.kc);
+  return stencil_blocks(g);
+}
+
 hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const double* w,
                       const double* phat, const double* rho, double rho0, const double* src,
                       double dt, double* b, hipStream_t st) {
+  if (rhs_tiles_fit(g)) {
+    const dim3 grid((unsigned)(g.nx / 64), (unsigned)(g.ny / g.tiled),
+                    (unsigned)((g.nz + g.kc - 1) / g.kc));
+    if (g.tiled == 16)
+      hipLaunchKernelGGL(k_rhs_tiled<16>, grid, dim3(256), 0, st, g, u, v, w, phat, rho, rho0,
+                         src, dt, b);
+    else
+      hipLaunchKernelGGL(k_rhs_tiled<8>, grid, dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src,
+                         dt, b);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_rhs, tile_grid(g), dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src, dt,
                      b);
   return hipGetLastError();
@@ -395,6 +708,17 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
                                 const double* phi, const double* qx, const double* qy,
                                 const double* qz, double* ue, double* ve, double* we, double* ug,
                                 double* vg, double* wg, hipStream_t st) {
+  if ((g.tiled == 8 || g.tiled == 16) && g.nx % 64 == 0 && g.ny % g.tiled == 0) {
+    const dim3 grid((unsigned)(g.nx / 64), (unsigned)(g.ny / g.tiled),
+                    (unsigned)((g.nz + g.kc - 1) / g.kc));
+    if (g.tiled == 16)
+      hipLaunchKernelGGL(k_step_epilogue_tiled<16>, grid, dim3(256), 0, st, g, u, v, w, p, phat,
+                         rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
+    else
+      hipLaunchKernelGGL(k_step_epilogue_tiled<8>, grid, dim3(256), 0, st, g, u, v, w, p, phat,
+                         rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_step_epilogue, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, p, phat,
                      rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
   return hipGetLastError();

@@ -142,6 +142,32 @@ def test_project_parity(torch_dev, shape, bc, beta):
     assert np.abs(d - (s - g.weighted_mean(s))).max() <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("shape,bc,beta", [((64, 32, 40), "NPN", 1.5), ((128, 64, 24), "PPP", None),
+                                           ((64, 16, 5), "NNN", None), ((256, 16, 9), "PNP", None)])
+def test_rhs_tiled_bit_identical(torch_dev, shape, bc, beta):
+    """The LDS-tiled right-hand side gives the plain kernel's projection bit for
+    bit, for several planes per block, and the oracle's within tolerance."""
+    torch = torch_dev
+    g = _grid(*shape, bc, beta)
+    us, vs, ws, phat, rho, rho0, s, dt, q = _step_inputs(g)
+    T = lambda a: _dev(torch, a)  # noqa: E731
+    plan = _plan(g)
+    outs = {}
+    for tiled in (0, 8, 16):
+        for kc in (1, 3, 8):
+            plan.tune("rhs_tiled", tiled)
+            plan.tune("stencil_planes", min(kc, g.nz))
+            u, v, w, p = plan.project(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt)
+            outs[(tiled, kc)] = [a.cpu().numpy() for a in (u, v, w, p)]
+    base = outs[(0, 1)]
+    for key, val in outs.items():
+        for a, b in zip(val, base):
+            assert np.array_equal(a, b), key
+    ref = oracle.project(us, vs, ws, phat, rho, rho0, s, dt, g)
+    for a, b in zip(base, ref):
+        assert rel_l2(a, b) <= FP64_TOL
+
+
 def test_project_without_source(torch_dev):
     torch = torch_dev
     g = _grid(32, 32, 32, "PPP")
@@ -455,14 +481,17 @@ def test_fused_step_parity(torch_dev, shape, bc, beta):
     # u_1^e is divergence-free (the Stefan source of both solves is the same s)
     dmax = np.abs(oracle.div(ue, ve, we, g)).max()
     assert dmax <= 1e-10 * np.abs(oracle.div(us, vs, ws, g)).max()
-    # marching several planes per block of the streaming stencils (a launch
-    # shape knob) changes no bit of any result
-    plan.tune("stream_planes", 3)
-    out3 = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt, T(s),
-                     q=tuple(T(a) for a in q), out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
-    torch.cuda.synchronize()
-    for a, b in zip(out3, (u, v, w, p, phi, ue, ve, we, ug, vg, wg)):
-        assert np.array_equal(a.cpu().numpy(), b)
+    # the epilogue's launch shapes (plain or LDS-staged tiles, planes per block)
+    # change no bit of any result
+    for tiled, planes in ((0, 1), (0, 3), (8, 1), (8, 5), (16, 2)):
+        plan.tune("epilogue_tiled", tiled)
+        plan.tune("epilogue_planes", min(planes, g.nz))
+        out3 = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt, T(s),
+                         q=tuple(T(a) for a in q),
+                         out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+        torch.cuda.synchronize()
+        for a, b in zip(out3, (u, v, w, p, phi, ue, ve, we, ug, vg, wg)):
+            assert np.array_equal(a.cpu().numpy(), b), (tiled, planes)
 
 
 def test_fused_step_graph_replay(torch_dev):
