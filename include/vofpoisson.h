@@ -223,8 +223,18 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 and y transform passes, 16 (radix-16 passes, default) or 8
  *                 (radix-8 passes: fewer registers and LDS per line, more
  *                 blocks per compute unit);
- *   "z_lines"   : lines per block of the z pass, 8, 16 (default) or 32
- *                 (capped so that lines * segments <= 512);
+ *   "z_lines"   : lines per block of the tridiagonal z pass, 8, 16 (default)
+ *                 or 32 (capped so that lines * segments <= 512);
+ *   "z_spectral": 1 (default where possible) solves a uniform z grid with nz a
+ *                 power of two in [8, 1024] by a real DFT (periodic) or DCT-II
+ *                 (walls) along z, a division by the 3-D eigenvalue and the
+ *                 inverse transform, in one pass; 0 uses the tridiagonal pass
+ *                 (VP_EUNSUPPORTED for 1 on other grids);
+ *   "z_radix"   : values per thread of the spectral z pass, 16 or 8;
+ *   "y_lines", "z_spectral_lines" : column pairs per block of the y passes
+ *                 and of the spectral z pass (a power of two up to 256; 0, the
+ *                 default: 256 threads' worth at radix 16; narrower tiles use
+ *                 less LDS, so more blocks fit on a compute unit);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
  *                 and residual kernels (1..nz; default chosen for ~16k blocks);
  *   "stream_planes" : z-planes marched by one block of the correction and
@@ -249,9 +259,13 @@ int poisson_plan_get_tuning(poisson_plan* plan, const char* key, int* value);
  * workspace (which it overwrites) for a batch of nb fields, on hip_stream
  * (synchronising it), median of 5 runs each, one knob after another (x
  * radix, y radix, z lines, stencil planes; the last only when the
- * workspace holds a second field: mixed plans or max_batch >= 2), and
- * leaves each at its fastest value.  chosen (may be NULL) receives the four
- * values in that order.  Not for use while other calls on the plan run.
+ * workspace holds a second field: mixed plans or max_batch >= 2), then,
+ * where the spectral z pass applies, the fastest of the tuned tridiagonal
+ * pass and the spectral pass at either radix and three tile widths (the y
+ * tile width is tuned after the y radix); it leaves each at its fastest
+ * value.  chosen (may be NULL) receives eight values: x_radix, y_radix,
+ * z_lines, stencil_planes, z_spectral, z_radix, y_lines, z_spectral_lines.
+ * Not for use while other calls on the plan run.
  */
 int poisson_plan_autotune(poisson_plan* plan, int nb, void* hip_stream, int* chosen);
 

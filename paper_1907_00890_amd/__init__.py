@@ -216,9 +216,10 @@ class Plan:
               "poisson_plan_last_mean")
         return out.value
 
-    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "stream_planes",
-                   "rhs_tiled", "epilogue_tiled", "epilogue_planes")
-    AUTOTUNED_KEYS = TUNING_KEYS[:4]
+    TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "z_spectral", "z_radix",
+                   "y_lines", "z_spectral_lines", "stream_planes", "rhs_tiled", "epilogue_tiled",
+                   "epilogue_planes")
+    AUTOTUNED_KEYS = TUNING_KEYS[:8]
 
     def tune(self, key: str, value: int):
         """Launch-shape knob (see poisson_plan_tune); results do not change."""
@@ -237,7 +238,7 @@ class Plan:
     def autotune(self, batch: int = 1, stream=None) -> dict:
         """Time every candidate of each tuning key on this plan's workspace and keep
         the fastest (see poisson_plan_autotune); returns the chosen values."""
-        chosen = (ctypes.c_int * 4)()
+        chosen = (ctypes.c_int * 8)()
         check(_lib.lib.poisson_plan_autotune(self._h, int(batch), _stream_ptr(stream), chosen),
               "poisson_plan_autotune")
         return dict(zip(self.AUTOTUNED_KEYS, list(chosen)))

@@ -43,12 +43,14 @@ int ypass_tile_cols(int nx, int ny);
 //   skip  : per-member flags; a member whose flag is set is left untouched
 //           (its blocks return at once); null: every member runs;
 //   norms : x inverse writes per-block sums of e^2 and p^2 (see k_xinv);
-//   nzm   : z-planes per member (y passes: member = plane / nzm).
+//   nzm   : z-planes per member (y passes: member = plane / nzm);
+//   lines : y passes: column pairs per block (a power of two; 0: default).
 struct PassOpts {
   const double* sub = nullptr;
   const int* skip = nullptr;
   double* norms = nullptr;
   int nzm = 0;
+  int lines = 0;
 };
 
 // x passes: `in`/`out` hold nb caller fields; the spectra of batch member b
@@ -71,9 +73,29 @@ hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& o
 long xpass_blocks(int nx, int pt, long nrows);
 // y passes over nplanes consecutive z-planes (nz * batch)
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const double* tab, int pt, hipStream_t st);
+                        const double* tab, int pt, int lines, hipStream_t st);
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const float* tab, int pt, const PassOpts& o, hipStream_t st);
+
+// spectral z pass for a uniform z grid with nz a power of two in [8, 1024]:
+// forward real DFT / DCT-II along z, division by the 3-D eigenvalue, inverse,
+// in one pass (transforms.hip)
+struct ZSpecArgs {
+  int nx, ny, nz;
+  int lx;              // log2(nx)
+  int bcz;
+  double scale;        // 1 / (nx * ny * nz)
+  const double* lamx;  // eigenvalue per packed x, y, z position
+  const double* lamy;
+  const double* lamz;
+  long batch_stride;
+  double* mean_out;    // removed mean of member b at [b], may be null
+  int lines;           // column pairs per block (a power of two; 0: the y pass's width)
+};
+hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
+                            hipStream_t st);
+hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, int pt, int nb,
+                            const int* skip, hipStream_t st);
 
 // zsolve.hip -----------------------------------------------------------------
 struct ZArgs {

@@ -85,6 +85,7 @@ struct poisson_plan {
   int bc[3] = {0, 0, 0};
   int precision = 0, max_batch = 1, dc_steps = 1;
   int x_pt = 16, y_pt = 16;  // radix schedules of the x and y passes (tuning knobs)
+  int y_lines = 0;           // column pairs per y block (0: the default width)
   double dx = 0, dy = 0, dz_sum = 0;
   int device = 0;
   long long bytes = 0;
@@ -93,6 +94,11 @@ struct poisson_plan {
   double *tabx64 = nullptr, *taby64 = nullptr;
   float *tabx32 = nullptr, *taby32 = nullptr;
   double *lamx = nullptr, *lamy = nullptr, *za = nullptr, *zc = nullptr;
+  // spectral z pass (uniform z, nz a power of two in [8, 1024])
+  double *lamz = nullptr, *tabz64 = nullptr;
+  float* tabz32 = nullptr;
+  vp::ZSpecArgs zs{};
+  int z_spec_ok = 0, z_spec = 0, z_pt = 16;
   double *dzf = nullptr, *dzc = nullptr, *mean = nullptr;
   double* work64 = nullptr;
   float* work32 = nullptr;
@@ -265,6 +271,32 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.mean_out = P->mean;
   Z.batch_stride = P->npts();
 
+  // a uniform z line of a transform length is diagonalised exactly by the
+  // real DFT (periodic) or DCT-II (walls) of the x and y passes
+  P->z_spec_ok = Z.uniform_z && nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0;
+  if (P->z_spec_ok) {
+    const std::vector<double> tz = make_table(nz);
+    if ((st = P->upload(&P->tabz64, tz, "table z"))) return st;
+    if (P->precision == VP_PRECISION_MIXED) {
+      std::vector<float> fz(tz.begin(), tz.end());
+      if ((st = P->upload(&P->tabz32, fz, "table z f32"))) return st;
+    }
+    if ((st = P->upload(&P->lamz, make_lambda(nz, f[0], P->bc[2]), "lambda z"))) return st;
+    vp::ZSpecArgs& A = P->zs;
+    A.nx = nx;
+    A.ny = ny;
+    A.nz = nz;
+    A.lx = Z.lx;
+    A.bcz = P->bc[2];
+    A.scale = 1.0 / ((double)nx * (double)ny * (double)nz);
+    A.lamx = P->lamx;
+    A.lamy = P->lamy;
+    A.lamz = P->lamz;
+    A.batch_stride = P->npts();
+    A.mean_out = P->mean;
+    P->z_spec = 1;
+  }
+
   vp::GridArgs& G = P->g;
   G.nx = nx; G.ny = ny; G.nz = nz;
   G.lx = 0;
@@ -295,9 +327,12 @@ int solve_f64(poisson_plan* P, int nb, const double* const* rhs, double* const* 
   const vp::Batch<const double> in = vp::batch_of(rhs, nb);
   const vp::Batch<double> out = vp::batch_of(sol, nb);
   VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, st), "x forward", st);
-  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, P->y_pt, st), "y forward", st);
-  VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, nb, st), "z solve", st);
-  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, P->y_pt, st), "y inverse", st);
+  VP_LAUNCH(P, K_YFWD, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, P->y_pt, P->y_lines, st), "y forward", st);
+  if (P->z_spec)
+    VP_LAUNCH(P, K_Z, vp::launch_zspec_f64(w, P->zs, P->tabz64, P->z_pt, nb, st), "z spectral", st);
+  else
+    VP_LAUNCH(P, K_Z, vp::launch_zsolve_f64(w, P->z, nb, st), "z solve", st);
+  VP_LAUNCH(P, K_YINV, vp::launch_y_f64(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, P->y_pt, P->y_lines, st), "y inverse", st);
   VP_LAUNCH(P, K_XINV, vp::launch_xinv_f64(w, N, out, nb, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, st), "x inverse", st);
   return VP_OK;
 }
@@ -317,12 +352,17 @@ int solve_f32(poisson_plan* P, int nb, const double* const* rhs, double* const* 
   vp::PassOpts fo = o, io = o;
   fo.norms = nullptr;
   io.sub = asub;
-  vp::PassOpts mo = o;  // y passes: flags only
+  vp::PassOpts mo = o;  // y passes: flags and tile width only
   mo.sub = nullptr;
   mo.norms = nullptr;
+  mo.lines = P->y_lines;
   VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx32, P->x_pt, fo, st), "x forward f32", st);
   VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby32, P->y_pt, mo, st), "y forward f32", st);
-  VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, z, nb, st), "z solve f32", st);
+  if (P->z_spec)
+    VP_LAUNCH(P, K_Z32, vp::launch_zspec_f32(w, P->zs, P->tabz32, P->z_pt, nb, o.skip, st),
+              "z spectral f32", st);
+  else
+    VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, z, nb, st), "z solve f32", st);
   VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby32, P->y_pt, mo, st), "y inverse f32", st);
   VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, ob, nb, P->nx, P->bc[0], nrows, accum, P->tabx32, P->x_pt, io, st),
             "x inverse f32", st);
@@ -604,6 +644,27 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     (k == "x_radix" ? P->x_pt : P->y_pt) = value;
     return VP_OK;
   }
+  if (k == "z_spectral") {
+    if (value != 0 && value != 1) return VP_EINVAL;
+    if (value == 1 && !P->z_spec_ok) return VP_EUNSUPPORTED;
+    P->z_spec = value;
+    return VP_OK;
+  }
+  if (k == "z_radix") {
+    if (value != 8 && value != 16) return VP_EINVAL;
+    P->z_pt = value;
+    return VP_OK;
+  }
+  if (k == "y_lines") {
+    if (value < 0 || value > 256 || (value & (value - 1))) return VP_EINVAL;
+    P->y_lines = value;
+    return VP_OK;
+  }
+  if (k == "z_spectral_lines") {
+    if (value < 0 || value > 256 || (value & (value - 1))) return VP_EINVAL;
+    P->zs.lines = value;
+    return VP_OK;
+  }
   if (k == "rhs_tiled") {
     if (value != 0 && value != 8 && value != 16) return VP_EINVAL;
     P->g.tiled = value;
@@ -711,7 +772,7 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
   }
   const vp::Batch<const double> bin = vp::batch_of(in64, nb);
   const vp::Batch<double> bout = vp::batch_of(out64, nb);
-  int res[4] = {P->x_pt, P->y_pt, P->z.lines, P->g.kc};
+  int res[8] = {P->x_pt, P->y_pt, P->z.lines, P->g.kc, P->z_spec, P->z_pt, P->y_lines, P->zs.lines};
   int s;
   auto hs = [](hipError_t e) { return e == hipSuccess ? VP_OK : hip_fail(e, "tune launch"); };
   // x passes: forward + inverse
@@ -731,25 +792,57 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
                                   P->x_pt, st));
   }, &res[0]);
   if (s) return s;
-  // y passes: forward + inverse
-  s = pick(st, &P->y_pt, {16, 8}, [&]() -> int {
+  // y passes: forward + inverse, radix then tile width
+  auto ypair = [&]() -> int {
+    vp::PassOpts yo{};
+    yo.lines = P->y_lines;
     for (int fwd = 1; fwd >= 0; --fwd) {
       const int e = mixed ? hs(vp::launch_y_f32(P->work32, P->nx, P->ny, P->nz * nb, P->bc[1],
-                                                fwd != 0, P->taby32, P->y_pt, vp::PassOpts{}, st))
+                                                fwd != 0, P->taby32, P->y_pt, yo, st))
                           : hs(vp::launch_y_f64(P->work64, P->nx, P->ny, P->nz * nb, P->bc[1],
-                                                fwd != 0, P->taby64, P->y_pt, st));
+                                                fwd != 0, P->taby64, P->y_pt, P->y_lines, st));
       if (e) return e;
     }
     return VP_OK;
-  }, &res[1]);
+  };
+  s = pick(st, &P->y_pt, {16, 8}, ypair, &res[1]);
   if (s) return s;
-  // z pass: lines per block
+  s = pick(st, &P->y_lines, {0, 8, 4}, ypair, nullptr);
+  if (s) return s;
+  // z pass: lines per block of the tridiagonal solve, then (uniform z) the
+  // spectral pass's radix against the best tridiagonal time
   if (P->nz > 1) {
-    s = pick(st, &P->z.lines, {8, 16, 32}, [&]() -> int {
+    const int spec = P->z_spec;
+    P->z_spec = 0;
+    auto zpass = [&]() -> int {
+      if (P->z_spec)
+        return mixed ? hs(vp::launch_zspec_f32(P->work32, P->zs, P->tabz32, P->z_pt, nb, nullptr, st))
+                     : hs(vp::launch_zspec_f64(P->work64, P->zs, P->tabz64, P->z_pt, nb, st));
       return mixed ? hs(vp::launch_zsolve_f32(P->work32, P->z, nb, st))
                    : hs(vp::launch_zsolve_f64(P->work64, P->z, nb, st));
-    }, &res[2]);
+    };
+    s = pick(st, &P->z.lines, {8, 16, 32}, zpass, &res[2]);
     if (s) return s;
+    if (P->z_spec_ok) {
+      // codes: 0 = tridiagonal (tuned lines), else spectral: radix * 1000 +
+      // column pairs per block (0: default width)
+      int mode = 0;
+      auto apply = [&](int m) {
+        P->z_spec = m != 0;
+        if (m) {
+          P->z_pt = m / 1000;
+          P->zs.lines = m % 1000;
+        }
+      };
+      s = pick(st, &mode, {0, 16000, 16008, 16004, 8000, 8008, 8004}, [&]() -> int {
+        apply(mode);
+        return zpass();
+      }, nullptr);
+      if (s) return s;
+      apply(mode);
+    } else {
+      P->z_spec = spec;
+    }
   }
   // marching stencils: planes per block of the right-hand-side kernel, when
   // the workspace has a second field to write to
@@ -769,8 +862,12 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
     }, &res[3]);
     if (s) return s;
   }
+  res[4] = P->z_spec;
+  res[5] = P->z_pt;
+  res[6] = P->y_lines;
+  res[7] = P->zs.lines;
   if (chosen)
-    for (int i = 0; i < 4; ++i) chosen[i] = res[i];
+    for (int i = 0; i < 8; ++i) chosen[i] = res[i];
   return VP_OK;
 }
 
@@ -783,6 +880,10 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "stencil_planes") *value = P->g.kc;
   else if (k == "stream_planes") *value = P->gs.kc;
   else if (k == "rhs_tiled") *value = P->g.tiled;
+  else if (k == "z_spectral") *value = P->z_spec;
+  else if (k == "z_radix") *value = P->z_pt;
+  else if (k == "z_spectral_lines") *value = P->zs.lines;
+  else if (k == "y_lines") *value = P->y_lines;
   else if (k == "epilogue_tiled") *value = P->ge.tiled;
   else if (k == "epilogue_planes") *value = P->ge.kc;
   else return VP_EINVAL;

@@ -213,6 +213,94 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// forward transform, per-coefficient scaling, inverse transform of two real
+// lines held in LDS, in one pass: `load(e, re, im)` gives element e of lines
+// a and b; `scale(c, a, b)` rescales the packed coefficient c of both lines
+// in place; `store(e, re, im)` writes element e.  Between the two transforms
+// a thread reads and writes only the LDS positions of its own modes m and
+// N - m (and N/2 for m = 0), so no barrier is needed there.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int BC, int PTM, typename L, typename Load, typename Scale,
+          typename Store>
+__device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict__ tab, Load load,
+                                              Scale scale, Store store) {
+  using S = FftShape<N, PTM>;
+  constexpr int PT = S::PT, TPL = S::TPL;
+  constexpr int R1 = PassRadix<N, 1, PTM>::R;
+  T vr[PT], vi[PT];
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    int e = t + r * TPL;
+    if constexpr (BC == BC_N) e = dct_perm<N>(e);
+    load(e, vr[r], vi[r]);
+  }
+  {
+    T wr[PT], wi[PT];
+    pass_compute<T, N, 1, -1, PTM>(vr, vi, wr, wi);
+  }
+#pragma unroll
+  for (int b = 0; b < PT / R1; ++b)
+#pragma unroll
+    for (int r = 0; r < R1; ++r)
+      lds.put(pass_out<N, 1, PTM>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
+  later_passes<T, N, R1, -1, false, PTM>(lds, t, tab, vr, vi);
+  __syncthreads();
+  const T* pc = tab + 2 * N;
+  const T* ps = tab + 2 * N + (N / 2 + 1);
+#pragma unroll
+  for (int u = 0; u < PT / 2; ++u) {
+    const int m = t + TPL * u;
+    T zr, zi;
+    lds.get(m, zr, zi);
+    if (m == 0) {
+      T hr, hi;
+      lds.get(N / 2, hr, hi);
+      // packed coefficients 0 and 1 (periodic) or 0 and N/2 (walls)
+      T a0 = zr, b0 = zi, a1 = hr, b1 = hi;
+      int c1 = 1;
+      if constexpr (BC == BC_N) {
+        const T h = T(0.70710678118654752440084436210485);
+        a1 *= h;
+        b1 *= h;
+        c1 = N / 2;
+      }
+      scale(0, a0, b0);
+      scale(c1, a1, b1);
+      if constexpr (BC == BC_N) {
+        const T r2 = T(1.4142135623730950488016887242097);
+        a1 *= r2;
+        b1 *= r2;
+      }
+      lds.put(0, a0, b0);
+      lds.put(N / 2, a1, b1);
+    } else {
+      T wr, wi;
+      lds.get(N - m, wr, wi);
+      T oa[2], ob[2];
+      RealPair<T, N, BC>::post(zr, zi, wr, wi, pc[m], ps[m], oa, ob);
+      const int c0 = BC == BC_P ? 2 * m : m, c1 = BC == BC_P ? 2 * m + 1 : N - m;
+      scale(c0, oa[0], ob[0]);
+      scale(c1, oa[1], ob[1]);
+      T z0r, z0i, z1r, z1i;
+      RealPair<T, N, BC>::pre(oa, ob, pc[m], ps[m], z0r, z0i, z1r, z1i);
+      lds.put(m, z0r, z0i);
+      lds.put(N - m, z1r, z1i);
+    }
+  }
+  later_passes<T, N, 1, +1, true, PTM>(lds, t, tab, vr, vi);
+  constexpr int NSL = last_ns<N, PTM>();
+  constexpr int RL = PassRadix<N, NSL, PTM>::R;
+#pragma unroll
+  for (int b = 0; b < PT / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int e = pass_out<N, NSL, PTM>(t, b, r);
+      if constexpr (BC == BC_N) e = dct_perm<N>(e);
+      store(e, vr[b * RL + r], vi[b * RL + r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x kernels: a block owns 2*LPB consecutive rows (nrows is even)
 // ---------------------------------------------------------------------------
 // SUB: member b's input is read as in[b] - sub[b] (FP64, before any
@@ -400,6 +488,57 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(T* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// spectral z pass (uniform z): block (tile, member); tile = 2*lines
+// consecutive (kx, ky) positions of the plane, each a z-line of N values
+// `plane` apart.  Per packed z coefficient c of line (kx, ky):
+//   x <- x * scale / (lamx[kx] + lamy[ky] + lamz[c]),  0 where that is 0
+// (only the constant mode), which is the pseudo-inverse; the removed
+// constant (the coefficient times scale: the mean) goes to mean_out[member].
+// ---------------------------------------------------------------------------
+template <typename T, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
+    T* __restrict__ data, int nx, int lx, long plane, int llines, const T* __restrict__ tab,
+    const double* __restrict__ lamx, const double* __restrict__ lamy,
+    const double* __restrict__ lamz, double scale, long batch_stride,
+    double* __restrict__ mean_out, const int* __restrict__ skip) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
+  const int lines = 1 << llines;
+  const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
+  const long pos = (long)blockIdx.x * 2 * lines + 2 * q;  // line a; line b = pos + 1
+  T2* col = reinterpret_cast<T2*>(data + blockIdx.y * batch_stride + pos);
+  const long pstride = plane >> 1;  // z stride in T2 units
+  const double la = lamx[pos & (nx - 1)] + lamy[pos >> lx];
+  const double lb = lamx[(pos + 1) & (nx - 1)] + lamy[(pos + 1) >> lx];
+  YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
+  spectral_body<T, N, BC, PTM>(
+      lds, t, tab,
+      [&](int e, T& r, T& i) {
+        const T2 v = col[(long)e * pstride];
+        r = v.x;
+        i = v.y;
+      },
+      [&](int c, T& a, T& b) {
+        const double lz = lamz[c];
+        const double da = la + lz, db = lb + lz;
+        if (da == 0.0) {
+          if (mean_out && c == 0) mean_out[blockIdx.y] = double(a) * scale;
+          a = T(0);
+        } else {
+          a = T(double(a) * (scale / da));
+        }
+        b = T(double(b) * (scale / db));
+      },
+      [&](int e, T r, T i) {
+        T2 v;
+        v.x = r;
+        v.y = i;
+        col[(long)e * pstride] = v;
+      });
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 #define VP_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
@@ -496,7 +635,8 @@ template <typename T, int BC, bool FWD, int PTM>
 static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
                               const PassOpts& o, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
-  const int lines = ypass_lines(nx, ny);
+  int lines = ypass_lines(nx, ny);
+  if (o.lines > 0 && o.lines < lines) lines = o.lines;
   int ll = 0;
   while ((1 << ll) < lines) ++ll;
   const long plane = (long)nx * ny;
@@ -528,6 +668,59 @@ static hipError_t launch_y_bc(T* data, int nx, int ny, int nplanes, const T* tab
                               const PassOpts& o, hipStream_t st) {
   return pt == 8 ? launch_y_pt<T, BC, FWD, 8>(data, nx, ny, nplanes, tab, o, st)
                  : launch_y_pt<T, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
+}
+
+template <typename T, int BC, int PTM>
+static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int nb,
+                                  const int* skip, hipStream_t st) {
+  using T2 = typename Vec2<T>::type;
+  const long plane = (long)a.nx * a.ny;
+  // tile width: as for the y pass of a line of the same length, or a.lines
+  int lines = a.nz >= 16 ? 256 / (a.nz / 16) : 256;
+  if (a.lines > 0 && a.lines < lines) lines = a.lines;
+  if (lines > plane / 2) lines = (int)(plane / 2);
+  int ll = 0;
+  while ((1 << ll) < lines) ++ll;
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(plane / (2 * lines)), (unsigned)nb);
+#define VP_ZS(NN)                                                                          \
+  case NN: {                                                                               \
+    const int nthr = lines * FftShape<NN, PTM>::TPL;                                       \
+    const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);                   \
+    auto kern = &k_zspec<T, NN, BC, PTM>;                                                  \
+    if (shm > 65536) {                                                                     \
+      const hipError_t e = allow_large_lds(kern);                                          \
+      if (e != hipSuccess) return e;                                                       \
+    }                                                                                      \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, a.nx, a.lx, plane, ll, tab,  \
+                       a.lamx, a.lamy, a.lamz, a.scale, a.batch_stride, a.mean_out, skip); \
+    break;                                                                                 \
+  }
+  switch (a.nz) {
+    VP_SIZES(VP_ZS)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_ZS
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_zspec_t(T* data, const ZSpecArgs& a, const T* tab, int pt, int nb,
+                                 const int* skip, hipStream_t st) {
+  if (a.bcz == BC_P)
+    return pt == 8 ? launch_zspec_pt<T, BC_P, 8>(data, a, tab, nb, skip, st)
+                   : launch_zspec_pt<T, BC_P, 16>(data, a, tab, nb, skip, st);
+  return pt == 8 ? launch_zspec_pt<T, BC_N, 8>(data, a, tab, nb, skip, st)
+                 : launch_zspec_pt<T, BC_N, 16>(data, a, tab, nb, skip, st);
+}
+
+hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
+                            hipStream_t st) {
+  return launch_zspec_t<double>(data, a, tab, pt, nb, nullptr, st);
+}
+hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, int pt, int nb,
+                            const int* skip, hipStream_t st) {
+  return launch_zspec_t<float>(data, a, tab, pt, nb, skip, st);
 }
 
 hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
@@ -575,8 +768,9 @@ hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& o
                                                             pt, o, st);
 }
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const double* tab, int pt, hipStream_t st) {
-  const PassOpts o{};
+                        const double* tab, int pt, int lines, hipStream_t st) {
+  PassOpts o{};
+  o.lines = lines;
   if (bc == BC_P)
     return fwd ? launch_y_bc<double, BC_P, true>(data, nx, ny, nplanes, tab, pt, o, st)
                : launch_y_bc<double, BC_P, false>(data, nx, ny, nplanes, tab, pt, o, st);

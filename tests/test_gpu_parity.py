@@ -272,6 +272,10 @@ def test_radix8_schedule_parity(torch_dev, case):
     p8 = plan.solve(_dev(torch, f)).cpu().numpy()
     assert rel_l2(p8, ref) <= FP64_TOL
     assert rel_l2(p8, p16) <= 1e-13
+    # narrower y tiles move the same data through the same passes
+    plan.tune("y_lines", 4)
+    assert np.array_equal(plan.solve(_dev(torch, f)).cpu().numpy(), p8)
+    plan.tune("y_lines", 0)
     mixed = _plan(g, precision="mixed")
     mixed.tune("x_radix", 8)
     mixed.tune("y_radix", 8)
@@ -306,6 +310,45 @@ def test_mixed_stops_on_error_estimate(torch_dev, case):
     assert s1 == 1
     err1 = rel_l2(p1, ref)
     assert err1 <= 10 * e1 + FP64_TOL
+
+
+@pytest.mark.parametrize("case", [(32, 32, 32, "PPP", None), (128, 128, 128, "PPN", None),
+                                  (16, 8, 16, "NNN", None), (8, 8, 1024, "PPP", None),
+                                  (64, 16, 8, "NPP", None), (16, 64, 512, "PNN", None)],
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
+def test_z_spectral_matches_tridiagonal(torch_dev, case):
+    """Uniform z: the spectral z pass (both radix schedules) and the tridiagonal
+    pass agree to rounding, match the oracle, and remove the same mean."""
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 31 + nz)  # non-zero mean on purpose
+    ref = oracle.solve(f, g)
+    plan = _plan(g)
+    assert plan.tuning()["z_spectral"] == 1
+    got = {}
+    for spec, radix, lines in ((0, 16, 0), (1, 16, 0), (1, 8, 0), (1, 8, 8), (1, 16, 4)):
+        plan.tune("z_spectral", spec)
+        plan.tune("z_radix", radix)
+        plan.tune("z_spectral_lines", lines)
+        got[(spec, radix, lines)] = (plan.solve(_dev(torch, f)).cpu().numpy(), plan.last_mean())
+    tri, tri_mean = got[(0, 16, 0)]
+    for key, (p, mean) in got.items():
+        assert rel_l2(p, ref) <= FP64_TOL, key
+        assert rel_l2(p, tri) <= 1e-13, key
+        assert abs(mean - tri_mean) <= 1e-14 * max(1.0, abs(tri_mean)), key
+    mixed = _plan(g, precision="mixed")
+    pm = mixed.solve(_dev(torch, f)).cpu().numpy()
+    assert rel_l2(pm, ref) <= MIXED_TOL
+
+
+def test_z_spectral_refused_on_stretched_grid(torch_dev):
+    from paper_1907_00890_amd import VofPoissonError
+    g = _grid(32, 32, 32, "PPN", 1.5)
+    plan = _plan(g)
+    assert plan.tuning()["z_spectral"] == 0
+    with pytest.raises(VofPoissonError):
+        plan.tune("z_spectral", 1)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
