@@ -69,6 +69,8 @@ def parse():
                     help="comma-separated request rates (req/s) of the serving mix; "
                          "'sweep' for 50,100,200,500,1000,2000; 'none' to skip")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 512x512x256 stretched step and the 512^3 mixed-vs-FP64 runs")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,6 +277,98 @@ def serve_bench(torch, dev, rates, n, lanes, max_batch):
                  "failed": st["failed"], "rejected": st["rejected"]}
 
 
+def stretched_step_run(torch, dev, steps, no_autotune):
+    """The 512x512x256 PPN tanh-stretched workload: `steps` time steps (two
+    solves each, stencils in the loop) and a bare solve; the z pass is the
+    partitioned tridiagonal solve (stretched z)."""
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+    cfg = vofsynth.config("ppn512s")
+    X = make_inputs(cfg, torch, dev)
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc)
+    tuned = plan.autotune(batch=1) if not no_autotune else plan.tuning()
+    p = torch.empty(cfg.shape, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(p)
+    ue = tuple(torch.empty_like(p) for _ in range(3))
+    ug = tuple(torch.empty_like(p) for _ in range(3))
+    q = (X["qx"], X["qy"], X["qz"])
+
+    def step():
+        plan.step(X["u"], X["v"], X["w"], X["phat"], X["rho"], X["rho0"], X["s"], X["dt"],
+                  X["s"], p=p, phi=phi, q=q, out=ue, gamma=ug)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / steps
+    plan.kernel_times()
+    plan.set_profiling(True)
+    out = torch.empty_like(p)
+    for _ in range(5):
+        plan.solve(X["f"], out)
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    n = cfg.npts
+    solve_ms = sum(ms for ms, _ in kt.values()) / 5
+    z = kt.get("z_solve", (0.0, 1))
+    res = {"workload": "ppn512s: 512x512x256 PPN, tanh beta=1.5 z, project + extend step",
+           "steps": steps, "ms_per_step": round(ms_step, 4),
+           "mpts_s": round(2 * n / (ms_step * 1e-3) / 1e6, 1),
+           "solve_ms": round(solve_ms, 4), "solve_model_gbs_80N": round(80 * n / (solve_ms * 1e-3) / 1e9, 1),
+           "z_tridiagonal_ms": round(z[0] / z[1], 4), "tuning": tuned}
+    del X, plan
+    torch.cuda.empty_cache()
+    return res
+
+
+def mixed512_run(torch, dev, reps, no_autotune):
+    """512^3 PPP, seeded N(0,1) RHS with its mean removed: FP64 against mixed
+    (FP32 chain + FP64 defect correction with the device-side stopping rule)."""
+    import numpy as np
+
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+    cfg = vofsynth.config("ppp512")
+    f = torch.from_numpy(np.ascontiguousarray(vofsynth.remove_weighted_mean(
+        vofsynth.gaussian_field(cfg.shape, 4), cfg.dzf()))).to(dev)
+    out = {}
+    res = {"workload": "ppp512: 512^3 triply periodic, uniform"}
+    for prec in ("fp64", "mixed"):
+        plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc, precision=prec)
+        if not no_autotune:
+            plan.autotune(batch=1)
+        o = torch.empty_like(f)
+        for _ in range(2):
+            plan.solve(f, o)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            plan.solve(f, o)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        res[prec] = {"ms": round(ms, 4), "mpts_s": round(cfg.npts / (ms * 1e-3) / 1e6, 1)}
+        if prec == "mixed":
+            (steps, est), = plan.mixed_report()
+            res[prec].update({"dc_steps": steps, "dc_error_estimate": est})
+        out[prec] = o
+        del plan
+    res["mixed"]["rel_l2_vs_fp64"] = (torch.linalg.vector_norm(out["mixed"] - out["fp64"]) /
+                                      torch.linalg.vector_norm(out["fp64"])).item()
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+    del out, f
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(sample_name):
     """Time the FP64 oracle's project + extend step on a bounded sample."""
     import numpy as np
@@ -466,6 +560,9 @@ def main():
         "kernel_ms_per_step": round(kern_ms_step, 4),
         "wall_s_timed": round(t_wall, 3),
     }
+    if not args.no_extra:
+        line["stretched_512x512x256"] = stretched_step_run(torch, dev, 20, args.no_autotune)
+        line["mixed_vs_fp64_512"] = mixed512_run(torch, dev, 5, args.no_autotune)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:

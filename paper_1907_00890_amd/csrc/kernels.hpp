@@ -103,7 +103,7 @@ struct ZArgs {
   int nx;              // for the (cx, cy) split of a line index (a power of two)
   int lx;              // log2(nx)
   int nz;
-  int seg;             // segment length bound M (16)
+  int seg;             // segment length bound M (16; 8 on stretched grids with nz <= 512)
   int lines;           // lines per block (8, 16 or 32; capped so lines * nseg <= 512)
   int nseg;            // S segments per line
   int seg_base;        // nz / S

@@ -171,6 +171,16 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   double* R1 = rho + nr * LB;
   double* R2 = R1 + nr * LB;
   double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line), then the twisted exchange
+  // stretched z: the row coefficients, shared by every line, staged once
+  double* cza = red + (S > 6 ? S : 6) * LB;
+  double* czc = cza + A.nz;
+  if (!UZ) {
+    for (int k = threadIdx.x; k < A.nz; k += blockDim.x) {
+      cza[k] = A.za[k];
+      czc[k] = A.zc[k];
+    }
+    __syncthreads();
+  }
 
   if (A.skip && A.skip[blockIdx.y]) return;  // member already converged (whole block)
   const int l = threadIdx.x % LB, s = threadIdx.x / LB;
@@ -303,8 +313,8 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
           a = A.hz2;
           c = A.hz2;
         } else {
-          a = A.za[k0 + i];
-          c = A.zc[k0 + i];
+          a = cza[k0 + i];
+          c = czc[k0 + i];
         }
         const double sig = ell + a * ratio;
         const double iu = rcp64(c + sig);
@@ -362,10 +372,10 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
         aE = A.hz2;
         cE = k1 == A.nz - 1 ? 0.0 : A.hz2;
       } else {
-        a0 = A.za[k0];
-        c0 = A.zc[k0];
-        aE = A.za[k1];
-        cE = A.zc[k1];
+        a0 = cza[k0];
+        c0 = czc[k0];
+        aE = cza[k1];
+        cE = czc[k1];
       }
       lo[oF] = a0;
       up[oF] = c0 * g1;
@@ -432,11 +442,12 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
 template <typename T, int LB, bool US, bool UZ>
 static hipError_t launch_z_shape(T* data, const ZArgs& a, int nb, hipStream_t st) {
   const int nr = 2 * a.nseg;
-  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)(a.nseg > 6 ? a.nseg : 6) * LB);
+  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)(a.nseg > 6 ? a.nseg : 6) * LB +
+                                        (UZ ? 0 : 2 * (size_t)a.nz));
   const dim3 grid((unsigned)((a.plane + LB - 1) / LB), (unsigned)nb);
   const dim3 block((unsigned)(LB * a.nseg));
-  if (a.seg != 16 || LB * a.nseg > 512) return hipErrorInvalidValue;
-  auto kern = &k_zsolve<T, 16, LB, US, UZ>;
+  if ((a.seg != 16 && a.seg != 8) || LB * a.nseg > 512) return hipErrorInvalidValue;
+  auto kern = a.seg == 8 ? &k_zsolve<T, 8, LB, US, UZ> : &k_zsolve<T, 16, LB, US, UZ>;
   if (shm > 65536 && allow_large_lds(kern) != hipSuccess) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, grid, block, shm, st, data, a);
   return hipGetLastError();

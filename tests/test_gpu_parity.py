@@ -492,6 +492,29 @@ def test_full_size_residual(torch_dev, name):
     assert rel <= 1e-10 and gauge <= 1e-12
 
 
+def test_full_size_mixed_512(torch_dev):
+    """512^3 triply periodic, seeded N(0,1) RHS (mean removed): the FP64 solve
+    satisfies the discrete equation, and the mixed solve (FP32 chain, FP64
+    defect correction with the device-side stopping rule) is within 1e-10 of it."""
+    torch = torch_dev
+    cfg = vofsynth.config("ppp512")
+    g = oracle.Grid.from_config(cfg)
+    f = vofsynth.remove_weighted_mean(vofsynth.gaussian_field(g.shape, 4), g.dzf)
+    fd = _dev(torch, f)
+    del f
+    p64 = _plan(g).solve(fd)
+    r = torch_laplacian(torch, p64, g) - fd
+    rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(fd)).item()
+    del r
+    mixed = _plan(g, precision="mixed")
+    pm = mixed.solve(fd)
+    (steps, est), = mixed.mixed_report()
+    err = (torch.linalg.vector_norm(pm - p64) / torch.linalg.vector_norm(p64)).item()
+    print(f"ppp512: residual {rel:.3e}; mixed {steps} steps, estimate {est:.2e}, vs FP64 {err:.3e}")
+    assert rel <= 1e-10
+    assert err <= MIXED_TOL and 1 <= steps <= 3
+
+
 def _step_inputs(g, seed=2):
     us, vs, ws, phat, rho, rho0, s, dt = _project_inputs(g, seed)
     C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, seed=seed)
