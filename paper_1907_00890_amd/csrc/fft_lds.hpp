@@ -155,8 +155,8 @@ struct PassRadix {
 };
 
 // Twiddles of one pass for this thread: w_N^{(j % NS) r N/(NS R)}, r = 1..R-1,
-// for each of its PT/R butterflies j = t + TPL b.  tab holds cos(2 pi k/N) at
-// [k] and sin(2 pi k/N) at [N + k].
+// for each of its PT/R butterflies j = t + TPL b.  tab holds the pairs
+// (cos, sin)(2 pi k/N) at [2k], [2k + 1].
 template <typename T, int N, int NS, int SIGN, int PTM>
 __device__ __forceinline__ void load_twiddles(const T* __restrict__ tab, int t, T* wr, T* wi) {
   constexpr int R = PassRadix<N, NS, PTM>::R;
@@ -168,8 +168,9 @@ __device__ __forceinline__ void load_twiddles(const T* __restrict__ tab, int t, 
 #pragma unroll
     for (int r = 1; r < R; ++r) {
       const int ti = k * r * (N / (NS * R));
-      wr[b * R + r] = tab[ti];
-      wi[b * R + r] = T(SIGN) * tab[N + ti];
+      const typename Vec2<T>::type w = reinterpret_cast<const typename Vec2<T>::type*>(tab)[ti];
+      wr[b * R + r] = w.x;
+      wi[b * R + r] = T(SIGN) * w.y;
     }
   }
 }
@@ -212,7 +213,7 @@ __device__ __forceinline__ int pass_out(int t, int b, int r) {
 // For mode m in [1, N/2) the two spectra A_m, B_m of the real lines a, b
 // follow from Z_m and Z_{N-m} of Z = FFT(a + i b):
 //   A = (Z_m + conj Z_{N-m}) / 2,  B = (Z_m - conj Z_{N-m}) / (2i).
-// pc[m] = cos(pi m/(2N)), ps[m] = sin(pi m/(2N)) (the DCT rotation).
+// c = cos(pi m/(2N)), s = sin(pi m/(2N)) (the DCT rotation).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int BC>
 struct RealPair {

@@ -34,8 +34,8 @@ inline Batch<T> batch_of(T* const* ptrs, int n) {
 }
 
 // transforms.hip -------------------------------------------------------------
-// tab layout per direction and precision: cos(2 pi k/N), sin(2 pi k/N) for
-// k < N, then cos(pi m/(2N)), sin(pi m/(2N)) for m <= N/2.
+// tab layout per direction and precision, (cos, sin) pairs: of 2 pi k/N for
+// k < N, then of pi m/(2N) for m <= N/2 (one 2-vector load per twiddle).
 int ypass_tile_cols(int nx, int ny);
 // Options of the FP32 passes of the mixed-precision chain:
 //   sub   : x forward reads member b as in[b] - sub[b] (FP64, before the

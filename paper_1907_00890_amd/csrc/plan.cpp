@@ -45,18 +45,18 @@ const char* const kClassNames[K_NCLASS] = {
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
     "residual", "rhs_assembly", "correction", "extension", "step_epilogue"};
 
-// Twiddle table of one direction: cos/sin(2 pi k/N), k < N, then
-// cos/sin(pi m/(2N)), m <= N/2 (the DCT post/pre rotation).
+// Twiddle table of one direction, (cos, sin) pairs: of 2 pi k/N for k < N,
+// then of pi m/(2N) for m <= N/2 (the DCT post/pre rotation).
 std::vector<double> make_table(int n) {
   std::vector<double> t(2 * n + 2 * (n / 2 + 1));
   const double pi = 3.14159265358979323846264338327950288;
   for (int k = 0; k < n; ++k) {
-    t[k] = std::cos(2.0 * pi * k / n);
-    t[n + k] = std::sin(2.0 * pi * k / n);
+    t[2 * k] = std::cos(2.0 * pi * k / n);
+    t[2 * k + 1] = std::sin(2.0 * pi * k / n);
   }
   for (int m = 0; m <= n / 2; ++m) {
-    t[2 * n + m] = std::cos(pi * m / (2.0 * n));
-    t[2 * n + (n / 2 + 1) + m] = std::sin(pi * m / (2.0 * n));
+    t[2 * n + 2 * m] = std::cos(pi * m / (2.0 * n));
+    t[2 * n + 2 * m + 1] = std::sin(pi * m / (2.0 * n));
   }
   return t;
 }

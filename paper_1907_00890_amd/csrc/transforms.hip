@@ -132,8 +132,8 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
       lds.put(pass_out<N, 1, PTM>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
   later_passes<T, N, R1, -1, false, PTM>(lds, t, tab, vr, vi);
   __syncthreads();
-  const T* pc = tab + 2 * N;
-  const T* ps = tab + 2 * N + (N / 2 + 1);
+  // (cos, sin)(pi m/(2N)) pairs of the DCT rotation
+  const typename Vec2<T>::type* rot = reinterpret_cast<const typename Vec2<T>::type*>(tab) + N;
 #pragma unroll
   for (int u = 0; u < PT / 2; ++u) {
     const int m = t + TPL * u;
@@ -152,7 +152,7 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
       T wr, wi;
       lds.get(N - m, wr, wi);
       T oa[2], ob[2];
-      RealPair<T, N, BC>::post(zr, zi, wr, wi, pc[m], ps[m], oa, ob);
+      RealPair<T, N, BC>::post(zr, zi, wr, wi, rot[m].x, rot[m].y, oa, ob);
       if constexpr (BC == BC_P)
         store(2 * m, oa[0], ob[0], 2 * m + 1, oa[1], ob[1]);
       else
@@ -168,8 +168,8 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
                                              Store store) {
   using S = FftShape<N, PTM>;
   constexpr int PT = S::PT, TPL = S::TPL;
-  const T* pc = tab + 2 * N;
-  const T* ps = tab + 2 * N + (N / 2 + 1);
+  // (cos, sin)(pi m/(2N)) pairs of the DCT rotation
+  const typename Vec2<T>::type* rot = reinterpret_cast<const typename Vec2<T>::type*>(tab) + N;
 #pragma unroll
   for (int u = 0; u < PT / 2; ++u) {
     const int m = t + TPL * u;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
       else
         load2(m, N - m, ia[0], ib[0], ia[1], ib[1]);
       T z0r, z0i, z1r, z1i;
-      RealPair<T, N, BC>::pre(ia, ib, pc[m], ps[m], z0r, z0i, z1r, z1i);
+      RealPair<T, N, BC>::pre(ia, ib, rot[m].x, rot[m].y, z0r, z0i, z1r, z1i);
       lds.put(m, z0r, z0i);
       lds.put(N - m, z1r, z1i);
     }
@@ -245,8 +245,8 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
       lds.put(pass_out<N, 1, PTM>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
   later_passes<T, N, R1, -1, false, PTM>(lds, t, tab, vr, vi);
   __syncthreads();
-  const T* pc = tab + 2 * N;
-  const T* ps = tab + 2 * N + (N / 2 + 1);
+  // (cos, sin)(pi m/(2N)) pairs of the DCT rotation
+  const typename Vec2<T>::type* rot = reinterpret_cast<const typename Vec2<T>::type*>(tab) + N;
 #pragma unroll
   for (int u = 0; u < PT / 2; ++u) {
     const int m = t + TPL * u;
@@ -277,12 +277,12 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
       T wr, wi;
       lds.get(N - m, wr, wi);
       T oa[2], ob[2];
-      RealPair<T, N, BC>::post(zr, zi, wr, wi, pc[m], ps[m], oa, ob);
+      RealPair<T, N, BC>::post(zr, zi, wr, wi, rot[m].x, rot[m].y, oa, ob);
       const int c0 = BC == BC_P ? 2 * m : m, c1 = BC == BC_P ? 2 * m + 1 : N - m;
       scale(c0, oa[0], ob[0]);
       scale(c1, oa[1], ob[1]);
       T z0r, z0i, z1r, z1i;
-      RealPair<T, N, BC>::pre(oa, ob, pc[m], ps[m], z0r, z0i, z1r, z1i);
+      RealPair<T, N, BC>::pre(oa, ob, rot[m].x, rot[m].y, z0r, z0i, z1r, z1i);
       lds.put(m, z0r, z0i);
       lds.put(N - m, z1r, z1i);
     }
