@@ -6,19 +6,26 @@ finite-difference Poisson equation with an FFT-based direct method and
 reaches exactly the solution of the discrete problem, so the oracle is that
 definition computed in the most transparent way available:
 
-1. x and y: library transforms that diagonalise the 1-D second difference --
-   a complex DFT for periodic directions (numpy.fft.fft) and an orthonormal
-   DCT-II for wall directions with zero normal gradient (scipy.fft.dct).
-   Their eigenvalues are -(4/h^2) sin^2(pi m / n) and -(4/h^2) sin^2(pi m / (2n)).
+1. x and y: library transforms that diagonalise the 1-D second difference
+   under each pair of end conditions (scipy.fft, orthonormal):
+     periodic                      complex DFT   -(4/h^2) sin^2(pi m / n)
+     wall / wall        (N N)      DCT-II        -(4/h^2) sin^2(pi m / (2n))
+     outflow / outflow  (D D)      DST-II        -(4/h^2) sin^2(pi (m+1) / (2n))
+     wall / outflow     (N D)      DCT-IV        -(4/h^2) sin^2(pi (2m+1) / (4n))
+     outflow / wall     (D N)      DST-IV        -(4/h^2) sin^2(pi (2m+1) / (4n))
+   (outflow: p = 0 on the boundary face, half a cell beyond the last centre).
 2. z: the tridiagonal z operator A = W^-1 S (S symmetric, W = diag(dzf)) is
    diagonalised by the generalised symmetric eigenproblem S v = mu W v
    (scipy.linalg.eigh), so (A + lambda I)^-1 = V diag(1/(mu+lambda)) V^T W.
    No tridiagonal sweep is used anywhere in the oracle.
-3. The single zero eigenvalue (the constant mode, reached only on the
-   (kx, ky) = (0, 0) line) is dropped: this is the W-weighted pseudo-inverse.
-   The volume-weighted mean is also subtracted explicitly from the
-   right-hand side before, and from the solution after, so that a large
-   constant offset cannot leak through the numerically computed null vector.
+3. Without an outflow end the operator is singular.  Its single zero
+   eigenvalue (the constant mode, reached only on the (kx, ky) = (0, 0) line)
+   is dropped: this is the W-weighted pseudo-inverse.  The volume-weighted
+   mean is also subtracted explicitly from the right-hand side before, and
+   from the solution after, so that a large constant offset cannot leak
+   through the numerically computed null vector.  With an outflow end every
+   eigenvalue is negative and the plain inverse is taken (no mean removed,
+   no gauge).
 4. Inverse transforms.
 5. One step of iterative refinement: the residual of the discrete equation,
    f - mean_W(f) - L_h p, is evaluated in extended precision (numpy
@@ -38,19 +45,32 @@ from .grid import Grid
 from .stencils import grad, div, lap, face_density
 
 
-def eigenvalues_1d(n: int, h: float, letter: str) -> np.ndarray:
-    """Eigenvalues of the 1-D second difference in the library transform's order."""
+def _pair(ends):
+    return (ends, ends) if isinstance(ends, str) and len(ends) == 1 else tuple(ends)
+
+
+def eigenvalues_1d(n: int, h: float, ends) -> np.ndarray:
+    """Eigenvalues of the 1-D second difference in the library transform's
+    order; ``ends`` is a letter (both ends) or a (lower, upper) pair."""
+    lo, hi = _pair(ends)
     m = np.arange(n, dtype=np.float64)
-    if letter == "P":
-        return -(4.0 / (h * h)) * np.sin(np.pi * m / n) ** 2
-    return -(4.0 / (h * h)) * np.sin(np.pi * m / (2.0 * n)) ** 2
+    if lo == "P":
+        arg = np.pi * m / n
+    elif lo == "N" and hi == "N":
+        arg = np.pi * m / (2.0 * n)
+    elif lo == "D" and hi == "D":
+        arg = np.pi * (m + 1.0) / (2.0 * n)
+    else:
+        arg = np.pi * (2.0 * m + 1.0) / (4.0 * n)
+    return -(4.0 / (h * h)) * np.sin(arg) ** 2
 
 
 def z_operator_dense(g: Grid):
     """S (symmetric) and W = diag(dzf) with A_z = W^-1 S the z second difference.
 
     Row k of A_z: [(p[k+1]-p[k]) / dzc[k] - (p[k]-p[k-1]) / dzc[k-1]] / dzf[k],
-    with zero flux through walls, or wrapped couplings when z is periodic.
+    with zero flux through walls, wrapped couplings when z is periodic, and
+    through an outflow face the flux (0 - p) / (dzf / 2) of the end cell.
     """
     nz = g.nz
     S = np.zeros((nz, nz))
@@ -60,54 +80,70 @@ def z_operator_dense(g: Grid):
         S[k + 1, k] += c
         S[k, k] -= c
         S[k + 1, k + 1] -= c
-    if g.bc[2] == "P":
+    if g.ends[2][0] == "P":
         c = 1.0 / g.dzc[nz - 1]
         S[nz - 1, 0] += c
         S[0, nz - 1] += c
         S[nz - 1, nz - 1] -= c
         S[0, 0] -= c
+    lo, hi = g.ends[2]
+    if lo == "D":
+        S[0, 0] -= 2.0 / g.dzf[0]
+    if hi == "D":
+        S[nz - 1, nz - 1] -= 2.0 / g.dzf[nz - 1]
     return S, np.diag(g.dzf)
 
 
-def _fwd(a, axis, letter):
-    if letter == "P":
+# (lower, upper) -> (library transform, type); periodic uses the complex DFT
+_R2R = {("N", "N"): ("dct", 2), ("D", "D"): ("dst", 2), ("N", "D"): ("dct", 4),
+        ("D", "N"): ("dst", 4)}
+
+
+def _fwd(a, axis, ends):
+    if ends[0] == "P":
         return np.fft.fft(a, axis=axis)
-    return sfft.dct(a, type=2, norm="ortho", axis=axis)
+    kind, t = _R2R[tuple(ends)]
+    f = sfft.dct if kind == "dct" else sfft.dst
+    return f(a, type=t, norm="ortho", axis=axis)
 
 
-def _inv(a, axis, letter):
-    if letter == "P":
+def _inv(a, axis, ends):
+    if ends[0] == "P":
         return np.fft.ifft(a, axis=axis)
-    return sfft.idct(a, type=2, norm="ortho", axis=axis)
+    kind, t = _R2R[tuple(ends)]
+    f = sfft.idct if kind == "dct" else sfft.idst
+    return f(a, type=t, norm="ortho", axis=axis)
 
 
 def _spectral(fc, g: Grid):
     """Eigen-decomposition solve of L_h p = fc for a compatible fc (steps 1-4)."""
     F = fc.astype(np.complex128)
-    F = _fwd(F, 2, g.bc[0])
-    F = _fwd(F, 1, g.bc[1])
-    lam = (eigenvalues_1d(g.ny, g.dy, g.bc[1])[:, None]
-           + eigenvalues_1d(g.nx, g.dx, g.bc[0])[None, :]).reshape(-1)
+    ex, ey, ez = g.ends
+    F = _fwd(F, 2, ex)
+    F = _fwd(F, 1, ey)
+    lam = (eigenvalues_1d(g.ny, g.dy, ey)[:, None]
+           + eigenvalues_1d(g.nx, g.dx, ex)[None, :]).reshape(-1)
 
     S, W = z_operator_dense(g)
     mu, V = sla.eigh(S, W)
-    null = int(np.argmin(np.abs(mu)))
-    # the constant mode is the only (numerically) zero eigenvalue
-    rest = np.delete(np.abs(mu), null)
-    if rest.size and not np.abs(mu[null]) < 1e-6 * rest.min():
-        raise RuntimeError("z operator has no isolated null mode")
 
     B = F.reshape(g.nz, -1)
     C = V.T @ (g.dzf[:, None] * B)
     den = mu[:, None] + lam[None, :]
     inv = np.zeros_like(den)
     nonzero = np.ones_like(den, dtype=bool)
-    nonzero[null, 0] = False  # line (0, 0): lam == 0 exactly
+    if g.singular:
+        null = int(np.argmin(np.abs(mu)))
+        # the constant mode is the only (numerically) zero eigenvalue
+        rest = np.delete(np.abs(mu), null)
+        if rest.size and not np.abs(mu[null]) < 1e-6 * rest.min():
+            raise RuntimeError("z operator has no isolated null mode")
+        nonzero[null, 0] = False  # line (0, 0): lam == 0 exactly
     inv[nonzero] = 1.0 / den[nonzero]
     P = (V @ (C * inv)).reshape(g.shape)
 
-    P = _inv(P, 1, g.bc[1])
-    P = _inv(P, 2, g.bc[0])
+    P = _inv(P, 1, ey)
+    P = _inv(P, 2, ex)
     return P.real.copy()
 
 
@@ -117,20 +153,26 @@ def _lap_extended(p, g: Grid):
 
 
 def solve(f, g: Grid, return_mean: bool = False):
-    """p with L_h p = f - mean_W(f) and sum(dV p) = 0 (FP64, any bc in P/N)."""
+    """FP64 solution of the discrete Poisson equation.
+
+    Without an outflow end: p with L_h p = f - mean_W(f) and sum(dV p) = 0.
+    With one: p = L_h^-1 f (the mean returned is then 0).
+    """
     f = np.asarray(f, dtype=np.float64)
     if f.shape != g.shape:
         raise ValueError(f"rhs shape {f.shape} != grid {g.shape}")
     # the definition: right-hand side minus its volume-weighted mean
-    fbar = g.weighted_mean(f)
+    fbar = g.weighted_mean(f) if g.singular else 0.0
     fc = f - fbar
     p = _spectral(fc, g)
     # step 5: one refinement step with an extended-precision residual
     r = (fc.astype(np.longdouble) - _lap_extended(p, g)).astype(np.float64)
-    r -= g.weighted_mean(r)
+    if g.singular:
+        r -= g.weighted_mean(r)
     p = p + _spectral(r, g)
-    # the gauge: zero volume-weighted mean (removes only round-off here)
-    p -= g.weighted_mean(p)
+    if g.singular:
+        # the gauge: zero volume-weighted mean (removes only round-off here)
+        p -= g.weighted_mean(p)
     if return_mean:
         return p, fbar
     return p
@@ -150,12 +192,18 @@ def assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid
     return rho0 * div(cx, cy, cz, g) + (rho0 / dt) * (div(ustar, vstar, wstar, g) - src)
 
 
+def _require_stored_faces(g: Grid):
+    if any(lo == "D" for lo, _ in g.ends):
+        raise ValueError("velocity updates need every outflow face stored: outflow only at upper ends")
+
+
 def project(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
     """Pressure-split projection step (section 3.2).
 
     Returns (u, v, w, p): p solves L_h p = b (assemble_pressure_rhs) and
     u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ].
     """
+    _require_stored_faces(g)
     b = assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g)
     p = solve(b, g)
     gpx, gpy, gpz = grad(p, g)
@@ -175,6 +223,7 @@ def extend(u, v, w, src, g: Grid, q=None):
     u_Gamma = u_1^e - q.  Returns (ue, ve, we, ug, vg, wg, phi); the u_Gamma
     entries are None without q.
     """
+    _require_stored_faces(g)
     phi = solve(src, g)
     gx, gy, gz = grad(phi, g)
     ue, ve, we = u - gx, v - gy, w - gz

@@ -11,14 +11,24 @@ from dataclasses import dataclass
 
 import numpy as np
 
-_BC_LETTERS = ("P", "N")
+_BC_LETTERS = ("P", "N", "D")
 
 
 def _check_bc(bc: str) -> str:
+    """The upper-end letter of each direction (x, y, z) from 3 letters (both
+    ends alike) or 6 (x-, x+, y-, y+, z-, z+) of P/N/D: the stored last face
+    of each direction is that end's face."""
     bc = bc.upper()
-    if len(bc) != 3 or any(c not in _BC_LETTERS for c in bc):
-        raise ValueError(f"bc must be 3 letters from P/N (x, y, z), got {bc!r}")
-    return bc
+    if len(bc) == 3:
+        pairs = [(c, c) for c in bc]
+    elif len(bc) == 6:
+        pairs = [(bc[2 * a], bc[2 * a + 1]) for a in range(3)]
+    else:
+        raise ValueError(f"bc must be 3 or 6 letters from P/N/D, got {bc!r}")
+    for lo, hi in pairs:
+        if lo not in _BC_LETTERS or hi not in _BC_LETTERS or (lo == "P") != (hi == "P"):
+            raise ValueError(f"bad bc {bc!r}")
+    return "".join(hi for _, hi in pairs)
 
 
 # ----------------------------------------------------------------------------
@@ -148,12 +158,15 @@ def grad_mag_central(C, dx, dy, dzf, bc: str):
 
 
 def _face_avg(a, axis, bc_letter):
-    """1/2 (a[i] + a[i+1]) on face i+1/2; zero on a wall face."""
+    """1/2 (a[i] + a[i+1]) on face i+1/2; zero on a wall face, the inner
+    cell's value on an outflow face."""
     out = 0.5 * (a + np.roll(a, -1, axis=axis))
+    sl = [slice(None)] * 3
+    sl[axis] = -1
     if bc_letter == "N":
-        sl = [slice(None)] * 3
-        sl[axis] = -1
         out[tuple(sl)] = 0.0
+    elif bc_letter == "D":
+        out[tuple(sl)] = a[tuple(sl)]
     return out
 
 
