@@ -21,15 +21,22 @@
  * has nx*ny*nz entries too: u[i,j,k] is on face i+1/2, v on j+1/2, w on
  * k+1/2.  With a wall ('N') in a direction the face with the last index is
  * the wall; the face at -1/2 is implicit.  G is the face gradient (zero on
- * wall faces), D the cell divergence, L = D(G(.)).  x and y are uniform
+ * wall faces), D the cell divergence, L = D(G(.)).  An outflow end ('D', the
+ * zero-pressure outflow boundary of the cases of section 4) puts p = 0 on the
+ * boundary face, half a cell beyond the end centre: G there is
+ * (0 - p_end) / (h/2) at an upper end and (p_end - 0) / (h/2) at a lower one,
+ * and an upper outflow face's velocity is stored like any other face (the one
+ * with the last index).  x and y are uniform
  * (dx, dy); z may be stretched: dz[k] is the width of cell k and the centre
  * distance across face k+1/2 is (dz[k] + dz[k+1]) / 2 (periodic z wraps).
  *
- * The Poisson solve returns the unique p with
+ * Without outflow ends the Poisson solve returns the unique p with
  *      L p = f - mean_W(f)   and   sum_k dV_k p_k = 0,
  * mean_W being the cell-volume-weighted mean.  A right-hand side with a
  * non-zero weighted mean is not an error: its mean is removed (and kept in
- * the plan as a diagnostic, poisson_plan_last_mean).
+ * the plan as a diagnostic, poisson_plan_last_mean).  With an outflow end
+ * anywhere L is non-singular and the solve returns p = L^-1 f (nothing is
+ * removed; poisson_plan_last_mean gives 0).
  *
  * Pointers: every field pointer is a DEVICE pointer owned by the caller and
  * must stay valid until the work queued on `hip_stream` has completed.
@@ -66,8 +73,15 @@ typedef struct poisson_plan poisson_plan;
  *   nx, ny : power of two in [8, 1024];
  *   nz     : >= 1 (>= 3 when z is periodic), at most 1024;
  *   dx, dy : > 0;  dz: HOST array of nz cell widths, each > 0 (copied);
- *   bc     : 3 characters for x, y, z: 'P' periodic, 'N' wall with zero
- *            normal gradient of p (zero normal velocity);
+ *   bc     : 3 characters for x, y, z (both ends alike) or 6 for the ends
+ *            x-, x+, y-, y+, z-, z+ (either case): 'P' periodic (both ends
+ *            of a direction), 'N' wall with zero normal gradient of p (zero
+ *            normal velocity), 'D' outflow (p = 0 on the boundary face).  x
+ *            and y take P, N N or D D (a wall at one end and an outflow at
+ *            the other is VP_EUNSUPPORTED there); z takes any N / D pair.
+ *            project, extend_liquid_velocity(_batched) and vof_step return
+ *            VP_EUNSUPPORTED for a plan with an outflow at a lower end (the
+ *            face -1/2 has no storage); the solves accept every combination;
  *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 transforms and
  *            FP32 tridiagonal storage with FP64 pivots, refined by FP64
  *            residual / defect-correction steps, see poisson_plan_set_mixed);

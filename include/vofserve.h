@@ -65,7 +65,7 @@ typedef struct vp_request {
   int nx, ny, nz;
   double dx, dy;
   const double* dz;     /* HOST, nz cell widths (copied by submit) */
-  const char* bc;       /* 3 letters as in poisson_plan_create (copied) */
+  const char* bc;       /* 3 or 6 letters as in poisson_plan_create (copied) */
   const double* rhs;    /* solve: device right-hand side */
   double* sol;          /* solve: device solution (may alias rhs) */
   vp_extend_fields ext; /* extend: device fields; phi required for mixed */

@@ -39,8 +39,10 @@ class Plan:
     """A solve plan: grid, boundary conditions, device tables and workspace.
 
     nx, ny: powers of two in [8, 1024]; nz >= 1; dz: nz cell widths (z may be
-    stretched); bc: three letters from 'P' (periodic) / 'N' (wall, zero
-    normal gradient) for x, y, z.  precision: 'fp64' or 'mixed'.
+    stretched); bc: three letters (x, y, z, both ends alike) or six (x-, x+,
+    y-, y+, z-, z+) from 'P' (periodic), 'N' (wall, zero normal gradient) and
+    'D' (outflow, p = 0 on the boundary face); x and y take P, NN or DD.
+    precision: 'fp64' or 'mixed'.
     """
 
     def __init__(self, nx, ny, nz, dx, dy, dz, bc, precision="fp64", max_batch=1):

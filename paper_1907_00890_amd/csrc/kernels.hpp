@@ -2,11 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "bc.hpp"
 #include "limits.hpp"
 
 namespace vp {
-
-enum : int { BC_P = 0, BC_N = 1 };  // periodic / wall with zero normal gradient
 
 // Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU (needed for
 // launches above 64 KB); done once per kernel instantiation.
@@ -83,7 +82,7 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool f
 struct ZSpecArgs {
   int nx, ny, nz;
   int lx;              // log2(nx)
-  int bcz;
+  int bcz;             // BC_P, BC_N or BC_D
   double scale;        // 1 / (nx * ny * nz)
   const double* lamx;  // eigenvalue per packed x, y, z position
   const double* lamy;
@@ -109,6 +108,9 @@ struct ZArgs {
   int seg_base;        // nz / S
   int seg_rem;         // nz % S (first seg_rem segments are one longer)
   int periodic;        // z periodic
+  int singular;        // no outflow end anywhere: line (0, 0) is singular
+  double dlo, dhi;     // outflow at z- / z+: 2 / dz^2 of the end cell added to the
+                       // diagonal of -(A + lambda); 0 at a wall
   double scale;        // 1 / (nx * ny)
   double dz_sum;       // sum of dzf
   const double* lamx;  // eigenvalue per packed x position
@@ -134,10 +136,13 @@ struct GridArgs {
   int kc;              // z-planes marched by one stencil block
   int tiled;           // right-hand side on LDS-staged 64 x tiled tiles (8 or 16 rows) where
                        // they fit; 0: plain 64 x 4 tiles
-  int bcx, bcy, bcz;   // 0 periodic, 1 wall
+  int bcx, bcy, bcz;   // 0 periodic, 1 wall or outflow
+  int outflow;         // bit 2d: outflow at the lower end of direction d (x, y, z),
+                       // bit 2d+1: at the upper end
   double dx, dy;
   const double* dzf;   // nz
-  const double* dzc;   // nz (last entry: wrap distance when z is periodic)
+  const double* dzc;   // nz (last entry: wrap distance when z is periodic, dzf[nz-1]
+                       // -- the distance to the mirrored ghost -- with an outflow at z+)
 };
 hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const double* w,
                       const double* phat, const double* rho, double rho0, const double* src,

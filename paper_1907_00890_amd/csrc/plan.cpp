@@ -6,7 +6,8 @@
 //   -> y pass (inverse) -> x pass (inverse)
 // The forward transforms are unnormalised; the z pass scales by 1/(nx*ny)
 // and the inverse transforms return N times their input, so the chain is
-// exactly the inverse operator on the zero-mean subspace.
+// exactly the inverse operator on the zero-mean subspace (the inverse itself
+// when an outflow end makes the operator non-singular).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +18,7 @@
 #include <string>
 #include <vector>
 
+#include "bc.hpp"
 #include "kernels.hpp"
 #include "vofpoisson.h"
 
@@ -61,7 +63,10 @@ std::vector<double> make_table(int n) {
   return t;
 }
 
-// Eigenvalue of the 1-D second difference for every packed coefficient position.
+// Eigenvalue of the 1-D second difference for every packed coefficient
+// position: periodic -(4/h^2) sin^2(pi m/n) (packed real DFT order), walls
+// -(4/h^2) sin^2(pi c/(2n)) (cosine mode c), outflow at both ends
+// -(4/h^2) sin^2(pi (n-c)/(2n)) = -(4/h^2) cos^2(pi c/(2n)) (sine mode n-1-c).
 std::vector<double> make_lambda(int n, double h, int bc) {
   const double pi = 3.14159265358979323846264338327950288;
   std::vector<double> l(n);
@@ -70,8 +75,10 @@ std::vector<double> make_lambda(int n, double h, int bc) {
     if (bc == vp::BC_P) {
       const int m = c == 0 ? 0 : (c == 1 ? n / 2 : c / 2);
       s = std::sin(pi * m / n);
-    } else {
+    } else if (bc == vp::BC_N) {
       s = std::sin(pi * c / (2.0 * n));
+    } else {
+      s = std::cos(pi * c / (2.0 * n));
     }
     l[c] = -4.0 / (h * h) * s * s;
   }
@@ -82,7 +89,9 @@ std::vector<double> make_lambda(int n, double h, int bc) {
 
 struct poisson_plan {
   int nx = 0, ny = 0, nz = 0;
-  int bc[3] = {0, 0, 0};
+  int bc[3] = {0, 0, 0};  // transform codes of x, y; z: BC_P, BC_N (walls or one outflow end), BC_D
+  char ends[6] = {};      // 'P' / 'N' / 'D' at x-, x+, y-, y+, z-, z+
+  bool singular = true;   // no outflow end: the constants are the null space
   int precision = 0, max_batch = 1, dc_steps = 1;
   int x_pt = 16, y_pt = 16;  // radix schedules of the x and y passes (tuning knobs)
   int y_lines = 0;           // column pairs per y block (0: the default width)
@@ -207,6 +216,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   for (int k = 0; k < nz; ++k) sum += f[k];
   for (int k = 0; k + 1 < nz; ++k) c[k] = 0.5 * (f[k] + f[k + 1]);
   if (zper) c[nz - 1] = 0.5 * (f[nz - 1] + f[0]);
+  else if (P->ends[5] == 'D') c[nz - 1] = f[nz - 1];  // to the mirrored ghost of the outflow face
   else c[nz - 1] = 1.0;  // unused (wall)
   // wall form of the operator; a periodic z adds the wrap face through one
   // flux unknown inside the z kernel (distance c[nz-1])
@@ -257,6 +267,9 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.seg_base = nz / Z.nseg;
   Z.seg_rem = nz % Z.nseg;
   Z.periodic = zper ? 1 : 0;
+  Z.singular = P->singular ? 1 : 0;
+  Z.dlo = P->ends[4] == 'D' ? 2.0 / (f[0] * f[0]) : 0.0;
+  Z.dhi = P->ends[5] == 'D' ? 2.0 / (f[nz - 1] * f[nz - 1]) : 0.0;
   Z.dzc_wrap = zper ? c[nz - 1] : 0.0;
   // a uniform grid (bitwise equal widths) lets the z kernel use one constant
   // coefficient; za / zc hold exactly that value in the interior
@@ -280,8 +293,11 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.batch_stride = P->npts();
 
   // a uniform z line of a transform length is diagonalised exactly by the
-  // real DFT (periodic) or DCT-II (walls) of the x and y passes
-  P->z_spec_ok = Z.uniform_z && nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0;
+  // real DFT (periodic), DCT-II (walls) or DST-II (outflow at both ends) of
+  // the x and y passes; a wall at one end and an outflow at the other keeps
+  // the tridiagonal pass
+  P->z_spec_ok = Z.uniform_z && nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0 &&
+                 vp::direction_code(P->ends[4], P->ends[5]) >= 0;
   if (P->z_spec_ok) {
     const std::vector<double> tz = make_table(nz);
     if ((st = P->upload(&P->tabz64, tz, "table z"))) return st;
@@ -311,7 +327,12 @@ int plan_init(poisson_plan* P, const double* dz) {
   while ((1 << G.lx) < nx) ++G.lx;
   G.ly = 0;
   while ((1 << G.ly) < ny) ++G.ly;
-  G.bcx = P->bc[0]; G.bcy = P->bc[1]; G.bcz = P->bc[2];
+  G.bcx = P->bc[0] == vp::BC_P ? 0 : 1;
+  G.bcy = P->bc[1] == vp::BC_P ? 0 : 1;
+  G.bcz = P->bc[2] == vp::BC_P ? 0 : 1;
+  G.outflow = 0;
+  for (int e = 0; e < 6; ++e)
+    if (P->ends[e] == 'D') G.outflow |= 1 << e;
   G.dx = P->dx; G.dy = P->dy;
   G.dzf = P->dzf; G.dzc = P->dzc;
   G.kc = vp::stencil_default_planes(nx, ny, nz);
@@ -382,7 +403,8 @@ int solve_f32(poisson_plan* P, int nb, const double* const* rhs, double* const* 
 //   e = S32(r - mean_W(r)) - mean_W(p),  p += e.
 // The FP32 chain cannot see the null (constant) mode, so the FP64 weighted
 // means are removed in every correction step instead: mean_W(r) equals
-// mean_W(f), which would otherwise dominate r and swamp its FP32 copy.
+// mean_W(f), which would otherwise dominate r and swamp its FP32 copy.  With
+// an outflow end there is no null mode: e = S32(r), nothing is removed.
 // Stopping, per member and on the device: the error left in p_k is bounded
 // by |e_1| after the first step and estimated as |e_k|^2 / |e_{k-1}| after
 // later ones, from norms the x-inverse pass reduces; once that is at most
@@ -417,8 +439,9 @@ int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const
   if (s) return s;
   VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, 0, P->dc_tol, P->dc_state, P->dc_flags, st),
          "dc update");
-  o.sub = rmeans;
+  o.sub = P->singular ? rmeans : nullptr;
   o.skip = P->dc_flags;
+  const double* const asub = P->singular ? pmeans : nullptr;
   for (int it = 1; it <= P->dc_steps; ++it) {
     for (int b = 0; b < nb; ++b)
       VP_LAUNCH(P, K_RESIDUAL,
@@ -426,7 +449,7 @@ int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const
                                     P->partial + 2L * b * vp::kResidualMaxBlocks, pmeans + b,
                                     rmeans + b, P->dz_sum, P->dc_flags + b, st),
                 "residual", st);
-    s = solve_f32(P, nb, r, sol, true, pmeans, o, st);
+    s = solve_f32(P, nb, r, sol, true, asub, o, st);
     if (s) return s;
     VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, it, P->dc_tol, P->dc_state, P->dc_flags, st),
            "dc update");
@@ -456,14 +479,21 @@ poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, 
   };
   const int chk = poisson_plan_check(nx, ny, nz, dx, dy, dz, bc, precision, max_batch);
   if (chk != VP_OK) return fail(chk);
+  char ends[6];
+  (void)vp::parse_ends(bc, ends);  // checked above
   int bcs[3];
-  for (int d = 0; d < 3; ++d) bcs[d] = (bc[d] == 'P' || bc[d] == 'p') ? vp::BC_P : vp::BC_N;
+  for (int d = 0; d < 2; ++d) bcs[d] = vp::direction_code(ends[2 * d], ends[2 * d + 1]);
+  bcs[2] = ends[4] == 'P' ? vp::BC_P
+           : (ends[4] == 'D' && ends[5] == 'D') ? vp::BC_D : vp::BC_N;
 
   poisson_plan* P = new (std::nothrow) poisson_plan();
   if (!P) return fail(VP_ENOMEM);
   P->nx = nx; P->ny = ny; P->nz = nz;
   P->dx = dx; P->dy = dy;
   P->bc[0] = bcs[0]; P->bc[1] = bcs[1]; P->bc[2] = bcs[2];
+  std::memcpy(P->ends, ends, 6);
+  P->singular = true;
+  for (int e = 0; e < 6; ++e) P->singular = P->singular && ends[e] != 'D';
   P->precision = precision;
   P->max_batch = max_batch;
   P->dc_steps = precision == VP_PRECISION_MIXED ? 3 : 0;
@@ -502,10 +532,19 @@ int poisson_solve_batched(poisson_plan* P, int n, const double* const* rhs, doub
   return solve_any(P, n, rhs, sol, static_cast<hipStream_t>(stream));
 }
 
+namespace {
+// The face stencils hold one face per cell and direction (the upper one): an
+// outflow face at a lower end, whose velocity is free, has no storage.
+bool faces_stored(const poisson_plan* P) {
+  return P->ends[0] != 'D' && P->ends[2] != 'D' && P->ends[4] != 'D';
+}
+}  // namespace
+
 int project(poisson_plan* P, double* u, double* v, double* w, const double* phat,
             const double* rho, double rho0, const double* src, double dt, double* p,
             void* stream) {
   if (!P || !u || !v || !w || !phat || !rho || !p || !(rho0 > 0) || !(dt > 0)) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   // mixed precision keeps the FP64 right-hand side for its residuals
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
@@ -530,6 +569,7 @@ int check_extend(const vp_extend_fields& a) {
 int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_fields* a,
                                    void* stream) {
   if (!P || !a || n < 0 || n > P->max_batch) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
   const long N = P->npts();
   const double* rhs[vp::kMaxBatch];
   double* phi[vp::kMaxBatch];
@@ -576,6 +616,7 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
   if ((ue || ve || we) && !he) return VP_EINVAL;
   if (hq != hg) return VP_EINVAL;
   if (phi == p) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),

@@ -2,6 +2,7 @@
 // footprint of a plan (no HIP calls; also used by the request server).
 #include <cmath>
 
+#include "bc.hpp"
 #include "limits.hpp"
 #include "vofpoisson.h"
 
@@ -11,6 +12,33 @@ namespace {
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 }  // namespace
 
+namespace vp {
+
+int parse_ends(const char* bc, char e[6]) {
+  if (!bc) return VP_EINVAL;
+  int n = 0;
+  while (n < 7 && bc[n]) ++n;
+  if (n != 3 && n != 6) return VP_EINVAL;
+  for (int i = 0; i < 6; ++i) {
+    char c = n == 3 ? bc[i / 2] : bc[i];
+    if (c >= 'a' && c <= 'z') c = (char)(c - 'a' + 'A');
+    if (c != 'P' && c != 'N' && c != 'D') return VP_EINVAL;
+    e[i] = c;
+  }
+  for (int d = 0; d < 3; ++d)
+    if ((e[2 * d] == 'P') != (e[2 * d + 1] == 'P')) return VP_EINVAL;
+  return VP_OK;
+}
+
+int direction_code(char lo, char hi) {
+  if (lo == 'P') return BC_P;
+  if (lo == 'N' && hi == 'N') return BC_N;
+  if (lo == 'D' && hi == 'D') return BC_D;
+  return -1;
+}
+
+}  // namespace vp
+
 extern "C" {
 
 int poisson_plan_check(int nx, int ny, int nz, double dx, double dy, const double* dz,
@@ -18,18 +46,15 @@ int poisson_plan_check(int nx, int ny, int nz, double dx, double dy, const doubl
   if (!dz || !bc || nx <= 0 || ny <= 0 || nz <= 0 || !(dx > 0) || !(dy > 0) || max_batch < 1 ||
       max_batch > VP_MAX_BATCH || !std::isfinite(dx) || !std::isfinite(dy))
     return VP_EINVAL;
-  bool dirichlet = false;
-  for (int d = 0; d < 3; ++d) {
-    const char ch = bc[d];
-    if (ch == 'D' || ch == 'd') dirichlet = true;
-    else if (ch != 'P' && ch != 'p' && ch != 'N' && ch != 'n') return VP_EINVAL;
-  }
-  if (bc[3] != '\0') return VP_EINVAL;
+  char e[6];
+  if (vp::parse_ends(bc, e) != VP_OK) return VP_EINVAL;
   for (int k = 0; k < nz; ++k)
     if (!(dz[k] > 0) || !std::isfinite(dz[k])) return VP_EINVAL;
-  if ((bc[2] == 'P' || bc[2] == 'p') && nz < 3) return VP_EINVAL;
+  if (e[4] == 'P' && nz < 3) return VP_EINVAL;
   if (precision != VP_PRECISION_FP64 && precision != VP_PRECISION_MIXED) return VP_EINVAL;
-  if (dirichlet) return VP_EUNSUPPORTED;
+  // x and y: periodic, walls at both ends or outflow at both ends
+  if (vp::direction_code(e[0], e[1]) < 0 || vp::direction_code(e[2], e[3]) < 0)
+    return VP_EUNSUPPORTED;
   if (!pow2_in(nx, 8, 1024) || !pow2_in(ny, 8, 1024) || nz > 1024) return VP_EUNSUPPORTED;
   return VP_OK;
 }

@@ -31,6 +31,7 @@
 #include <tuple>
 #include <vector>
 
+#include "bc.hpp"
 #include "vofpoisson.h"
 #include "vofserve.h"
 
@@ -56,11 +57,15 @@ double clock_us() {
 struct ClassKey {
   int nx, ny, nz, precision;
   double dx, dy;
-  char bc[4];
+  char bc[7];  // the six end letters (x-, x+, y-, y+, z-, z+), NUL-terminated
   std::vector<double> dz;
   bool operator<(const ClassKey& o) const {
-    return std::tie(nx, ny, nz, precision, dx, dy, bc[0], bc[1], bc[2], dz) <
-           std::tie(o.nx, o.ny, o.nz, o.precision, o.dx, o.dy, o.bc[0], o.bc[1], o.bc[2], o.dz);
+    const auto a = std::tie(nx, ny, nz, precision, dx, dy);
+    const auto b = std::tie(o.nx, o.ny, o.nz, o.precision, o.dx, o.dy);
+    if (a != b) return a < b;
+    const int c = std::strcmp(bc, o.bc);
+    if (c != 0) return c < 0;
+    return dz < o.dz;
   }
   bool operator==(const ClassKey& o) const { return !(*this < o) && !(o < *this); }
 };
@@ -148,8 +153,6 @@ struct vp_server {
 
 namespace {
 
-bool is_p(char c) { return c == 'P' || c == 'p'; }
-
 ClassKey key_of(const vp_request& r) {
   ClassKey k;
   k.nx = r.nx;
@@ -158,8 +161,9 @@ ClassKey key_of(const vp_request& r) {
   k.precision = r.precision;
   k.dx = r.dx;
   k.dy = r.dy;
-  for (int d = 0; d < 3; ++d) k.bc[d] = is_p(r.bc[d]) ? 'P' : 'N';
-  k.bc[3] = '\0';
+  // checked by poisson_plan_check at submit: "NNN" and "NNNNNN" are one class
+  (void)vp::parse_ends(r.bc, k.bc);
+  k.bc[6] = '\0';
   k.dz.assign(r.dz, r.dz + r.nz);
   return k;
 }

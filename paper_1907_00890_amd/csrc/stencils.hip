@@ -4,6 +4,12 @@
 //
 // Faces: u on i+1/2, v on j+1/2, w on k+1/2; a wall face (last index) has
 // zero gradient, the face at -1/2 of a wall direction is implicit and zero.
+// An outflow face (p = 0 on the face, half a cell beyond the centre) is
+// handled through a mirrored ghost cell: p, p_hat and phi of the ghost are
+// minus the end cell's, rho is the end cell's, at distance dz of the end
+// cell (the plan stores it as the last centre distance).  The face stencils
+// take such a face at the upper z end; the residual (the Laplacian alone)
+// takes one at any end.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -60,6 +66,11 @@ __device__ __forceinline__ int kminus(const GridArgs& g, int k) {
   return k > 0 ? k - 1 : (g.bcz == 0 ? g.nz - 1 : -1);
 }
 
+// the upper z-face of plane k is an outflow face
+__device__ __forceinline__ bool ztop_out(const GridArgs& g, int k) {
+  return k == g.nz - 1 && (g.outflow & 32);
+}
+
 // inverse of the face density 1 / ((rho_a + rho_b) / 2)
 __device__ __forceinline__ double inv_face_rho(double ra, double rb) { return 2.0 / (ra + rb); }
 
@@ -113,22 +124,26 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
   for (int k = t.kb; k < t.ke; ++k) {
     const long c = k * P + t.c0;
     const int kp = kplus(g, k);
+    const bool zph = kp >= 0 || ztop_out(g, k);
     double php = 0.0, rhp = 0.0;
     if (kp >= 0) {
       php = ph[kp * P + t.c0];
       rhp = rho[kp * P + t.c0];
+    } else if (zph) {
+      php = -phc;
+      rhp = rhc;
     }
     const RhsNbr xp{t.hxp ? ph[c + t.xp] : 0.0, t.hxp ? rho[c + t.xp] : 0.0, t.hxp};
     const RhsNbr xm{t.hxm ? ph[c + t.xm] : 0.0, t.hxm ? rho[c + t.xm] : 0.0, t.hxm};
     const RhsNbr yp{t.hyp ? ph[c + t.yp] : 0.0, t.hyp ? rho[c + t.yp] : 0.0, t.hyp};
     const RhsNbr ym{t.hym ? ph[c + t.ym] : 0.0, t.hym ? rho[c + t.ym] : 0.0, t.hym};
-    const RhsNbr zp{php, rhp, kp >= 0}, zm{phm, rhm, km >= 0};
+    const RhsNbr zp{php, rhp, zph}, zm{phm, rhm, km >= 0};
     const double wc = w[c];
     const double um = t.hxm ? u[c + t.xm] : 0.0;
     const double vm = t.hym ? v[c + t.ym] : 0.0;
     const double sv = src ? src[c] : 0.0;
     b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc, rhc, xp, xm, yp, ym, zp,
-                    kp >= 0 ? g.dzc[k] : 1.0, zm, km >= 0 ? g.dzc[km] : 1.0, g.dzf[k], u[c], um,
+                    zph ? g.dzc[k] : 1.0, zm, km >= 0 ? g.dzc[km] : 1.0, g.dzf[k], u[c], um,
                     v[c], vm, wc, wm, sv);
     phm = phc; phc = php;
     rhm = rhc; rhc = rhp;
@@ -210,6 +225,7 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
   }
   for (int k = kb; k < ke; ++k) {
     const int kp = kplus(g, k);
+    const bool zph = kp >= 0 || ztop_out(g, k);
     // every global load of this plane is issued before the barrier
     double php[RPT], rhp[RPT], uc[RPT], um[RPT], vc[RPT], vm[RPT], wcs[RPT], sv[RPT];
 #pragma unroll
@@ -219,6 +235,9 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
       if (kp >= 0) {
         php[m] = ph[kp * P + c0[m]];
         rhp[m] = rho[kp * P + c0[m]];
+      } else if (zph) {
+        php[m] = -phc[m];
+        rhp[m] = rhc[m];
       }
       uc[m] = u[c];
       um[m] = hxm ? u[c + xm] : 0.0;
@@ -236,14 +255,14 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
     }
     __syncthreads();
     const double dzf = g.dzf[k];
-    const double dzcp = kp >= 0 ? g.dzc[k] : 1.0, dzcm = km >= 0 ? g.dzc[km] : 1.0;
+    const double dzcp = zph ? g.dzc[k] : 1.0, dzcm = km >= 0 ? g.dzc[km] : 1.0;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
       const long c = k * P + c0[m];
       const int sl = (ty + 4 * m + 1) * W + tx + 1;
       const RhsNbr xp{sph[sl + 1], srh[sl + 1], hxp}, xm{sph[sl - 1], srh[sl - 1], hxm};
       const RhsNbr yp{sph[sl + W], srh[sl + W], hyp[m]}, ym{sph[sl - W], srh[sl - W], hym[m]};
-      const RhsNbr zp{php[m], rhp[m], kp >= 0}, zm{phm[m], rhm[m], km >= 0};
+      const RhsNbr zp{php[m], rhp[m], zph}, zm{phm[m], rhm[m], km >= 0};
       const double wc = wcs[m];
       b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xm, yp, ym, zp, dzcp, zm,
                       dzcm, dzf, uc[m], um[m], vc[m], vm[m], wc, wm[m], sv[m]);
@@ -274,11 +293,16 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
   for (int k = t.kb; k < t.ke; ++k) {
     const long c = k * P + t.c0;
     const int kp = kplus(g, k);
+    const bool zph = kp >= 0 || ztop_out(g, k);
     double pp = 0.0, hp = 0.0, rp = 0.0;
     if (kp >= 0) {
       pp = p[kp * P + t.c0];
       hp = ph[kp * P + t.c0];
       rp = rho[kp * P + t.c0];
+    } else if (zph) {
+      pp = -pc;
+      hp = -hc;
+      rp = rc;
     }
     if (t.hxp) {
       const double gp = (p[c + t.xp] - pc) * idx, gh = (ph[c + t.xp] - hc) * idx;
@@ -288,7 +312,7 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
       const double gp = (p[c + t.yp] - pc) * idy, gh = (ph[c + t.yp] - hc) * idy;
       v[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rho[c + t.yp]) - ir0) * gh);
     }
-    if (kp >= 0) {
+    if (zph) {
       const double h = g.dzc[k];
       const double gp = (pp - pc) / h, gh = (hp - hc) / h;
       w[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rp) - ir0) * gh);
@@ -318,10 +342,11 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
   for (int k = t.kb; k < t.ke; ++k) {
     const long c = k * P + t.c0;
     const int kp = kplus(g, k);
-    const double fp = kp >= 0 ? phi[kp * P + t.c0] : 0.0;
+    const bool zph = kp >= 0 || ztop_out(g, k);
+    const double fp = kp >= 0 ? phi[kp * P + t.c0] : (zph ? -fc : 0.0);
     const double gx = t.hxp ? (phi[c + t.xp] - fc) * idx : 0.0;
     const double gy = t.hyp ? (phi[c + t.yp] - fc) * idy : 0.0;
-    const double gz = kp >= 0 ? (fp - fc) / g.dzc[k] : 0.0;
+    const double gz = zph ? (fp - fc) / g.dzc[k] : 0.0;
     const double a = u[c] - gx, bb = v[c] - gy, cc = w[c] - gz;
     ue[c] = a;
     ve[c] = bb;
@@ -412,14 +437,20 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
       vn = epi_face(vn, dt, ir0, p[n], pc, rho[n], rc, ph[n], hc, phi[n], fc, idy, false, 0.0, &gy);
     }
     double pp = 0.0, hp = 0.0, rp = 0.0, fp = 0.0;
+    const bool zph = kp >= 0 || ztop_out(g, k);
     if (kp >= 0) {
       const long n = kp * P + t.c0;
       pp = p[n];
       hp = ph[n];
       rp = rho[n];
       fp = phi[n];
-      wn = epi_face(wn, dt, ir0, pp, pc, rp, rc, hp, hc, fp, fc, 0.0, true, g.dzc[k], &gz);
+    } else if (zph) {
+      pp = -pc;
+      hp = -hc;
+      rp = rc;
+      fp = -fc;
     }
+    if (zph) wn = epi_face(wn, dt, ir0, pp, pc, rp, rc, hp, hc, fp, fc, 0.0, true, g.dzc[k], &gz);
     epi_store(un, vn, wn, gx, gy, gz, c, u, v, w, qx, qy, qz, 0.0, 0.0, 0.0, false, ue, ve, we, ug,
               vg, wg);
     pc = pp;
@@ -481,6 +512,7 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
   }
   for (int k = kb; k < ke; ++k) {
     const int kp = kplus(g, k);
+    const bool zph = kp >= 0 || ztop_out(g, k);
     double pp[RPT], hp[RPT], rp[RPT], fp[RPT], un[RPT], vn[RPT], wn[RPT];
     double qxv[RPT] = {}, qyv[RPT] = {}, qzv[RPT] = {};
 #pragma unroll
@@ -493,6 +525,11 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
         hp[m] = ph[n];
         rp[m] = rho[n];
         fp[m] = phi[n];
+      } else if (zph) {
+        pp[m] = -pc[m];
+        hp[m] = -hc[m];
+        rp[m] = rc[m];
+        fp[m] = -fc[m];
       }
       un[m] = u[c];
       vn[m] = v[c];
@@ -531,7 +568,7 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
         vn[m] = epi_face(vn[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
                          sm[3 * AREA + n], fc[m], idy, false, 0.0, &gy);
       }
-      if (kp >= 0)
+      if (zph)
         wn[m] = epi_face(wn[m], dt, ir0, pp[m], pc[m], rp[m], rc[m], hp[m], hc[m], fp[m], fc[m], 0.0,
                          true, g.dzc[k], &gz);
       epi_store(un[m], vn[m], wn[m], gx, gy, gz, c, u, v, w, qx, qy, qz, qxv[m], qyv[m], qzv[m],
@@ -545,7 +582,7 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
   }
 }
 
-// r = f - L_h p (FP64 residual of the defect-correction steps).  Each block
+// r = f - L_h p (FP64 residual of the defect-correction steps, any ends).  Each block
 // also sums dzf[k] * p and dzf[k] * r over its cells (fixed order, no
 // atomics) into partial[block] and partial[kResidualMaxBlocks + block], so
 // the weighted means of p and r cost no extra pass.
@@ -568,13 +605,20 @@ __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double
       const long c = k * P + t.c0;
       const int kp = kplus(g, k);
       const double pp = kp >= 0 ? p[kp * P + t.c0] : 0.0;
+      // across an outflow face the ghost holds -pc
       double lx = 0.0, ly = 0.0, lz = 0.0;
       if (t.hxp) lx += p[c + t.xp] - pc;
+      else if (g.outflow & 2) lx += -pc - pc;
       if (t.hxm) lx -= pc - p[c + t.xm];
+      else if (g.outflow & 1) lx -= pc + pc;
       if (t.hyp) ly += p[c + t.yp] - pc;
+      else if (g.outflow & 8) ly += -pc - pc;
       if (t.hym) ly -= pc - p[c + t.ym];
+      else if (g.outflow & 4) ly -= pc + pc;
       if (kp >= 0) lz += (pp - pc) / g.dzc[k];
+      else if (g.outflow & 32) lz += (-pc - pc) / g.dzf[k];
       if (km >= 0) lz -= (pc - pm) / g.dzc[km];
+      else if (g.outflow & 16) lz -= (pc + pc) / g.dzf[k];
       const double rc = f[c] - (lx * idx2 + ly * idy2 + lz / g.dzf[k]);
       r[c] = rc;
       acc += g.dzf[k] * pc;

@@ -96,6 +96,20 @@ __device__ __forceinline__ void later_passes(L& lds, int t, const T* __restrict_
   }
 }
 
+// Outflow at both ends (BC_D): the sine transform (DST-II) of a line is the
+// cosine transform (DCT-II) of the line with every odd element negated, read
+// in reverse order: DST_k(x) = DCT_{N-1-k}((-1)^i x_i).  The forward pass
+// negates odd elements on load and the inverse negates them on store; the
+// packed coefficient c then belongs to sine mode N-1-c (the eigenvalue
+// tables are indexed by c accordingly).
+template <typename T>
+__device__ __forceinline__ void flip_odd(int e, T& re, T& im) {
+  if (e & 1) {
+    re = -re;
+    im = -im;
+  }
+}
+
 // stride NS of the last pass of the plan for length N
 template <int N, int PTM, int NS = 1>
 constexpr int last_ns() {
@@ -118,8 +132,9 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
     int e = t + r * TPL;
-    if constexpr (BC == BC_N) e = dct_perm<N>(e);
+    if constexpr (BC != BC_P) e = dct_perm<N>(e);
     load(e, vr[r], vi[r]);
+    if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
   }
   {
     T wr[PT], wi[PT];
@@ -207,7 +222,8 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       int e = pass_out<N, NSL, PTM>(t, b, r);
-      if constexpr (BC == BC_N) e = dct_perm<N>(e);
+      if constexpr (BC != BC_P) e = dct_perm<N>(e);
+      if constexpr (BC == BC_D) flip_odd(e, vr[b * RL + r], vi[b * RL + r]);
       store(e, vr[b * RL + r], vi[b * RL + r]);
     }
 }
@@ -231,8 +247,9 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
     int e = t + r * TPL;
-    if constexpr (BC == BC_N) e = dct_perm<N>(e);
+    if constexpr (BC != BC_P) e = dct_perm<N>(e);
     load(e, vr[r], vi[r]);
+    if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
   }
   {
     T wr[PT], wi[PT];
@@ -255,10 +272,10 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
     if (m == 0) {
       T hr, hi;
       lds.get(N / 2, hr, hi);
-      // packed coefficients 0 and 1 (periodic) or 0 and N/2 (walls)
+      // packed coefficients 0 and 1 (periodic) or 0 and N/2 (walls, outflow)
       T a0 = zr, b0 = zi, a1 = hr, b1 = hi;
       int c1 = 1;
-      if constexpr (BC == BC_N) {
+      if constexpr (BC != BC_P) {
         const T h = T(0.70710678118654752440084436210485);
         a1 *= h;
         b1 *= h;
@@ -266,7 +283,7 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
       }
       scale(0, a0, b0);
       scale(c1, a1, b1);
-      if constexpr (BC == BC_N) {
+      if constexpr (BC != BC_P) {
         const T r2 = T(1.4142135623730950488016887242097);
         a1 *= r2;
         b1 *= r2;
@@ -295,7 +312,8 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
 #pragma unroll
     for (int r = 0; r < RL; ++r) {
       int e = pass_out<N, NSL, PTM>(t, b, r);
-      if constexpr (BC == BC_N) e = dct_perm<N>(e);
+      if constexpr (BC != BC_P) e = dct_perm<N>(e);
+      if constexpr (BC == BC_D) flip_odd(e, vr[b * RL + r], vi[b * RL + r]);
       store(e, vr[b * RL + r], vi[b * RL + r]);
     }
 }
@@ -704,14 +722,25 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   return hipGetLastError();
 }
 
+// calls f(std::integral_constant<int, BC>{}) for the run-time boundary code
+template <typename F>
+static hipError_t with_bc(int bc, F&& f) {
+  switch (bc) {
+    case BC_P: return f(std::integral_constant<int, BC_P>{});
+    case BC_N: return f(std::integral_constant<int, BC_N>{});
+    case BC_D: return f(std::integral_constant<int, BC_D>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 static hipError_t launch_zspec_t(T* data, const ZSpecArgs& a, const T* tab, int pt, int nb,
                                  const int* skip, hipStream_t st) {
-  if (a.bcz == BC_P)
-    return pt == 8 ? launch_zspec_pt<T, BC_P, 8>(data, a, tab, nb, skip, st)
-                   : launch_zspec_pt<T, BC_P, 16>(data, a, tab, nb, skip, st);
-  return pt == 8 ? launch_zspec_pt<T, BC_N, 8>(data, a, tab, nb, skip, st)
-                 : launch_zspec_pt<T, BC_N, 16>(data, a, tab, nb, skip, st);
+  return with_bc(a.bcz, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return pt == 8 ? launch_zspec_pt<T, BC, 8>(data, a, tab, nb, skip, st)
+                   : launch_zspec_pt<T, BC, 16>(data, a, tab, nb, skip, st);
+  });
 }
 
 hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
@@ -727,63 +756,59 @@ hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, l
                            int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st) {
   const PassOpts o{};
-  return bc == BC_P ? launch_xfwd_bc<double, double, BC_P, false>(in, nb, out, ostride, nx, nrows,
-                                                                  tab, pt, o, st)
-                    : launch_xfwd_bc<double, double, BC_N, false>(in, nb, out, ostride, nx, nrows,
-                                                                  tab, pt, o, st);
+  return with_bc(bc, [&](auto B) {
+    return launch_xfwd_bc<double, double, decltype(B)::value, false>(in, nb, out, ostride, nx,
+                                                                     nrows, tab, pt, o, st);
+  });
 }
 hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& out, int nb,
                            int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st) {
   const PassOpts o{};
-  return bc == BC_P ? launch_xinv_bc<double, double, BC_P, false>(in, istride, out, nb, nx, nrows,
-                                                                  tab, pt, o, st)
-                    : launch_xinv_bc<double, double, BC_N, false>(in, istride, out, nb, nx, nrows,
-                                                                  tab, pt, o, st);
+  return with_bc(bc, [&](auto B) {
+    return launch_xinv_bc<double, double, decltype(B)::value, false>(in, istride, out, nb, nx,
+                                                                     nrows, tab, pt, o, st);
+  });
 }
 hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
                            int nx, int bc, long nrows, const float* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
-  if (o.sub)
-    return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, true>(in, nb, out, ostride, nx, nrows,
-                                                                  tab, pt, o, st)
-                      : launch_xfwd_bc<double, float, BC_N, true>(in, nb, out, ostride, nx, nrows,
-                                                                  tab, pt, o, st);
-  return bc == BC_P ? launch_xfwd_bc<double, float, BC_P, false>(in, nb, out, ostride, nx, nrows,
-                                                                 tab, pt, o, st)
-                    : launch_xfwd_bc<double, float, BC_N, false>(in, nb, out, ostride, nx, nrows,
-                                                                 tab, pt, o, st);
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return o.sub ? launch_xfwd_bc<double, float, BC, true>(in, nb, out, ostride, nx, nrows, tab,
+                                                           pt, o, st)
+                 : launch_xfwd_bc<double, float, BC, false>(in, nb, out, ostride, nx, nrows, tab,
+                                                            pt, o, st);
+  });
 }
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
                            int nx, int bc, long nrows, bool accum, const float* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
-  if (bc == BC_P)
-    return accum ? launch_xinv_bc<float, double, BC_P, true>(in, istride, out, nb, nx, nrows, tab,
-                                                             pt, o, st)
-                 : launch_xinv_bc<float, double, BC_P, false>(in, istride, out, nb, nx, nrows,
-                                                              tab, pt, o, st);
-  return accum ? launch_xinv_bc<float, double, BC_N, true>(in, istride, out, nb, nx, nrows, tab,
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return accum ? launch_xinv_bc<float, double, BC, true>(in, istride, out, nb, nx, nrows, tab,
                                                            pt, o, st)
-               : launch_xinv_bc<float, double, BC_N, false>(in, istride, out, nb, nx, nrows, tab,
+                 : launch_xinv_bc<float, double, BC, false>(in, istride, out, nb, nx, nrows, tab,
                                                             pt, o, st);
+  });
 }
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const double* tab, int pt, int lines, hipStream_t st) {
   PassOpts o{};
   o.lines = lines;
-  if (bc == BC_P)
-    return fwd ? launch_y_bc<double, BC_P, true>(data, nx, ny, nplanes, tab, pt, o, st)
-               : launch_y_bc<double, BC_P, false>(data, nx, ny, nplanes, tab, pt, o, st);
-  return fwd ? launch_y_bc<double, BC_N, true>(data, nx, ny, nplanes, tab, pt, o, st)
-             : launch_y_bc<double, BC_N, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return fwd ? launch_y_bc<double, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<double, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  });
 }
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const float* tab, int pt, const PassOpts& o, hipStream_t st) {
-  if (bc == BC_P)
-    return fwd ? launch_y_bc<float, BC_P, true>(data, nx, ny, nplanes, tab, pt, o, st)
-               : launch_y_bc<float, BC_P, false>(data, nx, ny, nplanes, tab, pt, o, st);
-  return fwd ? launch_y_bc<float, BC_N, true>(data, nx, ny, nplanes, tab, pt, o, st)
-             : launch_y_bc<float, BC_N, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return fwd ? launch_y_bc<float, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<float, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  });
 }
 
 }  // namespace vp

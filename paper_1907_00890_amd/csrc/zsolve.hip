@@ -36,7 +36,15 @@
 // on the right-hand side (a second right-hand side of the reduced system,
 // zero in every interior), and F_w follows from one scalar equation.
 //
-// The (kx, ky) = (0, 0) line has lambda = 0 and is singular.  It is solved in
+// An outflow end (p = 0 on the boundary face, half a cell beyond the end
+// centre) adds 2 / dzf^2 of the end cell to the diagonal of B: its row sum
+// becomes ell + 2 / dzf^2 > 0.  The end rows are always the first or last
+// unknown of a segment, so only the reduced system sees the term (in its row
+// sums rho, which keeps every pivot a sum of positive terms).  With an
+// outflow end anywhere no line is singular; line (0, 0) of a plan whose only
+// outflow ends are in z (lambda = 0) is then solved like any other line.
+//
+// Without outflow ends the (kx, ky) = (0, 0) line has lambda = 0 and is singular.  It is solved in
 // conservation form instead of by elimination: after its right-hand side
 // loses its dzf-weighted mean (compatibility), the face fluxes are the running
 // sum F[k+1/2] = sum_{j<=k} dzf[j] r[j] (plus a constant fixed by
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   x += blockIdx.y * A.batch_stride;
   const bool valid = line < A.plane;
   const bool blk0 = blockIdx.x == 0;
-  const bool sing = blk0 && l == 0;  // line 0: lambda_x + lambda_y == 0
+  const bool sing = blk0 && l == 0 && A.singular;  // line 0: lambda_x + lambda_y == 0
   const bool gen = valid && !sing;
   const bool per = A.periodic != 0;
   const long P = A.plane;
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   const double rfirst = al[0];
 
   // ---- singular line (block 0, lanes l == 0): segmented running sums ----
-  if (blk0) {
+  if (blk0 && A.singular) {
     // sums over the segments of this lane's line (block-wide barriers)
     auto line_sum = [&](double v) -> double {
       red[s * LB + l] = v;
@@ -379,11 +387,11 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
       }
       lo[oF] = a0;
       up[oF] = c0 * g1;
-      rho[oF] = ell * (1.0 + c0 * t1);
+      rho[oF] = ell * (1.0 + c0 * t1) + (k0 == 0 ? A.dlo : 0.0);
       R1[oF] = c0 * a1 - rfirst;
       lo[oE] = aE * bL;
       up[oE] = cE;
-      rho[oE] = ell * (1.0 + aE * tL);
+      rho[oE] = ell * (1.0 + aE * tL) + (k1 == A.nz - 1 ? A.dhi : 0.0);
       R1[oE] = aE * aL - rlast;
       // periodic: unit wrap flux entering at the first cell, leaving at the last
       R2[oF] = (per && s == 0) ? -1.0 / A.dzf[0] : 0.0;
@@ -423,18 +431,19 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   }
 }
 
-// nz == 1: every line is a single unknown, x = r / lambda (0 on the (0,0) line)
+// nz == 1: every line is a single unknown, x = r / (lambda - dlo - dhi)
+// (0 on the singular (0,0) line)
 template <typename T>
 __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
   const long line = (long)blockIdx.x * 256 + threadIdx.x;
   if (line >= A.plane || (A.skip && A.skip[blockIdx.y])) return;
   x += blockIdx.y * A.batch_stride;
   const double r = double(x[line]) * A.scale;
-  if (line == 0) {
+  if (line == 0 && A.singular) {
     if (A.mean_out) A.mean_out[blockIdx.y] = r;
     x[0] = T(0);
   } else {
-    const double lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx];
+    const double lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx] - (A.dlo + A.dhi);
     x[line] = T(r / lam);
   }
 }
