@@ -17,6 +17,12 @@ if not os.path.exists(LIB_PATH):
         f"libvofpoisson.so not found at {LIB_PATH}; build it first "
         "(python paper_1907_00890_amd/build.py or __graft_entry__.build())")
 
+# torch first: the library's HIP runtime dependency then resolves to the
+# runtime torch has already loaded, so the process holds one HIP / HSA runtime.
+# Loaded first, the library would bring in the system runtime next to torch's
+# own copy, and the second of the two to initialise cannot open the device.
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 _p = ctypes.c_void_p

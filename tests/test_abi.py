@@ -124,3 +124,22 @@ def test_footprint(lib):
     assert lib.poisson_plan_footprint(64, 64, 64, 0, 17) < 0
     assert lib.poisson_plan_device_bytes(None) < 0
 
+
+@pytest.mark.parametrize("first", ["paper_1907_00890_amd.serve", "paper_1907_00890_amd", "torch"])
+def test_one_hip_runtime_per_process(first):
+    """Whatever is imported first, the process maps a single HIP runtime and a
+    single HSA runtime (the library binds to the one torch holds): a second
+    copy next to torch's cannot open the device once torch has."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import importlib; importlib.import_module(%r)\n"
+        "import torch, paper_1907_00890_amd.serve\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "for key in ('amdhip64', 'hsa-runtime64'):\n"
+        "    paths = {l.split()[-1] for l in maps if key in l}\n"
+        "    assert len(paths) == 1, (key, sorted(paths))\n"
+        "print('ok')\n" % (ROOT, first))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
