@@ -4,10 +4,11 @@
 namespace vp {
 
 // Transform code of a direction: periodic; walls at both ends (zero normal
-// gradient, cosine transform); outflow (p = 0 on the boundary face) at both
-// ends (sine transform).  The z pass also takes a wall at one end and an
-// outflow at the other (zsolve).
-enum : int { BC_P = 0, BC_N = 1, BC_D = 2 };
+// gradient, cosine transform DCT-II); outflow (p = 0 on the boundary face)
+// at both ends (sine transform DST-II); a wall at the lower end and an
+// outflow at the upper (quarter-wave cosine transform DCT-IV), or the
+// reverse (the DCT-IV of the reversed line).
+enum : int { BC_P = 0, BC_N = 1, BC_D = 2, BC_ND = 3, BC_DN = 4 };
 
 // Per-end letters 'P', 'N' or 'D' of x-, x+, y-, y+, z-, z+ (upper case)
 // from 3 letters (both ends of x, y, z alike) or 6 (one per end), either
@@ -15,8 +16,7 @@ enum : int { BC_P = 0, BC_N = 1, BC_D = 2 };
 // one end only.
 int parse_ends(const char* bc, char ends[6]);
 
-// Transform code (BC_P, BC_N or BC_D) of a direction whose ends are lo, hi;
-// -1 for a wall at one end and an outflow at the other (no x / y transform).
+// Transform code of a direction whose ends are lo, hi (letters as above).
 int direction_code(char lo, char hi);
 
 }  // namespace vp

@@ -68,8 +68,8 @@ hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, lo
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
                            int nx, int bc, long nrows, bool accum, const float* tab, int pt,
                            const PassOpts& o, hipStream_t st);
-// blocks per member of an x pass (the norms partial sums of k_xinv)
-long xpass_blocks(int nx, int pt, long nrows);
+// blocks per member of an x pass (the norms partial sums of the x inverse)
+long xpass_blocks(int nx, int bc, int pt, long nrows);
 // y passes over nplanes consecutive z-planes (nz * batch)
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const double* tab, int pt, int lines, hipStream_t st);

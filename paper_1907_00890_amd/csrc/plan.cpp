@@ -48,25 +48,34 @@ const char* const kClassNames[K_NCLASS] = {
     "residual", "rhs_assembly", "correction", "extension", "step_epilogue"};
 
 // Twiddle table of one direction, (cos, sin) pairs: of 2 pi k/N for k < N,
-// then of pi m/(2N) for m <= N/2 (the DCT post/pre rotation).
-std::vector<double> make_table(int n) {
-  std::vector<double> t(2 * n + 2 * (n / 2 + 1));
+// then of pi m/(2N) for m <= N/2 (the DCT post/pre rotation).  For a wall at
+// one end and an outflow at the other (the quarter-wave transform, a complex
+// FFT of length H = N/2): of 2 pi j/H for j < H, of pi (4e+1)/(4N) for
+// e < H, of pi k/N for k < H.  Both layouts have the same size.
+std::vector<double> make_table(int n, int bc) {
+  std::vector<double> t(2 * n + 2 * (n / 2 + 1), 0.0);
   const double pi = 3.14159265358979323846264338327950288;
-  for (int k = 0; k < n; ++k) {
-    t[2 * k] = std::cos(2.0 * pi * k / n);
-    t[2 * k + 1] = std::sin(2.0 * pi * k / n);
+  auto put = [&](int pair, double angle) {
+    t[2 * pair] = std::cos(angle);
+    t[2 * pair + 1] = std::sin(angle);
+  };
+  if (bc == vp::BC_ND || bc == vp::BC_DN) {
+    const int h = n / 2;
+    for (int j = 0; j < h; ++j) put(j, 2.0 * pi * j / h);
+    for (int e = 0; e < h; ++e) put(h + e, pi * (4.0 * e + 1.0) / (4.0 * n));
+    for (int k = 0; k < h; ++k) put(2 * h + k, pi * k / n);
+    return t;
   }
-  for (int m = 0; m <= n / 2; ++m) {
-    t[2 * n + 2 * m] = std::cos(pi * m / (2.0 * n));
-    t[2 * n + 2 * m + 1] = std::sin(pi * m / (2.0 * n));
-  }
+  for (int k = 0; k < n; ++k) put(k, 2.0 * pi * k / n);
+  for (int m = 0; m <= n / 2; ++m) put(n + m, pi * m / (2.0 * n));
   return t;
 }
 
 // Eigenvalue of the 1-D second difference for every packed coefficient
 // position: periodic -(4/h^2) sin^2(pi m/n) (packed real DFT order), walls
 // -(4/h^2) sin^2(pi c/(2n)) (cosine mode c), outflow at both ends
-// -(4/h^2) sin^2(pi (n-c)/(2n)) = -(4/h^2) cos^2(pi c/(2n)) (sine mode n-1-c).
+// -(4/h^2) sin^2(pi (n-c)/(2n)) = -(4/h^2) cos^2(pi c/(2n)) (sine mode n-1-c),
+// a wall and an outflow -(4/h^2) sin^2(pi (2c+1)/(4n)) (quarter-wave mode c).
 std::vector<double> make_lambda(int n, double h, int bc) {
   const double pi = 3.14159265358979323846264338327950288;
   std::vector<double> l(n);
@@ -77,8 +86,10 @@ std::vector<double> make_lambda(int n, double h, int bc) {
       s = std::sin(pi * m / n);
     } else if (bc == vp::BC_N) {
       s = std::sin(pi * c / (2.0 * n));
-    } else {
+    } else if (bc == vp::BC_D) {
       s = std::cos(pi * c / (2.0 * n));
+    } else {
+      s = std::sin(pi * (2.0 * c + 1.0) / (4.0 * n));
     }
     l[c] = -4.0 / (h * h) * s * s;
   }
@@ -89,7 +100,7 @@ std::vector<double> make_lambda(int n, double h, int bc) {
 
 struct poisson_plan {
   int nx = 0, ny = 0, nz = 0;
-  int bc[3] = {0, 0, 0};  // transform codes of x, y; z: BC_P, BC_N (walls or one outflow end), BC_D
+  int bc[3] = {0, 0, 0};  // transform codes of x, y, z (vp::BC_*)
   char ends[6] = {};      // 'P' / 'N' / 'D' at x-, x+, y-, y+, z-, z+
   bool singular = true;   // no outflow end: the constants are the null space
   int precision = 0, max_batch = 1, dc_steps = 1;
@@ -198,7 +209,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   int st;
   // tables
-  const std::vector<double> tx = make_table(nx), ty = make_table(ny);
+  const std::vector<double> tx = make_table(nx, P->bc[0]), ty = make_table(ny, P->bc[1]);
   if ((st = P->upload(&P->tabx64, tx, "table x"))) return st;
   if ((st = P->upload(&P->taby64, ty, "table y"))) return st;
   if (P->precision == VP_PRECISION_MIXED) {
@@ -297,9 +308,9 @@ int plan_init(poisson_plan* P, const double* dz) {
   // the x and y passes; a wall at one end and an outflow at the other keeps
   // the tridiagonal pass
   P->z_spec_ok = Z.uniform_z && nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0 &&
-                 vp::direction_code(P->ends[4], P->ends[5]) >= 0;
+                 P->bc[2] <= vp::BC_D;
   if (P->z_spec_ok) {
-    const std::vector<double> tz = make_table(nz);
+    const std::vector<double> tz = make_table(nz, P->bc[2]);
     if ((st = P->upload(&P->tabz64, tz, "table z"))) return st;
     if (P->precision == VP_PRECISION_MIXED) {
       std::vector<float> fz(tz.begin(), tz.end());
@@ -431,7 +442,7 @@ int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const
   }
   double* const pmeans = P->mean + vp::kMaxBatch;      // FP64 weighted mean of p per member
   double* const rmeans = P->mean + 2 * vp::kMaxBatch;  // and of the residual
-  const long nblk = vp::xpass_blocks(P->nx, P->x_pt, nrows);
+  const long nblk = vp::xpass_blocks(P->nx, P->bc[0], P->x_pt, nrows);
   VP_HIP(vp::launch_dc_reset(P->dc_state, P->dc_flags, nb, st), "dc reset");
   vp::PassOpts o;
   o.norms = P->dc_norms;
@@ -482,9 +493,7 @@ poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, 
   char ends[6];
   (void)vp::parse_ends(bc, ends);  // checked above
   int bcs[3];
-  for (int d = 0; d < 2; ++d) bcs[d] = vp::direction_code(ends[2 * d], ends[2 * d + 1]);
-  bcs[2] = ends[4] == 'P' ? vp::BC_P
-           : (ends[4] == 'D' && ends[5] == 'D') ? vp::BC_D : vp::BC_N;
+  for (int d = 0; d < 3; ++d) bcs[d] = vp::direction_code(ends[2 * d], ends[2 * d + 1]);
 
   poisson_plan* P = new (std::nothrow) poisson_plan();
   if (!P) return fail(VP_ENOMEM);

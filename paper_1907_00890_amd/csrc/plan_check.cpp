@@ -32,9 +32,8 @@ int parse_ends(const char* bc, char e[6]) {
 
 int direction_code(char lo, char hi) {
   if (lo == 'P') return BC_P;
-  if (lo == 'N' && hi == 'N') return BC_N;
-  if (lo == 'D' && hi == 'D') return BC_D;
-  return -1;
+  if (lo == hi) return lo == 'N' ? BC_N : BC_D;
+  return lo == 'N' ? BC_ND : BC_DN;
 }
 
 }  // namespace vp
@@ -52,9 +51,6 @@ int poisson_plan_check(int nx, int ny, int nz, double dx, double dy, const doubl
     if (!(dz[k] > 0) || !std::isfinite(dz[k])) return VP_EINVAL;
   if (e[4] == 'P' && nz < 3) return VP_EINVAL;
   if (precision != VP_PRECISION_FP64 && precision != VP_PRECISION_MIXED) return VP_EINVAL;
-  // x and y: periodic, walls at both ends or outflow at both ends
-  if (vp::direction_code(e[0], e[1]) < 0 || vp::direction_code(e[2], e[3]) < 0)
-    return VP_EUNSUPPORTED;
   if (!pow2_in(nx, 8, 1024) || !pow2_in(ny, 8, 1024) || nz > 1024) return VP_EUNSUPPORTED;
   return VP_OK;
 }

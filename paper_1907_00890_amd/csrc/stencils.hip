@@ -8,8 +8,8 @@
 // handled through a mirrored ghost cell: p, p_hat and phi of the ghost are
 // minus the end cell's, rho is the end cell's, at distance dz of the end
 // cell (the plan stores it as the last centre distance).  The face stencils
-// take such a face at the upper z end; the residual (the Laplacian alone)
-// takes one at any end.
+// take such faces at upper ends (the last stored face of a direction); the
+// residual (the Laplacian alone) takes them at any end.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -70,6 +70,9 @@ __device__ __forceinline__ int kminus(const GridArgs& g, int k) {
 __device__ __forceinline__ bool ztop_out(const GridArgs& g, int k) {
   return k == g.nz - 1 && (g.outflow & 32);
 }
+// outflow at the upper x / y end (the face of the cell with the last index)
+__device__ __forceinline__ bool xtop_out(const GridArgs& g) { return (g.outflow & 2) != 0; }
+__device__ __forceinline__ bool ytop_out(const GridArgs& g) { return (g.outflow & 8) != 0; }
 
 // inverse of the face density 1 / ((rho_a + rho_b) / 2)
 __device__ __forceinline__ double inv_face_rho(double ra, double rb) { return 2.0 / (ra + rb); }
@@ -133,9 +136,11 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
       php = -phc;
       rhp = rhc;
     }
-    const RhsNbr xp{t.hxp ? ph[c + t.xp] : 0.0, t.hxp ? rho[c + t.xp] : 0.0, t.hxp};
+    const RhsNbr xp = t.hxp ? RhsNbr{ph[c + t.xp], rho[c + t.xp], true}
+                            : RhsNbr{-phc, rhc, xtop_out(g)};
     const RhsNbr xm{t.hxm ? ph[c + t.xm] : 0.0, t.hxm ? rho[c + t.xm] : 0.0, t.hxm};
-    const RhsNbr yp{t.hyp ? ph[c + t.yp] : 0.0, t.hyp ? rho[c + t.yp] : 0.0, t.hyp};
+    const RhsNbr yp = t.hyp ? RhsNbr{ph[c + t.yp], rho[c + t.yp], true}
+                            : RhsNbr{-phc, rhc, ytop_out(g)};
     const RhsNbr ym{t.hym ? ph[c + t.ym] : 0.0, t.hym ? rho[c + t.ym] : 0.0, t.hym};
     const RhsNbr zp{php, rhp, zph}, zm{phm, rhm, km >= 0};
     const double wc = w[c];
@@ -260,8 +265,12 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
     for (int m = 0; m < RPT; ++m) {
       const long c = k * P + c0[m];
       const int sl = (ty + 4 * m + 1) * W + tx + 1;
-      const RhsNbr xp{sph[sl + 1], srh[sl + 1], hxp}, xm{sph[sl - 1], srh[sl - 1], hxm};
-      const RhsNbr yp{sph[sl + W], srh[sl + W], hyp[m]}, ym{sph[sl - W], srh[sl - W], hym[m]};
+      const RhsNbr xp = hxp ? RhsNbr{sph[sl + 1], srh[sl + 1], true}
+                            : RhsNbr{-phc[m], rhc[m], xtop_out(g)};
+      const RhsNbr xm{sph[sl - 1], srh[sl - 1], hxm};
+      const RhsNbr yp = hyp[m] ? RhsNbr{sph[sl + W], srh[sl + W], true}
+                               : RhsNbr{-phc[m], rhc[m], ytop_out(g)};
+      const RhsNbr ym{sph[sl - W], srh[sl - W], hym[m]};
       const RhsNbr zp{php[m], rhp[m], zph}, zm{phm[m], rhm[m], km >= 0};
       const double wc = wcs[m];
       b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xm, yp, ym, zp, dzcp, zm,
@@ -304,13 +313,17 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
       hp = -hc;
       rp = rc;
     }
-    if (t.hxp) {
-      const double gp = (p[c + t.xp] - pc) * idx, gh = (ph[c + t.xp] - hc) * idx;
-      u[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rho[c + t.xp]) - ir0) * gh);
+    if (t.hxp || xtop_out(g)) {
+      const double pn = t.hxp ? p[c + t.xp] : -pc, hn = t.hxp ? ph[c + t.xp] : -hc;
+      const double rn = t.hxp ? rho[c + t.xp] : rc;
+      const double gp = (pn - pc) * idx, gh = (hn - hc) * idx;
+      u[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh);
     }
-    if (t.hyp) {
-      const double gp = (p[c + t.yp] - pc) * idy, gh = (ph[c + t.yp] - hc) * idy;
-      v[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rho[c + t.yp]) - ir0) * gh);
+    if (t.hyp || ytop_out(g)) {
+      const double pn = t.hyp ? p[c + t.yp] : -pc, hn = t.hyp ? ph[c + t.yp] : -hc;
+      const double rn = t.hyp ? rho[c + t.yp] : rc;
+      const double gp = (pn - pc) * idy, gh = (hn - hc) * idy;
+      v[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh);
     }
     if (zph) {
       const double h = g.dzc[k];
@@ -344,8 +357,8 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
     const int kp = kplus(g, k);
     const bool zph = kp >= 0 || ztop_out(g, k);
     const double fp = kp >= 0 ? phi[kp * P + t.c0] : (zph ? -fc : 0.0);
-    const double gx = t.hxp ? (phi[c + t.xp] - fc) * idx : 0.0;
-    const double gy = t.hyp ? (phi[c + t.yp] - fc) * idy : 0.0;
+    const double gx = t.hxp ? (phi[c + t.xp] - fc) * idx : (xtop_out(g) ? (-fc - fc) * idx : 0.0);
+    const double gy = t.hyp ? (phi[c + t.yp] - fc) * idy : (ytop_out(g) ? (-fc - fc) * idy : 0.0);
     const double gz = zph ? (fp - fc) / g.dzc[k] : 0.0;
     const double a = u[c] - gx, bb = v[c] - gy, cc = w[c] - gz;
     ue[c] = a;
@@ -431,10 +444,14 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
     if (t.hxp) {
       const long n = c + t.xp;
       un = epi_face(un, dt, ir0, p[n], pc, rho[n], rc, ph[n], hc, phi[n], fc, idx, false, 0.0, &gx);
+    } else if (xtop_out(g)) {
+      un = epi_face(un, dt, ir0, -pc, pc, rc, rc, -hc, hc, -fc, fc, idx, false, 0.0, &gx);
     }
     if (t.hyp) {
       const long n = c + t.yp;
       vn = epi_face(vn, dt, ir0, p[n], pc, rho[n], rc, ph[n], hc, phi[n], fc, idy, false, 0.0, &gy);
+    } else if (ytop_out(g)) {
+      vn = epi_face(vn, dt, ir0, -pc, pc, rc, rc, -hc, hc, -fc, fc, idy, false, 0.0, &gy);
     }
     double pp = 0.0, hp = 0.0, rp = 0.0, fp = 0.0;
     const bool zph = kp >= 0 || ztop_out(g, k);
@@ -562,11 +579,17 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
         const int n = sl + 1;
         un[m] = epi_face(un[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
                          sm[3 * AREA + n], fc[m], idx, false, 0.0, &gx);
+      } else if (xtop_out(g)) {
+        un[m] = epi_face(un[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m], fc[m],
+                         idx, false, 0.0, &gx);
       }
       if (hyp[m]) {
         const int n = sl + W;
         vn[m] = epi_face(vn[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
                          sm[3 * AREA + n], fc[m], idy, false, 0.0, &gy);
+      } else if (ytop_out(g)) {
+        vn[m] = epi_face(vn[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m], fc[m],
+                         idy, false, 0.0, &gy);
       }
       if (zph)
         wn[m] = epi_face(wn[m], dt, ir0, pp[m], pc[m], rp[m], rc[m], hp[m], hc[m], fp[m], fc[m], 0.0,

@@ -319,6 +319,72 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// A wall at one end and an outflow at the other (BC_ND: wall at the lower
+// end, BC_DN: at the upper): the eigenvectors of the second difference are
+// the quarter-wave cosines cos(pi (2k+1)(2i+1)/(4N)), i.e. the DCT-IV (for
+// BC_DN the same on the reversed line).  A DCT-IV of one real line of
+// length N is one complex FFT of length H = N/2:
+//   v_e = (x_{2e} + i x_{N-1-2e}) e^{-i pi (4e+1)/(4N)},  V = FFT_H(v),
+//   W_k = V_k e^{-i pi k/N},  X_{2k} = Re W_k,  X_{N-1-2k} = -Im W_k,
+// and the DCT-IV is its own inverse up to the factor N/2.  `load(e, v)`
+// gives element e of the line, `store(c, v)` writes element c of the
+// result.  tab: (cos, sin) pairs of 2 pi j/H for j < H, then of
+// pi (4e+1)/(4N) for e < H, then of pi k/N for k < H.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int PTM, typename L, typename Load, typename Store>
+__device__ __forceinline__ void quarter_body(L& lds, int t, const T* __restrict__ tab, Load load,
+                                             Store store) {
+  constexpr int H = N / 2;
+  using S = FftShape<H, PTM>;
+  constexpr int PT = S::PT, TPL = S::TPL;
+  constexpr int R1 = PassRadix<H, 1, PTM>::R;
+  using T2 = typename Vec2<T>::type;
+  const T2* pre = reinterpret_cast<const T2*>(tab) + H;
+  const T2* post = pre + H;
+  T vr[PT], vi[PT];
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    const int e = t + r * TPL;
+    T a, b;
+    load(2 * e, a);
+    load(N - 1 - 2 * e, b);
+    const T2 w = pre[e];
+    vr[r] = a * w.x + b * w.y;  // (a + i b)(cos - i sin)
+    vi[r] = b * w.x - a * w.y;
+  }
+  {
+    T wr[PT], wi[PT];
+    pass_compute<T, H, 1, -1, PTM>(vr, vi, wr, wi);
+  }
+  if constexpr (R1 < H) {
+#pragma unroll
+    for (int b = 0; b < PT / R1; ++b)
+#pragma unroll
+      for (int r = 0; r < R1; ++r)
+        lds.put(pass_out<H, 1, PTM>(t, b, r), vr[b * R1 + r], vi[b * R1 + r]);
+    later_passes<T, H, R1, -1, true, PTM>(lds, t, tab, vr, vi);
+  }
+  constexpr int NSL = last_ns<H, PTM>();
+  constexpr int RL = PassRadix<H, NSL, PTM>::R;
+#pragma unroll
+  for (int b = 0; b < PT / RL; ++b)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      const int k = pass_out<H, NSL, PTM>(t, b, r);
+      const T2 w = post[k];
+      const T xr = vr[b * RL + r], xi = vi[b * RL + r];
+      store(2 * k, xr * w.x + xi * w.y);
+      store(N - 1 - 2 * k, -(xi * w.x - xr * w.y));
+    }
+}
+
+// physical position of element e of a line for the quarter-wave transform
+template <int N, int BC>
+__device__ __forceinline__ int qpos(int e) {
+  return BC == BC_DN ? N - 1 - e : e;
+}
+
+// ---------------------------------------------------------------------------
 // x kernels: a block owns 2*LPB consecutive rows (nrows is even)
 // ---------------------------------------------------------------------------
 // SUB: member b's input is read as in[b] - sub[b] (FP64, before any
@@ -506,6 +572,137 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(T* __restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// quarter-wave x and y passes (BC_ND, BC_DN): one line per complex FFT of
+// length N/2.  x: a block owns LPB consecutive rows, TPL threads each.  y:
+// a block owns a tile of `cols` consecutive columns of one z-plane, thread
+// (q, t) with q fastest.  The forward pass writes the DCT-IV coefficients in
+// natural order; the inverse applies the same transform and doubles it, so
+// that inverse(forward(x)) = N x as for the other transforms.  The x
+// kernels take the same batch, shift, accumulation, skip and norm options as
+// k_xfwd / k_xinv.
+// ---------------------------------------------------------------------------
+template <int N, int PTM>
+constexpr int xq_rows_per_block() {
+  return 256 / FftShape<N / 2, PTM>::TPL;
+}
+
+template <typename TI, typename T, int N, int BC, bool SUB, int PTM>
+__global__ __launch_bounds__(256) void k_xqfwd(const Batch<const TI> in, T* __restrict__ out,
+                                                long ostride, long nrows,
+                                                const T* __restrict__ tab,
+                                                const double* __restrict__ sub,
+                                                const int* __restrict__ skip) {
+  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = 256 / TPL;
+  __shared__ T lds_mem[2 * LPB * lds_len<H>()];
+  if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
+  const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long row = (long)blockIdx.x * LPB + q;
+  const bool ok = row < nrows;
+  const TI* g = in.p[blockIdx.y] + row * N;
+  T* o = out + blockIdx.y * ostride + row * N;
+  TI shift = TI(0);
+  if constexpr (SUB) shift = TI(sub[blockIdx.y]);
+  XLds<T, H> lds(lds_mem, q, LPB);
+  quarter_body<T, N, PTM>(
+      lds, t, tab,
+      [&](int e, T& v) {
+        if constexpr (SUB) v = ok ? T(g[qpos<N, BC>(e)] - shift) : T(0);
+        else v = ok ? T(g[qpos<N, BC>(e)]) : T(0);
+      },
+      [&](int c, T v) {
+        if (ok) o[c] = v;
+      });
+}
+
+// block sums of e^2 and p^2 to norms[2 * (member * gridDim.x + block) + {0, 1}]
+// (fixed order, through the block's LDS, which the caller no longer needs)
+__device__ __forceinline__ void block_norms(double* red, double ee, double pp,
+                                            double* __restrict__ norms) {
+  __syncthreads();
+  red[threadIdx.x] = ee;
+  red[256 + threadIdx.x] = pp;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      red[256 + threadIdx.x] += red[256 + threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+    norms[o] = red[0];
+    norms[o + 1] = red[256];
+  }
+}
+
+template <typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
+__global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long istride,
+                                                const Batch<TO> out, long nrows,
+                                                const T* __restrict__ tab,
+                                                const double* __restrict__ sub,
+                                                const int* __restrict__ skip,
+                                                double* __restrict__ norms) {
+  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = 256 / TPL;
+  constexpr bool NORMS = !std::is_same<T, TO>::value;
+  // the norm reduction needs 512 doubles of LDS
+  constexpr int LDS_T = 2 * LPB * lds_len<H>();
+  constexpr int RED_T = 512 * (int)sizeof(double) / (int)sizeof(T);
+  __shared__ T lds_mem[LDS_T > RED_T ? LDS_T : RED_T];
+  if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
+  double ee = 0.0, pp = 0.0;
+  const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long row = (long)blockIdx.x * LPB + q;
+  const bool ok = row < nrows;
+  const T* ia = in + blockIdx.y * istride + row * N;
+  TO* o = out.p[blockIdx.y] + row * N;
+  TO shift = TO(0);
+  if constexpr (ACCUM) {
+    if (sub) shift = TO(sub[blockIdx.y]);
+  }
+  XLds<T, H> lds(lds_mem, q, LPB);
+  quarter_body<T, N, PTM>(
+      lds, t, tab, [&](int c, T& v) { v = ok ? ia[c] : T(0); },
+      [&](int e, T v) {
+        if (!ok) return;
+        const int p = qpos<N, BC>(e);
+        const TO d = TO(T(2) * v) - shift;
+        TO pv = d;
+        if constexpr (ACCUM) pv = o[p] + d;
+        o[p] = pv;
+        if constexpr (NORMS) {
+          ee += double(d) * double(d);
+          pp += double(pv) * double(pv);
+        }
+      });
+  if constexpr (NORMS) {
+    if (norms) block_norms(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
+  }
+}
+
+template <typename T, int N, int BC, bool INV, int PTM>
+__global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long plane, int lcols,
+                                             const T* __restrict__ tab, int nzm,
+                                             const int* __restrict__ skip) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
+  const int cols = 1 << lcols;
+  const int q = threadIdx.x & (cols - 1), t = threadIdx.x >> lcols;
+  T* col = data + (long)blockIdx.y * plane + (long)blockIdx.x * cols + q;
+  YLds<T, N / 2> lds(reinterpret_cast<T2*>(smem_raw), q, cols);
+  if constexpr (INV) {
+    quarter_body<T, N, PTM>(
+        lds, t, tab, [&](int c, T& v) { v = col[(long)c * nx]; },
+        [&](int e, T v) { col[(long)qpos<N, BC>(e) * nx] = T(2) * v; });
+  } else {
+    quarter_body<T, N, PTM>(
+        lds, t, tab, [&](int e, T& v) { v = col[(long)qpos<N, BC>(e) * nx]; },
+        [&](int c, T v) { col[(long)c * nx] = v; });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // spectral z pass (uniform z): block (tile, member); tile = 2*lines
 // consecutive (kx, ky) positions of the plane, each a z-line of N values
 // `plane` apart.  Per packed z coefficient c of line (kx, ky):
@@ -574,8 +771,21 @@ static long x_rows_per_block(int n) {
   }
 }
 
-long xpass_blocks(int nx, int pt, long nrows) {
-  const long rpb = pt == 8 ? x_rows_per_block<8>(nx) : x_rows_per_block<16>(nx);
+template <int PTM>
+static long xq_rows(int n) {
+  switch (n) {
+#define VP_RPB(NN) \
+  case NN: return xq_rows_per_block<NN, PTM>();
+    VP_SIZES(VP_RPB)
+#undef VP_RPB
+    default: return 0;
+  }
+}
+
+long xpass_blocks(int nx, int bc, int pt, long nrows) {
+  long rpb;
+  if (bc == BC_ND || bc == BC_DN) rpb = pt == 8 ? xq_rows<8>(nx) : xq_rows<16>(nx);
+  else rpb = pt == 8 ? x_rows_per_block<8>(nx) : x_rows_per_block<16>(nx);
   return rpb > 0 ? (nrows + rpb - 1) / rpb : 0;
 }
 
@@ -599,12 +809,38 @@ static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long
   return hipGetLastError();
 }
 
+template <typename TI, typename T, int BC, bool SUB, int PTM>
+static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
+                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+#define VP_XQF(NN)                                                                          \
+  case NN: {                                                                                \
+    constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
+    hipLaunchKernelGGL((k_xqfwd<TI, T, NN, BC, SUB, PTM>),                                  \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
+    break;                                                                                  \
+  }
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+  switch (n) {
+    VP_SIZES(VP_XQF)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_XQF
+  return hipGetLastError();
+}
+
 template <typename TI, typename T, int BC, bool SUB>
 static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
                                  long nrows, const T* tab, int pt, const PassOpts& o,
                                  hipStream_t st) {
-  return pt == 8 ? launch_xfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
-                 : launch_xfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
+  if constexpr (BC == BC_ND || BC == BC_DN)
+    return pt == 8
+               ? launch_xqfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
+               : launch_xqfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
+  else
+    return pt == 8
+               ? launch_xfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
+               : launch_xfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
 }
 
 template <typename T, typename TO, int BC, bool ACCUM, int PTM>
@@ -627,13 +863,38 @@ static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out
   return hipGetLastError();
 }
 
+template <typename T, typename TO, int BC, bool ACCUM, int PTM>
+static hipError_t launch_xqinv_pt(const T* in, long istride, const Batch<TO>& out, int nb, int n,
+                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+#define VP_XQI(NN)                                                                          \
+  case NN: {                                                                                \
+    constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
+    hipLaunchKernelGGL((k_xqinv<T, TO, NN, BC, ACCUM, PTM>),                                \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
+    break;                                                                                  \
+  }
+  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
+  switch (n) {
+    VP_SIZES(VP_XQI)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_XQI
+  return hipGetLastError();
+}
+
 template <typename T, typename TO, int BC, bool ACCUM>
 static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out, int nb, int n,
                                  long nrows, const T* tab, int pt, const PassOpts& o,
                                  hipStream_t st) {
-  return pt == 8
-             ? launch_xinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
-             : launch_xinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
+  if constexpr (BC == BC_ND || BC == BC_DN)
+    return pt == 8
+               ? launch_xqinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
+               : launch_xqinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
+  else
+    return pt == 8
+               ? launch_xinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
+               : launch_xinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
 }
 
 // y tile: `lines` column pairs per block (the radix-16 thread count of 256
@@ -649,17 +910,45 @@ static int ypass_lines(int nx, int ny) {
 
 int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
 
+// quarter-wave y pass: one column per line, 2*lines columns per block
 template <typename T, int BC, bool FWD, int PTM>
-static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
-                              const PassOpts& o, hipStream_t st) {
+static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+                               int nzm, const int* skip, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
-  int lines = ypass_lines(nx, ny);
-  if (o.lines > 0 && o.lines < lines) lines = o.lines;
+  const int cols = 2 * lines;
+  int lc = 0;
+  while ((1 << lc) < cols) ++lc;
+  const long plane = (long)nx * ny;
+  const dim3 grid((unsigned)(nx / cols), (unsigned)nplanes);
+#define VP_YQ(NN)                                                                  \
+  case NN: {                                                                       \
+    const int nthr = cols * FftShape<NN / 2, PTM>::TPL;                            \
+    const size_t shm = sizeof(T2) * (size_t)lds_len<NN / 2>() * (cols + 1);        \
+    auto kern = &k_yq<T, NN, BC, !FWD, PTM>;                                       \
+    if (nthr > 512) return hipErrorInvalidValue;                                   \
+    if (shm > 65536) {                                                             \
+      const hipError_t e = allow_large_lds(kern);                                  \
+      if (e != hipSuccess) return e;                                               \
+    }                                                                              \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, lc, tab, nzm, skip); \
+    break;                                                                         \
+  }
+  switch (ny) {
+    VP_SIZES(VP_YQ)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_YQ
+  return hipGetLastError();
+}
+
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+                                 int nzm, const PassOpts& o, hipStream_t st) {
+  using T2 = typename Vec2<T>::type;
   int ll = 0;
   while ((1 << ll) < lines) ++ll;
   const long plane = (long)nx * ny;
   const dim3 grid((unsigned)(nx / (2 * lines)), (unsigned)nplanes);
-  const int nzm = o.nzm > 0 ? o.nzm : nplanes;
 #define VP_Y(NN)                                                                   \
   case NN: {                                                                       \
     const int nthr = lines * FftShape<NN, PTM>::TPL;                               \
@@ -679,6 +968,18 @@ static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab
   }
 #undef VP_Y
   return hipGetLastError();
+}
+
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
+                              const PassOpts& o, hipStream_t st) {
+  int lines = ypass_lines(nx, ny);
+  if (o.lines > 0 && o.lines < lines) lines = o.lines;
+  const int nzm = o.nzm > 0 ? o.nzm : nplanes;
+  if constexpr (BC == BC_ND || BC == BC_DN)
+    return launch_yq_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o.skip, st);
+  else
+    return launch_ystd_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o, st);
 }
 
 template <typename T, int BC, bool FWD>
@@ -729,6 +1030,8 @@ static hipError_t with_bc(int bc, F&& f) {
     case BC_P: return f(std::integral_constant<int, BC_P>{});
     case BC_N: return f(std::integral_constant<int, BC_N>{});
     case BC_D: return f(std::integral_constant<int, BC_D>{});
+    case BC_ND: return f(std::integral_constant<int, BC_ND>{});
+    case BC_DN: return f(std::integral_constant<int, BC_DN>{});
     default: return hipErrorInvalidValue;
   }
 }
@@ -736,10 +1039,13 @@ static hipError_t with_bc(int bc, F&& f) {
 template <typename T>
 static hipError_t launch_zspec_t(T* data, const ZSpecArgs& a, const T* tab, int pt, int nb,
                                  const int* skip, hipStream_t st) {
-  return with_bc(a.bcz, [&](auto B) {
+  return with_bc(a.bcz, [&](auto B) -> hipError_t {
     constexpr int BC = decltype(B)::value;
-    return pt == 8 ? launch_zspec_pt<T, BC, 8>(data, a, tab, nb, skip, st)
-                   : launch_zspec_pt<T, BC, 16>(data, a, tab, nb, skip, st);
+    if constexpr (BC == BC_ND || BC == BC_DN)
+      return hipErrorInvalidValue;  // the tridiagonal pass takes these
+    else
+      return pt == 8 ? launch_zspec_pt<T, BC, 8>(data, a, tab, nb, skip, st)
+                     : launch_zspec_pt<T, BC, 16>(data, a, tab, nb, skip, st);
   });
 }
 

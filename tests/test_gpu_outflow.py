@@ -2,9 +2,11 @@
 through the C ABI against the FP64 oracle.
 
 Outflow at both ends of x or y runs the sine transform (the cosine transform
-of the sign-alternated line); in z the tridiagonal pass takes an outflow at
-either end (extra diagonal term of the end row) and the spectral z pass an
-outflow at both ends.  With an outflow end the operator is non-singular: no
+of the sign-alternated line); a wall at one end and an outflow at the other
+runs the quarter-wave cosine transform (DCT-IV through a half-length complex
+FFT; reversed lines for an outflow at the lower end); in z the tridiagonal
+pass takes an outflow at either end (extra diagonal term of the end row) and
+the spectral z pass an outflow at both ends.  With an outflow end the operator is non-singular: no
 mean is removed, and the mixed chain corrects without removing means.
 
 Tolerances: FP64 relative L2 <= 1e-12; mixed precision <= 1e-10.
@@ -64,6 +66,19 @@ SOLVE_CASES = [
     (32, 16, 1, "PPD", None),            # one-cell slab, outflow both z faces
     (32, 16, 1, "DDN", None),
     (16, 16, 2, "NNNNDN", None),
+    # a wall and an outflow in x or y (quarter-wave transforms), every length
+    (8, 16, 12, "NDPPNN", None),
+    (16, 8, 12, "DNNDNN", 1.2),
+    (32, 64, 10, "NDDNPP", None),
+    (64, 32, 20, "DNPPND", 1.4),
+    (128, 16, 9, "NDNNNN", None),
+    (256, 8, 7, "DNNNDD", None),
+    (512, 16, 3, "NDPPPP", None),
+    (1024, 8, 5, "DNNDNN", None),
+    (16, 128, 9, "PPNDNN", None),
+    (8, 256, 5, "NNDNND", None),
+    (16, 512, 4, "PPDNDD", None),
+    (8, 1024, 3, "DDNDNN", None),
 ]
 
 
@@ -134,7 +149,8 @@ def test_z_spectral_refused_for_one_outflow_end(torch_dev):
 
 
 @pytest.mark.parametrize("case", [(32, 32, 32, "DDD", None), (64, 32, 40, "NNNNND", 1.5),
-                                  (16, 16, 64, "PPPPDN", None)],
+                                  (16, 16, 64, "PPPPDN", None), (64, 32, 24, "NDDNND", 1.3),
+                                  (1024, 16, 4, "DNNDPP", None), (16, 1024, 4, "NDDNNN", None)],
                          ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
 def test_radix8_and_mixed(torch_dev, case):
     torch = torch_dev
@@ -156,7 +172,7 @@ def test_radix8_and_mixed(torch_dev, case):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batched_equals_single(torch_dev, prec):
     torch = torch_dev
-    g = _grid(32, 16, 24, "DDNNND", 1.4)
+    g = _grid(32, 16, 24, "NDDNND", 1.4)
     n = 3
     fs = [vofsynth.gaussian_field(g.shape, 60 + i) for i in range(n)]
     plan = _plan(g, precision=prec, max_batch=n)
@@ -180,7 +196,8 @@ def _step_inputs(g, seed=2):
 
 
 STEP_CASES = [((64, 64, 64), "NNNNND", None), ((64, 32, 48), "PPPPND", 1.5),
-              ((32, 32, 32), "NNPPND", None)]
+              ((32, 32, 32), "NNPPND", None), ((64, 64, 32), "NDNDND", 1.2),
+              ((128, 16, 16), "NDPPNN", None)]
 
 
 @pytest.mark.parametrize("shape,bc,beta", STEP_CASES)
