@@ -15,7 +15,9 @@ liquid-velocity extension and the interface velocity):
   the second-order marker-and-cell Laplacian D(G(.)) of section 3;
 * ``project`` -- the constant-coefficient split projection step;
 * ``extend``  -- the divergence-free liquid-velocity extension and the
-  interface velocity.
+  interface velocity;
+* ``interface_terms`` -- |grad C| by Youngs' finite differences, the Stefan
+  source s and the interface-velocity jump q on faces (sections 3.2, 3.4, 3.6).
 
 Every function names the passage it follows.  Pins against closed forms,
 brute-force dense solves and library special cases live in ``tests/``.
@@ -31,3 +33,4 @@ from .solver import (  # noqa: F401
     project,
     extend,
 )
+from .interface import interface_terms, youngs_gradient  # noqa: F401
