@@ -195,6 +195,29 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
              double* phi, void* hip_stream);
 
 /*
+ * Interface terms from the volume fraction (section 3.2: the regularised
+ * delta |grad C| by Youngs' finite differences; section 3.4: the normal
+ * n = grad C / |grad C|; section 3.6: the Stefan source and the jump of the
+ * interface velocity), one pass over the fields:
+ *   s  = mdot (1/rho2 - 1/rho1) |grad C|            (cell centres),
+ *   q  = (mdot / rho1) n on the faces (qx on i+1/2, qy on j+1/2, qz on k+1/2):
+ *        the mean of the two adjacent cells' values, 0 on a non-periodic
+ *        boundary face (n = 0 where grad C = 0).
+ * grad C at a cell centre is the mean of the gradients at its eight corners,
+ * each taken from the eight cells around the corner (dx, dy and the z centre
+ * distances), with periodic copies or mirrored values (zero normal gradient)
+ * beyond the domain; on a uniform grid that is the central difference
+ * weighted (1, 2, 1) in each transverse direction.  s and q are the src and
+ * q arguments of project / extend_liquid_velocity / vof_step.
+ *   C, mdot : device cell fields (volume fraction of phase 1, mass flux);
+ *   rho1, rho2 > 0 : the two densities;
+ *   s, qx, qy, qz : device outputs (must not alias C or mdot).
+ */
+int interface_terms(poisson_plan* plan, const double* C, const double* mdot, double rho1,
+                    double rho2, double* s, double* qx, double* qy, double* qz,
+                    void* hip_stream);
+
+/*
  * Mixed-precision control (plans created with VP_PRECISION_MIXED).  A mixed
  * solve is p_0 = S32(f) followed by at most dc_steps FP64 defect-correction
  * steps p_k = p_{k-1} + e_k, e_k = S32(f - L_h p_{k-1}) (FP64 residual and
@@ -292,7 +315,7 @@ int poisson_plan_autotune(poisson_plan* plan, int nb, void* hip_stream, int* cho
  * forgets the recorded launches.  Classes are numbered 0..VP_NUM_KERNEL_CLASSES-1;
  * poisson_kernel_class_name gives their names (NULL outside that range).
  */
-#define VP_NUM_KERNEL_CLASSES 15
+#define VP_NUM_KERNEL_CLASSES 16
 int poisson_plan_set_profiling(poisson_plan* plan, int class_mask);
 int poisson_plan_kernel_times(poisson_plan* plan, double* total_ms, int* launches, int n);
 const char* poisson_kernel_class_name(int cls);

@@ -40,12 +40,12 @@ int hip_fail(hipError_t e, const char* what) {
 enum KernelClass {
   K_XFWD = 0, K_YFWD, K_Z, K_YINV, K_XINV,
   K_XFWD32, K_YFWD32, K_Z32, K_YINV32, K_XINV32,
-  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_EPILOGUE, K_NCLASS
+  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_EPILOGUE, K_INTERFACE, K_NCLASS
 };
 const char* const kClassNames[K_NCLASS] = {
     "x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse",
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
-    "residual", "rhs_assembly", "correction", "extension", "step_epilogue"};
+    "residual", "rhs_assembly", "correction", "extension", "step_epilogue", "interface_terms"};
 
 // Twiddle table of one direction, (cos, sin) pairs: of 2 pi k/N for k < N,
 // then of pi m/(2N) for m <= N/2 (the DCT post/pre rotation).  For a wall at
@@ -638,6 +638,17 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
             vp::launch_step_epilogue(P->ge, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
                                      ve, we, ug, vg, wg, st),
             "step epilogue", st);
+  return VP_OK;
+}
+
+int interface_terms(poisson_plan* P, const double* C, const double* mdot, double rho1,
+                    double rho2, double* s, double* qx, double* qy, double* qz, void* stream) {
+  if (!P || !C || !mdot || !s || !qx || !qy || !qz || !(rho1 > 0) || !(rho2 > 0))
+    return VP_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  VP_LAUNCH(P, K_INTERFACE,
+            vp::launch_interface(P->g, C, mdot, rho1, rho2, s, qx, qy, qz, st),
+            "interface terms", st);
   return VP_OK;
 }
 

@@ -605,6 +605,148 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Interface terms from the volume fraction C and the mass flux mdot (section
+// 3.2: the regularised delta |grad C| by Youngs' finite differences; section
+// 3.6: the Stefan source and the interface-velocity jump):
+//   s = mdot (1/rho2 - 1/rho1) |grad C|             at cell centres,
+//   a = (mdot / rho1) grad C / |grad C|  (0 where grad C = 0),
+//   q on face i+1/2 = (a_i + a_{i+1}) / 2, 0 on a non-periodic boundary face.
+// grad C at a centre is the mean of the gradients at its eight corners, each
+// from the eight cells around the corner (ghost cells: periodic copies, or
+// mirrored values at walls and outflow ends); per component that is the
+// central difference weighted (1, 2, 1) / 4 in each transverse direction, in z
+// the mean of the two one-sided differences over the centre distances.
+// A block owns a TX x TY tile (TX = min(nx, 64), TY = 256 / TX, one cell per
+// thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
+// (-1, +2) halo in x and y sits in a ring of four LDS planes (one plane
+// loaded per step), a of planes k and k+1 on the tile plus its +x / +y halo in
+// two LDS planes, so each plane of C is read about once per block.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kIfMaxCW = 67;                   // TX + 3 for TX = 64
+constexpr int kIfMaxC = 469;                   // max over TX of (TX + 3)(256 / TX + 3)
+constexpr int kIfMaxA = 325;                   // max over TX of (TX + 1)(256 / TX + 1)
+
+// index i of a line of n cells, periodic (any i; tall tiles of narrow grids
+// reach several periods beyond the end) or mirrored into [0, n)
+__device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic) {
+  if (periodic) return ((i % n) + n) % n;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_interface(const GridArgs g, const double* __restrict__ C,
+                                                    const double* __restrict__ mdot,
+                                                    double rho1, double rho2,
+                                                    double* __restrict__ s,
+                                                    double* __restrict__ qx,
+                                                    double* __restrict__ qy,
+                                                    double* __restrict__ qz) {
+  __shared__ double cs[4][kIfMaxC];
+  __shared__ double as[2][3][kIfMaxA];
+  const int tx = g.nx < 64 ? g.nx : 64;
+  const int ty = 256 / tx;
+  const int cw = tx + 3, ch = ty + 3, aw = tx + 1, ah = ty + 1;
+  const int i0 = blockIdx.x * tx, j0 = blockIdx.y * ty;
+  const int kb = blockIdx.z * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
+  const bool px = g.bcx == 0, py = g.bcy == 0, pz = g.bcz == 0;
+  const long P = (long)g.nx * g.ny;
+  const int li = threadIdx.x % tx, lj = threadIdx.x / tx;
+  const int i = i0 + li, j = j0 + lj;
+  const bool own = j < g.ny;  // a cell of the domain (tall tiles of narrow grids)
+  const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho1;
+
+  // plane kk of C (any integer; wrapped or mirrored) into ring slot kk & 3
+  auto load_c = [&](int kk) {
+    const int m = wrap_or_clamp(kk, g.nz, pz);
+    double* dst = cs[kk & 3];
+    for (int e = threadIdx.x; e < cw * ch; e += 256) {
+      const int ei = e % cw, ej = e / cw;
+      const int gi = wrap_or_clamp(i0 - 1 + ei, g.nx, px);
+      const int gj = wrap_or_clamp(j0 - 1 + ej, g.ny, py);
+      dst[e] = C[m * P + (long)gj * g.nx + gi];
+    }
+  };
+  // a of plane kk on the tile and its +x / +y halo into as[kk & 1]; s of the
+  // tile cells written when `write_s`
+  auto make_a = [&](int kk, bool write_s) {
+    const int m = wrap_or_clamp(kk, g.nz, pz);
+    const double dzhi = m + 1 < g.nz ? g.dzc[m] : (pz ? g.dzc[g.nz - 1] : 1.0);
+    const double dzlo = m > 0 ? g.dzc[m - 1] : (pz ? g.dzc[g.nz - 1] : 1.0);
+    const double* cm = cs[(kk - 1) & 3];
+    const double* c0 = cs[kk & 3];
+    const double* cp = cs[(kk + 1) & 3];
+    double* ax = as[kk & 1][0];
+    double* ay = as[kk & 1][1];
+    double* az = as[kk & 1][2];
+    for (int e = threadIdx.x; e < aw * ah; e += 256) {
+      const int ai = e % aw, aj = e / aw;
+      const int o = (aj + 1) * cw + (ai + 1);  // centre in the C tile
+      const double w[3] = {1.0, 2.0, 1.0};
+      double sx = 0.0, sy = 0.0, szu = 0.0, szd = 0.0;
+#pragma unroll
+      for (int b = -1; b <= 1; ++b)
+#pragma unroll
+        for (int c = -1; c <= 1; ++c) {
+          const double wt = w[b + 1] * w[c + 1];
+          // x: transverse (y = b, z = c); y: transverse (x = b, z = c); z: (x = b, y = c)
+          const double* pl = c < 0 ? cm : (c > 0 ? cp : c0);
+          sx += wt * (pl[o + b * cw + 1] - pl[o + b * cw - 1]);
+          sy += wt * (pl[o + cw + b] - pl[o - cw + b]);
+          const int oz = o + c * cw + b;
+          szu += wt * (cp[oz] - c0[oz]);
+          szd += wt * (c0[oz] - cm[oz]);
+        }
+      const double gx = sx / (32.0 * g.dx), gy = sy / (32.0 * g.dy);
+      const double gz = (szu / dzhi + szd / dzlo) / 32.0;
+      const double mag = sqrt(gx * gx + gy * gy + gz * gz);
+      const int gi = wrap_or_clamp(i0 + ai, g.nx, px), gj = wrap_or_clamp(j0 + aj, g.ny, py);
+      const long cell = m * P + (long)gj * g.nx + gi;
+      const double md = mdot[cell];
+      const double sc = mag > 0.0 ? md * a_f / mag : 0.0;
+      ax[e] = sc * gx;
+      ay[e] = sc * gy;
+      az[e] = sc * gz;
+      if (write_s && ai < tx && aj < ty && j0 + aj < g.ny) s[cell] = md * src_f * mag;
+    }
+  };
+
+  load_c(kb - 1);
+  load_c(kb);
+  load_c(kb + 1);
+  __syncthreads();
+  make_a(kb, true);
+  for (int k = kb; k < ke; ++k) {
+    load_c(k + 2);
+    __syncthreads();
+    make_a(k + 1, k + 1 < ke);
+    __syncthreads();
+    if (own) {
+      const long c = k * P + (long)j * g.nx + i;
+      const int e = lj * aw + li;
+      const double* a0x = as[k & 1][0];
+      const double* a0y = as[k & 1][1];
+      const double* a0z = as[k & 1][2];
+      const double* a1z = as[(k + 1) & 1][2];
+      qx[c] = (i + 1 < g.nx || px) ? 0.5 * (a0x[e] + a0x[e + 1]) : 0.0;
+      qy[c] = (j + 1 < g.ny || py) ? 0.5 * (a0y[e] + a0y[e + aw]) : 0.0;
+      qz[c] = (k + 1 < g.nz || pz) ? 0.5 * (a0z[e] + a1z[e]) : 0.0;
+    }
+  }
+}
+
+hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
+                            double rho2, double* s, double* qx, double* qy, double* qz,
+                            hipStream_t st) {
+  const int tx = g.nx < 64 ? g.nx : 64, ty = 256 / tx;
+  if (g.nx < 8 || (g.nx & (g.nx - 1)) || g.kc < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
+                  (unsigned)((g.nz + g.kc - 1) / g.kc));
+  hipLaunchKernelGGL(k_interface, grid, dim3(256), 0, st, g, C, mdot, rho1, rho2, s, qx, qy, qz);
+  return hipGetLastError();
+}
+
 // r = f - L_h p (FP64 residual of the defect-correction steps, any ends).  Each block
 // also sums dzf[k] * p and dzf[k] * r over its cells (fixed order, no
 // atomics) into partial[block] and partial[kResidualMaxBlocks + block], so

@@ -1,0 +1,112 @@
+"""GPU parity of the interface terms (Youngs gradient of C, the Stefan source
+s and the interface-velocity jump q on faces) through the C ABI against the
+FP64 oracle, on every tile width (nx = 8 .. 1024), periodic / wall / outflow
+ends, stretched z and nz = 1; the planes marched per block change no bit."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.interface as oi
+import vofsynth
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1907_00890_amd  # noqa: F401  (fails loudly without the library)
+    return torch
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+CASES = [
+    # (nx, ny, nz, bc, beta, field)
+    (64, 64, 64, "PPN", None, "sphere"),
+    (32, 16, 24, "NPN", 1.5, "sphere"),
+    (16, 16, 16, "PPP", None, "random"),
+    (8, 32, 12, "NNNNND", 1.2, "random"),
+    (8, 8, 10, "PPP", None, "random"),      # tall tile wider than the grid in y
+    (128, 32, 5, "DDN", None, "random"),
+    (32, 32, 1, "PPN", None, "random"),     # one-cell slab
+    (1024, 8, 3, "PNN", None, "random"),
+    (256, 16, 40, "NNP", 1.0, "sphere"),
+]
+
+
+def _inputs(g, field, seed):
+    rng = np.random.default_rng(seed)
+    if field == "sphere":
+        C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, seed=seed)
+    else:
+        C = rng.uniform(0.0, 1.0, g.shape)
+    mdot = 0.01 * rng.uniform(0.5, 1.5, g.shape)
+    return C, mdot
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}-{c[5]}")
+def test_interface_terms_parity(torch_dev, case):
+    torch = torch_dev
+    from paper_1907_00890_amd import Plan
+    nx, ny, nz, bc, beta, field = case
+    dzf = vofsynth.uniform_dz(nz, 1.0) if beta is None else vofsynth.stretched_dz(nz, 1.0, beta)
+    g = oracle.Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, dzf, bc)
+    C, mdot = _inputs(g, field, 7 + nz)
+    rho1, rho2 = 1000.0, 1.0
+    ref = oi.interface_terms(C, mdot, rho1, rho2, g)[:4]
+    plan = Plan(nx, ny, nz, g.dx, g.dy, dzf, g.bc)
+    dC, dm = _dev(torch, C), _dev(torch, mdot)
+    out = plan.interface_terms(dC, dm, rho1, rho2)
+    torch.cuda.synchronize()
+    got = [a.cpu().numpy() for a in out]
+    for name, a, b in zip(("s", "qx", "qy", "qz"), got, ref):
+        if not np.any(b):
+            assert not np.any(a), name  # e.g. qz of a one-cell slab
+            continue
+        err = rel_l2(a, b)
+        print(f"interface {case} {name}: {err:.3e}")
+        assert err <= FP64_TOL, (name, err)
+    # planes marched per block: same bits
+    for planes in sorted({1, 3, nz}):
+        plan.tune("stencil_planes", min(planes, nz))
+        again = plan.interface_terms(dC, dm, rho1, rho2)
+        torch.cuda.synchronize()
+        for a, b in zip(again, got):
+            assert np.array_equal(a.cpu().numpy(), b), planes
+
+
+def test_interface_terms_feed_the_step(torch_dev):
+    """s and q from the kernel, used by the fused step, give the oracle's step
+    with the oracle's interface terms."""
+    torch = torch_dev
+    from paper_1907_00890_amd import Plan
+    g = oracle.Grid(64, 32, 48, 1 / 64, 1 / 32, vofsynth.stretched_dz(48, 1.0, 1.5), "PPN")
+    C, mdot = _inputs(g, "sphere", 3)
+    rho1, rho2 = 1000.0, 1.0
+    s_ref, qx, qy, qz, _ = oi.interface_terms(C, mdot, rho1, rho2, g)
+    us, vs, ws = vofsynth.random_faces(g.shape, 4, g.bc)
+    phat = vofsynth.gaussian_field(g.shape, 5)
+    rho = rho1 * C + rho2 * (1 - C)
+    dt = 0.2
+    u1, v1, w1, p1 = oracle.project(us, vs, ws, phat, rho, rho2, s_ref, dt, g)
+    ref = oracle.extend(u1, v1, w1, s_ref, g, q=(qx, qy, qz))
+    plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, g.bc)
+    T = lambda a: _dev(torch, a)  # noqa: E731
+    s, dqx, dqy, dqz = plan.interface_terms(T(C), T(mdot), rho1, rho2)
+    out = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho2, s, dt, s, q=(dqx, dqy, dqz),
+                    out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+    torch.cuda.synchronize()
+    u, v, w, p, phi, ue, ve, we, ug, vg, wg = (a.cpu().numpy() for a in out)
+    for name, a, b in [("u", u, u1), ("p", p, p1), ("phi", phi, ref[6]), ("we", we, ref[2]),
+                       ("ug", ug, ref[3]), ("wg", wg, ref[5])]:
+        assert rel_l2(a, b) <= FP64_TOL, name
