@@ -328,6 +328,83 @@ def stretched_step_run(torch, dev, steps, no_autotune):
     return res
 
 
+def interface_outflow_run(torch, dev, steps, no_autotune):
+    """256^3 with walls and an outflow top (p = 0 on the top face, the
+    container of section 4): the interface terms (Stefan source and
+    interface-velocity jump from C and mdot, Youngs gradient) in one pass,
+    the full step fed by them, and bare solves with outflow on every side
+    and in the container against the periodic-x/y walls-z solve."""
+    import numpy as np
+
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+    n = 256
+    dz = vofsynth.uniform_dz(n, 1.0)
+    C, _ = vofsynth.sphere_vof(n, n, n, 1.0 / n, 1.0 / n, dz, seed=2)
+    rho1, rho2 = 1000.0, 1.0
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    dC = T(C)
+    dm = torch.full_like(dC, 1e-2 / (1.0 / rho2 - 1.0 / rho1))
+    rho = T(rho1 * C + rho2 * (1.0 - C))
+    us, vs, ws = (T(a) for a in vofsynth.random_faces((n, n, n), 100, "NNNNND"))
+    phat = T(vofsynth.gaussian_field((n, n, n), 101))
+    f = T(vofsynth.gaussian_field((n, n, n), 200))
+    del C
+    plan = Plan(n, n, n, 1.0 / n, 1.0 / n, dz, "NNNNND")
+    tuned = plan.autotune(batch=1) if not no_autotune else plan.tuning()
+    terms = tuple(torch.empty_like(dC) for _ in range(4))
+    p, phi = torch.empty_like(dC), torch.empty_like(dC)
+    ue = tuple(torch.empty_like(dC) for _ in range(3))
+    ug = tuple(torch.empty_like(dC) for _ in range(3))
+
+    def step():
+        sq = plan.interface_terms(dC, dm, rho1, rho2, out=terms)
+        plan.step(us, vs, ws, phat, rho, rho2, sq[0], 1.0, sq[0], p=p, phi=phi, q=sq[1:],
+                  out=ue, gamma=ug)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / steps
+    plan.kernel_times()
+    plan.set_profiling(True, classes=["interface_terms"])
+    for _ in range(steps):
+        plan.interface_terms(dC, dm, rho1, rho2, out=terms)
+    torch.cuda.synchronize()
+    ms_if, cnt = plan.kernel_times()["interface_terms"]
+    plan.set_profiling(False)
+    ms_if /= cnt
+    npts = n ** 3
+    res = {"workload": "256x256x256, walls on the sides and the bottom, outflow top (NNNNND)",
+           "interface_terms": {"ms": round(ms_if, 4), "alg_bytes": 48 * npts,
+                               "gbs": round(48 * npts / (ms_if * 1e-3) / 1e9, 1)},
+           "step_with_interface_terms_ms": round(ms_step, 4), "tuning": tuned, "solve_ms": {}}
+    out = torch.empty_like(f)
+    for bc in ("NNNNND", "DDD", "PPN"):
+        sp = Plan(n, n, n, 1.0 / n, 1.0 / n, dz, bc)
+        if not no_autotune:
+            sp.autotune(batch=1)
+        for _ in range(2):
+            sp.solve(f, out)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(10):
+            sp.solve(f, out)
+        b.record()
+        torch.cuda.synchronize()
+        res["solve_ms"][bc] = round(a.elapsed_time(b) / 10, 4)
+        del sp
+    del plan, terms, ue, ug
+    torch.cuda.empty_cache()
+    return res
+
+
 def mixed512_run(torch, dev, reps, no_autotune):
     """512^3 PPP, seeded N(0,1) RHS with its mean removed: FP64 against mixed
     (FP32 chain + FP64 defect correction with the device-side stopping rule)."""
@@ -563,6 +640,7 @@ def main():
     if not args.no_extra:
         line["stretched_512x512x256"] = stretched_step_run(torch, dev, 20, args.no_autotune)
         line["mixed_vs_fp64_512"] = mixed512_run(torch, dev, 5, args.no_autotune)
+        line["interface_outflow_256"] = interface_outflow_run(torch, dev, 10, args.no_autotune)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:

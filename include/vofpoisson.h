@@ -280,6 +280,8 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 LDS-staged 64 x 8 (or 16) tiles marching that many planes
  *                 (defaults 8 and 1; tiled 0: plain one-row tiles; results
  *                 are bit-identical);
+ *   "interface_planes" : z-planes marched by one block of interface_terms
+ *                 (1..nz, default min(8, nz); results are bit-identical);
  *   "rhs_tiled" : 8 (default) or 16 assembles the projection's right-hand
  *                 side on LDS-staged 64 x 8 (x 16) tiles where nx % 64 == 0 and
  *                 ny divides by the tile height (bit-identical results), 0 on

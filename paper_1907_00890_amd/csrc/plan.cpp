@@ -135,6 +135,7 @@ struct poisson_plan {
   vp::GridArgs g{};   // marching stencils (right-hand side, residual)
   vp::GridArgs gs{};  // streaming stencils (correction, extension)
   vp::GridArgs ge{};  // fused step epilogue
+  vp::GridArgs gi{};  // interface terms
 
   // optional per-launch timing (HIP events on the caller's stream)
   struct Mark {
@@ -356,6 +357,10 @@ int plan_init(poisson_plan* P, const double* dz) {
   // marching more planes gains nothing)
   P->ge = G;
   P->ge.kc = 1;
+  // the interface terms march 8 planes per block: the four-plane prologue of
+  // a block (C of planes k-1 .. k+2) is then a small share of its loads
+  P->gi = G;
+  P->gi.kc = nz < 8 ? nz : 8;
   return VP_OK;
 }
 
@@ -647,7 +652,7 @@ int interface_terms(poisson_plan* P, const double* C, const double* mdot, double
     return VP_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   VP_LAUNCH(P, K_INTERFACE,
-            vp::launch_interface(P->g, C, mdot, rho1, rho2, s, qx, qy, qz, st),
+            vp::launch_interface(P->gi, C, mdot, rho1, rho2, s, qx, qy, qz, st),
             "interface terms", st);
   return VP_OK;
 }
@@ -747,6 +752,11 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
   if (k == "epilogue_planes") {
     if (value < 1 || value > P->nz) return VP_EINVAL;
     P->ge.kc = value;
+    return VP_OK;
+  }
+  if (k == "interface_planes") {
+    if (value < 1 || value > P->nz) return VP_EINVAL;
+    P->gi.kc = value;
     return VP_OK;
   }
   if (k == "stream_planes") {
@@ -955,6 +965,7 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "y_lines") *value = P->y_lines;
   else if (k == "epilogue_tiled") *value = P->ge.tiled;
   else if (k == "epilogue_planes") *value = P->ge.kc;
+  else if (k == "interface_planes") *value = P->gi.kc;
   else return VP_EINVAL;
   return VP_OK;
 }

@@ -616,17 +616,26 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
 // from the eight cells around the corner (ghost cells: periodic copies, or
 // mirrored values at walls and outflow ends); per component that is the
 // central difference weighted (1, 2, 1) / 4 in each transverse direction, in z
-// the mean of the two one-sided differences over the centre distances.
+// the mean of the two one-sided differences over the centre distances.  The
+// weights factor; differences are taken first (so a gradient at the rounding
+// level of C, where C saturates at 0 or 1, stays exact):
+//   dx[j][i] = sum_c w_c (C[k+c][j][i+1] - C[k+c][j][i-1]),   gx = sum_b w_b dx[j+b][i] / (32 dx),
+//   dy[j][i] = sum_c w_c (C[k+c][j+1][i] - C[k+c][j-1][i]),   gy = sum_b w_b dy[j][i+b] / (32 dy),
+//   zd[j][i] = (C[k+1] - C[k]) / dzc[k] + (C[k] - C[k-1]) / dzc[k-1],
+//                                            gz = sum_{b,c} w_b w_c zd[j+c][i+b] / 32.
 // A block owns a TX x TY tile (TX = min(nx, 64), TY = 256 / TX, one cell per
 // thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
-// (-1, +2) halo in x and y sits in a ring of four LDS planes (one plane
-// loaded per step), a of planes k and k+1 on the tile plus its +x / +y halo in
-// two LDS planes, so each plane of C is read about once per block.
+// (-1, +2) x / y halo sits in a ring of four LDS planes (the next plane is
+// loaded into registers while the current one is computed), dx, dy and zd of
+// the current plane in three more, and a of the current plane on the tile
+// plus its +x / +y halo in three, so each plane of C is read about once per
+// block.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int kIfMaxCW = 67;                   // TX + 3 for TX = 64
-constexpr int kIfMaxC = 469;                   // max over TX of (TX + 3)(256 / TX + 3)
-constexpr int kIfMaxA = 325;                   // max over TX of (TX + 1)(256 / TX + 1)
+constexpr int kIfMaxC = 469;  // max over TX of (TX + 3)(256 / TX + 3)
+constexpr int kIfMaxA = 325;  // max over TX of (TX + 1)(256 / TX + 1)
+constexpr int kIfRegs = 2;    // C-tile values per thread: ceil(469 / 256)
+constexpr int kIfARegs = 2;   // a positions per thread: ceil(325 / 256)
 
 // index i of a line of n cells, periodic (any i; tall tiles of narrow grids
 // reach several periods beyond the end) or mirrored into [0, n)
@@ -644,7 +653,8 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
                                                     double* __restrict__ qy,
                                                     double* __restrict__ qz) {
   __shared__ double cs[4][kIfMaxC];
-  __shared__ double as[2][3][kIfMaxA];
+  __shared__ double sdx[kIfMaxC], sdy[kIfMaxC], zd[kIfMaxC];
+  __shared__ double sax[kIfMaxA], say[kIfMaxA], saz[kIfMaxA];
   const int tx = g.nx < 64 ? g.nx : 64;
   const int ty = 256 / tx;
   const int cw = tx + 3, ch = ty + 3, aw = tx + 1, ah = ty + 1;
@@ -656,83 +666,125 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
   const int i = i0 + li, j = j0 + lj;
   const bool own = j < g.ny;  // a cell of the domain (tall tiles of narrow grids)
   const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho1;
+  const double fx = 1.0 / (32.0 * g.dx), fy = 1.0 / (32.0 * g.dy);
 
-  // plane kk of C (any integer; wrapped or mirrored) into ring slot kk & 3
-  auto load_c = [&](int kk) {
-    const int m = wrap_or_clamp(kk, g.nz, pz);
-    double* dst = cs[kk & 3];
-    for (int e = threadIdx.x; e < cw * ch; e += 256) {
-      const int ei = e % cw, ej = e / cw;
-      const int gi = wrap_or_clamp(i0 - 1 + ei, g.nx, px);
-      const int gj = wrap_or_clamp(j0 - 1 + ej, g.ny, py);
-      dst[e] = C[m * P + (long)gj * g.nx + gi];
-    }
+  // in-plane offsets of this thread's C-tile elements and a positions
+  long coff[kIfRegs], moff[kIfARegs];
+#pragma unroll
+  for (int r = 0; r < kIfRegs; ++r) {
+    const int e = threadIdx.x + 256 * r;
+    coff[r] = (long)wrap_or_clamp(j0 - 1 + e / cw, g.ny, py) * g.nx +
+              wrap_or_clamp(i0 - 1 + e % cw, g.nx, px);
+  }
+#pragma unroll
+  for (int r = 0; r < kIfARegs; ++r) {
+    const int e = threadIdx.x + 256 * r;
+    moff[r] = (long)wrap_or_clamp(j0 + e / aw, g.ny, py) * g.nx + wrap_or_clamp(i0 + e % aw, g.nx, px);
+  }
+  auto fetch = [&](int kk, double* v) {
+    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+#pragma unroll
+    for (int r = 0; r < kIfRegs; ++r)
+      if (threadIdx.x + 256 * r < cw * ch) v[r] = C[base + coff[r]];
   };
-  // a of plane kk on the tile and its +x / +y halo into as[kk & 1]; s of the
-  // tile cells written when `write_s`
-  auto make_a = [&](int kk, bool write_s) {
+  auto put = [&](int kk, const double* v) {
+#pragma unroll
+    for (int r = 0; r < kIfRegs; ++r)
+      if (threadIdx.x + 256 * r < cw * ch) cs[kk & 3][threadIdx.x + 256 * r] = v[r];
+  };
+  auto fetch_m = [&](int kk, double* md) {
+    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+#pragma unroll
+    for (int r = 0; r < kIfARegs; ++r)
+      if (threadIdx.x + 256 * r < aw * ah) md[r] = mdot[base + moff[r]];
+  };
+  // the z-weighted x and y differences and the z differences of plane kk
+  // over the C tile (dx where i-1 and i+1 are in the tile, dy where j-1 and
+  // j+1 are)
+  auto z_sums = [&](int kk) {
     const int m = wrap_or_clamp(kk, g.nz, pz);
-    const double dzhi = m + 1 < g.nz ? g.dzc[m] : (pz ? g.dzc[g.nz - 1] : 1.0);
-    const double dzlo = m > 0 ? g.dzc[m - 1] : (pz ? g.dzc[g.nz - 1] : 1.0);
+    const double ihi = 1.0 / (m + 1 < g.nz ? g.dzc[m] : (pz ? g.dzc[g.nz - 1] : 1.0));
+    const double ilo = 1.0 / (m > 0 ? g.dzc[m - 1] : (pz ? g.dzc[g.nz - 1] : 1.0));
     const double* cm = cs[(kk - 1) & 3];
     const double* c0 = cs[kk & 3];
     const double* cp = cs[(kk + 1) & 3];
-    double* ax = as[kk & 1][0];
-    double* ay = as[kk & 1][1];
-    double* az = as[kk & 1][2];
-    for (int e = threadIdx.x; e < aw * ah; e += 256) {
+    for (int e = threadIdx.x; e < cw * ch; e += 256) {
+      const int ei = e % cw, ej = e / cw;
+      const double a = cm[e], b = c0[e], c = cp[e];
+      zd[e] = (c - b) * ihi + (b - a) * ilo;
+      if (ei >= 1 && ei <= cw - 2)
+        sdx[e] = (cm[e + 1] - cm[e - 1]) + 2.0 * (c0[e + 1] - c0[e - 1]) + (cp[e + 1] - cp[e - 1]);
+      if (ej >= 1 && ej <= ch - 2)
+        sdy[e] = (cm[e + cw] - cm[e - cw]) + 2.0 * (c0[e + cw] - c0[e - cw]) +
+                 (cp[e + cw] - cp[e - cw]);
+    }
+  };
+  // gradient of C at a position (ai, aj) of the a region (centre o of the C tile)
+  auto grad_at = [&](int o, double& gx, double& gy, double& gz) {
+    gx = (sdx[o - cw] + 2.0 * sdx[o] + sdx[o + cw]) * fx;
+    gy = (sdy[o - 1] + 2.0 * sdy[o] + sdy[o + 1]) * fy;
+    const double r0 = zd[o - cw - 1] + 2.0 * zd[o - cw] + zd[o - cw + 1];
+    const double r1 = zd[o - 1] + 2.0 * zd[o] + zd[o + 1];
+    const double r2 = zd[o + cw - 1] + 2.0 * zd[o + cw] + zd[o + cw + 1];
+    gz = (r0 + 2.0 * r1 + r2) * (1.0 / 32.0);
+  };
+  // a of plane kk on the tile and its +x / +y halo into sax / say / saz (mdot
+  // of this thread's positions in md); s of the tile cells when `write_s`
+  auto make_a = [&](int kk, const double* md, bool write_s) {
+    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+#pragma unroll
+    for (int r = 0; r < kIfARegs; ++r) {
+      const int e = threadIdx.x + 256 * r;
+      if (e >= aw * ah) break;
       const int ai = e % aw, aj = e / aw;
-      const int o = (aj + 1) * cw + (ai + 1);  // centre in the C tile
-      const double w[3] = {1.0, 2.0, 1.0};
-      double sx = 0.0, sy = 0.0, szu = 0.0, szd = 0.0;
-#pragma unroll
-      for (int b = -1; b <= 1; ++b)
-#pragma unroll
-        for (int c = -1; c <= 1; ++c) {
-          const double wt = w[b + 1] * w[c + 1];
-          // x: transverse (y = b, z = c); y: transverse (x = b, z = c); z: (x = b, y = c)
-          const double* pl = c < 0 ? cm : (c > 0 ? cp : c0);
-          sx += wt * (pl[o + b * cw + 1] - pl[o + b * cw - 1]);
-          sy += wt * (pl[o + cw + b] - pl[o - cw + b]);
-          const int oz = o + c * cw + b;
-          szu += wt * (cp[oz] - c0[oz]);
-          szd += wt * (c0[oz] - cm[oz]);
-        }
-      const double gx = sx / (32.0 * g.dx), gy = sy / (32.0 * g.dy);
-      const double gz = (szu / dzhi + szd / dzlo) / 32.0;
+      double gx, gy, gz;
+      grad_at((aj + 1) * cw + (ai + 1), gx, gy, gz);
       const double mag = sqrt(gx * gx + gy * gy + gz * gz);
-      const int gi = wrap_or_clamp(i0 + ai, g.nx, px), gj = wrap_or_clamp(j0 + aj, g.ny, py);
-      const long cell = m * P + (long)gj * g.nx + gi;
-      const double md = mdot[cell];
-      const double sc = mag > 0.0 ? md * a_f / mag : 0.0;
-      ax[e] = sc * gx;
-      ay[e] = sc * gy;
-      az[e] = sc * gz;
-      if (write_s && ai < tx && aj < ty && j0 + aj < g.ny) s[cell] = md * src_f * mag;
+      const double sc = mag > 0.0 ? md[r] * a_f / mag : 0.0;
+      sax[e] = sc * gx;
+      say[e] = sc * gy;
+      saz[e] = sc * gz;
+      if (write_s && ai < tx && aj < ty && j0 + aj < g.ny) s[base + moff[r]] = md[r] * src_f * mag;
     }
   };
 
-  load_c(kb - 1);
-  load_c(kb);
-  load_c(kb + 1);
-  __syncthreads();
-  make_a(kb, true);
-  for (int k = kb; k < ke; ++k) {
-    load_c(k + 2);
+  // C of planes kb-1 .. kb+2 in the ring, then the march: step p computes a
+  // of plane p, writes s, q_x, q_y of plane p (p < ke) and q_z of plane p-1
+  // (p > kb; a_z of p-1 kept in a register); the ring gets plane p+2 at the
+  // end of step p, into the slot of plane p-2
+  double v[kIfRegs], md[kIfARegs], mdn[kIfARegs] = {};
+  fetch_m(kb, md);
+  for (int kk = kb - 1; kk <= kb + 2; ++kk) {
+    fetch(kk, v);
+    put(kk, v);
+  }
+  double az_prev = 0.0;
+  for (int p = kb; p <= ke; ++p) {
+    const bool load = p > kb && p + 2 <= ke + 1;  // plane p+2 is read by z_sums(p+1)
+    if (load) fetch(p + 2, v);                    // in flight while plane p is computed
+    if (p + 1 <= ke) fetch_m(p + 1, mdn);
+    __syncthreads();  // the ring holds planes p-1 .. p+1; the a planes are free
+    z_sums(p);
     __syncthreads();
-    make_a(k + 1, k + 1 < ke);
+    make_a(p, md, p < ke);
     __syncthreads();
     if (own) {
-      const long c = k * P + (long)j * g.nx + i;
       const int e = lj * aw + li;
-      const double* a0x = as[k & 1][0];
-      const double* a0y = as[k & 1][1];
-      const double* a0z = as[k & 1][2];
-      const double* a1z = as[(k + 1) & 1][2];
-      qx[c] = (i + 1 < g.nx || px) ? 0.5 * (a0x[e] + a0x[e + 1]) : 0.0;
-      qy[c] = (j + 1 < g.ny || py) ? 0.5 * (a0y[e] + a0y[e + aw]) : 0.0;
-      qz[c] = (k + 1 < g.nz || pz) ? 0.5 * (a0z[e] + a1z[e]) : 0.0;
+      if (p < ke) {
+        const long c = p * P + (long)j * g.nx + i;
+        qx[c] = (i + 1 < g.nx || px) ? 0.5 * (sax[e] + sax[e + 1]) : 0.0;
+        qy[c] = (j + 1 < g.ny || py) ? 0.5 * (say[e] + say[e + aw]) : 0.0;
+      }
+      const double az = saz[e];
+      if (p > kb) {
+        const long c = (p - 1) * P + (long)j * g.nx + i;
+        qz[c] = (p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0;
+      }
+      az_prev = az;
     }
+    if (load) put(p + 2, v);  // slot of plane p-2, last read by z_sums(p-1)
+#pragma unroll
+    for (int r = 0; r < kIfARegs; ++r) md[r] = mdn[r];
   }
 }
 

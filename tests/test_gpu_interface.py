@@ -78,7 +78,7 @@ def test_interface_terms_parity(torch_dev, case):
         assert err <= FP64_TOL, (name, err)
     # planes marched per block: same bits
     for planes in sorted({1, 3, nz}):
-        plan.tune("stencil_planes", min(planes, nz))
+        plan.tune("interface_planes", min(planes, nz))
         again = plan.interface_terms(dC, dm, rho1, rho2)
         torch.cuda.synchronize()
         for a, b in zip(again, got):
