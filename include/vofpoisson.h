@@ -200,7 +200,7 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
  * n = grad C / |grad C|; section 3.6: the Stefan source and the jump of the
  * interface velocity), one pass over the fields:
  *   s  = mdot (1/rho2 - 1/rho1) |grad C|            (cell centres),
- *   q  = (mdot / rho1) n on the faces (qx on i+1/2, qy on j+1/2, qz on k+1/2):
+ *   q  = (mdot / rho_e) n on the faces (qx on i+1/2, qy on j+1/2, qz on k+1/2):
  *        the mean of the two adjacent cells' values, 0 on a non-periodic
  *        boundary face (n = 0 where grad C = 0).
  * grad C at a cell centre is the mean of the gradients at its eight corners,
@@ -211,10 +211,15 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
  * q arguments of project / extend_liquid_velocity / vof_step.
  *   C, mdot : device cell fields (volume fraction of phase 1, mass flux);
  *   rho1, rho2 > 0 : the two densities;
+ *   phase : the phase whose divergence-free velocity extension builds the
+ *           interface velocity: 1 (the liquid, section 3.6; rho_e = rho1) or
+ *           2 (the vapour, for boiling, appendix A; rho_e = rho2).  The
+ *           potential and the extension u - grad phi are the same for both;
+ *           only the jump q changes;
  *   s, qx, qy, qz : device outputs (must not alias C or mdot).
  */
 int interface_terms(poisson_plan* plan, const double* C, const double* mdot, double rho1,
-                    double rho2, double* s, double* qx, double* qy, double* qz,
+                    double rho2, int phase, double* s, double* qx, double* qy, double* qz,
                     void* hip_stream);
 
 /*

@@ -4,8 +4,15 @@ Section 3.2 regularises the interface delta as |grad C| and section 3.4 takes
 the normal n = grad C / |grad C|, both with the gradient of C evaluated by
 Youngs' finite differences; section 3.6 then needs the Stefan source
 s = mdot (1/rho2 - 1/rho1) |grad C| at cell centres and the interface-velocity
-jump q = (mdot / rho1) n on the velocity faces.  The paper does not print the
-stencil; the reading taken here is Youngs' corner construction:
+jump q = (mdot / rho1) n on the velocity faces.  For boiling (appendix A) the
+interface velocity is built from the divergence-free extension of the vapour
+velocity instead of the liquid's.  The reading: the potential and the
+extension u - grad phi are the same (it follows whichever phase lies where the
+potential is harmonic and constant, e.g. inside a closed bubble), and the jump
+becomes q = (mdot / rho2) n (phase = 2).
+
+The paper does not print the stencil of the gradient; the reading taken here
+is Youngs' corner construction:
 
 1. ghost cells beyond the domain: periodic copies, or mirrored values
    (C and mdot continued with zero normal gradient) at walls and outflow
@@ -18,7 +25,8 @@ stencil; the reading taken here is Youngs' corner construction:
 3. the gradient at a cell centre as the mean of its eight corner gradients.
 On a uniform grid this is the central difference of C weighted (1, 2, 1) in
 each transverse direction.  Then |grad C|, n (0 where |grad C| = 0),
-s = mdot (1/rho2 - 1/rho1) |grad C| and the cell vector a = (mdot / rho1) n;
+s = mdot (1/rho2 - 1/rho1) |grad C| and the cell vector a = (mdot / rho) n
+(rho of the extended phase);
 q on face i+1/2 is the mean of a at cells i and i+1, and 0 on a non-periodic
 boundary face (the mirrored ghost carries the opposite normal component).
 """
@@ -77,14 +85,18 @@ def youngs_gradient(C, g):
     return tuple(out)
 
 
-def interface_terms(C, mdot, rho1, rho2, g):
-    """(s, qx, qy, qz, |grad C|) as described in the module docstring."""
+def interface_terms(C, mdot, rho1, rho2, g, phase=1):
+    """(s, qx, qy, qz, |grad C|) as described in the module docstring; `phase`
+    is the phase whose velocity the extension follows (1 liquid, 2 vapour)."""
+    if phase not in (1, 2):
+        raise ValueError("phase must be 1 (liquid) or 2 (vapour)")
     gx, gy, gz = youngs_gradient(C, g)
     mag = np.sqrt(gx * gx + gy * gy + gz * gz)
     mdot = np.asarray(mdot, dtype=np.float64)
     s = mdot * (1.0 / rho2 - 1.0 / rho1) * mag
     safe = np.where(mag > 0.0, mag, 1.0)
-    scale = np.where(mag > 0.0, mdot / rho1 / safe, 0.0)
+    rho_ext = rho1 if phase == 1 else rho2
+    scale = np.where(mag > 0.0, mdot / rho_ext / safe, 0.0)
     q = []
     for axis, comp in ((2, gx), (1, gy), (0, gz)):
         a = scale * comp

@@ -171,12 +171,14 @@ class Plan:
         check(_lib.lib.extend_liquid_velocity(*args), "extend_liquid_velocity")
         return (*out, *gs, phi)
 
-    def interface_terms(self, C, mdot, rho1, rho2, out=None, stream=None):
+    def interface_terms(self, C, mdot, rho1, rho2, phase=1, out=None, stream=None):
         """(s, qx, qy, qz): the Stefan source mdot (1/rho2 - 1/rho1)|grad C| at
-        centres and (mdot/rho1) n on faces, grad C by Youngs' differences."""
+        centres and (mdot/rho_e) n on faces, grad C by Youngs' differences;
+        rho_e = rho1 (phase 1, liquid extension) or rho2 (phase 2, boiling)."""
         if out is None:
             out = tuple(self._new(C) for _ in range(4))
-        args = [self._h, self._ptr(C, "C"), self._ptr(mdot, "mdot"), float(rho1), float(rho2)]
+        args = [self._h, self._ptr(C, "C"), self._ptr(mdot, "mdot"), float(rho1), float(rho2),
+                int(phase)]
         args += [self._ptr(t, "out") for t in out]
         check(_lib.lib.interface_terms(*args, _stream_ptr(stream)), "interface_terms")
         return tuple(out)

@@ -49,7 +49,7 @@ SIGNATURES = {
     "extend_liquid_velocity": (_i, [_p] + [_p] * 14 + [_p]),
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
-    "interface_terms": (_i, [_p, _p, _p, _d, _d, _p, _p, _p, _p, _p]),
+    "interface_terms": (_i, [_p, _p, _p, _d, _d, _i, _p, _p, _p, _p, _p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_set_mixed_tol": (_i, [_p, _d]),
     "poisson_plan_mixed_report": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), _p]),

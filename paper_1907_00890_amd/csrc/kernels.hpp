@@ -162,8 +162,8 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 // interface terms s, q from the volume fraction C and the mass flux mdot
 // (Youngs gradient of C; one z-marching pass, g.kc planes per block)
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
-                            double rho2, double* s, double* qx, double* qy, double* qz,
-                            hipStream_t st);
+                            double rho2, double rho_e, double* s, double* qx, double* qy,
+                            double* qz, hipStream_t st);
 // r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
 // r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);

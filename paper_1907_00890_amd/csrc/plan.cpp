@@ -647,12 +647,15 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
 }
 
 int interface_terms(poisson_plan* P, const double* C, const double* mdot, double rho1,
-                    double rho2, double* s, double* qx, double* qy, double* qz, void* stream) {
-  if (!P || !C || !mdot || !s || !qx || !qy || !qz || !(rho1 > 0) || !(rho2 > 0))
+                    double rho2, int phase, double* s, double* qx, double* qy, double* qz,
+                    void* stream) {
+  if (!P || !C || !mdot || !s || !qx || !qy || !qz || !(rho1 > 0) || !(rho2 > 0) ||
+      (phase != 1 && phase != 2))
     return VP_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   VP_LAUNCH(P, K_INTERFACE,
-            vp::launch_interface(P->gi, C, mdot, rho1, rho2, s, qx, qy, qz, st),
+            vp::launch_interface(P->gi, C, mdot, rho1, rho2, phase == 1 ? rho1 : rho2, s, qx,
+                                 qy, qz, st),
             "interface terms", st);
   return VP_OK;
 }

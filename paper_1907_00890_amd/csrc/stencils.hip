@@ -610,7 +610,9 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
 // 3.2: the regularised delta |grad C| by Youngs' finite differences; section
 // 3.6: the Stefan source and the interface-velocity jump):
 //   s = mdot (1/rho2 - 1/rho1) |grad C|             at cell centres,
-//   a = (mdot / rho1) grad C / |grad C|  (0 where grad C = 0),
+//   a = (mdot / rho_e) grad C / |grad C|  (0 where grad C = 0; rho_e the
+//       density of the phase whose velocity the extension follows: rho1, or
+//       rho2 for boiling, appendix A),
 //   q on face i+1/2 = (a_i + a_{i+1}) / 2, 0 on a non-periodic boundary face.
 // grad C at a centre is the mean of the gradients at its eight corners, each
 // from the eight cells around the corner (ghost cells: periodic copies, or
@@ -647,7 +649,7 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic) {
 
 __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const double* __restrict__ C,
                                                     const double* __restrict__ mdot,
-                                                    double rho1, double rho2,
+                                                    double rho1, double rho2, double rho_e,
                                                     double* __restrict__ s,
                                                     double* __restrict__ qx,
                                                     double* __restrict__ qy,
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
   const int li = threadIdx.x % tx, lj = threadIdx.x / tx;
   const int i = i0 + li, j = j0 + lj;
   const bool own = j < g.ny;  // a cell of the domain (tall tiles of narrow grids)
-  const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho1;
+  const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho_e;
   const double fx = 1.0 / (32.0 * g.dx), fy = 1.0 / (32.0 * g.dy);
 
   // in-plane offsets of this thread's C-tile elements and a positions
@@ -789,13 +791,14 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
 }
 
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
-                            double rho2, double* s, double* qx, double* qy, double* qz,
-                            hipStream_t st) {
+                            double rho2, double rho_e, double* s, double* qx, double* qy,
+                            double* qz, hipStream_t st) {
   const int tx = g.nx < 64 ? g.nx : 64, ty = 256 / tx;
   if (g.nx < 8 || (g.nx & (g.nx - 1)) || g.kc < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
                   (unsigned)((g.nz + g.kc - 1) / g.kc));
-  hipLaunchKernelGGL(k_interface, grid, dim3(256), 0, st, g, C, mdot, rho1, rho2, s, qx, qy, qz);
+  hipLaunchKernelGGL(k_interface, grid, dim3(256), 0, st, g, C, mdot, rho1, rho2, rho_e, s, qx, qy,
+                     qz);
   return hipGetLastError();
 }
 

@@ -76,6 +76,14 @@ def test_interface_terms_parity(torch_dev, case):
         err = rel_l2(a, b)
         print(f"interface {case} {name}: {err:.3e}")
         assert err <= FP64_TOL, (name, err)
+    # boiling: the vapour extension's jump (mdot/rho2) n, same source
+    vap = plan.interface_terms(dC, dm, rho1, rho2, phase=2)
+    torch.cuda.synchronize()
+    ref2 = oi.interface_terms(C, mdot, rho1, rho2, g, phase=2)[:4]
+    assert np.array_equal(vap[0].cpu().numpy(), got[0])
+    for a, b in zip(vap[1:], ref2[1:]):
+        if np.any(b):
+            assert rel_l2(a.cpu().numpy(), b) <= FP64_TOL
     # planes marched per block: same bits
     for planes in sorted({1, 3, nz}):
         plan.tune("interface_planes", min(planes, nz))

@@ -129,3 +129,21 @@ def test_periodic_shift_invariance():
     mag = a[4]
     ax = mdot / 10.0 * gx / mag
     assert np.allclose(a[1][:, :, -1], 0.5 * (ax[:, :, -1] + ax[:, :, 0]), rtol=1e-13, atol=0)
+
+
+def test_vapour_phase_jump():
+    """Boiling: the interface velocity follows the vapour (q = (mdot/rho2) n);
+    the source and the normal are unchanged, q scales by rho1 / rho2, and
+    u_Gamma from either phase's extension is the same field (the velocity
+    jump mdot (1/rho2 - 1/rho1) n lies between the two extensions)."""
+    g = oracle.Grid(12, 10, 8, 0.1, 0.1, np.full(8, 0.1), "PNN")
+    C, _ = vofsynth.sphere_vof(12, 10, 8, 0.1, 0.1, np.full(8, 0.1), seed=4)
+    mdot = np.random.default_rng(8).uniform(0.5, 1.5, g.shape)
+    rho1, rho2 = 800.0, 2.0
+    liq = oi.interface_terms(C, mdot, rho1, rho2, g, phase=1)
+    vap = oi.interface_terms(C, mdot, rho1, rho2, g, phase=2)
+    assert np.array_equal(liq[0], vap[0]) and np.array_equal(liq[4], vap[4])
+    for a, b in zip(liq[1:4], vap[1:4]):
+        assert np.allclose(b, a * (rho1 / rho2), rtol=1e-13, atol=0)
+    with pytest.raises(ValueError):
+        oi.interface_terms(C, mdot, rho1, rho2, g, phase=3)
