@@ -2,12 +2,14 @@
 // (the constant-coefficient direct solver of section 3.2 diagonalises the
 // 1-D second difference of the staggered grid in x and y).
 //
-// * Small DFTs in registers (radix 2, 4, 8, 16; radix 16 as 4 x 4).
+// * Small DFTs in registers (radix 2, 4, 5, 8, 16; radix 16 as 4 x 4).
 // * Stockham passes of radix 16 first, then the remainder (plan<N>):
 //   N = 256 -> 16 x 16, 512 -> 16 x 16 x 2, 1024 -> 16 x 16 x 4.  Each of the
 //   N/16 threads of a line holds 16 complex values; pass p reads positions
 //   j + r N/R and writes (j / NS) NS R + j % NS + r NS (NS = product of the
-//   earlier radices).
+//   earlier radices).  Lengths 5 * 2^k: 20 values per thread (so the threads
+//   of a line stay a power of two), a radix-5 pass, then radix 4 (and a last
+//   radix 2): 320 -> 5 x 4 x 4 x 4, 640 -> 5 x 4 x 4 x 4 x 2.
 // * Two real lines per complex transform.  Periodic lines use a real DFT in
 //   packed form, wall lines a DCT-II / DCT-III computed through the even/odd
 //   reordering of J. Makhoul ("A fast cosine transform in one and two
@@ -80,6 +82,31 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   r[7] = er[3] - t3r; i[7] = ei[3] - t3i;
 }
 
+// radix 5: with a_1 = x1 + x4, b_1 = x1 - x4, a_2 = x2 + x3, b_2 = x2 - x3,
+//   X0 = x0 + a_1 + a_2,
+//   X1, X4 = x0 + c1 a_1 + c2 a_2 +- SIGN i (s1 b_1 + s2 b_2),
+//   X2, X3 = x0 + c2 a_1 + c1 a_2 +- SIGN i (s2 b_1 - s1 b_2),
+// c_m = cos(2 pi m/5), s_m = sin(2 pi m/5)
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft5(T* r, T* i) {
+  const T c1 = T(0.30901699437494742410229341718281905886);   // (sqrt5 - 1)/4
+  const T c2 = T(-0.80901699437494742410229341718281905886);  // -(sqrt5 + 1)/4
+  const T s1 = T(0.95105651629515357211643933337938214340);
+  const T s2 = T(0.58778525229247312916870595463907276860);
+  const T a1r = r[1] + r[4], a1i = i[1] + i[4], b1r = r[1] - r[4], b1i = i[1] - i[4];
+  const T a2r = r[2] + r[3], a2i = i[2] + i[3], b2r = r[2] - r[3], b2i = i[2] - i[3];
+  const T t1r = r[0] + c1 * a1r + c2 * a2r, t1i = i[0] + c1 * a1i + c2 * a2i;
+  const T t2r = r[0] + c2 * a1r + c1 * a2r, t2i = i[0] + c2 * a1i + c1 * a2i;
+  const T u1r = T(SIGN) * (s1 * b1r + s2 * b2r), u1i = T(SIGN) * (s1 * b1i + s2 * b2i);
+  const T u2r = T(SIGN) * (s2 * b1r - s1 * b2r), u2i = T(SIGN) * (s2 * b1i - s1 * b2i);
+  r[0] = r[0] + a1r + a2r;
+  i[0] = i[0] + a1i + a2i;
+  r[1] = t1r - u1i; i[1] = t1i + u1r;  // t + i u
+  r[4] = t1r + u1i; i[4] = t1i - u1r;  // t - i u
+  r[2] = t2r - u2i; i[2] = t2i + u2r;
+  r[3] = t2r + u2i; i[3] = t2i - u2r;
+}
+
 // radix 16 as 4 x 4: DFT4 over n1 of x[4 n1 + n2] (index k1), twiddle
 // w16^{n2 k1}, DFT4 over n2; output X[k1 + 4 k2]
 template <int SIGN, typename T>
@@ -128,6 +155,7 @@ template <int R, int SIGN, typename T>
 __device__ __forceinline__ void dftR(T* r, T* i) {
   if constexpr (R == 16) dft16<SIGN>(r, i);
   else if constexpr (R == 8) dft8<SIGN>(r, i);
+  else if constexpr (R == 5) dft5<SIGN>(r, i);
   else if constexpr (R == 4) dft4<SIGN>(r, i);
   else dft2<SIGN>(r, i);
 }
@@ -142,16 +170,19 @@ __device__ __forceinline__ int dct_perm(int p) {
 // pass bookkeeping
 // ---------------------------------------------------------------------------
 // PTM: complex values per thread (16: radix-16 passes, 8: radix-8 passes;
-// the radix schedule of a length is greedy, largest radix first)
+// the radix schedule of a length is greedy, largest radix first).  Lengths
+// 5 * 2^k take 20 values per thread whatever PTM (radix 5, then 4, then 2).
 template <int N, int PTM = 16>
 struct FftShape {
-  static constexpr int PT = N >= PTM ? PTM : N;  // complex values per thread
-  static constexpr int TPL = N / PT;             // threads per line
+  static constexpr bool R5 = N % 5 == 0;
+  static constexpr int PT = R5 ? (N >= 20 ? 20 : N) : (N >= PTM ? PTM : N);  // values per thread
+  static constexpr int TPL = N / PT;                                         // threads per line
 };
 template <int N, int NS, int PTM = 16>
 struct PassRadix {
   static constexpr int REM = N / NS;
-  static constexpr int R = REM >= PTM ? PTM : REM;
+  static constexpr int R = N % 5 == 0 ? (NS == 1 ? 5 : (REM >= 4 ? 4 : REM))
+                                      : (REM >= PTM ? PTM : REM);
 };
 
 // Twiddles of one pass for this thread: w_N^{(j % NS) r N/(NS R)}, r = 1..R-1,

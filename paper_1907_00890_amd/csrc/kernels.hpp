@@ -76,7 +76,8 @@ hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool 
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const float* tab, int pt, const PassOpts& o, hipStream_t st);
 
-// spectral z pass for a uniform z grid with nz a power of two in [8, 1024]:
+// spectral z pass for a uniform z grid with nz a transform length (2^k in
+// [8, 1024] or 5 * 2^k in [40, 640]):
 // forward real DFT / DCT-II along z, division by the 3-D eigenvalue, inverse,
 // in one pass (transforms.hip)
 struct ZSpecArgs {
@@ -132,7 +133,7 @@ hipError_t launch_zsolve_f32(float* data, const ZArgs& a, int nb, hipStream_t st
 // stencils.hip ---------------------------------------------------------------
 struct GridArgs {
   int nx, ny, nz;
-  int lx, ly;          // log2(nx), log2(ny): nx and ny are powers of two
+  int txp;             // largest power of two dividing nx (tile widths divide it)
   int kc;              // z-planes marched by one stencil block
   int tiled;           // right-hand side on LDS-staged 64 x tiled tiles (8 or 16 rows) where
                        // they fit; 0: plain 64 x 4 tiles

@@ -308,7 +308,9 @@ int plan_init(poisson_plan* P, const double* dz) {
   // real DFT (periodic), DCT-II (walls) or DST-II (outflow at both ends) of
   // the x and y passes; a wall at one end and an outflow at the other keeps
   // the tridiagonal pass
-  P->z_spec_ok = Z.uniform_z && nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0 &&
+  const bool zlen = (nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0) ||
+                    (nz % 5 == 0 && nz / 5 >= 8 && nz / 5 <= 128 && ((nz / 5) & (nz / 5 - 1)) == 0);
+  P->z_spec_ok = Z.uniform_z && zlen &&
                  P->bc[2] <= vp::BC_D;
   if (P->z_spec_ok) {
     const std::vector<double> tz = make_table(nz, P->bc[2]);
@@ -335,10 +337,7 @@ int plan_init(poisson_plan* P, const double* dz) {
 
   vp::GridArgs& G = P->g;
   G.nx = nx; G.ny = ny; G.nz = nz;
-  G.lx = 0;
-  while ((1 << G.lx) < nx) ++G.lx;
-  G.ly = 0;
-  while ((1 << G.ly) < ny) ++G.ly;
+  G.txp = nx & -nx;
   G.bcx = P->bc[0] == vp::BC_P ? 0 : 1;
   G.bcy = P->bc[1] == vp::BC_P ? 0 : 1;
   G.bcz = P->bc[2] == vp::BC_P ? 0 : 1;

@@ -33,14 +33,19 @@ struct Tile {
   bool hxp, hxm, hyp, hym;
 };
 
-// TXMAX: 64 for the marching 7-point kernels (taller tiles, fewer halo
-// rows), 256 for the streaming ones (whole rows)
+// Tile width: the largest power of two dividing nx, at most TXMAX (64 for
+// the marching 7-point kernels: taller tiles, fewer halo rows; 256 for the
+// streaming ones: whole rows of power-of-two grids).
+template <int TXMAX>
+__host__ __device__ __forceinline__ int tile_w(const GridArgs& g) {
+  return g.txp < TXMAX ? g.txp : TXMAX;
+}
+
 template <int TXMAX>
 __device__ __forceinline__ Tile tile_of(const GridArgs& g) {
-  constexpr int LTXMAX = TXMAX == 256 ? 8 : 6;
   Tile t;
-  const int tx = g.nx < TXMAX ? g.nx : TXMAX;
-  const int ltx = g.lx < LTXMAX ? g.lx : LTXMAX;
+  const int tx = tile_w<TXMAX>(g);
+  const int ltx = __builtin_ctz(tx);
   t.i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
   t.j = blockIdx.y * (256 / tx) + (threadIdx.x >> ltx);
   t.kb = blockIdx.z * g.kc;
@@ -625,8 +630,8 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
 //   dy[j][i] = sum_c w_c (C[k+c][j+1][i] - C[k+c][j-1][i]),   gy = sum_b w_b dy[j][i+b] / (32 dy),
 //   zd[j][i] = (C[k+1] - C[k]) / dzc[k] + (C[k] - C[k-1]) / dzc[k-1],
 //                                            gz = sum_{b,c} w_b w_c zd[j+c][i+b] / 32.
-// A block owns a TX x TY tile (TX = min(nx, 64), TY = 256 / TX, one cell per
-// thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
+// A block owns a TX x TY tile (TX = the largest power of two dividing nx, at
+// most 64; TY = 256 / TX; one cell per thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
 // (-1, +2) x / y halo sits in a ring of four LDS planes (the next plane is
 // loaded into registers while the current one is computed), dx, dy and zd of
 // the current plane in three more, and a of the current plane on the tile
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
   __shared__ double cs[4][kIfMaxC];
   __shared__ double sdx[kIfMaxC], sdy[kIfMaxC], zd[kIfMaxC];
   __shared__ double sax[kIfMaxA], say[kIfMaxA], saz[kIfMaxA];
-  const int tx = g.nx < 64 ? g.nx : 64;
+  const int tx = tile_w<64>(g);
   const int ty = 256 / tx;
   const int cw = tx + 3, ch = ty + 3, aw = tx + 1, ah = ty + 1;
   const int i0 = blockIdx.x * tx, j0 = blockIdx.y * ty;
@@ -793,8 +798,8 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st) {
-  const int tx = g.nx < 64 ? g.nx : 64, ty = 256 / tx;
-  if (g.nx < 8 || (g.nx & (g.nx - 1)) || g.kc < 1) return hipErrorInvalidValue;
+  const int tx = tile_w<64>(g), ty = 256 / tx;
+  if (tx < 8 || g.nx % tx || g.kc < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
                   (unsigned)((g.nz + g.kc - 1) / g.kc));
   hipLaunchKernelGGL(k_interface, grid, dim3(256), 0, st, g, C, mdot, rho1, rho2, rho_e, s, qx, qy,
@@ -896,7 +901,7 @@ __global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ 
 
 template <int TXMAX = 64>
 static inline dim3 tile_grid(const GridArgs& g) {
-  const int tx = g.nx < TXMAX ? g.nx : TXMAX;
+  const int tx = tile_w<TXMAX>(g);
   const int ty = 256 / tx;
   return dim3((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
               (unsigned)((g.nz + g.kc - 1) / g.kc));
@@ -908,7 +913,8 @@ int stencil_blocks(const GridArgs& g) {
 }
 
 int stencil_default_planes(int nx, int ny, int nz) {
-  const int tx = nx < 64 ? nx : 64;
+  const int txp = nx & -nx;
+  const int tx = txp < 64 ? txp : 64;
   const long tiles = (long)(nx / tx) * ((ny + 256 / tx - 1) / (256 / tx));
   long kc = (nz * tiles + 16383) / 16384;
   if (kc < 1) kc = 1;

@@ -131,7 +131,8 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
   T vr[PT], vi[PT];
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
-    int e = t + r * TPL;
+    // inputs of the first pass's butterflies (t + r TPL when a thread holds one)
+    int e = pass_in<N, 1, PTM>(t, r / R1, r % R1);
     if constexpr (BC != BC_P) e = dct_perm<N>(e);
     load(e, vr[r], vi[r]);
     if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
@@ -246,7 +247,8 @@ __device__ __forceinline__ void spectral_body(L& lds, int t, const T* __restrict
   T vr[PT], vi[PT];
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
-    int e = t + r * TPL;
+    // inputs of the first pass's butterflies (t + r TPL when a thread holds one)
+    int e = pass_in<N, 1, PTM>(t, r / R1, r % R1);
     if constexpr (BC != BC_P) e = dct_perm<N>(e);
     load(e, vr[r], vi[r]);
     if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
@@ -344,7 +346,7 @@ __device__ __forceinline__ void quarter_body(L& lds, int t, const T* __restrict_
   T vr[PT], vi[PT];
 #pragma unroll
   for (int r = 0; r < PT; ++r) {
-    const int e = t + r * TPL;
+    const int e = pass_in<H, 1, PTM>(t, r / R1, r % R1);  // first-pass butterfly inputs
     T a, b;
     load(2 * e, a);
     load(N - 1 - 2 * e, b);
@@ -724,8 +726,8 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
   const long pos = (long)blockIdx.x * 2 * lines + 2 * q;  // line a; line b = pos + 1
   T2* col = reinterpret_cast<T2*>(data + blockIdx.y * batch_stride + pos);
   const long pstride = plane >> 1;  // z stride in T2 units
-  const double la = lamx[pos & (nx - 1)] + lamy[pos >> lx];
-  const double lb = lamx[(pos + 1) & (nx - 1)] + lamy[(pos + 1) >> lx];
+  const double la = lamx[pos % nx] + lamy[pos / nx];
+  const double lb = lamx[(pos + 1) % nx] + lamy[(pos + 1) / nx];
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   spectral_body<T, N, BC, PTM>(
       lds, t, tab,
@@ -756,7 +758,8 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-#define VP_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define VP_SIZES(X) \
+  X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(40) X(80) X(160) X(320) X(640)
 
 // pt: values per thread of the radix schedule, 16 or 8 (a tuning knob; the
 // results are the same up to rounding order)
@@ -900,11 +903,19 @@ static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out
 // y tile: `lines` column pairs per block (the radix-16 thread count of 256
 // when the plane is wide enough, so both schedules read equally wide tiles);
 // 2*lines columns divide nx (both powers of two)
+// threads per line of the radix-16 schedule of length n (20 values per
+// thread for lengths 5 * 2^k)
+static int fft_tpl(int n) {
+  if (n % 5 == 0) return n >= 20 ? n / 20 : 1;
+  return n >= 16 ? n / 16 : 1;
+}
+// largest power of two dividing n
+static long pow2_part(long n) { return n & -n; }
+
 static int ypass_lines(int nx, int ny) {
-  const int tpl = ny >= 16 ? ny / 16 : 1;
-  int lines = 256 / tpl;
+  int lines = 256 / fft_tpl(ny);
   if (lines < 1) lines = 1;
-  if (lines > nx / 2) lines = nx / 2;
+  if (lines > pow2_part(nx) / 2) lines = (int)(pow2_part(nx) / 2);  // 2 lines divide nx
   return lines;
 }
 
@@ -995,9 +1006,9 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   using T2 = typename Vec2<T>::type;
   const long plane = (long)a.nx * a.ny;
   // tile width: as for the y pass of a line of the same length, or a.lines
-  int lines = a.nz >= 16 ? 256 / (a.nz / 16) : 256;
+  int lines = 256 / fft_tpl(a.nz);
   if (a.lines > 0 && a.lines < lines) lines = a.lines;
-  if (lines > plane / 2) lines = (int)(plane / 2);
+  if (lines > pow2_part(plane) / 2) lines = (int)(pow2_part(plane) / 2);  // tiles divide the plane
   int ll = 0;
   while ((1 << ll) < lines) ++ll;
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   const bool per = A.periodic != 0;
   const long P = A.plane;
   double lam = 0.0;
-  if (valid) lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx];
+  if (valid) lam = A.lamx[line % A.nx] + A.lamy[line / A.nx];
   const double ell = -lam;
   const int k0 = US ? s * M : s * A.seg_base + (s < A.seg_rem ? s : A.seg_rem);
   const int m = US ? M : A.seg_base + (s < A.seg_rem ? 1 : 0);
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
     if (A.mean_out) A.mean_out[blockIdx.y] = r;
     x[0] = T(0);
   } else {
-    const double lam = A.lamx[line & (A.nx - 1)] + A.lamy[line >> A.lx] - (A.dlo + A.dhi);
+    const double lam = A.lamx[line % A.nx] + A.lamy[line / A.nx] - (A.dlo + A.dhi);
     x[line] = T(r / lam);
   }
 }
