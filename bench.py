@@ -328,6 +328,54 @@ def stretched_step_run(torch, dev, steps, no_autotune):
     return res
 
 
+def droplet_grid_run(torch, dev, steps, no_autotune):
+    """The 320 x 320 x 640 triply periodic grid of the three-dimensional
+    settling droplet (transform lengths 5 * 2^k, radix-5 passes): `steps`
+    time steps (two solves each, stencils in the loop) and a bare solve."""
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+    cfg = vofsynth.config("ppp320x320x640")
+    X = make_inputs(cfg, torch, dev)
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc)
+    tuned = plan.autotune(batch=1) if not no_autotune else plan.tuning()
+    p = torch.empty(cfg.shape, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(p)
+    ue = tuple(torch.empty_like(p) for _ in range(3))
+    ug = tuple(torch.empty_like(p) for _ in range(3))
+    q = (X["qx"], X["qy"], X["qz"])
+
+    def step():
+        plan.step(X["u"], X["v"], X["w"], X["phat"], X["rho"], X["rho0"], X["s"], X["dt"],
+                  X["s"], p=p, phi=phi, q=q, out=ue, gamma=ug)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / steps
+    out = torch.empty_like(p)
+    a.record()
+    for _ in range(steps):
+        plan.solve(X["f"], out)
+    b.record()
+    torch.cuda.synchronize()
+    solve_ms = a.elapsed_time(b) / steps
+    n = cfg.npts
+    res = {"workload": "ppp320x320x640: 320x320x640 triply periodic, cubic cells, project + "
+                       "extend step", "steps": steps, "ms_per_step": round(ms_step, 4),
+           "mpts_s": round(2 * n / (ms_step * 1e-3) / 1e6, 1), "solve_ms": round(solve_ms, 4),
+           "solve_mpts_s": round(n / (solve_ms * 1e-3) / 1e6, 1),
+           "solve_model_gbs_80N": round(80 * n / (solve_ms * 1e-3) / 1e9, 1), "tuning": tuned}
+    del X, plan
+    torch.cuda.empty_cache()
+    return res
+
+
 def interface_outflow_run(torch, dev, steps, no_autotune):
     """256^3 with walls and an outflow top (p = 0 on the top face, the
     container of section 4): the interface terms (Stefan source and
@@ -641,6 +689,7 @@ def main():
         line["stretched_512x512x256"] = stretched_step_run(torch, dev, 20, args.no_autotune)
         line["mixed_vs_fp64_512"] = mixed512_run(torch, dev, 5, args.no_autotune)
         line["interface_outflow_256"] = interface_outflow_run(torch, dev, 10, args.no_autotune)
+        line["droplet_320x320x640"] = droplet_grid_run(torch, dev, 10, args.no_autotune)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:

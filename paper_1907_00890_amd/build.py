@@ -22,7 +22,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvofpoisson.so")
 
-SOURCES = ["plan.cpp", "plan_check.cpp", "serve.cpp", "transforms.hip", "zsolve.hip", "stencils.hip"]
+# heaviest first (compiled in parallel, in this order)
+SOURCES = ["transforms_x.hip", "transforms_y.hip", "stencils.hip", "transforms_z.hip", "zsolve.hip",
+           "plan.cpp", "serve.cpp", "plan_check.cpp"]
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -56,7 +58,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile all sources and link libvofpoisson.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    workers = min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
+    workers = min(len(SOURCES), max(1, os.cpu_count() or 2))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -1,0 +1,207 @@
+// y passes of the spectral Poisson solve: every y-line (columns of a
+// z-plane), tiles of consecutive columns so that every row access of a
+// wavefront is contiguous.
+#include "transform_passes.hpp"
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// y kernels: block (tile, plane); tile = 2*lines columns x N rows; thread
+// (q, t) with q fastest, so a wavefront reads 2*lines consecutive columns
+// ---------------------------------------------------------------------------
+template <typename T, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yfwd(T* __restrict__ data, int nx,
+                                                               long plane, int llines,
+                                                               const T* __restrict__ tab,
+                                                               int nzm,
+                                                               const int* __restrict__ skip) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
+  const int lines = 1 << llines;
+  const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
+  T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
+                                  2 * q);
+  const int nx2 = nx >> 1;  // row stride in T2 units
+  YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
+  forward_body<T, N, BC, PTM>(
+      lds, t, tab,
+      [&](int e, T& r, T& i) {
+        const T2 v = col[(long)e * nx2];
+        r = v.x;
+        i = v.y;
+      },
+      [&](int c0, T a0, T b0, int c1, T a1, T b1) {
+        T2 v0, v1;
+        v0.x = a0;
+        v0.y = b0;
+        v1.x = a1;
+        v1.y = b1;
+        col[(long)c0 * nx2] = v0;
+        col[(long)c1 * nx2] = v1;
+      });
+}
+
+template <typename T, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(T* __restrict__ data, int nx,
+                                                               long plane, int llines,
+                                                               const T* __restrict__ tab,
+                                                               int nzm,
+                                                               const int* __restrict__ skip) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
+  const int lines = 1 << llines;
+  const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
+  T2* col = reinterpret_cast<T2*>(data + (long)blockIdx.y * plane + (long)blockIdx.x * 2 * lines +
+                                  2 * q);
+  const int nx2 = nx >> 1;
+  YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
+  inverse_body<T, N, BC, PTM>(
+      lds, t, tab,
+      [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
+        const T2 v0 = col[(long)c0 * nx2], v1 = col[(long)c1 * nx2];
+        a0 = v0.x;
+        b0 = v0.y;
+        a1 = v1.x;
+        b1 = v1.y;
+      },
+      [&](int e, T r, T i) {
+        T2 v;
+        v.x = r;
+        v.y = i;
+        col[(long)e * nx2] = v;
+      });
+}
+
+template <typename T, int N, int BC, bool INV, int PTM>
+__global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long plane, int lcols,
+                                             const T* __restrict__ tab, int nzm,
+                                             const int* __restrict__ skip) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  if (skip && skip[blockIdx.y / nzm]) return;  // member already converged (whole block)
+  const int cols = 1 << lcols;
+  const int q = threadIdx.x & (cols - 1), t = threadIdx.x >> lcols;
+  T* col = data + (long)blockIdx.y * plane + (long)blockIdx.x * cols + q;
+  YLds<T, N / 2> lds(reinterpret_cast<T2*>(smem_raw), q, cols);
+  if constexpr (INV) {
+    quarter_body<T, N, PTM>(
+        lds, t, tab, [&](int c, T& v) { v = col[(long)c * nx]; },
+        [&](int e, T v) { col[(long)qpos<N, BC>(e) * nx] = T(2) * v; });
+  } else {
+    quarter_body<T, N, PTM>(
+        lds, t, tab, [&](int e, T& v) { v = col[(long)qpos<N, BC>(e) * nx]; },
+        [&](int c, T v) { col[(long)c * nx] = v; });
+  }
+}
+
+static int ypass_lines(int nx, int ny) {
+  int lines = 256 / fft_tpl(ny);
+  if (lines < 1) lines = 1;
+  if (lines > pow2_part(nx) / 2) lines = (int)(pow2_part(nx) / 2);  // 2 lines divide nx
+  return lines;
+}
+
+int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
+
+// quarter-wave y pass: one column per line, 2*lines columns per block
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+                               int nzm, const int* skip, hipStream_t st) {
+  using T2 = typename Vec2<T>::type;
+  const int cols = 2 * lines;
+  int lc = 0;
+  while ((1 << lc) < cols) ++lc;
+  const long plane = (long)nx * ny;
+  const dim3 grid((unsigned)(nx / cols), (unsigned)nplanes);
+#define VP_YQ(NN)                                                                  \
+  case NN: {                                                                       \
+    const int nthr = cols * FftShape<NN / 2, PTM>::TPL;                            \
+    const size_t shm = sizeof(T2) * (size_t)lds_len<NN / 2>() * (cols + 1);        \
+    auto kern = &k_yq<T, NN, BC, !FWD, PTM>;                                       \
+    if (nthr > 512) return hipErrorInvalidValue;                                   \
+    if (shm > 65536) {                                                             \
+      const hipError_t e = allow_large_lds(kern);                                  \
+      if (e != hipSuccess) return e;                                               \
+    }                                                                              \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, lc, tab, nzm, skip); \
+    break;                                                                         \
+  }
+  switch (ny) {
+    VP_SIZES(VP_YQ)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_YQ
+  return hipGetLastError();
+}
+
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+                                 int nzm, const PassOpts& o, hipStream_t st) {
+  using T2 = typename Vec2<T>::type;
+  int ll = 0;
+  while ((1 << ll) < lines) ++ll;
+  const long plane = (long)nx * ny;
+  const dim3 grid((unsigned)(nx / (2 * lines)), (unsigned)nplanes);
+#define VP_Y(NN)                                                                   \
+  case NN: {                                                                       \
+    const int nthr = lines * FftShape<NN, PTM>::TPL;                               \
+    const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);           \
+    auto kern = FWD ? &k_yfwd<T, NN, BC, PTM> : &k_yinv<T, NN, BC, PTM>;           \
+    if (shm > 65536) {                                                             \
+      const hipError_t e = allow_large_lds(kern);                                  \
+      if (e != hipSuccess) return e;                                               \
+    }                                                                              \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, nx, plane, ll, tab, nzm, \
+                       o.skip);                                                    \
+    break;                                                                         \
+  }
+  switch (ny) {
+    VP_SIZES(VP_Y)
+    default: return hipErrorInvalidValue;
+  }
+#undef VP_Y
+  return hipGetLastError();
+}
+
+template <typename T, int BC, bool FWD, int PTM>
+static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
+                              const PassOpts& o, hipStream_t st) {
+  int lines = ypass_lines(nx, ny);
+  if (o.lines > 0 && o.lines < lines) lines = o.lines;
+  const int nzm = o.nzm > 0 ? o.nzm : nplanes;
+  if constexpr (BC == BC_ND || BC == BC_DN)
+    return launch_yq_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o.skip, st);
+  else
+    return launch_ystd_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o, st);
+}
+
+template <typename T, int BC, bool FWD>
+static hipError_t launch_y_bc(T* data, int nx, int ny, int nplanes, const T* tab, int pt,
+                              const PassOpts& o, hipStream_t st) {
+  return pt == 8 ? launch_y_pt<T, BC, FWD, 8>(data, nx, ny, nplanes, tab, o, st)
+                 : launch_y_pt<T, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
+}
+
+hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
+                        const double* tab, int pt, int lines, hipStream_t st) {
+  PassOpts o{};
+  o.lines = lines;
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return fwd ? launch_y_bc<double, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<double, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  });
+}
+
+hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
+                        const float* tab, int pt, const PassOpts& o, hipStream_t st) {
+  return with_bc(bc, [&](auto B) {
+    constexpr int BC = decltype(B)::value;
+    return fwd ? launch_y_bc<float, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<float, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+  });
+}
+
+}  // namespace vp

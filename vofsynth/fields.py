@@ -281,6 +281,9 @@ CONFIGS = {
     "ppn512s": Config("ppn512s", 512, 512, 256, "PPN", beta=1.5),
     # 512^3 triply periodic (mixed-precision comparison)
     "ppp512": Config("ppp512", 512, 512, 512, "PPP"),
+    # the three-dimensional settling droplet grid: 320 x 320 x 640 cubic cells,
+    # triply periodic (transform lengths 5 * 2^k)
+    "ppp320x320x640": Config("ppp320x320x640", 320, 320, 640, "PPP", lz=2.0),
     # serving classes
     "ppn64": Config("ppn64", 64, 64, 64, "PPN"),
     "ppn128x128x256s": Config("ppn128x128x256s", 128, 128, 256, "PPN", beta=1.5),
