@@ -47,8 +47,9 @@ ALG_BYTES_PER_POINT = {
     "extension": 104,             # u, v, w, phi, qx, qy, qz in; ue, ve, we, ug, vg, wg out
 }
 KERNEL_SOURCES = {
-    "x_forward": "transforms.hip", "y_forward": "transforms.hip", "y_inverse": "transforms.hip",
-    "x_inverse": "transforms.hip", "z_solve": "zsolve.hip", "rhs_assembly": "stencils.hip",
+    "x_forward": "transforms_x.hip", "y_forward": "transforms_y.hip",
+    "y_inverse": "transforms_y.hip", "x_inverse": "transforms_x.hip", "z_solve": "zsolve.hip",
+    "rhs_assembly": "stencils.hip",
     "correction": "stencils.hip", "extension": "stencils.hip", "step_epilogue": "stencils.hip",
 }
 

@@ -32,7 +32,7 @@ inline Batch<T> batch_of(T* const* ptrs, int n) {
   return b;
 }
 
-// transforms.hip -------------------------------------------------------------
+// transforms_x.hip, transforms_y.hip ------------------------------------------
 // tab layout per direction and precision, (cos, sin) pairs: of 2 pi k/N for
 // k < N, then of pi m/(2N) for m <= N/2 (one 2-vector load per twiddle).
 int ypass_tile_cols(int nx, int ny);
@@ -79,7 +79,7 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool f
 // spectral z pass for a uniform z grid with nz a transform length (2^k in
 // [8, 1024] or 5 * 2^k in [40, 640]):
 // forward real DFT / DCT-II along z, division by the 3-D eigenvalue, inverse,
-// in one pass (transforms.hip)
+// in one pass (transforms_z.hip)
 struct ZSpecArgs {
   int nx, ny, nz;
   int lx;              // log2(nx)
