@@ -634,9 +634,17 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),
             "rhs assembly", st);
-  int s = solve_one(P, b, p, st);
-  if (s) return s;
-  s = solve_one(P, src_ext, phi, st);
+  // the Stefan potential does not depend on the pressure: with room for two
+  // fields both solves run as one batch (one launch per pass, the same bits)
+  int s;
+  if (P->max_batch >= 2) {
+    const double* rhs2[2] = {b, src_ext};
+    double* sol2[2] = {p, phi};
+    s = solve_any(P, 2, rhs2, sol2, st);
+  } else {
+    s = solve_one(P, b, p, st);
+    if (!s) s = solve_one(P, src_ext, phi, st);
+  }
   if (s) return s;
   VP_LAUNCH(P, K_EPILOGUE,
             vp::launch_step_epilogue(P->ge, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,

@@ -407,19 +407,20 @@ __device__ __forceinline__ void epi_store(double un, double vn, double wn, doubl
                                           double* __restrict__ ug, double* __restrict__ vg,
                                           double* __restrict__ wg) {
 #pragma clang fp contract(off)
-  u[c] = un;
-  v[c] = vn;
-  w[c] = wn;
+  // the outputs are not read again by this kernel: non-temporal stores
+  __builtin_nontemporal_store(un, u + c);
+  __builtin_nontemporal_store(vn, v + c);
+  __builtin_nontemporal_store(wn, w + c);
   const double ex = un - gx, ey = vn - gy, ez = wn - gz;
   if (ue) {
-    ue[c] = ex;
-    ve[c] = ey;
-    we[c] = ez;
+    __builtin_nontemporal_store(ex, ue + c);
+    __builtin_nontemporal_store(ey, ve + c);
+    __builtin_nontemporal_store(ez, we + c);
   }
   if (ug) {
-    ug[c] = ex - (have_q ? qxv : qx[c]);
-    vg[c] = ey - (have_q ? qyv : qy[c]);
-    wg[c] = ez - (have_q ? qzv : qz[c]);
+    __builtin_nontemporal_store(ex - (have_q ? qxv : qx[c]), ug + c);
+    __builtin_nontemporal_store(ey - (have_q ? qyv : qy[c]), vg + c);
+    __builtin_nontemporal_store(ez - (have_q ? qzv : qz[c]), wg + c);
   }
 }
 
@@ -553,13 +554,14 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
         rp[m] = rc[m];
         fp[m] = -fc[m];
       }
-      un[m] = u[c];
-      vn[m] = v[c];
-      wn[m] = w[c];
+      // read once: non-temporal loads
+      un[m] = __builtin_nontemporal_load(u + c);
+      vn[m] = __builtin_nontemporal_load(v + c);
+      wn[m] = __builtin_nontemporal_load(w + c);
       if (ug) {
-        qxv[m] = qx[c];
-        qyv[m] = qy[c];
-        qzv[m] = qz[c];
+        qxv[m] = __builtin_nontemporal_load(qx + c);
+        qyv[m] = __builtin_nontemporal_load(qy + c);
+        qzv[m] = __builtin_nontemporal_load(qz + c);
       }
       const int sl = (ty + 4 * m) * W + tx;
       sm[sl] = pc[m];

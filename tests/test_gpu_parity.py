@@ -601,3 +601,22 @@ def test_fused_step_graph_replay(torch_dev):
         for a, b in zip(got, eager):
             assert torch.equal(a, b), f"replay {rep} differs"
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fused_step_batches_its_two_solves(torch_dev, prec):
+    """A plan with room for two fields runs the step's pressure and Stefan
+    solves as one batch: every output equals the one-field plan's, bit for bit."""
+    torch = torch_dev
+    g = _grid(64, 32, 24, "PPN", 1.3)
+    us, vs, ws, phat, rho, rho0, s, dt, q = _step_inputs(g)
+    T = lambda a: _dev(torch, a)  # noqa: E731
+    outs = []
+    for mb in (1, 2):
+        plan = _plan(g, precision=prec, max_batch=mb)
+        o = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt, T(s),
+                      q=tuple(T(a) for a in q), out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+        torch.cuda.synchronize()
+        outs.append([a.cpu().numpy() for a in o])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
