@@ -33,6 +33,13 @@ constexpr int lds_len() {
   return N + N / 16 + 1;
 }
 
+// threads of an x-pass block: 256, or 128 for lengths 5 * 2^k (20 values per
+// thread: a 256-thread block would hold about 88 KB of LDS, one block per CU)
+template <int N>
+constexpr int x_block_threads() {
+  return N % 5 == 0 ? 128 : 256;
+}
+
 // ---------------------------------------------------------------------------
 // LDS access policies: x lines as separate re/im rows, y lines interleaved
 // ---------------------------------------------------------------------------
@@ -405,7 +412,7 @@ __device__ __forceinline__ int qpos(int e) {
 // ---------------------------------------------------------------------------
 template <int N, int PTM>
 constexpr int xq_rows_per_block() {
-  return 256 / FftShape<N / 2, PTM>::TPL;
+  return x_block_threads<N>() / FftShape<N / 2, PTM>::TPL;
 }
 
 // ---------------------------------------------------------------------------

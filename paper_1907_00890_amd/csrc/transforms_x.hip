@@ -6,8 +6,33 @@
 
 namespace vp {
 
+// block sums of e^2 and p^2 to norms[2 * (member * gridDim.x + block) + {0, 1}]
+// (fixed order, through the block's LDS, which the caller no longer needs;
+// XB threads, red holds 2 XB doubles)
+template <int XB>
+__device__ __forceinline__ void block_norms(double* red, double ee, double pp,
+                                            double* __restrict__ norms) {
+  __syncthreads();
+  red[threadIdx.x] = ee;
+  red[XB + threadIdx.x] = pp;
+  __syncthreads();
+  for (int w = XB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      red[XB + threadIdx.x] += red[XB + threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
+    norms[o] = red[0];
+    norms[o + 1] = red[XB];
+  }
+}
+
 // ---------------------------------------------------------------------------
-// x kernels: a block owns 2*LPB consecutive rows (nrows is even)
+// x kernels: a block owns 2*LPB consecutive rows (nrows is even);
+// x_block_threads<N>() threads, TPL per line pair
 // ---------------------------------------------------------------------------
 // SUB: member b's input is read as in[b] - sub[b] (FP64, before any
 // conversion to T); without it the kernel reads its input unchanged.
@@ -17,7 +42,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __res
                                                const T* __restrict__ tab,
                                                const double* __restrict__ sub,
                                                const int* __restrict__ skip) {
-  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = 256 / TPL;
+  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = x_block_threads<N>() / TPL;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
@@ -60,7 +85,7 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
                                                const double* __restrict__ sub,
                                                const int* __restrict__ skip,
                                                double* __restrict__ norms) {
-  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = 256 / TPL;
+  constexpr int XB = x_block_threads<N>(), TPL = FftShape<N, PTM>::TPL, LPB = XB / TPL;
   constexpr bool NORMS = !std::is_same<T, TO>::value;
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
@@ -103,23 +128,7 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
   if constexpr (NORMS) {
     if (norms) {
       // fixed-order block reduction through the (now free) LDS of the transform
-      double* red = reinterpret_cast<double*>(lds_mem);
-      __syncthreads();
-      red[threadIdx.x] = ee;
-      red[256 + threadIdx.x] = pp;
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-          red[threadIdx.x] += red[threadIdx.x + w];
-          red[256 + threadIdx.x] += red[256 + threadIdx.x + w];
-        }
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) {
-        const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
-        norms[o] = red[0];
-        norms[o + 1] = red[256];
-      }
+      block_norms<XB>(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
     }
   }
 }
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(256) void k_xqfwd(const Batch<const TI> in, T* __re
                                                 const T* __restrict__ tab,
                                                 const double* __restrict__ sub,
                                                 const int* __restrict__ skip) {
-  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = 256 / TPL;
+  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = x_block_threads<N>() / TPL;
   __shared__ T lds_mem[2 * LPB * lds_len<H>()];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
@@ -152,28 +161,6 @@ __global__ __launch_bounds__(256) void k_xqfwd(const Batch<const TI> in, T* __re
       });
 }
 
-// block sums of e^2 and p^2 to norms[2 * (member * gridDim.x + block) + {0, 1}]
-// (fixed order, through the block's LDS, which the caller no longer needs)
-__device__ __forceinline__ void block_norms(double* red, double ee, double pp,
-                                            double* __restrict__ norms) {
-  __syncthreads();
-  red[threadIdx.x] = ee;
-  red[256 + threadIdx.x] = pp;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      red[256 + threadIdx.x] += red[256 + threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
-    norms[o] = red[0];
-    norms[o + 1] = red[256];
-  }
-}
-
 template <typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
 __global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long istride,
                                                 const Batch<TO> out, long nrows,
@@ -181,11 +168,12 @@ __global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long is
                                                 const double* __restrict__ sub,
                                                 const int* __restrict__ skip,
                                                 double* __restrict__ norms) {
-  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = 256 / TPL;
+  constexpr int XB = x_block_threads<N>();
+  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = XB / TPL;
   constexpr bool NORMS = !std::is_same<T, TO>::value;
   // the norm reduction needs 512 doubles of LDS
   constexpr int LDS_T = 2 * LPB * lds_len<H>();
-  constexpr int RED_T = 512 * (int)sizeof(double) / (int)sizeof(T);
+  constexpr int RED_T = 2 * XB * (int)sizeof(double) / (int)sizeof(T);
   __shared__ T lds_mem[LDS_T > RED_T ? LDS_T : RED_T];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   double ee = 0.0, pp = 0.0;
@@ -214,7 +202,7 @@ __global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long is
         }
       });
   if constexpr (NORMS) {
-    if (norms) block_norms(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
+    if (norms) block_norms<XB>(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
   }
 }
 
@@ -224,7 +212,7 @@ template <int PTM>
 static long x_rows_per_block(int n) {
   switch (n) {
 #define VP_RPB(NN) \
-  case NN: return 2L * (256 / FftShape<NN, PTM>::TPL);
+  case NN: return 2L * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);
     VP_SIZES(VP_RPB)
 #undef VP_RPB
     default: return 0;
@@ -254,9 +242,10 @@ static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long
                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
 #define VP_XF(NN)                                                                           \
   case NN: {                                                                                \
-    const long rpb = 2 * (256 / FftShape<NN, PTM>::TPL);                                    \
+    const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
     hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB, PTM>),                                   \
-                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
+                       dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
     break;                                                                                  \
   }
@@ -276,7 +265,8 @@ static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, T* out, lon
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
     hipLaunchKernelGGL((k_xqfwd<TI, T, NN, BC, SUB, PTM>),                                  \
-                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
+                       dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
     break;                                                                                  \
   }
@@ -308,9 +298,10 @@ static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out
                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
 #define VP_XI(NN)                                                                           \
   case NN: {                                                                                \
-    const long rpb = 2 * (256 / FftShape<NN, PTM>::TPL);                                    \
+    const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
     hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM, PTM>),                                 \
-                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
+                       dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
     break;                                                                                  \
   }
@@ -330,7 +321,8 @@ static hipError_t launch_xqinv_pt(const T* in, long istride, const Batch<TO>& ou
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
     hipLaunchKernelGGL((k_xqinv<T, TO, NN, BC, ACCUM, PTM>),                                \
-                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb), dim3(256), 0, \
+                       dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
+                       dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
     break;                                                                                  \
   }

@@ -97,7 +97,8 @@ __global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long p
 }
 
 static int ypass_lines(int nx, int ny) {
-  int lines = 256 / fft_tpl(ny);
+  // 128 threads for lengths 5 * 2^k (20 values per thread: LDS per block)
+  int lines = (ny % 5 == 0 ? 128 : 256) / fft_tpl(ny);
   if (lines < 1) lines = 1;
   if (lines > pow2_part(nx) / 2) lines = (int)(pow2_part(nx) / 2);  // 2 lines divide nx
   return lines;

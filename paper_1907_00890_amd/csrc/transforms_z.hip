@@ -61,7 +61,7 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   using T2 = typename Vec2<T>::type;
   const long plane = (long)a.nx * a.ny;
   // tile width: as for the y pass of a line of the same length, or a.lines
-  int lines = 256 / fft_tpl(a.nz);
+  int lines = (a.nz % 5 == 0 ? 128 : 256) / fft_tpl(a.nz);  // 128 threads for 5 * 2^k
   if (a.lines > 0 && a.lines < lines) lines = a.lines;
   if (lines > pow2_part(plane) / 2) lines = (int)(pow2_part(plane) / 2);  // tiles divide the plane
   int ll = 0;
