@@ -11,9 +11,10 @@
 // segments; a lane owns one segment in registers and eliminates its interior
 // rows for the data and for the two couplings to the segment's end values
 // (x_i = alpha_i + beta_i x_first + gamma_i x_last).  The end values of all
-// segments then satisfy a tridiagonal system of 2S unknowns, which two lanes
-// per line solve in LDS from both ends (a twisted factorisation that meets in
-// the middle); each lane finally rebuilds its interior.  Lines run on
+// segments then satisfy a tridiagonal system of 2S unknowns, which the S
+// lanes of the line solve in LDS by parallel cyclic reduction (ceil(log2 2S)
+// strides instead of S dependent rows); each lane finally rebuilds its
+// interior.  Lines run on
 // consecutive lanes, so every load and store of a z-plane row is coalesced.
 // When every segment has exactly M rows and/or the z grid is uniform, the
 // kernel is specialised at compile time (no per-row guards, constant
@@ -70,100 +71,66 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // Reduced system of line l (rows r*LB + l) in M-matrix form,
 //   -lo_r u_{r-1} + (rho_r + lo_r + up_r) u_r - up_r u_{r+1} = R_r,
-// with one or two right-hand sides (R1, and R2 when `two`); solutions
-// overwrite R1 / R2.  Twisted factorisation: the lane with half == 0
-// eliminates rows 0..h-1 downwards, the lane with half == 1 rows nr-1..h+1
-// upwards, both in row-sum form; row h then has the pivot
-//   rho_h + lo_h ratio_top + up_h ratio_bottom
-// (a sum of positive terms) and each lane substitutes back over its half.
-// ex: 6 * LB doubles of LDS for the exchange at row h.  All lanes of the
-// block call this (it contains barriers); `act` marks the two working lanes.
+// with one or two right-hand sides (R1, and R2 when `two`), solved by
+// parallel cyclic reduction with every lane of the line at work: lane s owns
+// rows 2s and 2s+1.  At stride d each row
+// eliminates its neighbours at distance d,
+//   a = lo_i / D_{i-d},  b = up_i / D_{i+d}   (D = lo + up + rho),
+//   lo_i <- a lo_{i-d},  up_i <- b up_{i+d},  rho_i <- rho_i + a rho_{i-d} + b rho_{i+d},
+//   R_i <- R_i + a R_{i-d} + b R_{i+d},
+// which keeps every row in row-sum form (D a sum of positive terms); after
+// ceil(log2 nr) strides the rows decouple and R_i / rho_i is the solution,
+// written to R1 (and R2 when `two`).  All lanes of the block call this.
 template <int LB>
-__device__ __forceinline__ void red_twisted(double* lo, double* up, const double* rho, double* R1,
-                                            double* R2, double* ex, bool two, int nr, int l,
-                                            bool act, int half) {
-  const int h = nr / 2;
-  if (act && half == 0) {
-    double ratio = 0.0, y1 = 0.0, y2 = 0.0;
-    for (int r = 0; r < h; ++r) {
-      const int o = r * LB + l;
-      const double lr = lo[o], ur = up[o];
-      const double sig = rho[o] + lr * ratio;
-      const double iu = rcp64(ur + sig);
-      ratio = sig * iu;
-      y1 = (R1[o] + lr * y1) * iu;
-      R1[o] = y1;
-      if (two) {
-        y2 = (R2[o] + lr * y2) * iu;
-        R2[o] = y2;
+__device__ __forceinline__ void red_pcr(double* lo, double* up, double* rho, double* R1,
+                                        double* R2, bool two, int nr, int l, int s) {
+  for (int d = 1; d < nr; d <<= 1) {
+    double nlo[2], nup[2], nrh[2], n1[2], n2[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = 2 * s + q;
+      const int o = i * LB + l;
+      double rh = rho[o], a1 = R1[o], a2 = two ? R2[o] : 0.0, l2 = 0.0, u2 = 0.0;
+      if (i - d >= 0) {
+        const int m = (i - d) * LB + l;
+        const double a = lo[o] * rcp64(lo[m] + up[m] + rho[m]);
+        l2 = a * lo[m];
+        rh += a * rho[m];
+        a1 += a * R1[m];
+        if (two) a2 += a * R2[m];
       }
-      up[o] = ur * iu;
-    }
-    ex[0 * LB + l] = ratio;
-    ex[1 * LB + l] = y1;
-    ex[2 * LB + l] = y2;
-    if (nr == 2) {  // one segment: no lane below row h
-      ex[3 * LB + l] = 0.0;
-      ex[4 * LB + l] = 0.0;
-      ex[5 * LB + l] = 0.0;
-    }
-  } else if (act && half == 1) {
-    double ratio = 0.0, z1 = 0.0, z2 = 0.0;
-    for (int r = nr - 1; r > h; --r) {
-      const int o = r * LB + l;
-      const double lr = lo[o], ur = up[o];
-      const double sig = rho[o] + ur * ratio;
-      const double iv = rcp64(lr + sig);
-      ratio = sig * iv;
-      z1 = (R1[o] + ur * z1) * iv;
-      R1[o] = z1;
-      if (two) {
-        z2 = (R2[o] + ur * z2) * iv;
-        R2[o] = z2;
+      if (i + d < nr) {
+        const int p = (i + d) * LB + l;
+        const double b = up[o] * rcp64(lo[p] + up[p] + rho[p]);
+        u2 = b * up[p];
+        rh += b * rho[p];
+        a1 += b * R1[p];
+        if (two) a2 += b * R2[p];
       }
-      lo[o] = lr * iv;
+      nlo[q] = l2;
+      nup[q] = u2;
+      nrh[q] = rh;
+      n1[q] = a1;
+      n2[q] = a2;
     }
-    ex[3 * LB + l] = ratio;
-    ex[4 * LB + l] = z1;
-    ex[5 * LB + l] = z2;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int o = (2 * s + q) * LB + l;
+      lo[o] = nlo[q];
+      up[o] = nup[q];
+      rho[o] = nrh[q];
+      R1[o] = n1[q];
+      if (two) R2[o] = n2[q];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (act) {
-    const int o = h * LB + l;
-    const double lr = lo[o], ur = up[o];
-    const double rt = ex[0 * LB + l], yt1 = ex[1 * LB + l], yt2 = ex[2 * LB + l];
-    const double rb = ex[3 * LB + l], zb1 = ex[4 * LB + l], zb2 = ex[5 * LB + l];
-    const double ip = rcp64(rho[o] + lr * rt + ur * rb);
-    double x1 = (R1[o] + lr * yt1 + ur * zb1) * ip;
-    double x2 = two ? (R2[o] + lr * yt2 + ur * zb2) * ip : 0.0;
-    const double xh1 = x1, xh2 = x2;
-    if (half == 0) {
-      for (int r = h - 1; r >= 0; --r) {
-        const int q = r * LB + l;
-        x1 = R1[q] + up[q] * x1;
-        R1[q] = x1;
-        if (two) {
-          x2 = R2[q] + up[q] * x2;
-          R2[q] = x2;
-        }
-      }
-      if (nr == 2) {  // one segment: this lane also owns row h
-        R1[o] = xh1;
-        if (two) R2[o] = xh2;
-      }
-    } else {
-      for (int r = h + 1; r < nr; ++r) {
-        const int q = r * LB + l;
-        x1 = R1[q] + lo[q] * x1;
-        R1[q] = x1;
-        if (two) {
-          x2 = R2[q] + lo[q] * x2;
-          R2[q] = x2;
-        }
-      }
-      R1[o] = xh1;
-      if (two) R2[o] = xh2;
-    }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int o = (2 * s + q) * LB + l;
+    const double ir = rcp64(rho[o]);
+    R1[o] *= ir;
+    if (two) R2[o] *= ir;
   }
 }
 
@@ -178,9 +145,9 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
   double* rho = up + nr * LB;
   double* R1 = rho + nr * LB;
   double* R2 = R1 + nr * LB;
-  double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line), then the twisted exchange
+  double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line)
   // stretched z: the row coefficients, shared by every line, staged once
-  double* cza = red + (S > 6 ? S : 6) * LB;
+  double* cza = red + S * LB;
   double* czc = cza + A.nz;
   if (!UZ) {
     for (int k = threadIdx.x; k < A.nz; k += blockDim.x) {
@@ -402,7 +369,7 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     }
   }
   __syncthreads();
-  red_twisted<LB>(lo, up, rho, R1, R2, red, per, nr, l, gen && s < 2, s);
+  red_pcr<LB>(lo, up, rho, R1, R2, per, nr, l, s);
   __syncthreads();
 
   if (gen) {
@@ -451,7 +418,7 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
 template <typename T, int LB, bool US, bool UZ>
 static hipError_t launch_z_shape(T* data, const ZArgs& a, int nb, hipStream_t st) {
   const int nr = 2 * a.nseg;
-  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)(a.nseg > 6 ? a.nseg : 6) * LB +
+  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)a.nseg * LB +
                                         (UZ ? 0 : 2 * (size_t)a.nz));
   const dim3 grid((unsigned)((a.plane + LB - 1) / LB), (unsigned)nb);
   const dim3 block((unsigned)(LB * a.nseg));
