@@ -285,6 +285,9 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 LDS-staged 64 x 8 (or 16) tiles marching that many planes
  *                 (defaults 8 and 1; tiled 0: plain one-row tiles; results
  *                 are bit-identical);
+ *   "z_segment" : rows per segment of the partitioned tridiagonal z solve,
+ *                 8 or 16 (at most 64 segments; default 8 on stretched grids
+ *                 with nz <= 512, else 16; the autotuner tries both);
  *   "interface_planes" : z-planes marched by one block of interface_terms
  *                 (1..nz, default min(8, nz); results are bit-identical);
  *   "rhs_tiled" : 8 (default) or 16 assembles the projection's right-hand

@@ -96,6 +96,15 @@ std::vector<double> make_lambda(int n, double h, int bc) {
   return l;
 }
 
+// segment length of the partitioned z solve (8 or 16 rows): S = ceil(nz / M)
+// segments, the first nz % S one row longer
+void set_z_segment(vp::ZArgs& Z, int seg) {
+  Z.seg = seg;
+  Z.nseg = (Z.nz + seg - 1) / seg;
+  Z.seg_base = Z.nz / Z.nseg;
+  Z.seg_rem = Z.nz % Z.nseg;
+}
+
 }  // namespace
 
 struct poisson_plan {
@@ -267,17 +276,13 @@ int plan_init(poisson_plan* P, const double* dz) {
   Z.nz = nz;
   // segments of at most 16 rows; 8 on stretched grids with nz <= 512 (fewer
   // registers per lane for the row coefficients: measured 549 against 588 us
-  // at 512 x 512 x 256; uniform grids run faster with 16)
-  Z.seg = 16;
+  // at 512 x 512 x 256); a tuning knob, tried by the autotuner
   {
     bool uni = true;
     for (int k = 1; k < nz; ++k) uni = uni && f[k] == f[0];
-    if (!uni && nz <= 512) Z.seg = 8;
+    set_z_segment(Z, (!uni && nz <= 512) ? 8 : 16);
   }
   Z.lines = 16;
-  Z.nseg = (nz + Z.seg - 1) / Z.seg;
-  Z.seg_base = nz / Z.nseg;
-  Z.seg_rem = nz % Z.nseg;
   Z.periodic = zper ? 1 : 0;
   Z.singular = P->singular ? 1 : 0;
   Z.dlo = P->ends[4] == 'D' ? 2.0 / (f[0] * f[0]) : 0.0;
@@ -764,6 +769,11 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     P->ge.kc = value;
     return VP_OK;
   }
+  if (k == "z_segment") {
+    if ((value != 8 && value != 16) || (P->nz + value - 1) / value > 64) return VP_EINVAL;
+    set_z_segment(P->z, value);
+    return VP_OK;
+  }
   if (k == "interface_planes") {
     if (value < 1 || value > P->nz) return VP_EINVAL;
     P->gi.kc = value;
@@ -910,8 +920,23 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
       return mixed ? hs(vp::launch_zsolve_f32(P->work32, P->z, nb, st))
                    : hs(vp::launch_zsolve_f64(P->work64, P->z, nb, st));
     };
-    s = pick(st, &P->z.lines, {8, 16, 32}, zpass, &res[2]);
+    // segment length and lines per block together (at most 64 segments)
+    int zcode = P->z.seg * 100 + P->z.lines;
+    std::vector<int> zc;
+    for (int seg : {16, 8})
+      if ((P->nz + seg - 1) / seg <= 64)
+        for (int lines : {8, 16, 32}) zc.push_back(seg * 100 + lines);
+    auto zapply = [&](int code) {
+      set_z_segment(P->z, code / 100);
+      P->z.lines = code % 100;
+    };
+    s = pick(st, &zcode, zc, [&]() -> int {
+      zapply(zcode);
+      return zpass();
+    }, nullptr);
     if (s) return s;
+    zapply(zcode);
+    res[2] = P->z.lines;
     if (P->z_spec_ok) {
       // codes: 0 = tridiagonal (tuned lines), else spectral: radix * 1000 +
       // column pairs per block (0: default width)
@@ -976,6 +1001,7 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "epilogue_tiled") *value = P->ge.tiled;
   else if (k == "epilogue_planes") *value = P->ge.kc;
   else if (k == "interface_planes") *value = P->gi.kc;
+  else if (k == "z_segment") *value = P->z.seg;
   else return VP_EINVAL;
   return VP_OK;
 }

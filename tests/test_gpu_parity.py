@@ -620,3 +620,23 @@ def test_fused_step_batches_its_two_solves(torch_dev, prec):
         outs.append([a.cpu().numpy() for a in o])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("case", [(32, 32, 256, "PPN", None), (16, 16, 300, "NNP", 1.5),
+                                  (16, 8, 512, "PPN", 1.3), (8, 8, 40, "NNNNND", None)],
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
+def test_z_segment_lengths(torch_dev, case):
+    """Segments of 8 or 16 rows in the partitioned z solve (a tuning knob):
+    both match the oracle."""
+    torch = torch_dev
+    nx, ny, nz, bc, beta = case
+    g = _grid(nx, ny, nz, bc, beta)
+    f = vofsynth.gaussian_field(g.shape, 91 + nz)
+    ref = oracle.solve(f, g)
+    plan = _plan(g)
+    plan.tune("z_spectral", 0) if plan.tuning()["z_spectral"] else None
+    for seg in (8, 16):
+        plan.tune("z_segment", seg)
+        assert plan.tuning()["z_segment"] == seg
+        p = plan.solve(_dev(torch, f)).cpu().numpy()
+        assert rel_l2(p, ref) <= FP64_TOL, seg
