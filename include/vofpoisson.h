@@ -70,15 +70,18 @@ typedef struct poisson_plan poisson_plan;
 
 /*
  * Create a plan on the current HIP device.
- *   nx, ny : power of two in [8, 1024];
+ *   nx, ny : a transform length: 2^k in [8, 1024], 3 * 2^k in [24, 768]
+ *            or 5 * 2^k in [40, 640] (radix 2/4/8/16 passes after one
+ *            radix-3 or radix-5 pass);
  *   nz     : >= 1 (>= 3 when z is periodic), at most 1024;
  *   dx, dy : > 0;  dz: HOST array of nz cell widths, each > 0 (copied);
  *   bc     : 3 characters for x, y, z (both ends alike) or 6 for the ends
  *            x-, x+, y-, y+, z-, z+ (either case): 'P' periodic (both ends
  *            of a direction), 'N' wall with zero normal gradient of p (zero
- *            normal velocity), 'D' outflow (p = 0 on the boundary face).  x
- *            and y take P, N N or D D (a wall at one end and an outflow at
- *            the other is VP_EUNSUPPORTED there); z takes any N / D pair.
+ *            normal velocity), 'D' outflow (p = 0 on the boundary face).
+ *            Every direction takes P or any pair of N and D (a wall at one
+ *            end and an outflow at the other: a quarter-wave cosine
+ *            transform in x and y, the tridiagonal pass in z).
  *            project, extend_liquid_velocity(_batched) and vof_step return
  *            VP_EUNSUPPORTED for a plan with an outflow at a lower end (the
  *            face -1/2 has no storage); the solves accept every combination;
@@ -268,8 +271,9 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *   "z_lines"   : lines per block of the tridiagonal z pass, 8, 16 (default)
  *                 or 32 (capped so that lines * segments <= 512);
  *   "z_spectral": 1 (default where possible) solves a uniform z grid with nz a
- *                 power of two in [8, 1024] by a real DFT (periodic) or DCT-II
- *                 (walls) along z, a division by the 3-D eigenvalue and the
+ *                 transform length (as nx, ny) and the same condition at both
+ *                 ends by a real DFT (periodic), DCT-II (walls) or DST-II
+ *                 (outflow) along z, a division by the 3-D eigenvalue and the
  *                 inverse transform, in one pass; 0 uses the tridiagonal pass
  *                 (VP_EUNSUPPORTED for 1 on other grids);
  *   "z_radix"   : values per thread of the spectral z pass, 16 or 8;

@@ -22,9 +22,14 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvofpoisson.so")
 
-# heaviest first (compiled in parallel, in this order)
-SOURCES = ["transforms_x.hip", "transforms_y.hip", "stencils.hip", "transforms_z.hip", "zsolve.hip",
-           "plan.cpp", "serve.cpp", "plan_check.cpp"]
+# (source, parts): a source with several parts is compiled once per part with
+# -DVP_PART=k (each object holds a share of its entry points, so the template
+# instantiations of one file spread over parallel jobs).  Heaviest first
+# (compiled in parallel, in this order).
+SOURCES = [("transforms_x.hip", 3), ("transforms_y.hip", 2), ("transforms_z.hip", 2),
+           ("zsolve.hip", 1), ("stencils.hip", 1), ("plan.cpp", 1), ("serve.cpp", 1),
+           ("plan_check.cpp", 1)]
+JOBS = [(src, k if n > 1 else 0) for src, n in SOURCES for k in range(1, n + 1)]
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -44,23 +49,27 @@ def common_flags():
     ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(job) -> str:
+    src, part = job
+    stem = os.path.splitext(src)[0] + (f".p{part}" if part else "")
+    obj = os.path.join(BUILD, stem + ".o")
     cmd = [hipcc()] + common_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if part:
+        cmd.append(f"-DVP_PART={part}")
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed on {stem}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
 def build(verbose: bool = False) -> str:
     """Compile all sources and link libvofpoisson.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
-    workers = min(len(SOURCES), max(1, os.cpu_count() or 2))
+    workers = min(len(JOBS), max(1, os.cpu_count() or 2))
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, JOBS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

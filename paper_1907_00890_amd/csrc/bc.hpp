@@ -19,4 +19,8 @@ int parse_ends(const char* bc, char ends[6]);
 // Transform code of a direction whose ends are lo, hi (letters as above).
 int direction_code(char lo, char hi);
 
+// A length the x / y / spectral z transforms take: 2^k in [8, 1024],
+// 3 * 2^k in [24, 768] or 5 * 2^k in [40, 640].
+bool fft_length(int n);
+
 }  // namespace vp

@@ -2,14 +2,15 @@
 // (the constant-coefficient direct solver of section 3.2 diagonalises the
 // 1-D second difference of the staggered grid in x and y).
 //
-// * Small DFTs in registers (radix 2, 4, 5, 8, 16; radix 16 as 4 x 4).
+// * Small DFTs in registers (radix 2, 3, 4, 5, 8, 16; radix 16 as 4 x 4).
 // * Stockham passes of radix 16 first, then the remainder (plan<N>):
 //   N = 256 -> 16 x 16, 512 -> 16 x 16 x 2, 1024 -> 16 x 16 x 4.  Each of the
 //   N/16 threads of a line holds 16 complex values; pass p reads positions
 //   j + r N/R and writes (j / NS) NS R + j % NS + r NS (NS = product of the
-//   earlier radices).  Lengths 5 * 2^k: 20 values per thread (so the threads
-//   of a line stay a power of two), a radix-5 pass, then radix 4 (and a last
-//   radix 2): 320 -> 5 x 4 x 4 x 4, 640 -> 5 x 4 x 4 x 4 x 2.
+//   earlier radices).  Lengths F * 2^k with an odd factor F = 3 or 5: 4F
+//   values per thread (so the threads of a line stay a power of two), a
+//   radix-F pass, then radix 4 (and a last radix 2): 320 -> 5 x 4 x 4 x 4,
+//   640 -> 5 x 4 x 4 x 4 x 2, 384 -> 3 x 4 x 4 x 4 x 2, 768 -> 3 x 4 x 4 x 4 x 4.
 // * Two real lines per complex transform.  Periodic lines use a real DFT in
 //   packed form, wall lines a DCT-II / DCT-III computed through the even/odd
 //   reordering of J. Makhoul ("A fast cosine transform in one and two
@@ -80,6 +81,20 @@ __device__ __forceinline__ void dft8(T* r, T* i) {
   r[6] = er[2] - t2r; i[6] = ei[2] - t2i;
   r[3] = er[3] + t3r; i[3] = ei[3] + t3i;
   r[7] = er[3] - t3r; i[7] = ei[3] - t3i;
+}
+
+// radix 3: with a = x1 + x2, b = x1 - x2,
+//   X0 = x0 + a,  X1, X2 = x0 - a/2 +- SIGN i (sqrt3/2) b
+template <int SIGN, typename T>
+__device__ __forceinline__ void dft3(T* r, T* i) {
+  const T h = T(0.86602540378443864676372317075293618347);  // sqrt(3)/2
+  const T ar = r[1] + r[2], ai = i[1] + i[2];
+  const T ur = T(SIGN) * h * (r[1] - r[2]), ui = T(SIGN) * h * (i[1] - i[2]);
+  const T tr = r[0] - T(0.5) * ar, ti = i[0] - T(0.5) * ai;
+  r[0] = r[0] + ar;
+  i[0] = i[0] + ai;
+  r[1] = tr - ui; i[1] = ti + ur;  // t + i u
+  r[2] = tr + ui; i[2] = ti - ur;  // t - i u
 }
 
 // radix 5: with a_1 = x1 + x4, b_1 = x1 - x4, a_2 = x2 + x3, b_2 = x2 - x3,
@@ -157,6 +172,7 @@ __device__ __forceinline__ void dftR(T* r, T* i) {
   else if constexpr (R == 8) dft8<SIGN>(r, i);
   else if constexpr (R == 5) dft5<SIGN>(r, i);
   else if constexpr (R == 4) dft4<SIGN>(r, i);
+  else if constexpr (R == 3) dft3<SIGN>(r, i);
   else dft2<SIGN>(r, i);
 }
 
@@ -171,18 +187,24 @@ __device__ __forceinline__ int dct_perm(int p) {
 // ---------------------------------------------------------------------------
 // PTM: complex values per thread (16: radix-16 passes, 8: radix-8 passes;
 // the radix schedule of a length is greedy, largest radix first).  Lengths
-// 5 * 2^k take 20 values per thread whatever PTM (radix 5, then 4, then 2).
+// F * 2^k (F = 3, 5) take 4F values per thread whatever PTM (radix F, then 4,
+// then 2).
+__host__ __device__ constexpr int odd_factor(int n) {
+  return n % 3 == 0 ? 3 : (n % 5 == 0 ? 5 : 1);
+}
 template <int N, int PTM = 16>
 struct FftShape {
-  static constexpr bool R5 = N % 5 == 0;
-  static constexpr int PT = R5 ? (N >= 20 ? 20 : N) : (N >= PTM ? PTM : N);  // values per thread
-  static constexpr int TPL = N / PT;                                         // threads per line
+  static constexpr int F = odd_factor(N);
+  static constexpr int PT = F > 1 ? (N >= 4 * F ? 4 * F : N)  // values per thread
+                                  : (N >= PTM ? PTM : N);
+  static constexpr int TPL = N / PT;  // threads per line
 };
 template <int N, int NS, int PTM = 16>
 struct PassRadix {
   static constexpr int REM = N / NS;
-  static constexpr int R = N % 5 == 0 ? (NS == 1 ? 5 : (REM >= 4 ? 4 : REM))
-                                      : (REM >= PTM ? PTM : REM);
+  static constexpr int F = odd_factor(N);
+  static constexpr int R = F > 1 ? (NS == 1 ? F : (REM >= 4 ? 4 : REM))
+                                 : (REM >= PTM ? PTM : REM);
 };
 
 // Twiddles of one pass for this thread: w_N^{(j % NS) r N/(NS R)}, r = 1..R-1,

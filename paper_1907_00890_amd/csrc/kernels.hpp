@@ -77,12 +77,11 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool f
                         const float* tab, int pt, const PassOpts& o, hipStream_t st);
 
 // spectral z pass for a uniform z grid with nz a transform length (2^k in
-// [8, 1024] or 5 * 2^k in [40, 640]):
+// [8, 1024], 3 * 2^k in [24, 768] or 5 * 2^k in [40, 640]):
 // forward real DFT / DCT-II along z, division by the 3-D eigenvalue, inverse,
 // in one pass (transforms_z.hip)
 struct ZSpecArgs {
   int nx, ny, nz;
-  int lx;              // log2(nx)
   int bcz;             // BC_P, BC_N or BC_D
   double scale;        // 1 / (nx * ny * nz)
   const double* lamx;  // eigenvalue per packed x, y, z position
@@ -100,8 +99,7 @@ hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, i
 // zsolve.hip -----------------------------------------------------------------
 struct ZArgs {
   long plane;          // nx * ny lines
-  int nx;              // for the (cx, cy) split of a line index (a power of two)
-  int lx;              // log2(nx)
+  int nx;              // for the (cx, cy) split of a line index
   int nz;
   int seg;             // segment length bound M (16; 8 on stretched grids with nz <= 512)
   int lines;           // lines per block (8, 16 or 32; capped so lines * nseg <= 512)

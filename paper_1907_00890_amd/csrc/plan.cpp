@@ -271,8 +271,6 @@ int plan_init(poisson_plan* P, const double* dz) {
   vp::ZArgs& Z = P->z;
   Z.plane = (long)nx * ny;
   Z.nx = nx;
-  Z.lx = 0;
-  while ((1 << Z.lx) < nx) ++Z.lx;
   Z.nz = nz;
   // segments of at most 16 rows; 8 on stretched grids with nz <= 512 (fewer
   // registers per lane for the row coefficients: measured 549 against 588 us
@@ -313,9 +311,7 @@ int plan_init(poisson_plan* P, const double* dz) {
   // real DFT (periodic), DCT-II (walls) or DST-II (outflow at both ends) of
   // the x and y passes; a wall at one end and an outflow at the other keeps
   // the tridiagonal pass
-  const bool zlen = (nz >= 8 && nz <= 1024 && (nz & (nz - 1)) == 0) ||
-                    (nz % 5 == 0 && nz / 5 >= 8 && nz / 5 <= 128 && ((nz / 5) & (nz / 5 - 1)) == 0);
-  P->z_spec_ok = Z.uniform_z && zlen &&
+  P->z_spec_ok = Z.uniform_z && vp::fft_length(nz) &&
                  P->bc[2] <= vp::BC_D;
   if (P->z_spec_ok) {
     const std::vector<double> tz = make_table(nz, P->bc[2]);
@@ -329,7 +325,6 @@ int plan_init(poisson_plan* P, const double* dz) {
     A.nx = nx;
     A.ny = ny;
     A.nz = nz;
-    A.lx = Z.lx;
     A.bcz = P->bc[2];
     A.scale = 1.0 / ((double)nx * (double)ny * (double)nz);
     A.lamx = P->lamx;

@@ -10,13 +10,14 @@ static_assert(vp::kMaxBatch == VP_MAX_BATCH, "batch limit of the kernels and the
 
 namespace {
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
-// a transform length: 2^k in [8, 1024] or 5 * 2^k in [40, 640]
-bool fft_length(int n) {
-  return pow2_in(n, 8, 1024) || (n % 5 == 0 && pow2_in(n / 5, 8, 128));
-}
 }  // namespace
 
 namespace vp {
+
+bool fft_length(int n) {
+  return pow2_in(n, 8, 1024) || (n % 5 == 0 && pow2_in(n / 5, 8, 128)) ||
+         (n % 3 == 0 && pow2_in(n / 3, 8, 256));
+}
 
 int parse_ends(const char* bc, char e[6]) {
   if (!bc) return VP_EINVAL;
@@ -55,7 +56,7 @@ int poisson_plan_check(int nx, int ny, int nz, double dx, double dy, const doubl
     if (!(dz[k] > 0) || !std::isfinite(dz[k])) return VP_EINVAL;
   if (e[4] == 'P' && nz < 3) return VP_EINVAL;
   if (precision != VP_PRECISION_FP64 && precision != VP_PRECISION_MIXED) return VP_EINVAL;
-  if (!fft_length(nx) || !fft_length(ny) || nz > 1024) return VP_EUNSUPPORTED;
+  if (!vp::fft_length(nx) || !vp::fft_length(ny) || nz > 1024) return VP_EUNSUPPORTED;
   return VP_OK;
 }
 

@@ -24,6 +24,15 @@
 #include "fft_lds.hpp"
 #include "kernels.hpp"
 
+// The build compiles each transform source as several objects, one per part
+// of its entry points (VP_PART = 1, 2, ...), so that the template
+// instantiations of one file spread over parallel compiler jobs; without
+// VP_PART one object holds every entry point.
+#ifndef VP_PART
+#define VP_PART 0
+#endif
+#define VP_IN_PART(k) (VP_PART == 0 || VP_PART == (k))
+
 namespace vp {
 
 __device__ __forceinline__ int lds_pos(int e) { return e + (e >> 4); }
@@ -37,7 +46,14 @@ constexpr int lds_len() {
 // thread: a 256-thread block would hold about 88 KB of LDS, one block per CU)
 template <int N>
 constexpr int x_block_threads() {
-  return N % 5 == 0 ? 128 : 256;
+  return odd_factor(N) == 5 ? 128 : 256;
+}
+
+// The radix knob (PTM 16 or 8) does not change the schedule of a length with
+// an odd factor: both knob values launch the one PTM = 16 instantiation.
+template <int N, int PTM>
+constexpr int canon_ptm() {
+  return odd_factor(N) > 1 ? 16 : PTM;
 }
 
 // ---------------------------------------------------------------------------
@@ -418,16 +434,22 @@ constexpr int xq_rows_per_block() {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-#define VP_SIZES(X) \
-  X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(40) X(80) X(160) X(320) X(640)
+#define VP_SIZES(X)                                                                      \
+  X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(40) X(80) X(160) X(320) X(640) X(24) \
+      X(48) X(96) X(192) X(384) X(768)
 
 // y tile: `lines` column pairs per block (the radix-16 thread count of 256
 // when the plane is wide enough, so both schedules read equally wide tiles);
 // 2*lines columns divide nx (both powers of two)
-// threads per line of the radix-16 schedule of length n (20 values per
-// thread for lengths 5 * 2^k)
+// threads of a y-pass or spectral z-pass block at the default tile width
+// (128 for lengths 5 * 2^k: 20 values per thread, LDS per block)
+static inline int pass_threads(int n) { return odd_factor(n) == 5 ? 128 : 256; }
+
+// threads per line of the radix-16 schedule of length n (4F values per
+// thread for lengths F * 2^k, F = 3, 5)
 static inline int fft_tpl(int n) {
-  if (n % 5 == 0) return n >= 20 ? n / 20 : 1;
+  const int f = odd_factor(n);
+  if (f > 1) return n >= 4 * f ? n / (4 * f) : 1;
   return n >= 16 ? n / 16 : 1;
 }
 

@@ -230,12 +230,14 @@ static long xq_rows(int n) {
   }
 }
 
+#if VP_IN_PART(1)
 long xpass_blocks(int nx, int bc, int pt, long nrows) {
   long rpb;
   if (bc == BC_ND || bc == BC_DN) rpb = pt == 8 ? xq_rows<8>(nx) : xq_rows<16>(nx);
   else rpb = pt == 8 ? x_rows_per_block<8>(nx) : x_rows_per_block<16>(nx);
   return rpb > 0 ? (nrows + rpb - 1) / rpb : 0;
 }
+#endif
 
 template <typename TI, typename T, int BC, bool SUB, int PTM>
 static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
@@ -243,7 +245,7 @@ static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long
 #define VP_XF(NN)                                                                           \
   case NN: {                                                                                \
     const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
-    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB, PTM>),                                   \
+    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB, canon_ptm<NN, PTM>()>),                 \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
@@ -264,7 +266,7 @@ static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, T* out, lon
 #define VP_XQF(NN)                                                                          \
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
-    hipLaunchKernelGGL((k_xqfwd<TI, T, NN, BC, SUB, PTM>),                                  \
+    hipLaunchKernelGGL((k_xqfwd<TI, T, NN, BC, SUB, canon_ptm<NN, PTM>()>),                \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
@@ -299,7 +301,7 @@ static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out
 #define VP_XI(NN)                                                                           \
   case NN: {                                                                                \
     const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
-    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM, PTM>),                                 \
+    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),               \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
@@ -320,7 +322,7 @@ static hipError_t launch_xqinv_pt(const T* in, long istride, const Batch<TO>& ou
 #define VP_XQI(NN)                                                                          \
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
-    hipLaunchKernelGGL((k_xqinv<T, TO, NN, BC, ACCUM, PTM>),                                \
+    hipLaunchKernelGGL((k_xqinv<T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),              \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
                        st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
@@ -349,6 +351,7 @@ static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out
                : launch_xinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
 }
 
+#if VP_IN_PART(1)
 hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
                            int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st) {
@@ -368,7 +371,9 @@ hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& 
                                                                      nrows, tab, pt, o, st);
   });
 }
+#endif
 
+#if VP_IN_PART(2)
 hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
                            int nx, int bc, long nrows, const float* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
@@ -380,7 +385,9 @@ hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, lo
                                                             pt, o, st);
   });
 }
+#endif
 
+#if VP_IN_PART(3)
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
                            int nx, int bc, long nrows, bool accum, const float* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
@@ -392,5 +399,6 @@ hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& o
                                                             pt, o, st);
   });
 }
+#endif
 
 }  // namespace vp

@@ -97,14 +97,15 @@ __global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long p
 }
 
 static int ypass_lines(int nx, int ny) {
-  // 128 threads for lengths 5 * 2^k (20 values per thread: LDS per block)
-  int lines = (ny % 5 == 0 ? 128 : 256) / fft_tpl(ny);
+  int lines = pass_threads(ny) / fft_tpl(ny);
   if (lines < 1) lines = 1;
   if (lines > pow2_part(nx) / 2) lines = (int)(pow2_part(nx) / 2);  // 2 lines divide nx
   return lines;
 }
 
+#if VP_IN_PART(1)
 int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
+#endif
 
 // quarter-wave y pass: one column per line, 2*lines columns per block
 template <typename T, int BC, bool FWD, int PTM>
@@ -120,7 +121,7 @@ static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* ta
   case NN: {                                                                       \
     const int nthr = cols * FftShape<NN / 2, PTM>::TPL;                            \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN / 2>() * (cols + 1);        \
-    auto kern = &k_yq<T, NN, BC, !FWD, PTM>;                                       \
+    auto kern = &k_yq<T, NN, BC, !FWD, canon_ptm<NN, PTM>()>;                              \
     if (nthr > 512) return hipErrorInvalidValue;                                   \
     if (shm > 65536) {                                                             \
       const hipError_t e = allow_large_lds(kern);                                  \
@@ -149,7 +150,8 @@ static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* 
   case NN: {                                                                       \
     const int nthr = lines * FftShape<NN, PTM>::TPL;                               \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);           \
-    auto kern = FWD ? &k_yfwd<T, NN, BC, PTM> : &k_yinv<T, NN, BC, PTM>;           \
+    constexpr int PC = canon_ptm<NN, PTM>();                                               \
+    auto kern = FWD ? &k_yfwd<T, NN, BC, PC> : &k_yinv<T, NN, BC, PC>;                     \
     if (shm > 65536) {                                                             \
       const hipError_t e = allow_large_lds(kern);                                  \
       if (e != hipSuccess) return e;                                               \
@@ -185,6 +187,7 @@ static hipError_t launch_y_bc(T* data, int nx, int ny, int nplanes, const T* tab
                  : launch_y_pt<T, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
 }
 
+#if VP_IN_PART(1)
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const double* tab, int pt, int lines, hipStream_t st) {
   PassOpts o{};
@@ -195,7 +198,9 @@ hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool 
                : launch_y_bc<double, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
   });
 }
+#endif
 
+#if VP_IN_PART(2)
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const float* tab, int pt, const PassOpts& o, hipStream_t st) {
   return with_bc(bc, [&](auto B) {
@@ -204,5 +209,6 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool f
                : launch_y_bc<float, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
   });
 }
+#endif
 
 }  // namespace vp

@@ -14,7 +14,7 @@ namespace vp {
 // ---------------------------------------------------------------------------
 template <typename T, int N, int BC, int PTM>
 __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
-    T* __restrict__ data, int nx, int lx, long plane, int llines, const T* __restrict__ tab,
+    T* __restrict__ data, int nx, long plane, int llines, const T* __restrict__ tab,
     const double* __restrict__ lamx, const double* __restrict__ lamy,
     const double* __restrict__ lamz, double scale, long batch_stride,
     double* __restrict__ mean_out, const int* __restrict__ skip) {
@@ -61,7 +61,7 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   using T2 = typename Vec2<T>::type;
   const long plane = (long)a.nx * a.ny;
   // tile width: as for the y pass of a line of the same length, or a.lines
-  int lines = (a.nz % 5 == 0 ? 128 : 256) / fft_tpl(a.nz);  // 128 threads for 5 * 2^k
+  int lines = pass_threads(a.nz) / fft_tpl(a.nz);
   if (a.lines > 0 && a.lines < lines) lines = a.lines;
   if (lines > pow2_part(plane) / 2) lines = (int)(pow2_part(plane) / 2);  // tiles divide the plane
   int ll = 0;
@@ -72,12 +72,12 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   case NN: {                                                                               \
     const int nthr = lines * FftShape<NN, PTM>::TPL;                                       \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);                   \
-    auto kern = &k_zspec<T, NN, BC, PTM>;                                                  \
+    auto kern = &k_zspec<T, NN, BC, canon_ptm<NN, PTM>()>;                                 \
     if (shm > 65536) {                                                                     \
       const hipError_t e = allow_large_lds(kern);                                          \
       if (e != hipSuccess) return e;                                                       \
     }                                                                                      \
-    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, a.nx, a.lx, plane, ll, tab,  \
+    hipLaunchKernelGGL(kern, grid, dim3(nthr), shm, st, data, a.nx, plane, ll, tab,        \
                        a.lamx, a.lamy, a.lamz, a.scale, a.batch_stride, a.mean_out, skip); \
     break;                                                                                 \
   }
@@ -102,14 +102,18 @@ static hipError_t launch_zspec_t(T* data, const ZSpecArgs& a, const T* tab, int 
   });
 }
 
+#if VP_IN_PART(1)
 hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
                             hipStream_t st) {
   return launch_zspec_t<double>(data, a, tab, pt, nb, nullptr, st);
 }
+#endif
 
+#if VP_IN_PART(2)
 hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, int pt, int nb,
                             const int* skip, hipStream_t st) {
   return launch_zspec_t<float>(data, a, tab, pt, nb, skip, st);
 }
+#endif
 
 }  // namespace vp

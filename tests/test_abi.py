@@ -50,6 +50,9 @@ def test_plan_check_matches_create(lib):
     dz = (ctypes.c_double * 8)(*([0.125] * 8))
     assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == 0
     assert lib.poisson_plan_check(12, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == -2
+    for n in (24, 48, 96, 192, 384, 768, 40, 80, 160, 320, 640):  # 3 * 2^k, 5 * 2^k
+        assert lib.poisson_plan_check(n, 8, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == 0, n
+        assert lib.poisson_plan_check(8, n, 8, 0.1, 0.1, dz, b"PPN", 0, 1) == 0, n
     # outflow ends: any pair of wall / outflow in every direction
     for bc in (b"PPD", b"DDD", b"NNNNND", b"ddnnpp", b"PPPPDN", b"DPN", b"NDPPNN", b"PPDNNN"):
         assert lib.poisson_plan_check(8, 8, 8, 0.1, 0.1, dz, bc, 0, 1) == 0, bc
@@ -80,7 +83,11 @@ def _create(lib, nx, ny, nz, bc, dz=None, precision=0, max_batch=1, dx=0.1, dy=0
     ((8, 8, 8, b"PP"), -1),
     ((8, 8, 8, b"PPPP"), -1),
     ((8, 8, 2, b"PPP"), -1),        # periodic z needs nz >= 3
-    ((12, 8, 8, b"PPN"), -2),       # not a power of two
+    ((12, 8, 8, b"PPN"), -2),       # 3 * 4: below the shortest 3 * 2^k (24)
+    ((36, 8, 8, b"PPN"), -2),       # 9 * 4: no radix-9 schedule
+    ((8, 1536, 8, b"PPN"), -2),     # 3 * 512: too long
+    ((20, 8, 8, b"PPN"), -2),       # 5 * 4: below the shortest 5 * 2^k (40)
+    ((8, 1280, 8, b"PPN"), -2),     # 5 * 256: too long
     ((8, 2048, 8, b"PPN"), -2),     # too long
     ((4, 8, 8, b"PPN"), -2),        # too short
     ((8, 8, 8, b"PNNNNN"), -1),     # periodic at one end only

@@ -1,5 +1,6 @@
-"""GPU parity for transform lengths 5 * 2^k (40 .. 640; the 320 x 320 x 640
-grid of the paper's three-dimensional droplet case): radix-5 Stockham passes
+"""GPU parity for transform lengths with an odd factor, 5 * 2^k (40 .. 640;
+the 320 x 320 x 640 grid of the paper's three-dimensional droplet case) and
+3 * 2^k (24 .. 768): a radix-5 or radix-3 Stockham pass, then radix 4 and 2,
 in every transform (real DFT, cosine, sine and quarter-wave; x, y and the
 spectral z pass), tile widths that divide such lengths in the stencils, and
 the interface terms, against the FP64 oracle."""
@@ -55,6 +56,21 @@ SOLVE_CASES = [
     (160, 40, 10, "NDNNND", None),   # quarter-wave x (half length 80), y walls
     (40, 80, 20, "DNPPND", 1.2),     # quarter-wave x (half length 20)
     (320, 320, 4, "PPP", None),      # the droplet grid's x-y plane
+    # 3 * 2^k: 12 values per thread, a radix-3 pass first
+    (48, 48, 48, "PPP", None),       # spectral z of length 48
+    (384, 16, 9, "PPN", None),       # x real DFT, 32 threads per line
+    (16, 384, 7, "NNN", 1.3),        # y cosine transform
+    (96, 192, 12, "DDN", 1.5),       # sine transforms
+    (768, 8, 3, "PNN", None),        # longest x
+    (8, 768, 3, "NPP", None),        # longest y
+    (24, 8, 384, "PPN", None),       # spectral z cosine, 384
+    (8, 8, 768, "PPP", None),        # spectral z real DFT, 768
+    (24, 24, 24, "DDD", None),       # spectral z sine, shortest length
+    (192, 24, 10, "NDNNND", None),   # quarter-wave x (half length 96)
+    (24, 48, 20, "DNPPND", 1.2),     # quarter-wave x (half length 12)
+    (16, 96, 8, "PPNDNN", None),     # quarter-wave y (half length 48)
+    (384, 384, 4, "PPP", None),
+    (40, 48, 24, "NNPPNN", None),    # radix 5 in x, radix 3 in y and spectral z
 ]
 
 
@@ -69,7 +85,7 @@ def test_solve_parity(torch_dev, case):
     p = plan.solve(_dev(torch, f))
     torch.cuda.synchronize()
     err = rel_l2(p.cpu().numpy(), ref)
-    print(f"radix5 solve {case}: rel L2 {err:.3e}")
+    print(f"odd-length solve {case}: rel L2 {err:.3e}")
     assert err <= FP64_TOL, err
     if plan.tuning()["z_spectral"]:
         plan.tune("z_spectral", 0)
@@ -85,9 +101,10 @@ def test_solve_parity(torch_dev, case):
     assert rel_l2(r, ref) <= FP64_TOL
 
 
-def test_mixed_and_batched(torch_dev):
+@pytest.mark.parametrize("shape", [(80, 40, 40), (96, 48, 24)])
+def test_mixed_and_batched(torch_dev, shape):
     torch = torch_dev
-    g = _grid(80, 40, 40, "PPN", None)
+    g = _grid(*shape, "PPN", None)
     fs = [vofsynth.gaussian_field(g.shape, 70 + i) for i in range(3)]
     plan = _plan(g, precision="mixed", max_batch=3)
     singles = [plan.solve(_dev(torch, f)).cpu().numpy() for f in fs]
@@ -99,10 +116,11 @@ def test_mixed_and_batched(torch_dev):
 
 
 @pytest.mark.parametrize("shape,bc", [((320, 40, 16), "PPN"), ((40, 80, 12), "NPN"),
-                                      ((160, 32, 8), "NNNNND")])
+                                      ((160, 32, 8), "NNNNND"), ((384, 24, 16), "PPN"),
+                                      ((48, 96, 12), "NNNNND")])
 def test_step_parity(torch_dev, shape, bc):
-    """Projection + extension with tile widths dividing 5 * 2^k rows (LDS-staged
-    and plain stencils), and the interface terms."""
+    """Projection + extension with tile widths dividing 5 * 2^k and 3 * 2^k
+    rows (LDS-staged and plain stencils), and the interface terms."""
     torch = torch_dev
     g = _grid(*shape, bc, 1.3)
     us, vs, ws = vofsynth.random_faces(g.shape, 1, g.bc)
@@ -133,7 +151,7 @@ def test_step_parity(torch_dev, shape, bc):
     for name, a, b in [("u", u, u1), ("v", v, v1), ("w", w, w1), ("p", p, p1), ("phi", phi, ref[6]),
                        ("ue", ue, ref[0]), ("ug", ug, ref[3]), ("wg", wg, ref[5])]:
         err = rel_l2(a, b)
-        print(f"radix5 step {shape} {bc} {name}: {err:.3e}")
+        print(f"odd-length step {shape} {bc} {name}: {err:.3e}")
         assert err <= FP64_TOL, (name, err)
     for a, b in zip(got[0], got[8]):
         assert np.array_equal(a, b)

@@ -121,7 +121,7 @@ def test_too_big_and_unsupported_rejected_at_submit():
             solve(srv, g)
         assert e.value.status == serve.VP_ETOOBIG
         with pytest.raises(ServeError) as e:
-            solve(srv, grid(24, 32, 8))
+            solve(srv, grid(36, 32, 8))
         assert e.value.status == -2
         with pytest.raises(ServeError) as e:
             srv.submit_raw(serve.SOLVE, grid(), rhs=0, sol=FAKE)  # no rhs
