@@ -293,7 +293,12 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 8 or 16 (at most 64 segments; default 8 on stretched grids
  *                 with nz <= 512, else 16; the autotuner tries both);
  *   "interface_planes" : z-planes marched by one block of interface_terms
- *                 (1..nz, default min(8, nz); results are bit-identical);
+ *                 (1..nz; default 64, halved down to 8 while the grid would
+ *                 give fewer than 512 blocks, at most nz; results are
+ *                 bit-identical);
+ *   "interface_tile" : tile width of interface_terms (8, 16, 32 or 64, at
+ *                 most the largest power of two dividing nx, the default;
+ *                 the tile holds 512 cells; results are bit-identical);
  *   "rhs_tiled" : 8 (default) or 16 assembles the projection's right-hand
  *                 side on LDS-staged 64 x 8 (x 16) tiles where nx % 64 == 0 and
  *                 ny divides by the tile height (bit-identical results), 0 on

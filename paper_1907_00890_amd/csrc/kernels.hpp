@@ -159,7 +159,10 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
                                 const double* qz, double* ue, double* ve, double* we, double* ug,
                                 double* vg, double* wg, hipStream_t st);
 // interface terms s, q from the volume fraction C and the mass flux mdot
-// (Youngs gradient of C; one z-marching pass, g.kc planes per block)
+// (Youngs gradient of C; one z-marching pass, g.kc planes per block of
+// kInterfaceThreads threads on a min(txp, 64) x (kInterfaceThreads / width)
+// tile)
+constexpr int kInterfaceThreads = 512;
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st);

@@ -356,10 +356,18 @@ int plan_init(poisson_plan* P, const double* dz) {
   // marching more planes gains nothing)
   P->ge = G;
   P->ge.kc = 1;
-  // the interface terms march 8 planes per block: the four-plane prologue of
-  // a block (C of planes k-1 .. k+2) is then a small share of its loads
+  // the interface terms march up to 64 planes per block (the four-plane
+  // prologue of a block, C of planes k-1 .. k+2, is then a small share of its
+  // loads), fewer where the grid would give under two blocks per compute unit
+  // (measured at 256^3: 8 planes 0.27 ms, 64 planes 0.19 ms)
   P->gi = G;
-  P->gi.kc = nz < 8 ? nz : 8;
+  {
+    const int tx = P->g.txp < 64 ? P->g.txp : 64, ty = vp::kInterfaceThreads / tx;
+    const long tiles = (long)(nx / tx) * ((ny + ty - 1) / ty);
+    int kc = 64;
+    while (kc > 8 && tiles * ((nz + kc - 1) / kc) < 512) kc /= 2;
+    P->gi.kc = kc < nz ? kc : nz;
+  }
   return VP_OK;
 }
 
@@ -774,6 +782,11 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     P->gi.kc = value;
     return VP_OK;
   }
+  if (k == "interface_tile") {
+    if (value < 8 || value > 64 || (value & (value - 1)) || value > P->g.txp) return VP_EINVAL;
+    P->gi.txp = value;  // the tile width is min(txp, 64)
+    return VP_OK;
+  }
   if (k == "stream_planes") {
     if (value < 1 || value > P->nz) return VP_EINVAL;
     P->gs.kc = value;
@@ -996,6 +1009,7 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "epilogue_tiled") *value = P->ge.tiled;
   else if (k == "epilogue_planes") *value = P->ge.kc;
   else if (k == "interface_planes") *value = P->gi.kc;
+  else if (k == "interface_tile") *value = P->gi.txp < 64 ? P->gi.txp : 64;
   else if (k == "z_segment") *value = P->z.seg;
   else return VP_EINVAL;
   return VP_OK;

@@ -12,6 +12,8 @@
 // residual (the Laplacian alone) takes them at any end.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace vp {
@@ -633,18 +635,28 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
 //   zd[j][i] = (C[k+1] - C[k]) / dzc[k] + (C[k] - C[k-1]) / dzc[k-1],
 //                                            gz = sum_{b,c} w_b w_c zd[j+c][i+b] / 32.
 // A block owns a TX x TY tile (TX = the largest power of two dividing nx, at
-// most 64; TY = 256 / TX; one cell per thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
-// (-1, +2) x / y halo sits in a ring of four LDS planes (the next plane is
-// loaded into registers while the current one is computed), dx, dy and zd of
-// the current plane in three more, and a of the current plane on the tile
-// plus its +x / +y halo in three, so each plane of C is read about once per
-// block.
+// most 64, or a narrower width set by the plan; TY = 512 / TX; one cell per
+// thread) and marches through g.kc planes: C of planes k-1 .. k+2 with a
+// (-1, +2) x / y halo sits in a ring of four LDS planes (loads run two planes
+// ahead of the computation, through registers), dx, dy and zd of the current
+// plane in three more, and a of the current plane on the tile plus its +x / +y
+// halo in three, so each plane of C is read about once per block.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int kIfMaxC = 469;  // max over TX of (TX + 3)(256 / TX + 3)
-constexpr int kIfMaxA = 325;  // max over TX of (TX + 1)(256 / TX + 1)
-constexpr int kIfRegs = 2;    // C-tile values per thread: ceil(469 / 256)
-constexpr int kIfARegs = 2;   // a positions per thread: ceil(325 / 256)
+constexpr int kIfThreads = kInterfaceThreads;  // threads of a block = cells of its tile
+// largest (TX + h)(kIfThreads / TX + h) over the tile widths TX = 8 .. 64
+constexpr int if_region(int h) {
+  int m = 0;
+  for (int tx = 8; tx <= 64; tx *= 2) {
+    const int n = (tx + h) * (kIfThreads / tx + h);
+    m = n > m ? n : m;
+  }
+  return m;
+}
+constexpr int kIfMaxC = if_region(3);  // C tile with its (-1, +2) halo
+constexpr int kIfMaxA = if_region(1);  // a region with its +1 halo
+constexpr int kIfRegs = (kIfMaxC + kIfThreads - 1) / kIfThreads;   // C-tile values per thread
+constexpr int kIfARegs = (kIfMaxA + kIfThreads - 1) / kIfThreads;  // a positions per thread
 
 // index i of a line of n cells, periodic (any i; tall tiles of narrow grids
 // reach several periods beyond the end) or mirrored into [0, n)
@@ -654,18 +666,16 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic) {
 }
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_interface(const GridArgs g, const double* __restrict__ C,
-                                                    const double* __restrict__ mdot,
-                                                    double rho1, double rho2, double rho_e,
-                                                    double* __restrict__ s,
-                                                    double* __restrict__ qx,
-                                                    double* __restrict__ qy,
-                                                    double* __restrict__ qz) {
+template <bool FULL>
+__global__ __launch_bounds__(kIfThreads) void k_interface(
+    const GridArgs g, const double* __restrict__ C, const double* __restrict__ mdot,
+    const double* __restrict__ dzc, double rho1, double rho2, double rho_e, double* __restrict__ s,
+    double* __restrict__ qx, double* __restrict__ qy, double* __restrict__ qz) {
   __shared__ double cs[4][kIfMaxC];
   __shared__ double sdx[kIfMaxC], sdy[kIfMaxC], zd[kIfMaxC];
-  __shared__ double sax[kIfMaxA], say[kIfMaxA], saz[kIfMaxA];
+  __shared__ double sax[kIfMaxA], say[kIfMaxA], saz[kIfMaxA], ssrc[kIfMaxA];
   const int tx = tile_w<64>(g);
-  const int ty = 256 / tx;
+  const int ty = kIfThreads / tx;
   const int cw = tx + 3, ch = ty + 3, aw = tx + 1, ah = ty + 1;
   const int i0 = blockIdx.x * tx, j0 = blockIdx.y * ty;
   const int kb = blockIdx.z * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
@@ -673,62 +683,82 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
   const long P = (long)g.nx * g.ny;
   const int li = threadIdx.x % tx, lj = threadIdx.x / tx;
   const int i = i0 + li, j = j0 + lj;
-  const bool own = j < g.ny;  // a cell of the domain (tall tiles of narrow grids)
+  // a cell of the domain (FULL: the tiles cover y exactly; else tall tiles of
+  // narrow grids reach beyond ny)
+  const bool own = FULL || j < g.ny;
   const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho_e;
   const double fx = 1.0 / (32.0 * g.dx), fy = 1.0 / (32.0 * g.dy);
 
-  // in-plane offsets of this thread's C-tile elements and a positions
+  // This thread's C-tile elements e = threadIdx.x + kIfThreads r and a positions,
+  // fixed for the march: in-plane offsets (a thread with fewer elements than
+  // registers repeats its last valid one, so that every load is issued
+  // unconditionally and the waits for them stay exact), which differences an
+  // element carries, the centre of an a position in the C tile and whether
+  // it is a cell of the block.
   long coff[kIfRegs], moff[kIfARegs];
+  bool cin[kIfRegs], cdx[kIfRegs], cdy[kIfRegs], ain[kIfARegs];
+  int ao[kIfARegs];
 #pragma unroll
   for (int r = 0; r < kIfRegs; ++r) {
-    const int e = threadIdx.x + 256 * r;
-    coff[r] = (long)wrap_or_clamp(j0 - 1 + e / cw, g.ny, py) * g.nx +
-              wrap_or_clamp(i0 - 1 + e % cw, g.nx, px);
+    const int e0 = threadIdx.x + kIfThreads * r, e = min(e0, cw * ch - 1);
+    const int ei = e % cw, ej = e / cw;
+    coff[r] = (long)wrap_or_clamp(j0 - 1 + ej, g.ny, py) * g.nx + wrap_or_clamp(i0 - 1 + ei, g.nx, px);
+    cin[r] = e0 < cw * ch;
+    cdx[r] = ei >= 1 && ei <= cw - 2;
+    cdy[r] = ej >= 1 && ej <= ch - 2;
   }
 #pragma unroll
   for (int r = 0; r < kIfARegs; ++r) {
-    const int e = threadIdx.x + 256 * r;
-    moff[r] = (long)wrap_or_clamp(j0 + e / aw, g.ny, py) * g.nx + wrap_or_clamp(i0 + e % aw, g.nx, px);
+    const int e0 = threadIdx.x + kIfThreads * r, e = min(e0, aw * ah - 1);
+    const int ai = e % aw, aj = e / aw;
+    moff[r] = (long)wrap_or_clamp(j0 + aj, g.ny, py) * g.nx + wrap_or_clamp(i0 + ai, g.nx, px);
+    ain[r] = e0 < aw * ah;
+    ao[r] = (aj + 1) * cw + (ai + 1);
   }
+  // plane of index kk in [-1, nz + 1]: wrapped (periodic z, nz >= 3) or clamped
+  auto plane = [&](int kk) {
+    if (pz) return kk < 0 ? kk + g.nz : (kk >= g.nz ? kk - g.nz : kk);
+    return kk < 0 ? 0 : (kk >= g.nz ? g.nz - 1 : kk);
+  };
   auto fetch = [&](int kk, double* v) {
-    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+    const long base = (long)plane(kk) * P;
 #pragma unroll
-    for (int r = 0; r < kIfRegs; ++r)
-      if (threadIdx.x + 256 * r < cw * ch) v[r] = C[base + coff[r]];
+    for (int r = 0; r < kIfRegs; ++r) v[r] = C[base + coff[r]];
   };
   auto put = [&](int kk, const double* v) {
 #pragma unroll
     for (int r = 0; r < kIfRegs; ++r)
-      if (threadIdx.x + 256 * r < cw * ch) cs[kk & 3][threadIdx.x + 256 * r] = v[r];
+      if (cin[r]) cs[kk & 3][threadIdx.x + kIfThreads * r] = v[r];
   };
   auto fetch_m = [&](int kk, double* md) {
-    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+    const long base = (long)plane(kk) * P;
 #pragma unroll
-    for (int r = 0; r < kIfARegs; ++r)
-      if (threadIdx.x + 256 * r < aw * ah) md[r] = mdot[base + moff[r]];
+    for (int r = 0; r < kIfARegs; ++r) md[r] = mdot[base + moff[r]];
   };
   // the z-weighted x and y differences and the z differences of plane kk
   // over the C tile (dx where i-1 and i+1 are in the tile, dy where j-1 and
   // j+1 are)
   auto z_sums = [&](int kk) {
-    const int m = wrap_or_clamp(kk, g.nz, pz);
-    const double ihi = 1.0 / (m + 1 < g.nz ? g.dzc[m] : (pz ? g.dzc[g.nz - 1] : 1.0));
-    const double ilo = 1.0 / (m > 0 ? g.dzc[m - 1] : (pz ? g.dzc[g.nz - 1] : 1.0));
+    const int m = plane(kk);
+    const double ihi = 1.0 / (m + 1 < g.nz ? dzc[m] : (pz ? dzc[g.nz - 1] : 1.0));
+    const double ilo = 1.0 / (m > 0 ? dzc[m - 1] : (pz ? dzc[g.nz - 1] : 1.0));
     const double* cm = cs[(kk - 1) & 3];
     const double* c0 = cs[kk & 3];
     const double* cp = cs[(kk + 1) & 3];
-    for (int e = threadIdx.x; e < cw * ch; e += 256) {
-      const int ei = e % cw, ej = e / cw;
+#pragma unroll
+    for (int r = 0; r < kIfRegs; ++r) {
+      if (!cin[r]) break;
+      const int e = threadIdx.x + kIfThreads * r;
       const double a = cm[e], b = c0[e], c = cp[e];
       zd[e] = (c - b) * ihi + (b - a) * ilo;
-      if (ei >= 1 && ei <= cw - 2)
+      if (cdx[r])
         sdx[e] = (cm[e + 1] - cm[e - 1]) + 2.0 * (c0[e + 1] - c0[e - 1]) + (cp[e + 1] - cp[e - 1]);
-      if (ej >= 1 && ej <= ch - 2)
+      if (cdy[r])
         sdy[e] = (cm[e + cw] - cm[e - cw]) + 2.0 * (c0[e + cw] - c0[e - cw]) +
                  (cp[e + cw] - cp[e - cw]);
     }
   };
-  // gradient of C at a position (ai, aj) of the a region (centre o of the C tile)
+  // gradient of C at a position of the a region (centre o of the C tile)
   auto grad_at = [&](int o, double& gx, double& gy, double& gz) {
     gx = (sdx[o - cw] + 2.0 * sdx[o] + sdx[o + cw]) * fx;
     gy = (sdy[o - 1] + 2.0 * sdy[o] + sdy[o + 1]) * fy;
@@ -737,75 +767,98 @@ __global__ __launch_bounds__(256) void k_interface(const GridArgs g, const doubl
     const double r2 = zd[o + cw - 1] + 2.0 * zd[o + cw] + zd[o + cw + 1];
     gz = (r0 + 2.0 * r1 + r2) * (1.0 / 32.0);
   };
-  // a of plane kk on the tile and its +x / +y halo into sax / say / saz (mdot
-  // of this thread's positions in md); s of the tile cells when `write_s`
-  auto make_a = [&](int kk, const double* md, bool write_s) {
-    const long base = (long)wrap_or_clamp(kk, g.nz, pz) * P;
+  // a of plane kk on the tile and its +x / +y halo into sax / say / saz, and
+  // the source s into ssrc (mdot of this thread's positions in md)
+  auto make_a = [&](const double* md) {
 #pragma unroll
     for (int r = 0; r < kIfARegs; ++r) {
-      const int e = threadIdx.x + 256 * r;
-      if (e >= aw * ah) break;
-      const int ai = e % aw, aj = e / aw;
+      if (!ain[r]) break;
+      const int e = threadIdx.x + kIfThreads * r;
       double gx, gy, gz;
-      grad_at((aj + 1) * cw + (ai + 1), gx, gy, gz);
+      grad_at(ao[r], gx, gy, gz);
       const double mag = sqrt(gx * gx + gy * gy + gz * gz);
       const double sc = mag > 0.0 ? md[r] * a_f / mag : 0.0;
       sax[e] = sc * gx;
       say[e] = sc * gy;
       saz[e] = sc * gz;
-      if (write_s && ai < tx && aj < ty && j0 + aj < g.ny) s[base + moff[r]] = md[r] * src_f * mag;
+      ssrc[e] = md[r] * src_f * mag;
     }
   };
 
-  // C of planes kb-1 .. kb+2 in the ring, then the march: step p computes a
-  // of plane p, writes s, q_x, q_y of plane p (p < ke) and q_z of plane p-1
-  // (p > kb; a_z of p-1 kept in a register); the ring gets plane p+2 at the
-  // end of step p, into the slot of plane p-2
-  double v[kIfRegs], md[kIfARegs], mdn[kIfARegs] = {};
-  fetch_m(kb, md);
+  // C of planes kb-1 .. kb+2 in the ring, then the march.  Step p computes a
+  // and s of plane p and writes s, q_x, q_y of plane p (not on the last step,
+  // p = ke) and q_z of plane p-1 (not on the first, p = kb; a_z of p-1 kept in
+  // a register).  Loads run two steps ahead: at the end of step p the ring
+  // takes plane p+3 (into the slot of plane p-1, last read by z_sums(p)) from
+  // a register set, which then receives plane p+5; mdot of plane p+2 goes
+  // into the set make_a(p) has just consumed.  Steps alternate between two
+  // register sets (sa / sb for C, ma / mb for mdot), so no register is copied
+  // while its load is in flight.  Every load is issued on every step (plane
+  // indices beyond the block's range are clamped to it: a few planes are
+  // read twice at the end of the march) and, with FULL tiles, every store of
+  // an interior step too, so the compiler counts the outstanding memory
+  // operations exactly and waits only for the loads it needs.
+  double sa[kIfRegs] = {}, sb[kIfRegs] = {}, ma[kIfARegs] = {}, mb[kIfARegs] = {};
   for (int kk = kb - 1; kk <= kb + 2; ++kk) {
-    fetch(kk, v);
-    put(kk, v);
+    fetch(kk, sa);
+    put(kk, sa);
   }
+  fetch(min(kb + 3, ke + 1), sa);
+  fetch(min(kb + 4, ke + 1), sb);
+  fetch_m(kb, ma);
+  fetch_m(kb + 1, mb);
   double az_prev = 0.0;
-  for (int p = kb; p <= ke; ++p) {
-    const bool load = p > kb && p + 2 <= ke + 1;  // plane p+2 is read by z_sums(p+1)
-    if (load) fetch(p + 2, v);                    // in flight while plane p is computed
-    if (p + 1 <= ke) fetch_m(p + 1, mdn);
+  const int ea = lj * aw + li;  // this thread's cell in the a region
+  auto step = [&](int p, double* sr, double* mr, auto first_c, auto last_c) {
+    constexpr bool first = decltype(first_c)::value, last = decltype(last_c)::value;
     __syncthreads();  // the ring holds planes p-1 .. p+1; the a planes are free
     z_sums(p);
     __syncthreads();
-    make_a(p, md, p < ke);
+    make_a(mr);
+    fetch_m(min(p + 2, ke), mr);
     __syncthreads();
+    const double az = saz[ea];
     if (own) {
-      const int e = lj * aw + li;
-      if (p < ke) {
-        const long c = p * P + (long)j * g.nx + i;
-        qx[c] = (i + 1 < g.nx || px) ? 0.5 * (sax[e] + sax[e + 1]) : 0.0;
-        qy[c] = (j + 1 < g.ny || py) ? 0.5 * (say[e] + say[e + aw]) : 0.0;
+      const long c = p * P + (long)j * g.nx + i;
+      if constexpr (!last) {
+        s[c] = ssrc[ea];
+        qx[c] = (i + 1 < g.nx || px) ? 0.5 * (sax[ea] + sax[ea + 1]) : 0.0;
+        qy[c] = (j + 1 < g.ny || py) ? 0.5 * (say[ea] + say[ea + aw]) : 0.0;
       }
-      const double az = saz[e];
-      if (p > kb) {
-        const long c = (p - 1) * P + (long)j * g.nx + i;
-        qz[c] = (p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0;
-      }
-      az_prev = az;
+      if constexpr (!first) qz[c - P] = (p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0;
     }
-    if (load) put(p + 2, v);  // slot of plane p-2, last read by z_sums(p-1)
-#pragma unroll
-    for (int r = 0; r < kIfARegs; ++r) md[r] = mdn[r];
+    az_prev = az;
+    put(p + 3, sr);  // beyond ke + 1: a clamped plane no step reads
+    fetch(min(p + 5, ke + 1), sr);
+  };
+  using F = std::false_type;
+  using T = std::true_type;
+  // kc >= 1, so the march has at least the steps kb (first) and ke (last);
+  // step q uses the sets a when q - kb is even
+  step(kb, sa, ma, T{}, F{});
+  int p = kb + 1;
+  for (; p + 1 < ke; p += 2) {
+    step(p, sb, mb, F{}, F{});
+    step(p + 1, sa, ma, F{}, F{});
+  }
+  if (p < ke) {
+    step(p, sb, mb, F{}, F{});
+    step(ke, sa, ma, F{}, T{});
+  } else {
+    step(ke, sb, mb, F{}, T{});
   }
 }
 
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st) {
-  const int tx = tile_w<64>(g), ty = 256 / tx;
+  const int tx = tile_w<64>(g), ty = kIfThreads / tx;
   if (tx < 8 || g.nx % tx || g.kc < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
                   (unsigned)((g.nz + g.kc - 1) / g.kc));
-  hipLaunchKernelGGL(k_interface, grid, dim3(256), 0, st, g, C, mdot, rho1, rho2, rho_e, s, qx, qy,
-                     qz);
+  auto kern = g.ny % ty == 0 ? &k_interface<true> : &k_interface<false>;
+  hipLaunchKernelGGL(kern, grid, dim3(kIfThreads), 0, st, g, C, mdot, g.dzc, rho1, rho2, rho_e, s,
+                     qx, qy, qz);
   return hipGetLastError();
 }
 

@@ -84,13 +84,19 @@ def test_interface_terms_parity(torch_dev, case):
     for a, b in zip(vap[1:], ref2[1:]):
         if np.any(b):
             assert rel_l2(a.cpu().numpy(), b) <= FP64_TOL
-    # planes marched per block: same bits
-    for planes in sorted({1, 3, nz}):
+    # planes marched per block and tile widths: same bits
+    txp = nx & -nx
+    for planes, tile in sorted({(1, 8), (3, 16), (nz, 32), (min(16, nz), 64)}):
+        if tile > txp:
+            with pytest.raises(Exception):
+                plan.tune("interface_tile", tile)
+            continue
         plan.tune("interface_planes", min(planes, nz))
+        plan.tune("interface_tile", tile)
         again = plan.interface_terms(dC, dm, rho1, rho2)
         torch.cuda.synchronize()
         for a, b in zip(again, got):
-            assert np.array_equal(a.cpu().numpy(), b), planes
+            assert np.array_equal(a.cpu().numpy(), b), (planes, tile)
 
 
 def test_interface_terms_feed_the_step(torch_dev):
