@@ -58,6 +58,9 @@ KERNEL_SOURCES = {
 }
 
 
+EXTRAS = ("stretched", "mixed512", "interface", "droplet")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +78,10 @@ def parse():
                          "'sweep' for 50,100,200,500,1000,2000; 'none' to skip")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 512x512x256 stretched step and the 512^3 mixed-vs-FP64 runs")
+                    help="skip the extra workloads (same as --extra none)")
+    ap.add_argument("--extra", default="all",
+                    help="comma-separated extra workloads after the main line: stretched, "
+                         "mixed512, interface, droplet; 'all' (default) or 'none'")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -441,10 +447,12 @@ def interface_outflow_run(torch, dev, steps, no_autotune):
     ms_if, cnt = plan.kernel_times()["interface_terms"]
     plan.set_profiling(False)
     ms_if /= cnt
+    knobs = plan.tuning()
     npts = n ** 3
     res = {"workload": "256x256x256, walls on the sides and the bottom, outflow top (NNNNND)",
            "interface_terms": {"ms": round(ms_if, 4), "alg_bytes": 48 * npts,
-                               "gbs": round(48 * npts / (ms_if * 1e-3) / 1e9, 1)},
+                               "gbs": round(48 * npts / (ms_if * 1e-3) / 1e9, 1),
+                               "planes": knobs["interface_planes"], "tile": knobs["interface_tile"]},
            "step_with_interface_terms_ms": round(ms_step, 4), "tuning": tuned, "solve_ms": {}}
     out = torch.empty_like(f)
     for bc in ("NNNNND", "DDD", "PPN"):
@@ -700,10 +708,19 @@ def main():
         "kernel_ms_per_step": round(kern_ms_step, 4),
         "wall_s_timed": round(t_wall, 3),
     }
-    if not args.no_extra:
+    extras = EXTRAS if args.extra == "all" else [e for e in args.extra.split(",") if e != "none"]
+    if args.no_extra:
+        extras = []
+    for e in extras:
+        if e not in EXTRAS:
+            raise SystemExit(f"unknown extra workload {e!r} (one of {', '.join(EXTRAS)})")
+    if "stretched" in extras:
         line["stretched_512x512x256"] = stretched_step_run(torch, dev, 20, args.no_autotune)
+    if "mixed512" in extras:
         line["mixed_vs_fp64_512"] = mixed512_run(torch, dev, 5, args.no_autotune)
+    if "interface" in extras:
         line["interface_outflow_256"] = interface_outflow_run(torch, dev, 10, args.no_autotune)
+    if "droplet" in extras:
         line["droplet_320x320x640"] = droplet_grid_run(torch, dev, 10, args.no_autotune)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
