@@ -171,15 +171,20 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
 // while the block marches through its planes, so every value of the two
 // 7-point fields is read from HBM about once (halo: 2/TY rows, 2/64 columns,
 // 2/kc planes).  A thread owns column tx of rows ty, ty+4, ... of the tile.
-// The per-cell arithmetic is k_rhs's, term for term.
+// The loads of plane k+1 are issued before plane k is computed, into the
+// other of two register sets (steps alternate between them, so no register
+// is copied while its load is in flight).  Every load is unconditional (at a
+// wall, or for a thread without a halo cell, the address is a valid cell
+// whose value is not used; without s the u* stream stands in), so the
+// compiler counts the outstanding memory operations exactly and waits only
+// for the plane it computes.  The per-cell arithmetic is k_rhs's, term for
+// term.
 template <int TY>
-__global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const double* __restrict__ u,
-                                                    const double* __restrict__ v,
-                                                    const double* __restrict__ w,
-                                                    const double* __restrict__ ph,
-                                                    const double* __restrict__ rho, double rho0,
-                                                    const double* __restrict__ src, double dt,
-                                                    double* __restrict__ b) {
+__global__ __launch_bounds__(256) void k_rhs_tiled(
+    const GridArgs g, const double* __restrict__ u, const double* __restrict__ v,
+    const double* __restrict__ w, const double* __restrict__ ph, const double* __restrict__ rho,
+    double rho0, const double* __restrict__ src, double dt, const double* __restrict__ dzf,
+    const double* __restrict__ dzc, double* __restrict__ b) {
   constexpr int TX = 64, W = TX + 2, RPT = TY / 4;
   __shared__ double sph[(TY + 2) * W], srh[(TY + 2) * W];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -190,6 +195,8 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
   const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, r0dt = rho0 / dt;
   const bool hxp = i + 1 < g.nx || g.bcx == 0, hxm = i > 0 || g.bcx == 0;
   const long xm = i > 0 ? -1 : (long)(g.nx - 1);
+  const bool has_src = src != nullptr;
+  const double* sp = has_src ? src : u;
   // halo cell h of this plane (threads 0 .. 2*TY + 2*TX - 1): LDS slot and
   // in-plane offset; wrapped when periodic, clamped (and unused) at walls
   int hslot = -1;
@@ -235,61 +242,93 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(const GridArgs g, const doubl
     phc[m] = ph[kb * P + c0[m]];
     rhc[m] = rho[kb * P + c0[m]];
   }
-  for (int k = kb; k < ke; ++k) {
+  // the loads of one plane k: the z+1 neighbours of p_hat and rho (plane k
+  // itself at a wall), u* and v* with their x- / y- neighbours, w*, s, and
+  // this thread's halo cell of p_hat and rho
+  struct PlaneLoads {
+    double php[RPT], rhp[RPT], uc[RPT], um[RPT], vc[RPT], vm[RPT], wc[RPT], sv[RPT], hph, hrh;
+  };
+  auto issue = [&](int k, PlaneLoads& L) {
     const int kp = kplus(g, k);
-    const bool zph = kp >= 0 || ztop_out(g, k);
-    // every global load of this plane is issued before the barrier
-    double php[RPT], rhp[RPT], uc[RPT], um[RPT], vc[RPT], vm[RPT], wcs[RPT], sv[RPT];
+    const long ko = (long)k * P, kpo = (long)(kp >= 0 ? kp : k) * P;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
-      const long c = k * P + c0[m];
-      php[m] = rhp[m] = 0.0;
-      if (kp >= 0) {
-        php[m] = ph[kp * P + c0[m]];
-        rhp[m] = rho[kp * P + c0[m]];
-      } else if (zph) {
-        php[m] = -phc[m];
-        rhp[m] = rhc[m];
-      }
-      uc[m] = u[c];
-      um[m] = hxm ? u[c + xm] : 0.0;
-      vc[m] = v[c];
-      vm[m] = hym[m] ? v[c + ymo[m]] : 0.0;
-      wcs[m] = w[c];
-      sv[m] = src ? src[c] : 0.0;
+      L.php[m] = ph[kpo + c0[m]];
+      L.rhp[m] = rho[kpo + c0[m]];
+      L.uc[m] = u[ko + c0[m]];
+      L.um[m] = u[ko + c0[m] + xm];
+      L.vc[m] = v[ko + c0[m]];
+      L.vm[m] = v[ko + c0[m] + ymo[m]];
+      L.wc[m] = w[ko + c0[m]];
+      L.sv[m] = sp[ko + c0[m]];
+    }
+    L.hph = ph[ko + hoff];
+    L.hrh = rho[ko + hoff];
+  };
+  // plane k from the loads L; with `pref`, plane k+1's loads go into Ln first
+  auto step = [&](int k, PlaneLoads& L, PlaneLoads& Ln, auto pref_c) {
+    if constexpr (decltype(pref_c)::value) issue(k + 1, Ln);
+    const int kp = kplus(g, k);
+    const bool zph = kp >= 0 || ztop_out(g, k);
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
       const int slot = (ty + 4 * m + 1) * W + tx + 1;
       sph[slot] = phc[m];
       srh[slot] = rhc[m];
     }
     if (hslot >= 0) {
-      sph[hslot] = ph[k * P + hoff];
-      srh[hslot] = rho[k * P + hoff];
+      sph[hslot] = L.hph;
+      srh[hslot] = L.hrh;
     }
     __syncthreads();
-    const double dzf = g.dzf[k];
-    const double dzcp = zph ? g.dzc[k] : 1.0, dzcm = km >= 0 ? g.dzc[km] : 1.0;
+    const double dzfk = dzf[k];
+    const double dzcp = zph ? dzc[k] : 1.0, dzcm = km >= 0 ? dzc[km] : 1.0;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
       const long c = k * P + c0[m];
       const int sl = (ty + 4 * m + 1) * W + tx + 1;
+      double php = 0.0, rhp = 0.0;
+      if (kp >= 0) {
+        php = L.php[m];
+        rhp = L.rhp[m];
+      } else if (zph) {
+        php = -phc[m];
+        rhp = rhc[m];
+      }
       const RhsNbr xp = hxp ? RhsNbr{sph[sl + 1], srh[sl + 1], true}
                             : RhsNbr{-phc[m], rhc[m], xtop_out(g)};
-      const RhsNbr xm{sph[sl - 1], srh[sl - 1], hxm};
+      const RhsNbr xmn{sph[sl - 1], srh[sl - 1], hxm};
       const RhsNbr yp = hyp[m] ? RhsNbr{sph[sl + W], srh[sl + W], true}
                                : RhsNbr{-phc[m], rhc[m], ytop_out(g)};
       const RhsNbr ym{sph[sl - W], srh[sl - W], hym[m]};
-      const RhsNbr zp{php[m], rhp[m], zph}, zm{phm[m], rhm[m], km >= 0};
-      const double wc = wcs[m];
-      b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xm, yp, ym, zp, dzcp, zm,
-                      dzcm, dzf, uc[m], um[m], vc[m], vm[m], wc, wm[m], sv[m]);
+      const RhsNbr zp{php, rhp, zph}, zm{phm[m], rhm[m], km >= 0};
+      const double wc = L.wc[m];
+      b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xmn, yp, ym, zp, dzcp, zm,
+                      dzcm, dzfk, L.uc[m], hxm ? L.um[m] : 0.0, L.vc[m],
+                      hym[m] ? L.vm[m] : 0.0, wc, wm[m], has_src ? L.sv[m] : 0.0);
       phm[m] = phc[m];
-      phc[m] = php[m];
+      phc[m] = php;
       rhm[m] = rhc[m];
-      rhc[m] = rhp[m];
+      rhc[m] = rhp;
       wm[m] = wc;
     }
     km = k;
     __syncthreads();  // the tile is rewritten for the next plane
+  };
+  using F = std::false_type;
+  using T = std::true_type;
+  PlaneLoads la, lb;
+  issue(kb, la);
+  int k = kb;
+  for (; k + 2 < ke; k += 2) {
+    step(k, la, lb, T{});
+    step(k + 1, lb, la, T{});
+  }
+  if (k + 1 < ke) {
+    step(k, la, lb, T{});
+    step(k + 1, lb, la, F{});
+  } else {
+    step(k, la, lb, F{});
   }
 }
 
@@ -997,10 +1036,10 @@ hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const
                     (unsigned)((g.nz + g.kc - 1) / g.kc));
     if (g.tiled == 16)
       hipLaunchKernelGGL(k_rhs_tiled<16>, grid, dim3(256), 0, st, g, u, v, w, phat, rho, rho0,
-                         src, dt, b);
+                         src, dt, g.dzf, g.dzc, b);
     else
       hipLaunchKernelGGL(k_rhs_tiled<8>, grid, dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src,
-                         dt, b);
+                         dt, g.dzf, g.dzc, b);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_rhs, tile_grid(g), dim3(256), 0, st, g, u, v, w, phat, rho, rho0, src, dt,
