@@ -31,7 +31,7 @@ struct Tile {
   int i, j, kb, ke;
   bool ok;
   long c0;     // offset of (i, j, 0)
-  long xp, xm, yp, ym;  // in-plane neighbour offsets, 0 with `has` false
+  long xp, xm, yp, ym;  // in-plane neighbour offsets (wrapped: valid cells also at walls)
   bool hxp, hxm, hyp, hym;
 };
 
@@ -904,9 +904,16 @@ hipError_t launch_interface(const GridArgs& g, const double* C, const double* md
 // r = f - L_h p (FP64 residual of the defect-correction steps, any ends).  Each block
 // also sums dzf[k] * p and dzf[k] * r over its cells (fixed order, no
 // atomics) into partial[block] and partial[kResidualMaxBlocks + block], so
-// the weighted means of p and r cost no extra pass.
+// the weighted means of p and r cost no extra pass.  A block marches through
+// g.kc planes of a one-row tile; the loads of plane k+1 are issued before
+// plane k is computed, into the other of two register sets, and every load
+// is unconditional (the tile's neighbour offsets wrap to valid cells at
+// walls, where the value is not used), so the compiler waits only for the
+// plane it computes.
 __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double* __restrict__ f,
                                                    const double* __restrict__ p,
+                                                   const double* __restrict__ dzf,
+                                                   const double* __restrict__ dzc,
                                                    double* __restrict__ r,
                                                    double* __restrict__ partial,
                                                    const int* __restrict__ skip) {
@@ -920,31 +927,62 @@ __global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double
     int km = kminus(g, t.kb);
     double pm = km >= 0 ? p[km * P + t.c0] : 0.0;
     double pc = p[t.kb * P + t.c0];
-    for (int k = t.kb; k < t.ke; ++k) {
+    // the loads of plane k: p of the z+1 neighbour (plane k itself at a
+    // wall), the four in-plane neighbours of p, and f
+    struct PlaneLoads {
+      double pp, xp, xm, yp, ym, fc;
+    };
+    auto issue = [&](int k, PlaneLoads& L) {
       const long c = k * P + t.c0;
       const int kp = kplus(g, k);
-      const double pp = kp >= 0 ? p[kp * P + t.c0] : 0.0;
+      L.pp = p[(long)(kp >= 0 ? kp : k) * P + t.c0];
+      L.xp = p[c + t.xp];
+      L.xm = p[c + t.xm];
+      L.yp = p[c + t.yp];
+      L.ym = p[c + t.ym];
+      L.fc = f[c];
+    };
+    auto step = [&](int k, PlaneLoads& L, PlaneLoads& Ln, auto pref_c) {
+      if constexpr (decltype(pref_c)::value) issue(k + 1, Ln);
+      const long c = k * P + t.c0;
+      const int kp = kplus(g, k);
+      const double pp = kp >= 0 ? L.pp : 0.0;
       // across an outflow face the ghost holds -pc
       double lx = 0.0, ly = 0.0, lz = 0.0;
-      if (t.hxp) lx += p[c + t.xp] - pc;
+      if (t.hxp) lx += L.xp - pc;
       else if (g.outflow & 2) lx += -pc - pc;
-      if (t.hxm) lx -= pc - p[c + t.xm];
+      if (t.hxm) lx -= pc - L.xm;
       else if (g.outflow & 1) lx -= pc + pc;
-      if (t.hyp) ly += p[c + t.yp] - pc;
+      if (t.hyp) ly += L.yp - pc;
       else if (g.outflow & 8) ly += -pc - pc;
-      if (t.hym) ly -= pc - p[c + t.ym];
+      if (t.hym) ly -= pc - L.ym;
       else if (g.outflow & 4) ly -= pc + pc;
-      if (kp >= 0) lz += (pp - pc) / g.dzc[k];
-      else if (g.outflow & 32) lz += (-pc - pc) / g.dzf[k];
-      if (km >= 0) lz -= (pc - pm) / g.dzc[km];
-      else if (g.outflow & 16) lz -= (pc + pc) / g.dzf[k];
-      const double rc = f[c] - (lx * idx2 + ly * idy2 + lz / g.dzf[k]);
+      if (kp >= 0) lz += (pp - pc) / dzc[k];
+      else if (g.outflow & 32) lz += (-pc - pc) / dzf[k];
+      if (km >= 0) lz -= (pc - pm) / dzc[km];
+      else if (g.outflow & 16) lz -= (pc + pc) / dzf[k];
+      const double rc = L.fc - (lx * idx2 + ly * idy2 + lz / dzf[k]);
       r[c] = rc;
-      acc += g.dzf[k] * pc;
-      accr += g.dzf[k] * rc;
+      acc += dzf[k] * pc;
+      accr += dzf[k] * rc;
       pm = pc;
       pc = pp;
       km = k;
+    };
+    using F = std::false_type;
+    using T = std::true_type;
+    PlaneLoads la, lb;
+    issue(t.kb, la);
+    int k = t.kb;
+    for (; k + 2 < t.ke; k += 2) {
+      step(k, la, lb, T{});
+      step(k + 1, lb, la, T{});
+    }
+    if (k + 1 < t.ke) {
+      step(k, la, lb, T{});
+      step(k + 1, lb, la, F{});
+    } else {
+      step(k, la, lb, F{});
     }
   }
   red[0][threadIdx.x] = acc;
@@ -1093,7 +1131,8 @@ hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, 
                            const int* skip, hipStream_t st) {
   const int nb = stencil_blocks(g);
   if (nb > kResidualMaxBlocks) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, r, partial, skip);
+  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, g.dzf, g.dzc, r, partial,
+                     skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double denom = (double)g.nx * (double)g.ny * dz_sum;
