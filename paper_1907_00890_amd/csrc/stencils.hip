@@ -177,8 +177,9 @@ __global__ __launch_bounds__(256) void k_rhs(const GridArgs g, const double* __r
 // wall, or for a thread without a halo cell, the address is a valid cell
 // whose value is not used; without s the u* stream stands in), so the
 // compiler counts the outstanding memory operations exactly and waits only
-// for the plane it computes.  The per-cell arithmetic is k_rhs's, term for
-// term.
+// for the plane it computes.  w* and s, read by one cell each, are loaded
+// non-temporally, and b is stored so (measured at 256^3: 210 -> 205 us).
+// The per-cell arithmetic is k_rhs's, term for term.
 template <int TY>
 __global__ __launch_bounds__(256) void k_rhs_tiled(
     const GridArgs g, const double* __restrict__ u, const double* __restrict__ v,
@@ -259,8 +260,8 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(
       L.um[m] = u[ko + c0[m] + xm];
       L.vc[m] = v[ko + c0[m]];
       L.vm[m] = v[ko + c0[m] + ymo[m]];
-      L.wc[m] = w[ko + c0[m]];
-      L.sv[m] = sp[ko + c0[m]];
+      L.wc[m] = __builtin_nontemporal_load(w + ko + c0[m]);
+      L.sv[m] = __builtin_nontemporal_load(sp + ko + c0[m]);
     }
     L.hph = ph[ko + hoff];
     L.hrh = rho[ko + hoff];
@@ -303,9 +304,11 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(
       const RhsNbr ym{sph[sl - W], srh[sl - W], hym[m]};
       const RhsNbr zp{php, rhp, zph}, zm{phm[m], rhm[m], km >= 0};
       const double wc = L.wc[m];
-      b[c] = rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xmn, yp, ym, zp, dzcp, zm,
-                      dzcm, dzfk, L.uc[m], hxm ? L.um[m] : 0.0, L.vc[m],
-                      hym[m] ? L.vm[m] : 0.0, wc, wm[m], has_src ? L.sv[m] : 0.0);
+      __builtin_nontemporal_store(
+          rhs_cell(rho0, ir0, idx, idy, r0dt, phc[m], rhc[m], xp, xmn, yp, ym, zp, dzcp, zm, dzcm,
+                   dzfk, L.uc[m], hxm ? L.um[m] : 0.0, L.vc[m], hym[m] ? L.vm[m] : 0.0, wc, wm[m],
+                   has_src ? L.sv[m] : 0.0),
+          b + c);
       phm[m] = phc[m];
       phc[m] = php;
       rhm[m] = rhc[m];
