@@ -105,10 +105,25 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
   inverse_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
-        a0 = ok ? ia[c0] : T(0);
-        b0 = ok ? ib[c0] : T(0);
-        a1 = ok ? ia[c1] : T(0);
-        b1 = ok ? ib[c1] : T(0);
+        if constexpr (BC == BC_P) {
+          // the packed real DFT pairs positions c0 (even) and c1 = c0 + 1:
+          // one vector load per row
+          using T2 = typename Vec2<T>::type;
+          T2 va{T(0), T(0)}, vb{T(0), T(0)};
+          if (ok) {
+            va = *reinterpret_cast<const T2*>(ia + c0);
+            vb = *reinterpret_cast<const T2*>(ib + c0);
+          }
+          a0 = va.x;
+          a1 = va.y;
+          b0 = vb.x;
+          b1 = vb.y;
+        } else {
+          a0 = ok ? ia[c0] : T(0);
+          b0 = ok ? ib[c0] : T(0);
+          a1 = ok ? ia[c1] : T(0);
+          b1 = ok ? ib[c1] : T(0);
+        }
       },
       [&](int e, T r, T i) {
         if (!ok) return;
