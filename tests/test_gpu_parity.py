@@ -152,17 +152,22 @@ def test_rhs_tiled_bit_identical(torch_dev, shape, bc, beta):
     us, vs, ws, phat, rho, rho0, s, dt, q = _step_inputs(g)
     T = lambda a: _dev(torch, a)  # noqa: E731
     plan = _plan(g)
-    outs = {}
+    outs, nosrc = {}, {}
     for tiled in (0, 8, 16):
-        for kc in (1, 3, 8):
+        for kc in (1, 2, 3, 4, 8):
             plan.tune("rhs_tiled", tiled)
             plan.tune("stencil_planes", min(kc, g.nz))
             u, v, w, p = plan.project(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt)
             outs[(tiled, kc)] = [a.cpu().numpy() for a in (u, v, w, p)]
+            if kc in (1, 3):  # without a source term (s = 0)
+                u, v, w, p = plan.project(T(us), T(vs), T(ws), T(phat), T(rho), rho0, None, dt)
+                nosrc[(tiled, kc)] = [a.cpu().numpy() for a in (u, v, w, p)]
+    for res in (outs, nosrc):
+        base = res[(0, 1)]
+        for key, val in res.items():
+            for a, b in zip(val, base):
+                assert np.array_equal(a, b), key
     base = outs[(0, 1)]
-    for key, val in outs.items():
-        for a, b in zip(val, base):
-            assert np.array_equal(a, b), key
     ref = oracle.project(us, vs, ws, phat, rho, rho0, s, dt, g)
     for a, b in zip(base, ref):
         assert rel_l2(a, b) <= FP64_TOL
@@ -244,6 +249,11 @@ def test_mixed_parity(torch_dev, case, dc):
     err = rel_l2(p.cpu().numpy(), ref)
     print(f"mixed {case} dc={dc}: rel L2 {err:.3e}")
     assert err <= MIXED_TOL, err
+    # planes marched per block by the residual (one, an odd count, all)
+    for kc in (1, 3, nz):
+        plan.tune("stencil_planes", kc)
+        q = plan.solve(_dev(torch, f)).cpu().numpy()
+        assert rel_l2(q, ref) <= MIXED_TOL, kc
 
 
 RADIX8_CASES = [
