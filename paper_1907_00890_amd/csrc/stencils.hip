@@ -532,7 +532,10 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
 // +y halo, are staged in LDS once per block and plane, and their +z values
 // (the next plane's centre values) stay in registers, so each of these four
 // fields is read from HBM about once.  All loads of a plane are issued
-// before its barrier.  The per-face arithmetic is k_step_epilogue's.
+// before its barrier.  Blocks take the tile rows and plane chunks last
+// first: the x inverse before it writes p and phi in row order, so the last
+// rows are the likeliest to still sit in the Infinity Cache (measured at
+// 256^3: 487 -> 479 us).  The per-face arithmetic is k_step_epilogue's.
 template <int TY>
 __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
     const GridArgs g, double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
@@ -544,8 +547,9 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
   constexpr int TX = 64, W = TX + 1, RPT = TY / 4, AREA = (TY + 1) * W;
   __shared__ double sm[4 * AREA];  // p, p_hat, rho, phi
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-  const int kb = blockIdx.z * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
+  const int by = gridDim.y - 1 - blockIdx.y, bz = gridDim.z - 1 - blockIdx.z;  // last first
+  const int i0 = blockIdx.x * TX, j0 = by * TY;
+  const int kb = bz * g.kc, ke = kb + g.kc < g.nz ? kb + g.kc : g.nz;
   const int i = i0 + tx;
   const long P = (long)g.nx * g.ny;
   const double ir0 = 1.0 / rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy;
