@@ -314,3 +314,24 @@ def test_residual_gauge_shift(name, stretch):
     assert abs((p * dv).sum()) < 1e-13 * np.abs(p * dv).sum()
     p2 = oracle.solve(f + 3.25, g)
     assert np.allclose(p2, p, rtol=0, atol=1e-12 * np.abs(p).max())
+
+
+@pytest.mark.parametrize("shape,bc", [((24, 4, 3), "PPN"), ((4, 24, 3), "NPN"),
+                                      ((40, 3, 4), "PNN"), ((3, 40, 4), "NNP"),
+                                      ((12, 20, 3), "PPP"), ((48, 3, 3), "NNN")],
+                         ids=lambda c: c if isinstance(c, str) else "x".join(map(str, c)))
+def test_brute_force_dense_odd_lengths(shape, bc):
+    """Lengths with an odd factor (3 * 2^k, 5 * 2^k, as the GPU transforms
+    take them) with periodic and wall ends: the oracle's solve equals the
+    bordered dense solve of the loop-built operator."""
+    nx, ny, nz = shape
+    dx, dy = 1.0 / nx, 0.7 / ny
+    dzf = random_dz(nz, 9) * 1.1
+    g = oracle.Grid(nx, ny, nz, dx, dy, dzf, bc)
+    A = loop_laplacian(nx, ny, nz, dx, dy, dzf, bc)
+    f = np.random.default_rng(6).standard_normal(g.shape)
+    dv = np.broadcast_to(g.cell_volume(), g.shape).reshape(-1)
+    p_ref, _ = bordered_solve(A, f.reshape(-1), dv)
+    p = oracle.solve(f, g)
+    err = np.linalg.norm(p.reshape(-1) - p_ref) / np.linalg.norm(p_ref)
+    assert err < 1e-12, err
