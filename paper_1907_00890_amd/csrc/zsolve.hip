@@ -59,16 +59,6 @@
 
 namespace vp {
 
-// 1/x for a positive normal x: hardware reciprocal estimate refined by two
-// Newton-Raphson steps (r <- r + r (1 - x r)), accurate to about one ulp.
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
 // Reduced system of line l (rows r*LB + l) in M-matrix form,
 //   -lo_r u_{r-1} + (rho_r + lo_r + up_r) u_r - up_r u_{r+1} = R_r,
 // with one or two right-hand sides (R1, and R2 when `two`), solved by
