@@ -133,8 +133,10 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
           pa = oa[e] + da;
           pb = ob[e] + db;
         }
-        oa[e] = pa;
-        ob[e] = pb;
+        // non-temporal: the result is not read again by this pass (measured at
+        // 256^3, two fields per launch: 107 -> 86 us)
+        __builtin_nontemporal_store(pa, oa + e);
+        __builtin_nontemporal_store(pb, ob + e);
         if constexpr (NORMS) {
           ee += double(da) * double(da) + double(db) * double(db);
           pp += double(pa) * double(pa) + double(pb) * double(pb);
