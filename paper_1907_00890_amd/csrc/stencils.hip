@@ -373,18 +373,18 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
       const double pn = t.hxp ? p[c + t.xp] : -pc, hn = t.hxp ? ph[c + t.xp] : -hc;
       const double rn = t.hxp ? rho[c + t.xp] : rc;
       const double gp = (pn - pc) * idx, gh = (hn - hc) * idx;
-      u[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh);
+      __builtin_nontemporal_store(u[c] - dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh), u + c);
     }
     if (t.hyp || ytop_out(g)) {
       const double pn = t.hyp ? p[c + t.yp] : -pc, hn = t.hyp ? ph[c + t.yp] : -hc;
       const double rn = t.hyp ? rho[c + t.yp] : rc;
       const double gp = (pn - pc) * idy, gh = (hn - hc) * idy;
-      v[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh);
+      __builtin_nontemporal_store(v[c] - dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh), v + c);
     }
     if (zph) {
       const double ih = 1.0 / g.dzc[k];
       const double gp = (pp - pc) * ih, gh = (hp - hc) * ih;
-      w[c] -= dt * (ir0 * gp + (inv_face_rho(rc, rp) - ir0) * gh);
+      __builtin_nontemporal_store(w[c] - dt * (ir0 * gp + (inv_face_rho(rc, rp) - ir0) * gh), w + c);
     }
     pc = pp;
     hc = hp;
@@ -417,13 +417,13 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
     const double gy = t.hyp ? (phi[c + t.yp] - fc) * idy : (ytop_out(g) ? (-fc - fc) * idy : 0.0);
     const double gz = zph ? (fp - fc) * (1.0 / g.dzc[k]) : 0.0;
     const double a = u[c] - gx, bb = v[c] - gy, cc = w[c] - gz;
-    ue[c] = a;
-    ve[c] = bb;
-    we[c] = cc;
+    __builtin_nontemporal_store(a, ue + c);
+    __builtin_nontemporal_store(bb, ve + c);
+    __builtin_nontemporal_store(cc, we + c);
     if (ug) {
-      ug[c] = a - qx[c];
-      vg[c] = bb - qy[c];
-      wg[c] = cc - qz[c];
+      __builtin_nontemporal_store(a - qx[c], ug + c);
+      __builtin_nontemporal_store(bb - qy[c], vg + c);
+      __builtin_nontemporal_store(cc - qz[c], wg + c);
     }
     fc = fp;
   }
