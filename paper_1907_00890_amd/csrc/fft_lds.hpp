@@ -181,6 +181,11 @@ template <int N>
 __device__ __forceinline__ int dct_perm(int p) {
   return p < N / 2 ? 2 * p : 2 * (N - 1 - p) + 1;
 }
+// its inverse: the FFT input position that holds element j
+template <int N>
+__device__ __forceinline__ int dct_unperm(int j) {
+  return (j & 1) ? N - 1 - (j >> 1) : (j >> 1);
+}
 
 // ---------------------------------------------------------------------------
 // pass bookkeeping

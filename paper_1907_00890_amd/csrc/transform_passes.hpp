@@ -150,22 +150,42 @@ constexpr int last_ns() {
 // ---------------------------------------------------------------------------
 // forward pass body shared by x and y: `load(e, re, im)` gives element e of
 // lines a and b; `store(c0, a0, b0, c1, a1, b1)` writes packed coefficients
-// c0 and c1 of both lines
+// c0 and c1 of both lines.  ROW (x passes, contiguous lines): the cosine and
+// sine transforms load the line in element order and reorder it through LDS
+// (the even/odd reordering read straight from HBM would take every other
+// element of a row per load); y lines (ROW false) reorder whole rows of a
+// tile, which stay contiguous, and load straight into the first pass.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC, int PTM, typename L, typename Load, typename Store>
+template <typename T, int N, int BC, int PTM, bool ROW = false, typename L, typename Load,
+          typename Store>
 __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict__ tab, Load load,
                                              Store store) {
   using S = FftShape<N, PTM>;
   constexpr int PT = S::PT, TPL = S::TPL;
   constexpr int R1 = PassRadix<N, 1, PTM>::R;
   T vr[PT], vi[PT];
+  if constexpr (ROW && BC != BC_P) {
 #pragma unroll
-  for (int r = 0; r < PT; ++r) {
-    // inputs of the first pass's butterflies (t + r TPL when a thread holds one)
-    int e = pass_in<N, 1, PTM>(t, r / R1, r % R1);
-    if constexpr (BC != BC_P) e = dct_perm<N>(e);
-    load(e, vr[r], vi[r]);
-    if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
+    for (int k = 0; k < PT; ++k) {
+      const int j = t + TPL * k;
+      T re, im;
+      load(j, re, im);
+      if constexpr (BC == BC_D) flip_odd(j, re, im);
+      lds.put(dct_unperm<N>(j), re, im);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PT; ++r) lds.get(pass_in<N, 1, PTM>(t, r / R1, r % R1), vr[r], vi[r]);
+    __syncthreads();  // the first pass writes back over these positions
+  } else {
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      // inputs of the first pass's butterflies (t + r TPL when a thread holds one)
+      int e = pass_in<N, 1, PTM>(t, r / R1, r % R1);
+      if constexpr (BC != BC_P) e = dct_perm<N>(e);
+      load(e, vr[r], vi[r]);
+      if constexpr (BC == BC_D) flip_odd(e, vr[r], vi[r]);
+    }
   }
   {
     T wr[PT], wi[PT];
@@ -208,8 +228,11 @@ __device__ __forceinline__ void forward_body(L& lds, int t, const T* __restrict_
 }
 
 // inverse body: `load2(c0, c1, a0, b0, a1, b1)` reads packed coefficients c0
-// and c1 of both lines; `store(e, re, im)` writes element e of lines a and b
-template <typename T, int N, int BC, int PTM, typename L, typename Load2, typename Store>
+// and c1 of both lines; `store(e, re, im)` writes element e of lines a and b.
+// ROW: as for forward_body, the cosine and sine inverses of x lines undo the
+// even/odd reordering through LDS and store the line in element order.
+template <typename T, int N, int BC, int PTM, bool ROW = false, typename L, typename Load2,
+          typename Store>
 __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict__ tab, Load2 load2,
                                              Store store) {
   using S = FftShape<N, PTM>;
@@ -244,6 +267,19 @@ __device__ __forceinline__ void inverse_body(L& lds, int t, const T* __restrict_
     }
   }
   T vr[PT], vi[PT];
+  if constexpr (ROW && BC != BC_P) {
+    later_passes<T, N, 1, +1, false, PTM>(lds, t, tab, vr, vi);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int j = t + TPL * k;
+      T re, im;
+      lds.get(dct_unperm<N>(j), re, im);
+      if constexpr (BC == BC_D) flip_odd(j, re, im);
+      store(j, re, im);
+    }
+    return;
+  }
   later_passes<T, N, 1, +1, true, PTM>(lds, t, tab, vr, vi);
   // the last pass is in registers: store to HBM
   constexpr int NSL = last_ns<N, PTM>();

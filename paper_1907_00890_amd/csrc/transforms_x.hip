@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __res
   TI shift = TI(0);
   if constexpr (SUB) shift = TI(sub[blockIdx.y]);
   XLds<T, N> lds(lds_mem, q, LPB);
-  forward_body<T, N, BC, PTM>(
+  forward_body<T, N, BC, PTM, true>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
         if constexpr (SUB) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
     if (sub) shift = TO(sub[blockIdx.y]);
   }
   XLds<T, N> lds(lds_mem, q, LPB);
-  inverse_body<T, N, BC, PTM>(
+  inverse_body<T, N, BC, PTM, true>(
       lds, t, tab,
       [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
         if constexpr (BC == BC_P) {
@@ -133,19 +133,11 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
           pa = oa[e] + da;
           pb = ob[e] + db;
         }
-        if constexpr (BC == BC_P) {
-          // periodic lines store whole rows in order: non-temporally (the
-          // result is not read again by this pass; measured at 256^3, two
-          // fields per launch: 107 -> 86 us).  The cosine / sine inverses
-          // store through the even / odd reordering, every other element of
-          // a row per store: those partial lines are merged in the cache
-          // (non-temporal there: 54 -> 95 us).
-          __builtin_nontemporal_store(pa, oa + e);
-          __builtin_nontemporal_store(pb, ob + e);
-        } else {
-          oa[e] = pa;
-          ob[e] = pb;
-        }
+        // rows are stored in element order, non-temporally (the result is
+        // not read again by this pass; measured at 256^3, two fields per
+        // launch: 107 -> 86 us)
+        __builtin_nontemporal_store(pa, oa + e);
+        __builtin_nontemporal_store(pb, ob + e);
         if constexpr (NORMS) {
           ee += double(da) * double(da) + double(db) * double(db);
           pp += double(pa) * double(pa) + double(pb) * double(pb);
