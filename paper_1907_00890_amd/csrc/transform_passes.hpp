@@ -12,10 +12,13 @@
 // intermediate passes exchange through LDS, and the real-pair step reads the
 // last pass from LDS and writes the packed spectrum straight to HBM.  The
 // inverse mirrors it: the real-pair step loads from HBM into LDS and the last
-// Stockham pass stores to HBM.  One block owns 2*LPB whole rows (x) or a
-// tile of 2*LINES columns of one z-plane (y), so every HBM access is a
-// contiguous chunk.  LDS rows are padded by one slot every 16 values, which
-// spreads the strided writes of the first pass over the banks.
+// Stockham pass stores to HBM.  The cosine and sine transforms of x rows
+// instead take one more LDS round trip for their even/odd reordering, so that
+// rows are still read and written in element order.  One block owns 2*LPB
+// whole rows (x) or a tile of 2*LINES columns of one z-plane (y), so every
+// HBM access is a contiguous chunk.  LDS rows are padded by one slot every
+// 16 values, which spreads the strided writes of the first pass over the
+// banks.
 #pragma once
 #include <hip/hip_runtime.h>
 
