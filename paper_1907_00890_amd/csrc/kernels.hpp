@@ -89,8 +89,8 @@ hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool f
 
 // spectral z pass for a uniform z grid with nz a transform length (2^k in
 // [8, 1024], 3 * 2^k in [24, 768] or 5 * 2^k in [40, 640]):
-// forward real DFT / DCT-II along z, division by the 3-D eigenvalue, inverse,
-// in one pass (transforms_z.hip)
+// forward real DFT / DCT-II / DST-II along z, division by the 3-D eigenvalue,
+// inverse, in one pass (transforms_z.hip)
 struct ZSpecArgs {
   int nx, ny, nz;
   int bcz;             // BC_P, BC_N or BC_D
