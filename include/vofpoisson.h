@@ -199,9 +199,12 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
 
 /*
  * Interface terms from the volume fraction (section 3.2: the regularised
- * delta |grad C| by Youngs' finite differences; section 3.4: the normal
- * n = grad C / |grad C|; section 3.6: the Stefan source and the jump of the
- * interface velocity), one pass over the fields:
+ * delta |grad C| by Youngs' finite differences; section 3.4: the normal from
+ * the gradient of C; section 3.6: the Stefan source and the jump of the
+ * interface velocity), one pass over the fields.  The normal is
+ * n = -grad C / |grad C|: it points into phase 2, as the jump condition of
+ * section 2 (eq. rankine) orients it, since C is 1 in phase 1; so for mdot > 0
+ * (evaporation) u_Gamma = u_1^e - q moves the interface into the liquid:
  *   s  = mdot (1/rho2 - 1/rho1) |grad C|            (cell centres),
  *   q  = (mdot / rho_e) n on the faces (qx on i+1/2, qy on j+1/2, qz on k+1/2):
  *        the mean of the two adjacent cells' values, 0 on a non-periodic

@@ -1,10 +1,19 @@
 """Interface terms from the volume fraction C (test oracle, FP64).
 
 Section 3.2 regularises the interface delta as |grad C| and section 3.4 takes
-the normal n = grad C / |grad C|, both with the gradient of C evaluated by
+the normal from grad C / |grad C|, both with the gradient of C evaluated by
 Youngs' finite differences; section 3.6 then needs the Stefan source
 s = mdot (1/rho2 - 1/rho1) |grad C| at cell centres and the interface-velocity
-jump q = (mdot / rho1) n on the velocity faces.  For boiling (appendix A) the
+jump q = (mdot / rho1) n on the velocity faces.
+
+Orientation of n.  The jump condition of section 2 (eq. rankine) defines n as
+pointing into phase 2, and the interface velocity of section 3.6 (eq.
+int_vel) is derived from it; C is 1 in phase 1 (eq. ind_fun), so grad C points
+into phase 1.  Section 3.4 writes n = grad C / |grad C| for the mass-flux
+formula; taken literally that orientation would make u_Gamma = u_1^e - q move
+an evaporating interface (mdot > 0) into the gas.  The reading taken here is
+the one eq. int_vel needs: n = -grad C / |grad C| (into phase 2), so that an
+evaporating droplet's interface recedes into the liquid at mdot / rho1.  For boiling (appendix A) the
 interface velocity is built from the divergence-free extension of the vapour
 velocity instead of the liquid's.  The reading: the potential and the
 extension u - grad phi are the same (it follows whichever phase lies where the
@@ -24,7 +33,8 @@ is Youngs' corner construction:
    difference is zero);
 3. the gradient at a cell centre as the mean of its eight corner gradients.
 On a uniform grid this is the central difference of C weighted (1, 2, 1) in
-each transverse direction.  Then |grad C|, n (0 where |grad C| = 0),
+each transverse direction.  Then |grad C|, n = -grad C / |grad C| (0 where
+|grad C| = 0),
 s = mdot (1/rho2 - 1/rho1) |grad C| and the cell vector a = (mdot / rho) n
 (rho of the extended phase);
 q on face i+1/2 is the mean of a at cells i and i+1, and 0 on a non-periodic
@@ -96,7 +106,8 @@ def interface_terms(C, mdot, rho1, rho2, g, phase=1):
     s = mdot * (1.0 / rho2 - 1.0 / rho1) * mag
     safe = np.where(mag > 0.0, mag, 1.0)
     rho_ext = rho1 if phase == 1 else rho2
-    scale = np.where(mag > 0.0, mdot / rho_ext / safe, 0.0)
+    # n = -grad C / |grad C|: into phase 2 (see the module docstring)
+    scale = np.where(mag > 0.0, -mdot / rho_ext / safe, 0.0)
     q = []
     for axis, comp in ((2, gx), (1, gy), (0, gz)):
         a = scale * comp

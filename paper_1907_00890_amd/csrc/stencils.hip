@@ -666,9 +666,11 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
 // 3.2: the regularised delta |grad C| by Youngs' finite differences; section
 // 3.6: the Stefan source and the interface-velocity jump):
 //   s = mdot (1/rho2 - 1/rho1) |grad C|             at cell centres,
-//   a = (mdot / rho_e) grad C / |grad C|  (0 where grad C = 0; rho_e the
-//       density of the phase whose velocity the extension follows: rho1, or
-//       rho2 for boiling, appendix A),
+//   a = (mdot / rho_e) n,  n = -grad C / |grad C|  (0 where grad C = 0):
+//       the unit normal pointing into phase 2, as the Rankine-Hugoniot jump
+//       condition of section 2 orients it (C is 1 in phase 1, so grad C
+//       points into phase 1); rho_e is the density of the phase whose
+//       velocity the extension follows: rho1, or rho2 for boiling, appendix A,
 //   q on face i+1/2 = (a_i + a_{i+1}) / 2, 0 on a non-periodic boundary face.
 // grad C at a centre is the mean of the gradients at its eight corners, each
 // from the eight cells around the corner (ghost cells: periodic copies, or
@@ -733,7 +735,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(
   // a cell of the domain (FULL: the tiles cover y exactly; else tall tiles of
   // narrow grids reach beyond ny)
   const bool own = FULL || j < g.ny;
-  const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = 1.0 / rho_e;
+  const double src_f = 1.0 / rho2 - 1.0 / rho1, a_f = -1.0 / rho_e;  // n = -grad C / |grad C|
   const double fx = 1.0 / (32.0 * g.dx), fy = 1.0 / (32.0 * g.dy);
 
   // This thread's C-tile elements e = threadIdx.x + kIfThreads r and a positions,

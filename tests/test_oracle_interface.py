@@ -93,8 +93,9 @@ def test_one_dimensional_interface():
     on = mag > 0
     assert np.allclose(np.abs(gx[on]), mag[on], rtol=1e-15, atol=0)
     assert np.abs(qy).max() == 0 and np.abs(qz).max() == 0
-    # q_x is the face mean of -mdot/rho1 (n_x = -1 where C falls)
-    a = np.where(on, -0.02 / 1000.0, 0.0)
+    # q_x is the face mean of +mdot/rho1: C falls along +x, so the normal
+    # into phase 2 is n_x = +1
+    a = np.where(on, 0.02 / 1000.0, 0.0)
     assert np.allclose(qx[:, :, :-1], 0.5 * (a[:, :, :-1] + a[:, :, 1:]), rtol=1e-14, atol=0)
     assert np.all(qx[:, :, -1] == 0.0)  # wall face
     assert np.allclose(s, 0.02 * (1.0 - 1e-3) * mag, rtol=1e-15, atol=0)
@@ -127,7 +128,7 @@ def test_periodic_shift_invariance():
     # periodic: the last face is a real face, the mean with the wrapped cell
     gx, _, _ = oi.youngs_gradient(C, g)
     mag = a[4]
-    ax = mdot / 10.0 * gx / mag
+    ax = -mdot / 10.0 * gx / mag
     assert np.allclose(a[1][:, :, -1], 0.5 * (ax[:, :, -1] + ax[:, :, 0]), rtol=1e-13, atol=0)
 
 
@@ -147,3 +148,43 @@ def test_vapour_phase_jump():
         assert np.allclose(b, a * (rho1 / rho2), rtol=1e-13, atol=0)
     with pytest.raises(ValueError):
         oi.interface_terms(C, mdot, rho1, rho2, g, phase=3)
+
+
+def test_evaporating_sphere_recedes():
+    """A resting liquid sphere (phase 1, C = 1 inside) evaporating at mdot > 0:
+    the one-fluid velocity is the pure Stefan flow u = G psi with L psi = s,
+    so the liquid extension is zero and u_Gamma = -q.  The jump condition of
+    section 2 (n into phase 2) makes the interface recede into the liquid at
+    mdot / rho1: u_Gamma . r_hat < 0 at every face the interface crosses,
+    close to -mdot / rho1 where the interface is thin."""
+    n = 24
+    h = 1.0 / n
+    g = oracle.Grid(n, n, n, h, h, np.full(n, h), "NNN")
+    c = (np.arange(n) + 0.5) * h - 0.5
+    x, y, z = c[None, None, :], c[None, :, None], c[:, None, None]
+    r = np.sqrt(x * x + y * y + z * z)
+    C = 0.5 * (1 - np.tanh((r - 0.3) / (1.5 * h)))
+    rho1, rho2, mdot0 = 1000.0, 1.0, 0.5
+    mdot = np.full(g.shape, mdot0)
+    s, qx, qy, qz, mag = oi.interface_terms(C, mdot, rho1, rho2, g)
+    psi = oracle.solve(s, g)
+    u = oracle.grad(psi, g)
+    ue, ve, we, ug, vg, wg, _ = oracle.extend(*u, s, g, q=(qx, qy, qz))
+    assert max(np.abs(a).max() for a in (ue, ve, we)) <= 1e-12 * max(np.abs(a).max() for a in u)
+    # radial component of u_Gamma at the faces (face centres' radial direction)
+    xf, yf, zf = x + 0.5 * h, y + 0.5 * h, z + 0.5 * h
+    ur_x = ug * xf / np.sqrt(xf * xf + y * y + z * z)
+    ur_y = vg * yf / np.sqrt(x * x + yf * yf + z * z)
+    ur_z = wg * zf / np.sqrt(x * x + y * y + zf * zf)
+    band = np.abs(r - 0.3) < 1.5 * h  # cells the interface crosses
+    for comp in (ur_x, ur_y, ur_z):
+        sel = band & (np.abs(comp) > 1e-3 * mdot0 / rho1)
+        assert sel.sum() > 100
+        assert np.all(comp[sel] < 0.0)
+    # the velocity of the interface along the normal: u_Gamma . n = -mdot/rho1
+    # at the centres of the band (q averaged back from the faces)
+    qc = (0.5 * (qx + np.roll(qx, 1, axis=2)), 0.5 * (qy + np.roll(qy, 1, axis=1)),
+          0.5 * (qz + np.roll(qz, 1, axis=0)))
+    qr = (qc[0] * x + qc[1] * y + qc[2] * z) / r
+    thin = np.abs(r - 0.3) < 0.5 * h
+    assert np.allclose(-qr[thin], -mdot0 / rho1, rtol=0.05, atol=0)

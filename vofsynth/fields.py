@@ -171,7 +171,8 @@ def _face_avg(a, axis, bc_letter):
 
 
 def interface_normal_faces(C, dx, dy, dzf, bc: str, scale: float):
-    """scale * n on faces, n = grad C / |grad C| at centres, averaged to faces.
+    """scale * n on faces, n = -grad C / |grad C| at centres (the normal
+    pointing out of the phase where C = 1), averaged to faces.
 
     With scale = mdot / rho1 this is the q term of the interface velocity
     u_G = u_1^e - (mdot / rho1) n (section 3.6).
@@ -179,9 +180,9 @@ def interface_normal_faces(C, dx, dy, dzf, bc: str, scale: float):
     bc = _check_bc(bc)
     mag, (gx, gy, gz) = grad_mag_central(C, dx, dy, dzf, bc)
     safe = np.where(mag > 1e-12, mag, 1.0)
-    nxc = np.where(mag > 1e-12, gx / safe, 0.0) * scale
-    nyc = np.where(mag > 1e-12, gy / safe, 0.0) * scale
-    nzc = np.where(mag > 1e-12, gz / safe, 0.0) * scale
+    nxc = -np.where(mag > 1e-12, gx / safe, 0.0) * scale
+    nyc = -np.where(mag > 1e-12, gy / safe, 0.0) * scale
+    nzc = -np.where(mag > 1e-12, gz / safe, 0.0) * scale
     return (_face_avg(nxc, 2, bc[0]), _face_avg(nyc, 1, bc[1]),
             _face_avg(nzc, 0, bc[2]))
 
