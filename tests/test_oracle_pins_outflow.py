@@ -275,3 +275,44 @@ def test_brute_force_dense_odd_lengths(shape, bc):
     ref = np.linalg.solve(A, f.reshape(-1)).reshape(g.shape)
     p = oracle.solve(f, g)
     assert np.abs(p - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("axis,bc", [(2, "NDPPPP"), (1, "PPNDNN"), (0, "PPPPND")])
+def test_projection_layered_outflow_face_density(axis, bc):
+    """Density and p_hat varying along a direction with a wall at its lower end
+    and an outflow at its upper end, u* = 0, s = 0: the projected velocity
+    is divergence-free and zero on the wall, hence zero on every face of that
+    direction, so the split correction balances face by face:
+        G p / rho0 = -(1/rho_f - 1/rho0) G p_hat.
+    On the outflow face (p = p_hat = 0 on the face, half a cell beyond the
+    last centre) this gives p_last = -(rho0/rho_out - 1) p_hat_last, which
+    fixes the density taken on that face (the end cell's); inward,
+    p_i = p_{i+1} + rho0 (1/rho_f - 1/rho0)(p_hat_{i+1} - p_hat_i) with rho_f
+    the mean of the two cells.  Written here in a loop, independently of the
+    oracle's stencils (stretched cells along z)."""
+    n = 12
+    shape = [3, 4, 5]
+    shape[axis] = n
+    nz, ny, nx = shape
+    dzf = (np.random.default_rng(40).uniform(0.5, 1.5, nz) / nz if axis == 0
+           else np.full(nz, 1.0 / nz))
+    g = oracle.Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, dzf, bc)
+    r = np.random.default_rng(41 + axis)
+    rl = r.uniform(1.0, 50.0, n)
+    pl = r.standard_normal(n)
+    bshape = [1, 1, 1]
+    bshape[axis] = n
+    rho = np.broadcast_to(rl.reshape(bshape), g.shape).copy()
+    phat = np.broadcast_to(pl.reshape(bshape), g.shape).copy()
+    z = np.zeros(g.shape)
+    rho0 = 1.0
+    u, v, w, p = oracle.project(z, z, z, phat, rho, rho0, z, 0.4, g)
+    expect = np.zeros(n)
+    expect[n - 1] = -(rho0 / rl[n - 1] - 1.0) * pl[n - 1]
+    for i in range(n - 2, -1, -1):
+        rf = 0.5 * (rl[i] + rl[i + 1])
+        expect[i] = expect[i + 1] + rho0 * (1.0 / rf - 1.0 / rho0) * (pl[i + 1] - pl[i])
+    want = np.broadcast_to(expect.reshape(bshape), g.shape)
+    assert np.abs(p - want).max() <= 1e-11 * np.abs(expect).max()
+    for vel in (u, v, w):
+        assert np.abs(vel).max() <= 1e-10 * np.abs(pl).max() * n
