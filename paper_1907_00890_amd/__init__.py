@@ -38,11 +38,13 @@ def _stream_ptr(stream):
 class Plan:
     """A solve plan: grid, boundary conditions, device tables and workspace.
 
-    nx, ny: powers of two in [8, 1024]; nz >= 1; dz: nz cell widths (z may be
-    stretched); bc: three letters (x, y, z, both ends alike) or six (x-, x+,
-    y-, y+, z-, z+) from 'P' (periodic), 'N' (wall, zero normal gradient) and
-    'D' (outflow, p = 0 on the boundary face); x and y take P, NN or DD.
-    precision: 'fp64' or 'mixed'.
+    nx, ny: transform lengths, 2^k in [8, 1024], 3 * 2^k in [24, 768] or
+    5 * 2^k in [40, 640]; nz in [1, 1024] (>= 3 when z is periodic); dz: nz
+    cell widths (z may be stretched); bc: three letters (x, y, z, both ends
+    alike) or six (x-, x+, y-, y+, z-, z+) from 'P' (periodic, both ends of a
+    direction), 'N' (wall, zero normal gradient) and 'D' (outflow, p = 0 on
+    the boundary face); every direction takes P or any pair of N and D (NN,
+    DD, ND, DN).  precision: 'fp64' or 'mixed'.
     """
 
     def __init__(self, nx, ny, nz, dx, dy, dz, bc, precision="fp64", max_batch=1):

@@ -378,6 +378,11 @@ void vp_server::launch(BatchRun* b, std::vector<Req*>& done) {
     }
   }
   if (status != VP_OK) {
+    // A launch chain that failed part way may have left passes queued on the
+    // lane's stream, still writing the plan's workspace: wait for them before
+    // the plan can be handed to another lane (an injected failure launched
+    // nothing).
+    if (!injected && !cfg.dry_run) (void)hipStreamSynchronize(L.stream);
     for (Req* q : b->reqs) {
       q->status = status;
       done.push_back(q);
