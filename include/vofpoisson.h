@@ -128,6 +128,26 @@ int poisson_solve_batched(poisson_plan* plan, int n, const double* const* rhs,
                           double* const* sol, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * solve of poisson_solve, the same kernels and the same result bit for bit,
+ * with its spectrum in a static device array of the library instead of the
+ * plan's workspace.  The call allocates nothing and leaves the plan's
+ * workspace untouched.  The array holds VP_NOALLOC_MAX_POINTS doubles
+ * (64 MiB); every GPU the library runs on holds its own copy until the
+ * process ends (its address is taken once per device when the first plan is
+ * created there).  All calls on one GPU share that array, which keeps the
+ * last call's contents: calls that overlap on one GPU (two streams, or two
+ * host threads) race and must be serialised by the caller.
+ *   plan : an FP64 plan on the current device with nx*ny*nz at most
+ *          VP_NOALLOC_MAX_POINTS (VP_EUNSUPPORTED otherwise: a mixed plan or
+ *          a larger grid; VP_EINVAL if another device is current);
+ *   rhs, sol, hip_stream : as for poisson_solve (sol may alias rhs).
+ */
+#define VP_NOALLOC_MAX_POINTS 8388608 /* 2^23 points, e.g. 256 x 256 x 128 */
+int poisson_solve_noalloc(poisson_plan* plan, const double* rhs, double* sol, void* hip_stream);
+
+/*
  * Pressure projection of section 3.2 (constant-coefficient split):
  *   b   = rho0 D[(1/rho0 - 1/rho_f) G p_hat] + (rho0/dt) (D u* - s)
  *   p   = Poisson solve of b

@@ -94,6 +94,17 @@ class Plan:
                                      _stream_ptr(stream)), "poisson_solve")
         return out
 
+    def solve_noalloc(self, rhs, out=None, stream=None):
+        """As solve, with the spectrum in the library's static device array
+        (poisson_solve_noalloc: no allocation; FP64 plans of at most
+        2^23 points; overlapping calls on one GPU race)."""
+        if out is None:
+            out = self._new(rhs)
+        check(_lib.lib.poisson_solve_noalloc(self._h, self._ptr(rhs, "rhs"),
+                                             self._ptr(out, "out"), _stream_ptr(stream)),
+              "poisson_solve_noalloc")
+        return out
+
     def solve_batched(self, rhs_list, out_list=None, stream=None):
         n = len(rhs_list)
         if out_list is None:

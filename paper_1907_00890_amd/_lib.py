@@ -45,6 +45,7 @@ SIGNATURES = {
     "poisson_plan_destroy": (None, [_p]),
     "poisson_solve": (_i, [_p, _p, _p, _p]),
     "poisson_solve_batched": (_i, [_p, _i, ctypes.POINTER(_p), ctypes.POINTER(_p), _p]),
+    "poisson_solve_noalloc": (_i, [_p, _p, _p, _p]),
     "project": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p, _p]),
     "extend_liquid_velocity": (_i, [_p] + [_p] * 14 + [_p]),
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
@@ -75,6 +76,7 @@ VP_OK, VP_EINVAL, VP_EUNSUPPORTED, VP_ENOMEM, VP_EHIP = 0, -1, -2, -3, -4
 NUM_KERNEL_CLASSES = 16
 MAX_BATCH = 16
 PRECISION = {"fp64": 0, "mixed": 1}
+NOALLOC_MAX_POINTS = 1 << 23
 
 
 class VofPoissonError(RuntimeError):

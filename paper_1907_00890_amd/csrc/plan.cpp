@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -103,6 +104,42 @@ void set_z_segment(vp::ZArgs& Z, int seg) {
   Z.nseg = (Z.nz + seg - 1) / seg;
   Z.seg_base = Z.nz / Z.nseg;
   Z.seg_rem = Z.nz % Z.nseg;
+}
+
+}  // namespace
+
+// Spectrum slot of poisson_solve_noalloc: a static device array (every GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never uses its name as an address: the per-device address comes from
+// hipGetSymbolAddress, taken once per device at set-up (plan creation, or
+// the entry point's first call on a device) with that device current.
+static_assert(VP_NOALLOC_MAX_POINTS == (1 << 23), "size of the static spectrum slot");
+static __device__ __align__(256) double scratch[VP_NOALLOC_MAX_POINTS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `device` (the current device), or null
+// with the HIP error kept for poisson_strerror
+double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    g_last_error = "noalloc scratch: device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      g_last_error = std::string("noalloc scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[device];
 }
 
 }  // namespace
@@ -371,11 +408,13 @@ int plan_init(poisson_plan* P, const double* dz) {
   return VP_OK;
 }
 
-// FP64 chain over nb fields: rhs[b] -> sol[b] (sol[b] may alias rhs[b])
+// FP64 chain over nb fields: rhs[b] -> sol[b] (sol[b] may alias rhs[b]);
+// the spectra live in nb consecutive slots of N values from `work` (the
+// plan's workspace unless a caller passes another buffer)
 int solve_f64(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
-              hipStream_t st) {
+              hipStream_t st, double* work = nullptr) {
   const long nrows = (long)P->ny * P->nz, N = P->npts();
-  double* w = P->work64;
+  double* w = work ? work : P->work64;
   const vp::Batch<const double> in = vp::batch_of(rhs, nb);
   const vp::Batch<double> out = vp::batch_of(sol, nb);
   VP_LAUNCH(P, K_XFWD, vp::launch_xfwd_f64(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, st), "x forward", st);
@@ -522,6 +561,13 @@ poisson_plan* poisson_plan_create(int nx, int ny, int nz, double dx, double dy, 
     delete P;
     return fail(VP_EHIP);
   }
+  // set-up of poisson_solve_noalloc on this device (the plan's device is the
+  // current one): its static spectrum slot's address, once per device
+  if (precision == VP_PRECISION_FP64 && P->npts() <= VP_NOALLOC_MAX_POINTS &&
+      !scratch_on(P->device)) {
+    delete P;
+    return fail(VP_EHIP);
+  }
   const int st = plan_init(P, dz);
   if (st != VP_OK) {
     P->release();
@@ -551,6 +597,23 @@ int poisson_solve_batched(poisson_plan* P, int n, const double* const* rhs, doub
     if (!rhs[i] || !sol[i]) return VP_EINVAL;
   if (n == 0) return VP_OK;
   return solve_any(P, n, rhs, sol, static_cast<hipStream_t>(stream));
+}
+
+int poisson_solve_noalloc(poisson_plan* P, const double* rhs, double* sol, void* stream) {
+  if (!P || !rhs || !sol) return VP_EINVAL;
+  if (P->precision != VP_PRECISION_FP64 || P->npts() > VP_NOALLOC_MAX_POINTS)
+    return VP_EUNSUPPORTED;
+  int dev = -1;
+  VP_HIP(hipGetDevice(&dev), "noalloc device");
+  if (dev != P->device) return VP_EINVAL;
+  double* w = scratch_on(dev);
+  if (!w) return VP_EHIP;
+  // no profiling brackets here: they may create events
+  const unsigned prof = P->profiling;
+  P->profiling = 0;
+  const int s = solve_f64(P, 1, &rhs, &sol, static_cast<hipStream_t>(stream), w);
+  P->profiling = prof;
+  return s;
 }
 
 namespace {
