@@ -17,7 +17,10 @@ liquid-velocity extension and the interface velocity):
 * ``extend``  -- the divergence-free liquid-velocity extension and the
   interface velocity;
 * ``interface_terms`` -- |grad C| by Youngs' finite differences, the Stefan
-  source s and the interface-velocity jump q on faces (sections 3.2, 3.4, 3.6).
+  source s and the interface-velocity jump q on faces (sections 3.2, 3.4, 3.6);
+* ``advect`` -- the VoF advection of section 3.1 (eqs. cadv, fluxes,
+  final_corr_1, final_corr_2) with the MTHINC flux of the method it cites,
+  consuming the interface velocity.
 
 Every function names the passage it follows.  Pins against closed forms,
 brute-force dense solves and library special cases live in ``tests/``.
@@ -34,3 +37,4 @@ from .solver import (  # noqa: F401
     extend,
 )
 from .interface import interface_terms, youngs_gradient  # noqa: F401
+from .advection import advect  # noqa: F401
