@@ -45,6 +45,9 @@ ALG_BYTES_PER_POINT = {
     "rhs_assembly": 56,           # u*, v*, w*, p_hat, rho, s in; b out
     "correction": 72,             # u*, v*, w*, p, p_hat, rho in; u, v, w out
     "extension": 104,             # u, v, w, phi, qx, qy, qz in; ue, ve, we, ug, vg, wg out
+    "advect_x": 24,               # C, u_G in; C* out
+    "advect_y": 24,               # C*, v_G in; C** out
+    "advect_z": 48,               # C**, w_G, C*, u_G, v_G in; C^{n+1} out
 }
 # fields per launch of the solve passes inside the step (pressure and Stefan
 # potential batched)
@@ -58,7 +61,7 @@ KERNEL_SOURCES = {
 }
 
 
-EXTRAS = ("stretched", "mixed512", "interface", "droplet")
+EXTRAS = ("stretched", "mixed512", "interface", "droplet", "advect")
 
 
 def parse():
@@ -81,7 +84,7 @@ def parse():
                     help="skip the extra workloads (same as --extra none)")
     ap.add_argument("--extra", default="all",
                     help="comma-separated extra workloads after the main line: stretched, "
-                         "mixed512, interface, droplet; 'all' (default) or 'none'")
+                         "mixed512, interface, droplet, advect; 'all' (default) or 'none'")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -474,6 +477,61 @@ def interface_outflow_run(torch, dev, steps, no_autotune):
     return res
 
 
+def advect_run(torch, dev, steps):
+    """VoF advection of section 3.1 on the 256^3 workload: the benchmark's
+    sphere C advected by the interface velocity of one step (the extension of
+    the projected velocity minus the jump), at CFL 0.4, `steps` consecutive
+    advection steps; per-sweep kernel times and HBM rates on the algorithmic
+    bytes (24 N + 24 N + 48 N per step)."""
+    import numpy as np
+
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+    cfg = vofsynth.config("ppn256")
+    X = make_inputs(cfg, torch, dev)
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc)
+    e = lambda: torch.empty_like(X["u"])  # noqa: E731
+    ug = (e(), e(), e())
+    plan.step(X["u"].clone(), X["v"].clone(), X["w"].clone(), X["phat"], X["rho"], X["rho0"],
+              X["s"], X["dt"], X["s"], q=(X["qx"], X["qy"], X["qz"]), gamma=ug)
+    C, _ = vofsynth.sphere_vof(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), seed=2)
+    dt = 0.4 * cfg.dx / max(a.abs().max().item() for a in ug)
+    bufs = [torch.from_numpy(np.ascontiguousarray(C)).to(dev), e()]
+    for _ in range(2):
+        plan.advect(bufs[0], *ug, dt, out=bufs[1])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for it in range(steps):
+        plan.advect(bufs[it % 2], *ug, dt, out=bufs[(it + 1) % 2])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    plan.kernel_times()
+    plan.set_profiling(True, classes=["advect_x", "advect_y", "advect_z"])
+    for it in range(steps):
+        plan.advect(bufs[it % 2], *ug, dt, out=bufs[(it + 1) % 2])
+    torch.cuda.synchronize()
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    n = cfg.npts
+    kern = {}
+    for name, (tot, cnt) in kt.items():
+        per = tot / cnt
+        alg = ALG_BYTES_PER_POINT[name] * n
+        kern[name] = {"avg_ms": round(per, 5), "alg_bytes": alg,
+                      "gbs": round(alg / (per * 1e-3) / 1e9, 1)}
+    band = ((bufs[0] > 1e-8) & (bufs[0] < 1 - 1e-8)).sum().item()
+    res = {"workload": "256x256x256 PPN: the sphere's C advected by the step's interface "
+                       "velocity, CFL 0.4, MTHINC beta = 1, deflation on", "steps": steps,
+           "ms_per_advect": round(ms, 4), "mpts_s": round(n / (ms * 1e-3) / 1e6, 1),
+           "alg_bytes_96N": 96 * n, "gbs_96N": round(96 * n / (ms * 1e-3) / 1e9, 1),
+           "band_cells": int(band), "kernels": kern}
+    del X, plan, bufs, ug
+    torch.cuda.empty_cache()
+    return res
+
+
 def mixed512_run(torch, dev, reps, no_autotune):
     """512^3 PPP, seeded N(0,1) RHS with its mean removed: FP64 against mixed
     (FP32 chain + FP64 defect correction with the device-side stopping rule)."""
@@ -722,6 +780,8 @@ def main():
         line["interface_outflow_256"] = interface_outflow_run(torch, dev, 10, args.no_autotune)
     if "droplet" in extras:
         line["droplet_320x320x640"] = droplet_grid_run(torch, dev, 10, args.no_autotune)
+    if "advect" in extras:
+        line["advect_256"] = advect_run(torch, dev, 10)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:

@@ -249,6 +249,38 @@ int interface_terms(poisson_plan* plan, const double* C, const double* mdot, dou
                     void* hip_stream);
 
 /*
+ * VoF advection of section 3.1: C^{n+1} from C^n and the interface velocity
+ * u_Gamma of section 3.6 (eq. cadv) by directional splitting, x then y then
+ * z, each sweep implicit in its own result through the divergence of its
+ * velocity component (eq. fluxes), then the final correction
+ *   deflation = 1: C^{n+1} = C*** - dt F + dt C^{n+1} div(u_Gamma)  (eq. final_corr_2),
+ *   deflation = 0: C^{n+1} = C*** - dt F                            (eq. final_corr_1),
+ * F = C* du/dx + C** dv/dy + C*** dw/dz.  The fluxes are those of the MTHINC
+ * method the paper cites (Ii et al. 2012), linear reconstruction: in a cell
+ * of local coordinates X in [-1/2, 1/2]^3, H = 1/2 (1 + tanh(beta (m.X + d))),
+ * m the unit Youngs normal in cell coordinates (dx g_x, dy g_y, dz_k g_z),
+ * d fixed by the cell's volume; integrals of H exact along the dominant
+ * axis of m and 2-point Gauss-Legendre in the other two; a face's flux is
+ * sign(V) h times the integral of H over the part of the upwind cell the
+ * face sweeps in dt.  Cells with C within 1e-8 of 0 or 1 (or a change of C
+ * across the cell below 1e-12) are uniform; ghost cells beyond a
+ * non-periodic end are uniform with the end cell's C.
+ *   C      : device volume fraction C^n (cell centres);
+ *   ug,vg,wg : device interface velocity on the faces (u_Gamma of
+ *            extend_liquid_velocity / vof_step), zero on wall faces;
+ *   dt > 0 : time step, with |V| dt at most the upwind cell's width along
+ *            each sweep (one cell per step; larger steps are clamped to it);
+ *   beta > 0 : sharpness of the tanh profile (1 is the usual choice);
+ *   deflation : 1 (the paper's method) or 0;
+ *   C_new  : device output C^{n+1} (must not alias C).
+ * Uses workspace slot 0 of the plan (C** between the sweeps).  VP_EUNSUPPORTED
+ * for a plan with an outflow at a lower end (the face -1/2 has no storage).
+ */
+int vof_advect(poisson_plan* plan, const double* C, const double* ug, const double* vg,
+               const double* wg, double dt, double beta, int deflation, double* C_new,
+               void* hip_stream);
+
+/*
  * Mixed-precision control (plans created with VP_PRECISION_MIXED).  A mixed
  * solve is p_0 = S32(f) followed by at most dc_steps FP64 defect-correction
  * steps p_k = p_{k-1} + e_k, e_k = S32(f - L_h p_{k-1}) (FP64 residual and
@@ -357,7 +389,7 @@ int poisson_plan_autotune(poisson_plan* plan, int nb, void* hip_stream, int* cho
  * forgets the recorded launches.  Classes are numbered 0..VP_NUM_KERNEL_CLASSES-1;
  * poisson_kernel_class_name gives their names (NULL outside that range).
  */
-#define VP_NUM_KERNEL_CLASSES 16
+#define VP_NUM_KERNEL_CLASSES 19
 int poisson_plan_set_profiling(poisson_plan* plan, int class_mask);
 int poisson_plan_kernel_times(poisson_plan* plan, double* total_ms, int* launches, int n);
 const char* poisson_kernel_class_name(int cls);

@@ -196,6 +196,17 @@ class Plan:
         check(_lib.lib.interface_terms(*args, _stream_ptr(stream)), "interface_terms")
         return tuple(out)
 
+    def advect(self, C, ug, vg, wg, dt, beta=1.0, deflation=True, out=None, stream=None):
+        """C^{n+1} from C^n and the interface velocity on the faces (vof_advect:
+        directional split, MTHINC flux, volume deflation when `deflation`)."""
+        if out is None:
+            out = self._new(C)
+        check(_lib.lib.vof_advect(self._h, self._ptr(C, "C"), self._ptr(ug, "ug"),
+                                  self._ptr(vg, "vg"), self._ptr(wg, "wg"), float(dt),
+                                  float(beta), 1 if deflation else 0, self._ptr(out, "out"),
+                                  _stream_ptr(stream)), "vof_advect")
+        return out
+
     def step(self, u, v, w, phat, rho, rho0, src_p, dt, src_ext, p=None, phi=None, q=None,
              out=None, gamma=None, stream=None):
         """One time step: projection of (u, v, w) = u* (in place) and extension of the

@@ -51,6 +51,7 @@ SIGNATURES = {
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "interface_terms": (_i, [_p, _p, _p, _d, _d, _i, _p, _p, _p, _p, _p]),
+    "vof_advect": (_i, [_p, _p, _p, _p, _p, _d, _d, _i, _p, _p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_set_mixed_tol": (_i, [_p, _d]),
     "poisson_plan_mixed_report": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), _p]),
@@ -73,7 +74,7 @@ for _name, (_res, _args) in SIGNATURES.items():
     _f.argtypes = _args
 
 VP_OK, VP_EINVAL, VP_EUNSUPPORTED, VP_ENOMEM, VP_EHIP = 0, -1, -2, -3, -4
-NUM_KERNEL_CLASSES = 16
+NUM_KERNEL_CLASSES = 19
 MAX_BATCH = 16
 PRECISION = {"fp64": 0, "mixed": 1}
 NOALLOC_MAX_POINTS = 1 << 23

@@ -1,0 +1,299 @@
+// VoF advection of section 3.1: the volume fraction C carried by the
+// interface velocity u_Gamma of section 3.6 (eq. cadv) with directional
+// splitting, x then y then z (eq. fluxes), each sweep implicit in its own
+// result through the divergence of its velocity component, and the final
+// correction with the implicit volume-deflation term (eq. final_corr_2; the
+// original correction eq. final_corr_1 on request).
+//
+// Flux: the MTHINC method the paper cites (Ii et al., J. Comput. Phys. 231,
+// 2012), linear reconstruction.  In a cell with local coordinates
+// X in [-1/2, 1/2]^3 the indicator is H = 1/2 (1 + tanh(beta (m.X + d))),
+// m the unit normal of the Youngs gradient in cell coordinates
+// (dx g_x, dy g_y, dz_k g_z), d fixed by the cell's volume (the integral of H
+// over the cell is C).  Integrals of H over a box of the cell are exact along
+// the dominant axis of m (the first of x, y, z within a factor 1 - 1e-9 of
+// the largest component) and 2-point Gauss-Legendre in the other two.  The
+// flux through a face of velocity V is sign(V) h times the integral over the
+// part of the upwind cell (width h along the sweep) that the face sweeps in
+// dt, the last xi = |V| dt / h of it (clamped to 1).  Cells with C within
+// 1e-8 of 0 or 1, or a change of C across the cell below 1e-12, are uniform
+// (H = C); ghost cells beyond a non-periodic end are uniform with the end
+// cell's C.
+//
+// Launch shape: one thread per cell on TX x TY tiles of one plane
+// (TX = min(largest power of two dividing nx, 64), 256 threads).  A thread
+// computes the fluxes of both faces of its cell along the sweep with one
+// function of the face's own data, so the two cells sharing a face take the
+// same bits from it and the fluxes telescope exactly (the scheme's volume
+// balance holds to rounding of the updates alone).  The reconstruction runs
+// only where the upwind cell is an interface cell (a thin band); elsewhere a
+// face costs its velocity and the upwind C.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace vp {
+
+namespace {
+
+constexpr double kBandEps = 1e-8;
+constexpr double kGradMin = 1e-12;
+constexpr double kAxisTol = 1e-9;
+constexpr double kGauss = 0.28867513459481287;  // 1 / (2 sqrt 3): 2-point nodes on [-1/2, 1/2]
+constexpr double kLn2 = 0.69314718055994531;
+
+__device__ __forceinline__ int wrap_clamp(int i, int n, bool periodic) {
+  if (periodic) return ((i % n) + n) % n;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ double lncosh(double x) {
+#pragma clang fp contract(off)
+  const double a = fabs(x);
+  return a + log1p(exp(-2.0 * a)) - kLn2;
+}
+
+__device__ __forceinline__ double tanh_of(double x) {
+#pragma clang fp contract(off)
+  const double e = exp(-2.0 * fabs(x));
+  return copysign((1.0 - e) / (1.0 + e), x);
+}
+
+// the reconstruction of one cell
+struct Rec {
+  double m0, m1, m2;  // unit normal in cell coordinates (x, y, z)
+  double d;
+  int a;              // dominant axis
+};
+
+__device__ __forceinline__ double comp(const Rec& r, int ax) {
+  return ax == 0 ? r.m0 : (ax == 1 ? r.m1 : r.m2);
+}
+
+// Youngs gradient of C at cell (i, j, k) scaled to cell coordinates:
+// (dx g_x, dy g_y, dzf_k g_z).  g is the mean of the gradients at the cell's
+// eight corners, each from the eight cells around the corner; per component
+// the central difference weighted (1, 2, 1) in each transverse direction,
+// in z the mean of the two one-sided differences over the centre distances.
+// Ghost cells: periodic copies, or the end cell's value.
+__device__ void youngs_scaled(const GridArgs& g, const double* __restrict__ C, int i, int j, int k,
+                              double& hx, double& hy, double& hz) {
+#pragma clang fp contract(off)
+  const bool px = g.bcx == 0, py = g.bcy == 0, pz = g.bcz == 0;
+  int ii[3], jj[3], kk[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    ii[o] = wrap_clamp(i + o - 1, g.nx, px);
+    jj[o] = wrap_clamp(j + o - 1, g.ny, py);
+    kk[o] = wrap_clamp(k + o - 1, g.nz, pz);
+  }
+  double c[3][3][3];  // [dz][dy][dx]
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+        c[a][b][o] = C[(long)ii[o] + (long)g.nx * (jj[b] + (long)g.ny * kk[a])];
+  const double w[3] = {1.0, 2.0, 1.0};
+  // centre distances across the faces k-1/2 and k+1/2 (the difference across
+  // a ghost face is zero, its distance only has to be positive)
+  const double dzc_m = k > 0 ? g.dzc[k - 1] : (pz ? g.dzc[g.nz - 1] : 1.0);
+  const double dzc_p = k + 1 < g.nz ? g.dzc[k] : (pz ? g.dzc[g.nz - 1] : 1.0);
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      sx += w[a] * w[b] * (c[a][b][2] - c[a][b][0]);
+      sy += w[a] * w[b] * (c[a][2][b] - c[a][0][b]);
+      sz += w[a] * w[b] * ((c[2][a][b] - c[1][a][b]) / dzc_p + (c[1][a][b] - c[0][a][b]) / dzc_m);
+    }
+  const double gx = sx / (32.0 * g.dx), gy = sy / (32.0 * g.dy), gz = sz / 32.0;
+  hx = g.dx * gx;
+  hy = g.dy * gy;
+  hz = g.dzf[k] * gz;
+}
+
+// Integral of H over the box that is [s0, s1] along axis `ax` and the whole
+// cell along the other two; also its derivative with respect to d.
+__device__ void box_integral(const Rec& r, int ax, double s0, double s1, double beta, double& val,
+                             double& dval) {
+#pragma clang fp contract(off)
+  const int a = r.a;
+  const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+  const double ma = comp(r, a), m1 = comp(r, t1), m2 = comp(r, t2);
+  // extent of each axis: [s0, s1] along ax, [-1/2, 1/2] otherwise
+  const double a0 = ax == a ? s0 : -0.5, a1 = ax == a ? s1 : 0.5;
+  const double lo1 = ax == t1 ? s0 : -0.5, hi1 = ax == t1 ? s1 : 0.5;
+  const double lo2 = ax == t2 ? s0 : -0.5, hi2 = ax == t2 ? s1 : 0.5;
+  const double c1 = 0.5 * (lo1 + hi1), r1 = hi1 - lo1;
+  const double c2 = 0.5 * (lo2 + hi2), r2 = hi2 - lo2;
+  const double inv = 1.0 / (2.0 * beta * ma);
+  double tot = 0.0, dtot = 0.0;
+#pragma unroll
+  for (int p = -1; p <= 1; p += 2)
+#pragma unroll
+    for (int q = -1; q <= 1; q += 2) {
+      const double y = c1 + (double)p * kGauss * r1;
+      const double z = c2 + (double)q * kGauss * r2;
+      const double A = r.d + m1 * y + m2 * z;
+      const double x1 = beta * (ma * a1 + A), x0 = beta * (ma * a0 + A);
+      const double J = 0.5 * (a1 - a0) + (lncosh(x1) - lncosh(x0)) * inv;
+      const double dJ = (tanh_of(x1) - tanh_of(x0)) * (beta * inv);
+      tot = tot + 0.25 * r1 * r2 * J;
+      dtot = dtot + 0.25 * r1 * r2 * dJ;
+    }
+  val = tot;
+  dval = dtot;
+}
+
+// d with the integral of H over the cell equal to C: safeguarded Newton
+// from the one-dimensional closed form along the dominant axis, inside the
+// bracket [-(2 + 25 / beta), 2 + 25 / beta] (bisection where a step leaves it)
+__device__ double solve_d(Rec& r, double C, double beta) {
+#pragma clang fp contract(off)
+  const double ma = fabs(comp(r, r.a));
+  const double bp = beta * ma;
+  const double R = exp(bp * (2.0 * C - 1.0)), b = exp(bp);
+  double d = ma * (log((R * b - 1.0) / (b - R)) / (2.0 * bp));
+  const double span = 2.0 + 25.0 / beta;
+  double lo = -span, hi = span;
+  if (!(d > lo && d < hi)) d = 0.0;
+  for (int it = 0; it < 60; ++it) {
+    r.d = d;
+    double f, df;
+    box_integral(r, 0, -0.5, 0.5, beta, f, df);
+    f = f - C;
+    if (fabs(f) <= 2e-16) break;
+    if (f < 0.0) lo = d;
+    else hi = d;
+    double dn = df > 0.0 ? d - f / df : 0.5 * (lo + hi);
+    if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
+    const bool done = fabs(dn - d) <= 1e-15 * (1.0 + fabs(d));
+    d = dn;
+    if (done) break;
+  }
+  r.d = d;
+  return d;
+}
+
+// index helpers of a sweep along AX
+template <int AX>
+__device__ __forceinline__ int extent(const GridArgs& g) {
+  return AX == 0 ? g.nx : (AX == 1 ? g.ny : g.nz);
+}
+template <int AX>
+__device__ __forceinline__ bool periodic_along(const GridArgs& g) {
+  return (AX == 0 ? g.bcx : (AX == 1 ? g.bcy : g.bcz)) == 0;
+}
+template <int AX>
+__device__ __forceinline__ double width(const GridArgs& g, int s) {
+  return AX == 0 ? g.dx : (AX == 1 ? g.dy : g.dzf[s]);
+}
+
+// Flux through the face between cells f - 1 and f along AX (f = 0 .. n, the
+// cells' other coordinates i, j, k), with face velocity V.
+template <int AX>
+__device__ double face_flux(const GridArgs& g, const double* __restrict__ C, int f, int i, int j,
+                            int k, double V, double dt, double beta) {
+#pragma clang fp contract(off)
+  if (V == 0.0) return 0.0;
+  const int n = extent<AX>(g);
+  const bool per = periodic_along<AX>(g);
+  const bool pos = V > 0.0;
+  int up = pos ? f - 1 : f;
+  const bool ghost = !per && (up < 0 || up >= n);
+  up = wrap_clamp(up, n, per);
+  const int ci = AX == 0 ? up : i, cj = AX == 1 ? up : j, ck = AX == 2 ? up : k;
+  const double cu = C[(long)ci + (long)g.nx * (cj + (long)g.ny * ck)];
+  const double h = width<AX>(g, AX == 2 ? ck : 0);
+  double xi = fabs(V) * dt / h;
+  xi = xi < 1.0 ? xi : 1.0;
+  const double sgn = pos ? 1.0 : -1.0;
+  if (ghost || !(cu > kBandEps && cu < 1.0 - kBandEps)) return sgn * h * xi * cu;
+  double hx, hy, hz;
+  youngs_scaled(g, C, ci, cj, ck, hx, hy, hz);
+  const double mag = sqrt(hx * hx + hy * hy + hz * hz);
+  if (!(mag > kGradMin)) return sgn * h * xi * cu;
+  Rec r;
+  r.m0 = hx / mag;
+  r.m1 = hy / mag;
+  r.m2 = hz / mag;
+  const double a0 = fabs(r.m0), a1 = fabs(r.m1), a2 = fabs(r.m2);
+  const double big = fmax(a0, fmax(a1, a2)) * (1.0 - kAxisTol);
+  r.a = a0 >= big ? 0 : (a1 >= big ? 1 : 2);
+  solve_d(r, cu, beta);
+  double I, dI;
+  if (pos) box_integral(r, AX, 0.5 - xi, 0.5, beta, I, dI);
+  else box_integral(r, AX, -0.5, -0.5 + xi, beta, I, dI);
+  return sgn * h * I;
+}
+
+// One split step along AX: out = (C - (f_{s+1/2} - f_{s-1/2}) / h) / (1 - dt (V_{s+1/2} - V_{s-1/2}) / h).
+// FINAL (AX = 2): also the final correction of the three sweeps, with C1
+// (the x sweep's result at the cell; may alias out) and the x / y face
+// velocities u, v:  F = C1 du/dx + C2 dv/dy + C3 dw/dz,
+//   deflation: out = (C3 - dt F) / (1 - dt (du/dx + dv/dy + dw/dz)),  else C3 - dt F.
+template <int AX, bool FINAL>
+__global__ __launch_bounds__(256) void k_adv_sweep(const GridArgs g, const double* __restrict__ C,
+                                                  const double* __restrict__ V, double* out,
+                                                  double dt, double beta, int deflation,
+                                                  const double* C1, const double* __restrict__ u,
+                                                  const double* __restrict__ v) {
+#pragma clang fp contract(off)
+  const int tx = g.txp < 64 ? g.txp : 64;
+  const int ltx = __builtin_ctz(tx);
+  const int i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
+  const int j = blockIdx.y * (256 / tx) + (threadIdx.x >> ltx);
+  const int k = blockIdx.z;
+  if (j >= g.ny) return;
+  const long idx = (long)i + (long)g.nx * (j + (long)g.ny * k);
+  const int n = extent<AX>(g);
+  const bool per = periodic_along<AX>(g);
+  const int s = AX == 0 ? i : (AX == 1 ? j : k);
+  const long stride = AX == 0 ? 1L : (AX == 1 ? (long)g.nx : (long)g.nx * g.ny);
+  const double vup = V[idx];
+  const double vlo = s > 0 ? V[idx - stride] : (per ? V[idx + (long)(n - 1) * stride] : 0.0);
+  const double h = width<AX>(g, AX == 2 ? k : 0);
+  const double flo = face_flux<AX>(g, C, s, i, j, k, vlo, dt, beta);
+  const double fup = face_flux<AX>(g, C, s + 1, i, j, k, vup, dt, beta);
+  const double delta = (vup - vlo) / h;
+  const double cn = (C[idx] - (fup - flo) / h) / (1.0 - dt * delta);
+  if (!FINAL) {
+    out[idx] = cn;
+    return;
+  }
+  const double uup = u[idx];
+  const double ulo = i > 0 ? u[idx - 1] : (g.bcx == 0 ? u[idx + g.nx - 1] : 0.0);
+  const double wy = v[idx];
+  const double wyl = j > 0 ? v[idx - g.nx] : (g.bcy == 0 ? v[idx + (long)(g.ny - 1) * g.nx] : 0.0);
+  const double ddx = (uup - ulo) / g.dx, ddy = (wy - wyl) / g.dy;
+  const double F = C1[idx] * ddx + C[idx] * ddy + cn * delta;
+  const double r = cn - dt * F;
+  out[idx] = deflation ? r / (1.0 - dt * (ddx + ddy + delta)) : r;
+}
+
+}  // namespace
+
+hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
+                         const double* wg, double dt, double beta, int deflation, double* work,
+                         double* out, int sweep, hipStream_t st) {
+  const int tx = g.txp < 64 ? g.txp : 64;
+  if (tx < 1 || g.nx % tx) return hipErrorInvalidValue;
+  const int ty = 256 / tx;
+  const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty), (unsigned)g.nz);
+  // x: C -> out (C*); y: out -> work (C**); z: work -> out (C^{n+1}), with C* read from out
+  if (sweep == 0)
+    hipLaunchKernelGGL((k_adv_sweep<0, false>), grid, dim3(256), 0, st, g, C, ug, out, dt, beta,
+                       deflation, nullptr, nullptr, nullptr);
+  else if (sweep == 1)
+    hipLaunchKernelGGL((k_adv_sweep<1, false>), grid, dim3(256), 0, st, g, out, vg, work, dt, beta,
+                       deflation, nullptr, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_adv_sweep<2, true>), grid, dim3(256), 0, st, g, work, wg, out, dt, beta,
+                       deflation, out, ug, vg);
+  return hipGetLastError();
+}
+
+}  // namespace vp

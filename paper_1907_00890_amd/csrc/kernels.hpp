@@ -177,6 +177,13 @@ constexpr int kInterfaceThreads = 512;
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st);
+// advect.hip: VoF advection of section 3.1 (directional split, MTHINC flux,
+// volume deflation).  sweep 0: x sweep C -> out; 1: y sweep out -> work;
+// 2: z sweep work -> out with the final correction (C* read back from out).
+// g.txp sets the tile width (one thread per cell, 256 per block).
+hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
+                         const double* wg, double dt, double beta, int deflation, double* work,
+                         double* out, int sweep, hipStream_t st);
 // r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
 // r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);

@@ -41,12 +41,15 @@ int hip_fail(hipError_t e, const char* what) {
 enum KernelClass {
   K_XFWD = 0, K_YFWD, K_Z, K_YINV, K_XINV,
   K_XFWD32, K_YFWD32, K_Z32, K_YINV32, K_XINV32,
-  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_EPILOGUE, K_INTERFACE, K_NCLASS
+  K_RESIDUAL, K_RHS, K_CORRECT, K_EXTEND, K_EPILOGUE, K_INTERFACE,
+  K_ADV_X, K_ADV_Y, K_ADV_Z, K_NCLASS
 };
+static_assert(K_NCLASS <= VP_NUM_KERNEL_CLASSES, "kernel classes of the C interface");
 const char* const kClassNames[K_NCLASS] = {
     "x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse",
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
-    "residual", "rhs_assembly", "correction", "extension", "step_epilogue", "interface_terms"};
+    "residual", "rhs_assembly", "correction", "extension", "step_epilogue", "interface_terms",
+    "advect_x", "advect_y", "advect_z"};
 
 // Twiddle table of one direction, (cos, sin) pairs: of 2 pi k/N for k < N,
 // then of pi m/(2N) for m <= N/2 (the DCT post/pre rotation).  For a wall at
@@ -735,6 +738,24 @@ int interface_terms(poisson_plan* P, const double* C, const double* mdot, double
             vp::launch_interface(P->gi, C, mdot, rho1, rho2, phase == 1 ? rho1 : rho2, s, qx,
                                  qy, qz, st),
             "interface terms", st);
+  return VP_OK;
+}
+
+int vof_advect(poisson_plan* P, const double* C, const double* ug, const double* vg,
+               const double* wg, double dt, double beta, int deflation, double* C_new,
+               void* stream) {
+  if (!P || !C || !ug || !vg || !wg || !C_new || C_new == C || !(dt > 0) || !(beta > 0) ||
+      (deflation != 0 && deflation != 1))
+    return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // C** of the y sweep lives in workspace slot 0
+  VP_LAUNCH(P, K_ADV_X, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 0, st),
+            "advect x", st);
+  VP_LAUNCH(P, K_ADV_Y, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 1, st),
+            "advect y", st);
+  VP_LAUNCH(P, K_ADV_Z, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 2, st),
+            "advect z", st);
   return VP_OK;
 }
 
