@@ -20,13 +20,13 @@
 // (H = C); ghost cells beyond a non-periodic end are uniform with the end
 // cell's C.
 //
-// Launch shape: one thread per cell on TX x TY tiles of one plane
-// (TX = min(largest power of two dividing nx, 64), 256 threads).  A thread
-// computes the fluxes of both faces of its cell along the sweep with one
-// function of the face's own data, so the two cells sharing a face take the
-// same bits from it and the fluxes telescope exactly (the scheme's volume
-// balance holds to rounding of the updates alone).  The reconstruction runs
-// only where the upwind cell is an interface cell (a thin band); elsewhere a
+// Launch shape: one thread per cell, 256 per block.  Every face flux is
+// computed once and used by both cells sharing the face (LDS within the x and
+// y tiles, a register carried from plane to plane in the z march; the faces
+// on a tile's lower edge are computed by both tiles with the same function of
+// the same data), so the fluxes telescope exactly and the scheme's volume
+// balance holds to the rounding of the updates alone.  The reconstruction
+// runs only where the upwind cell is an interface cell (a band); elsewhere a
 // face costs its velocity and the upwind C.
 #include <hip/hip_runtime.h>
 
@@ -150,7 +150,13 @@ __device__ void box_integral(const Rec& r, int ax, double s0, double s1, double 
 
 // d with the integral of H over the cell equal to C: safeguarded Newton
 // from the one-dimensional closed form along the dominant axis, inside the
-// bracket [-(2 + 25 / beta), 2 + 25 / beta] (bisection where a step leaves it)
+// bracket [-(2 + 25 / beta), 2 + 25 / beta] (bisection where a step leaves
+// it).  The volume error falls quadratically from the first guess (about
+// 1e-2) to the rounding level of its O(10)-sized terms (a few 1e-15) in four
+// to six steps.  The solve stops one Newton step after the error is below
+// 1e-13 or a step below 1e-8 (1 + |d|), or when a step vanishes in rounding;
+// a step landing on a bracket end is a Newton step (the end is the last
+// iterate once the step is below half an ulp), not a reason to bisect.
 __device__ double solve_d(Rec& r, double C, double beta) {
 #pragma clang fp contract(off)
   const double ma = fabs(comp(r, r.a));
@@ -160,19 +166,23 @@ __device__ double solve_d(Rec& r, double C, double beta) {
   const double span = 2.0 + 25.0 / beta;
   double lo = -span, hi = span;
   if (!(d > lo && d < hi)) d = 0.0;
-  for (int it = 0; it < 60; ++it) {
+  bool done = false;
+  for (int it = 0; it < 40; ++it) {
     r.d = d;
     double f, df;
     box_integral(r, 0, -0.5, 0.5, beta, f, df);
     f = f - C;
-    if (fabs(f) <= 2e-16) break;
+    if (f == 0.0) break;
     if (f < 0.0) lo = d;
     else hi = d;
-    double dn = df > 0.0 ? d - f / df : 0.5 * (lo + hi);
-    if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
-    const bool done = fabs(dn - d) <= 1e-15 * (1.0 + fabs(d));
+    double dn = d - f / df;
+    const bool newton = df > 0.0 && dn >= lo && dn <= hi;
+    if (!newton) dn = 0.5 * (lo + hi);
+    if (dn == d) break;
+    const double step = fabs(dn - d);
     d = dn;
     if (done) break;
+    done = newton && (fabs(f) <= 1e-13 || step <= 1e-8 * (1.0 + fabs(d)));
   }
   r.d = d;
   return d;
@@ -230,34 +240,20 @@ __device__ double face_flux(const GridArgs& g, const double* __restrict__ C, int
   return sgn * h * I;
 }
 
-// One split step along AX: out = (C - (f_{s+1/2} - f_{s-1/2}) / h) / (1 - dt (V_{s+1/2} - V_{s-1/2}) / h).
-// FINAL (AX = 2): also the final correction of the three sweeps, with C1
-// (the x sweep's result at the cell; may alias out) and the x / y face
+// The cell update of a split step along AX from its two face fluxes:
+// (C - (f_{s+1/2} - f_{s-1/2}) / h) / (1 - dt (V_{s+1/2} - V_{s-1/2}) / h);
+// FINAL (AX = 2) adds the final correction of the three sweeps with C1 (the
+// x sweep's result at the cell; may alias out) and the x / y face
 // velocities u, v:  F = C1 du/dx + C2 dv/dy + C3 dw/dz,
 //   deflation: out = (C3 - dt F) / (1 - dt (du/dx + dv/dy + dw/dz)),  else C3 - dt F.
 template <int AX, bool FINAL>
-__global__ __launch_bounds__(256) void k_adv_sweep(const GridArgs g, const double* __restrict__ C,
-                                                  const double* __restrict__ V, double* out,
-                                                  double dt, double beta, int deflation,
-                                                  const double* C1, const double* __restrict__ u,
-                                                  const double* __restrict__ v) {
+__device__ __forceinline__ void update_cell(const GridArgs& g, const double* __restrict__ C,
+                                            long idx, int i, int j, double h, double vlo,
+                                            double vup, double flo, double fup, double* out,
+                                            double dt, int deflation, const double* C1,
+                                            const double* __restrict__ u,
+                                            const double* __restrict__ v) {
 #pragma clang fp contract(off)
-  const int tx = g.txp < 64 ? g.txp : 64;
-  const int ltx = __builtin_ctz(tx);
-  const int i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
-  const int j = blockIdx.y * (256 / tx) + (threadIdx.x >> ltx);
-  const int k = blockIdx.z;
-  if (j >= g.ny) return;
-  const long idx = (long)i + (long)g.nx * (j + (long)g.ny * k);
-  const int n = extent<AX>(g);
-  const bool per = periodic_along<AX>(g);
-  const int s = AX == 0 ? i : (AX == 1 ? j : k);
-  const long stride = AX == 0 ? 1L : (AX == 1 ? (long)g.nx : (long)g.nx * g.ny);
-  const double vup = V[idx];
-  const double vlo = s > 0 ? V[idx - stride] : (per ? V[idx + (long)(n - 1) * stride] : 0.0);
-  const double h = width<AX>(g, AX == 2 ? k : 0);
-  const double flo = face_flux<AX>(g, C, s, i, j, k, vlo, dt, beta);
-  const double fup = face_flux<AX>(g, C, s + 1, i, j, k, vup, dt, beta);
   const double delta = (vup - vlo) / h;
   const double cn = (C[idx] - (fup - flo) / h) / (1.0 - dt * delta);
   if (!FINAL) {
@@ -274,25 +270,104 @@ __global__ __launch_bounds__(256) void k_adv_sweep(const GridArgs g, const doubl
   out[idx] = deflation ? r / (1.0 - dt * (ddx + ddy + delta)) : r;
 }
 
+// x and y sweeps: a TX x TY tile of one plane, one thread per cell.  Each
+// thread takes the flux of its cell's upper face into LDS; the first cell of
+// each line along the sweep also takes its lower face; the update reads both
+// faces from LDS, so every face of the tile is computed once.
+template <int AX>
+__global__ __launch_bounds__(256) void k_adv_xy(const GridArgs g, int tx,
+                                               const double* __restrict__ C,
+                                               const double* __restrict__ V,
+                                               double* __restrict__ out, double dt, double beta) {
+#pragma clang fp contract(off)
+  __shared__ double fl[256 + 64];
+  const int ltx = __builtin_ctz(tx);
+  const int ty = 256 >> ltx;
+  const int li = threadIdx.x & (tx - 1), lj = threadIdx.x >> ltx;
+  const int i = blockIdx.x * tx + li;
+  const int j = blockIdx.y * ty + lj;
+  const int k = blockIdx.z;
+  const bool own = j < g.ny;
+  const long idx = (long)i + (long)g.nx * ((own ? j : 0) + (long)g.ny * k);
+  const int n = extent<AX>(g);
+  const bool per = periodic_along<AX>(g);
+  const int s = AX == 0 ? i : j;
+  const long stride = AX == 0 ? 1L : (long)g.nx;
+  // LDS slot of a face: x sweep, row lj holds faces i0-1/2 .. i0+tx-1/2 at
+  // lj * (tx + 1) + 0 .. tx; y sweep, face row r = 0 .. ty at r * tx + li
+  const int up_slot = AX == 0 ? lj * (tx + 1) + li + 1 : (lj + 1) * tx + li;
+  const int lo_slot = AX == 0 ? lj * (tx + 1) + li : lj * tx + li;
+  const bool first = (AX == 0 ? li : lj) == 0;
+  double vup = 0.0, vlo = 0.0;
+  if (own) {
+    vup = V[idx];
+    vlo = s > 0 ? V[idx - stride] : (per ? V[idx + (long)(n - 1) * stride] : 0.0);
+    fl[up_slot] = face_flux<AX>(g, C, s + 1, i, j, k, vup, dt, beta);
+    if (first) fl[lo_slot] = face_flux<AX>(g, C, s, i, j, k, vlo, dt, beta);
+  }
+  __syncthreads();
+  if (!own) return;
+  update_cell<AX, false>(g, C, idx, i, j, width<AX>(g, 0), vlo, vup, fl[lo_slot], fl[up_slot], out,
+                         dt, 0, nullptr, nullptr, nullptr);
+}
+
+// z sweep with the final correction: a TX x TY tile of the x-y plane marching
+// through kc planes; the flux of the upper face of plane k is carried to
+// plane k+1 as its lower face, so each face is computed once (the block's
+// first lower face aside).
+__global__ __launch_bounds__(256) void k_adv_z(const GridArgs g, int tx, int kc,
+                                              const double* __restrict__ C,
+                                              const double* __restrict__ W, double* out,
+                                              double dt, double beta, int deflation,
+                                              const double* C1, const double* __restrict__ u,
+                                              const double* __restrict__ v) {
+#pragma clang fp contract(off)
+  const int ltx = __builtin_ctz(tx);
+  const int ty = 256 >> ltx;
+  const int i = blockIdx.x * tx + (threadIdx.x & (tx - 1));
+  const int j = blockIdx.y * ty + (threadIdx.x >> ltx);
+  if (j >= g.ny) return;
+  const int kb = blockIdx.z * kc, ke = kb + kc < g.nz ? kb + kc : g.nz;
+  const bool per = g.bcz == 0;
+  const long P = (long)g.nx * g.ny;
+  const long col = (long)i + (long)g.nx * j;
+  double vlo = kb > 0 ? W[col + (long)(kb - 1) * P] : (per ? W[col + (long)(g.nz - 1) * P] : 0.0);
+  double flo = face_flux<2>(g, C, kb, i, j, kb, vlo, dt, beta);
+  for (int k = kb; k < ke; ++k) {
+    const long idx = col + (long)k * P;
+    const double vup = W[idx];
+    const double fup = face_flux<2>(g, C, k + 1, i, j, k, vup, dt, beta);
+    update_cell<2, true>(g, C, idx, i, j, g.dzf[k], vlo, vup, flo, fup, out, dt, deflation, C1, u,
+                         v);
+    vlo = vup;
+    flo = fup;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
                          const double* wg, double dt, double beta, int deflation, double* work,
                          double* out, int sweep, hipStream_t st) {
-  const int tx = g.txp < 64 ? g.txp : 64;
-  if (tx < 1 || g.nx % tx) return hipErrorInvalidValue;
+  if (g.txp < 1 || g.nx % g.txp) return hipErrorInvalidValue;
+  // x sweep: 64-wide tiles (rows of faces, one extra face per row); y sweep:
+  // 16-wide tiles, 16 rows (one extra row of faces per 16); z sweep: 64 x 4
+  // tiles marching 16 planes
+  const int tx = sweep == 1 ? (g.txp < 16 ? g.txp : 16) : (g.txp < 64 ? g.txp : 64);
   const int ty = 256 / tx;
-  const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty), (unsigned)g.nz);
+  const unsigned bx = (unsigned)(g.nx / tx), by = (unsigned)((g.ny + ty - 1) / ty);
   // x: C -> out (C*); y: out -> work (C**); z: work -> out (C^{n+1}), with C* read from out
-  if (sweep == 0)
-    hipLaunchKernelGGL((k_adv_sweep<0, false>), grid, dim3(256), 0, st, g, C, ug, out, dt, beta,
-                       deflation, nullptr, nullptr, nullptr);
-  else if (sweep == 1)
-    hipLaunchKernelGGL((k_adv_sweep<1, false>), grid, dim3(256), 0, st, g, out, vg, work, dt, beta,
-                       deflation, nullptr, nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((k_adv_sweep<2, true>), grid, dim3(256), 0, st, g, work, wg, out, dt, beta,
-                       deflation, out, ug, vg);
+  if (sweep == 0) {
+    hipLaunchKernelGGL((k_adv_xy<0>), dim3(bx, by, (unsigned)g.nz), dim3(256), 0, st, g, tx, C, ug,
+                       out, dt, beta);
+  } else if (sweep == 1) {
+    hipLaunchKernelGGL((k_adv_xy<1>), dim3(bx, by, (unsigned)g.nz), dim3(256), 0, st, g, tx, out,
+                       vg, work, dt, beta);
+  } else {
+    const int kc = g.nz < 16 ? g.nz : 16;
+    hipLaunchKernelGGL(k_adv_z, dim3(bx, by, (unsigned)((g.nz + kc - 1) / kc)), dim3(256), 0, st, g,
+                       tx, kc, work, wg, out, dt, beta, deflation, out, ug, vg);
+  }
   return hipGetLastError();
 }
 
