@@ -74,6 +74,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning the plans")
+    ap.add_argument("--tune", default="",
+                    help="launch shapes of the main workload's FP64 plan, 'key=value,...' "
+                         "(poisson_plan_tune keys), applied instead of autotuning it")
+    ap.add_argument("--tune-mixed", default="",
+                    help="the same for the main workload's mixed plan")
     ap.add_argument("--cpu-sample", default="ppn256",
                     help="workload the CPU oracle is timed on (bounded sample)")
     ap.add_argument("--serve-rates", default="1000",
@@ -91,6 +96,19 @@ def parse():
                     help="end with three plain device copies of one field (a known byte "
                          "count for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def shape_plan(plan, batch, spec, no_autotune):
+    """Apply `spec` ('key=value,...') to the plan, or autotune it for `batch`
+    fields (unless no_autotune); returns the plan's launch shapes."""
+    if spec:
+        for item in spec.split(","):
+            key, value = item.split("=")
+            plan.tune(key.strip(), int(value))
+        return plan.tuning()
+    if no_autotune:
+        return plan.tuning()
+    return plan.autotune(batch=batch)
 
 
 def source_sha(name):
@@ -633,7 +651,7 @@ def main():
 
     q = (X["qx"], X["qy"], X["qz"])
     # launch shapes and radix schedules picked by the autotuner (before timing)
-    tuned = plan.autotune(batch=STEP_BATCH) if not args.no_autotune else plan.tuning()
+    tuned = shape_plan(plan, STEP_BATCH, args.tune, args.no_autotune)
 
     def step():
         # one time step through the fused entry point (all outputs written)
@@ -713,7 +731,7 @@ def main():
     # mixed: FP32 chain + FP64 defect correction, up to 3 steps, stopping on the
     # device once the estimated error is at most 1e-11 (the library default)
     mixed = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc, precision="mixed")
-    tuned_mixed = mixed.autotune(batch=1) if not args.no_autotune else mixed.tuning()
+    tuned_mixed = shape_plan(mixed, 1, args.tune_mixed, args.no_autotune)
     out32 = torch.empty_like(f)
     for _ in range(3):
         mixed.solve(f, out32)
