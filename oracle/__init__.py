@@ -27,7 +27,7 @@ brute-force dense solves and library special cases live in ``tests/``.
 """
 
 from .grid import Grid  # noqa: F401
-from .stencils import grad, div, lap, face_density  # noqa: F401
+from .stencils import grad, div, lap, face_density, grad_lower, face_density_lower  # noqa: F401
 from .solver import (  # noqa: F401
     solve,
     z_operator_dense,

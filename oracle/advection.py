@@ -58,9 +58,9 @@ J. Comput. Phys. 231 (2012); the paper only cites it).  Reading, linear
 
 Boundaries: periodic faces wrap; the lower face of a wall direction is
 implicit with zero velocity, the stored upper face is taken as stored (the
-caller keeps it zero at a wall); an outflow at an upper end takes its stored
-face velocity, inflow through it carrying the ghost's C.  A lower outflow end
-has a face the layout does not store and is refused.
+caller keeps it zero at a wall); an outflow end takes its face velocity (the
+stored last face at an upper end, the plane of `lower` at a lower end, as in
+``oracle.stencils``), inflow through it carrying the ghost's C.
 """
 from __future__ import annotations
 
@@ -177,22 +177,26 @@ def _band(C, mag):
     return (C > EPS) & (C < 1.0 - EPS) & (mag > GRAD_MIN)
 
 
-def _face_velocities(V, g: Grid, direction: str):
+def _face_velocities(V, g: Grid, direction: str, lower_plane=None):
     """Velocities of the n+1 faces -1/2 .. n-1/2 along `direction` (first
-    array axis = face index), from the stored n faces."""
+    array axis = face index), from the stored n faces (and, at a lower
+    outflow end, the plane of the face at -1/2)."""
     ax = _AX[direction]
     lo, _ = g.ends[{"x": 0, "y": 1, "z": 2}[direction]]
-    if lo == "D":
-        raise ValueError("an outflow at the lower end has a face the layout does not store")
     q = np.moveaxis(np.asarray(V, dtype=np.float64), ax, 0)
     faces = np.zeros((q.shape[0] + 1,) + q.shape[1:])
     faces[1:] = q
+    if lo == "D":
+        if lower_plane is None:
+            raise ValueError("an outflow at the lower end needs its face's velocity "
+                             "(the layout stores no face at -1/2)")
+        faces[0] = lower_plane
     if lo == "P":
         faces[0] = q[-1]
     return faces
 
 
-def sweep(C, V, direction: str, dt: float, g: Grid, beta: float = 1.0):
+def sweep(C, V, direction: str, dt: float, g: Grid, beta: float = 1.0, lower_plane=None):
     """One split step of eq. (fluxes) along `direction` ('x', 'y' or 'z').
     Returns (C_new, delta) with delta = (V_{+1/2} - V_{-1/2}) / h at every cell."""
     C = np.asarray(C, dtype=np.float64)
@@ -216,7 +220,7 @@ def sweep(C, V, direction: str, dt: float, g: Grid, beta: float = 1.0):
         d[band] = solve_d(mb, C[band], beta)
 
     # faces -1/2 .. n-1/2 along the axis: velocity, upwind cell
-    Vf = _face_velocities(V, g, direction)  # (n+1, ...) along axis 0
+    Vf = _face_velocities(V, g, direction, lower_plane)  # (n+1, ...) along axis 0
     Cm = np.moveaxis(C, ax, 0)
     mm = [np.moveaxis(c, ax, 0) for c in m]
     dm = np.moveaxis(d, ax, 0)
@@ -264,13 +268,15 @@ def sweep(C, V, direction: str, dt: float, g: Grid, beta: float = 1.0):
 
 
 def advect(C, ug, vg, wg, dt: float, g: Grid, beta: float = 1.0, deflation: bool = True,
-           return_stages: bool = False):
+           return_stages: bool = False, lower=None):
     """C^{n+1} from C^n and the interface velocity (ug, vg, wg) on the faces:
     eq. (fluxes) then eq. (final_corr_2) (deflation=True, the paper's method)
-    or eq. (final_corr_1) (deflation=False)."""
-    C1, dx_ = sweep(C, ug, "x", dt, g, beta)
-    C2, dy_ = sweep(C1, vg, "y", dt, g, beta)
-    C3, dz_ = sweep(C2, wg, "z", dt, g, beta)
+    or eq. (final_corr_1) (deflation=False); `lower` holds the interface
+    velocity on the faces at -1/2 of lower outflow ends (x, y, z planes)."""
+    lw = (None, None, None) if lower is None else lower
+    C1, dx_ = sweep(C, ug, "x", dt, g, beta, lw[0])
+    C2, dy_ = sweep(C1, vg, "y", dt, g, beta, lw[1])
+    C3, dz_ = sweep(C2, wg, "z", dt, g, beta, lw[2])
     F = C1 * dx_ + C2 * dy_ + C3 * dz_
     if deflation:
         Cn = (C3 - dt * F) / (1.0 - dt * (dx_ + dy_ + dz_))

@@ -42,7 +42,7 @@ import scipy.fft as sfft
 import scipy.linalg as sla
 
 from .grid import Grid
-from .stencils import grad, div, lap, face_density
+from .stencils import grad, div, lap, face_density, grad_lower, face_density_lower
 
 
 def _pair(ends):
@@ -178,33 +178,53 @@ def solve(f, g: Grid, return_mean: bool = False):
     return p
 
 
-def assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
+def _has_lower_outflow(g: Grid):
+    return any(lo == "D" for lo, _ in g.ends)
+
+
+def _check_lower(g: Grid, lower):
+    if lower is None:
+        if _has_lower_outflow(g):
+            raise ValueError("an outflow at a lower end needs the velocities of its faces at -1/2 "
+                             "(`lower`)")
+        return
+    for (lo, _), plane in zip(g.ends, lower):
+        if (lo == "D") != (plane is not None):
+            raise ValueError("`lower` holds a plane exactly for the directions with a lower outflow")
+
+
+def assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid, lower=None):
     """Right-hand side b of L_h p = b (section 3.2, pressure equation x rho0).
 
     b = rho0 D[(1/rho0 - 1/rho_f) G p_hat] + (rho0/dt) (D u* - s), with
-    s = mdot (1/rho2 - 1/rho1) delta_Gamma the phase-change source.
+    s = mdot (1/rho2 - 1/rho1) delta_Gamma the phase-change source; `lower`
+    holds u* on the faces at -1/2 of lower outflow ends.
     """
     gx, gy, gz = grad(phat, g)
     rfx, rfy, rfz = face_density(rho, g)
     cx = (1.0 / rho0 - 1.0 / rfx) * gx
     cy = (1.0 / rho0 - 1.0 / rfy) * gy
     cz = (1.0 / rho0 - 1.0 / rfz) * gz
-    return rho0 * div(cx, cy, cz, g) + (rho0 / dt) * (div(ustar, vstar, wstar, g) - src)
+    clow = None
+    if lower is not None:
+        gl = grad_lower(phat, g)
+        rl = face_density_lower(rho, g)
+        clow = tuple(None if a is None else (1.0 / rho0 - 1.0 / r) * a for a, r in zip(gl, rl))
+    return (rho0 * div(cx, cy, cz, g, clow)
+            + (rho0 / dt) * (div(ustar, vstar, wstar, g, lower) - src))
 
 
-def _require_stored_faces(g: Grid):
-    if any(lo == "D" for lo, _ in g.ends):
-        raise ValueError("velocity updates need every outflow face stored: outflow only at upper ends")
-
-
-def project(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
+def project(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid, lower=None):
     """Pressure-split projection step (section 3.2).
 
     Returns (u, v, w, p): p solves L_h p = b (assemble_pressure_rhs) and
-    u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ].
+    u^{n+1} = u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ].  With an
+    outflow at a lower end, `lower` holds u* on the faces at -1/2 (planes,
+    see ``oracle.stencils``) and the result gains a fifth entry, u^{n+1} on
+    those faces (rho there is the first cell's).
     """
-    _require_stored_faces(g)
-    b = assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g)
+    _check_lower(g, lower)
+    b = assemble_pressure_rhs(ustar, vstar, wstar, phat, rho, rho0, src, dt, g, lower)
     p = solve(b, g)
     gpx, gpy, gpz = grad(p, g)
     ghx, ghy, ghz = grad(phat, g)
@@ -212,21 +232,34 @@ def project(ustar, vstar, wstar, phat, rho, rho0, src, dt, g: Grid):
     u = ustar - dt * (gpx / rho0 + (1.0 / rfx - 1.0 / rho0) * ghx)
     v = vstar - dt * (gpy / rho0 + (1.0 / rfy - 1.0 / rho0) * ghy)
     w = wstar - dt * (gpz / rho0 + (1.0 / rfz - 1.0 / rho0) * ghz)
-    return u, v, w, p
+    if lower is None:
+        return u, v, w, p
+    gpl, ghl, rl = grad_lower(p, g), grad_lower(phat, g), face_density_lower(rho, g)
+    new_lower = tuple(None if a is None else a - dt * (b_ / rho0 + (1.0 / r - 1.0 / rho0) * c)
+                      for a, b_, c, r in zip(lower, gpl, ghl, rl))
+    return u, v, w, p, new_lower
 
 
-def extend(u, v, w, src, g: Grid, q=None):
+def extend(u, v, w, src, g: Grid, q=None, lower=None):
     """Liquid-velocity extension and interface velocity (section 3.6).
 
     phi solves L_h phi = s (the Stefan potential, s = mdot (1/rho2 - 1/rho1)|grad C|),
     u_1^e = u - G phi and, when q = (mdot/rho1) n on faces is given,
     u_Gamma = u_1^e - q.  Returns (ue, ve, we, ug, vg, wg, phi); the u_Gamma
-    entries are None without q.
+    entries are None without q.  With an outflow at a lower end, `lower`
+    holds u on the faces at -1/2 and the result gains an eighth entry, u_1^e
+    on those faces; u_Gamma equals it there (q is zero on a non-periodic
+    boundary face).
     """
-    _require_stored_faces(g)
+    _check_lower(g, lower)
     phi = solve(src, g)
     gx, gy, gz = grad(phi, g)
     ue, ve, we = u - gx, v - gy, w - gz
     if q is None:
-        return ue, ve, we, None, None, None, phi
-    return ue, ve, we, ue - q[0], ve - q[1], we - q[2], phi
+        out = (ue, ve, we, None, None, None, phi)
+    else:
+        out = (ue, ve, we, ue - q[0], ve - q[1], we - q[2], phi)
+    if lower is None:
+        return out
+    gl = grad_lower(phi, g)
+    return out + (tuple(None if a is None else a - b for a, b in zip(lower, gl)),)

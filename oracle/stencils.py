@@ -18,9 +18,11 @@ Every direction has n+1 faces, -1/2 .. n-1/2; the arrays hold the n faces
   reading used for rho at velocity points in the split of section 3.2; on a
   boundary face, the inner cell's density.
 
-An outflow at a lower end ('D' at x-, y- or z-) is supported by L_h (and so by
-the Poisson solve) but not by grad/div on stored faces: the outflow face at
--1/2 carries a velocity that the n-face layout does not hold.
+An outflow at a lower end ('D' at x-, y- or z-) has a face at -1/2 whose
+velocity the n-face layout does not hold: it travels as a separate plane per
+direction, ``lower = (u_lo, v_lo, w_lo)`` shaped (nz, ny), (nz, nx) and
+(ny, nx) (None for a direction without a lower outflow), which ``div`` takes
+and ``grad_lower`` / ``face_density_lower`` complete.
 """
 from __future__ import annotations
 
@@ -89,21 +91,49 @@ def grad(p, g):
     return tuple(np.moveaxis(grad_all_faces(p, g, axis)[1:], 0, axis) for axis in (2, 1, 0))
 
 
-def div(u, v, w, g):
-    """D(u, v, w) at cell centres from the stored faces."""
+def _lower_index(axis):
+    return {2: 0, 1: 1, 0: 2}[axis]
+
+
+def div(u, v, w, g, lower=None):
+    """D(u, v, w) at cell centres from the stored faces; `lower` holds the
+    velocities on the faces at -1/2 of the directions with an outflow at
+    their lower end (see the module docstring)."""
     out = None
     for arr, axis in ((u, 2), (v, 1), (w, 0)):
         lo, _ = _ends(g, axis)
-        if lo == "D":
-            raise ValueError("an outflow at the lower end has a face the layout does not store")
         q = _as_axis0(np.asarray(arr), axis)
         faces = np.zeros((q.shape[0] + 1,) + q.shape[1:], dtype=np.result_type(q, np.float64))
         faces[1:] = q
+        if lo == "D":
+            plane = None if lower is None else lower[_lower_index(axis)]
+            if plane is None:
+                raise ValueError("an outflow at the lower end needs its face's velocity "
+                                 "(the layout stores no face at -1/2)")
+            faces[0] = plane
         if lo == "P":
             faces[0] = q[-1]
         term = div_all_faces(faces, g, axis)
         out = term if out is None else out + term
     return out
+
+
+def grad_lower(p, g):
+    """G(p) on the faces at -1/2 of the directions with a lower outflow end
+    ((p_0 - 0) / (h / 2)), as (x, y, z) planes; None elsewhere."""
+    p = np.asarray(p)
+    if p.dtype != np.longdouble:
+        p = p.astype(np.float64, copy=False)
+    return tuple(grad_all_faces(p, g, axis)[0] if _ends(g, axis)[0] == "D" else None
+                 for axis in (2, 1, 0))
+
+
+def face_density_lower(rho, g):
+    """rho on the faces at -1/2 of the directions with a lower outflow end:
+    the inner (first) cell's density, as (x, y, z) planes; None elsewhere."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return tuple(np.take(rho, 0, axis=axis) if _ends(g, axis)[0] == "D" else None
+                 for axis in (2, 1, 0))
 
 
 def lap(p, g):

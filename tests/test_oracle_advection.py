@@ -299,3 +299,26 @@ def test_normal_in_cell_coordinates_stretched():
         assert np.abs(got - want[:, None, None]).max() <= 1e-12, k
         assert np.abs(mag[k][1:-1, 1:-1] - np.linalg.norm(h)).max() <= 1e-13
     assert np.all(adv.dominant_axis((mx, my, mz))[inner] >= 0)
+
+
+def test_one_dimensional_lower_outflow_inflow():
+    """x ends outflow (lower) and wall (upper): inflow through the face at
+    -1/2 (velocity from its plane, > 0) carries the ghost's C (the first
+    cell's, uniform); the 1-D loop with that face."""
+    n = 24
+    g = oracle.Grid(n, 3, 3, 1.0 / n, 1.0 / 3, np.full(3, 1.0 / 3), "DNPPPP")
+    x = (np.arange(n) + 0.5) / n
+    c = 0.5 * (1 - np.tanh((x - 0.35) / 0.05))
+    r = np.random.default_rng(19)
+    ux = r.uniform(0.05, 0.9, n)
+    ux[-1] = 0.0  # the wall
+    ulo = 0.6     # inflow through the lower outflow face
+    dt = 0.6 / n
+    C = np.broadcast_to(c[None, None, :], g.shape).copy()
+    U = np.broadcast_to(ux[None, None, :], g.shape).copy()
+    Z = np.zeros(g.shape)
+    lower = (np.full((g.nz, g.ny), ulo), None, None)
+    Cn = adv.advect(C, U, Z, Z, dt, g, lower=lower)
+    faces = np.concatenate([[ulo], ux])
+    want = _loop_1d(c, faces, dt, 1.0 / n, ("D", "N"), 1.0)
+    assert np.abs(Cn - want[None, None, :]).max() <= 1e-13

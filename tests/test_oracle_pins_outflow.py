@@ -316,3 +316,121 @@ def test_projection_layered_outflow_face_density(axis, bc):
     assert np.abs(p - want).max() <= 1e-11 * np.abs(expect).max()
     for vel in (u, v, w):
         assert np.abs(vel).max() <= 1e-10 * np.abs(pl).max() * n
+
+
+def _lower_planes(g, seed):
+    """Random velocities on the faces at -1/2 of the lower outflow ends."""
+    r = np.random.default_rng(seed)
+    shapes = ((g.nz, g.ny), (g.nz, g.nx), (g.ny, g.nx))
+    return tuple(r.standard_normal(shp) if lo == "D" else None
+                 for (lo, _), shp in zip(g.ends, shapes))
+
+
+def test_stencils_pointwise_lower_outflow():
+    """Outflow at every end ('DDD'): the face gradient on the faces at -1/2
+    is (p_0 - 0) / (h / 2) and the divergence reads those faces from their
+    planes, written as loops (stretched z)."""
+    nx, ny, nz = 5, 4, 6
+    dx, dy = 0.3, 0.2
+    dzf = np.random.default_rng(12).uniform(0.1, 0.3, nz)
+    g = oracle.Grid(nx, ny, nz, dx, dy, dzf, "DDD")
+    p = vofsynth.gaussian_field(g.shape, 11)
+    gxl, gyl, gzl = oracle.grad_lower(p, g)
+    ul, vl, wl = _lower_planes(g, 13)
+    u, v, w = (vofsynth.gaussian_field(g.shape, s) for s in (14, 15, 16))
+    d = oracle.div(u, v, w, g, (ul, vl, wl))
+    for k in range(nz):
+        for j in range(ny):
+            assert np.isclose(gxl[k, j], p[k, j, 0] / (dx / 2), rtol=1e-15, atol=0)
+            for i in range(nx):
+                if j == 0:
+                    assert np.isclose(gyl[k, i], p[k, 0, i] / (dy / 2), rtol=1e-15, atol=0)
+                if k == 0:
+                    assert np.isclose(gzl[j, i], p[0, j, i] / (dzf[0] / 2), rtol=1e-15, atol=0)
+                um = u[k, j, i - 1] if i > 0 else ul[k, j]
+                vm = v[k, j - 1, i] if j > 0 else vl[k, i]
+                wm = w[k - 1, j, i] if k > 0 else wl[j, i]
+                ed = (u[k, j, i] - um) / dx + (v[k, j, i] - vm) / dy + (w[k, j, i] - wm) / dzf[k]
+                assert np.isclose(d[k, j, i], ed, rtol=1e-13, atol=1e-13)
+    rl = oracle.face_density_lower(np.arange(g.nx * g.ny * g.nz, dtype=float).reshape(g.shape), g)
+    assert np.array_equal(rl[0], np.arange(g.nx * g.ny * g.nz, dtype=float).reshape(g.shape)[:, :, 0])
+
+
+@pytest.mark.parametrize("bc", ["DDD", "DNDNDN", "DDPPND", "NNDNPP"])
+def test_projection_exact_divergence_lower_faces(bc):
+    """Lower outflow ends (the box of section 4 with zero-pressure outflow on
+    every side, 'DDD', among them): with the faces at -1/2 carried as planes,
+    the projection meets D u^{n+1} = s exactly, lower faces included."""
+    g = oracle.Grid(24, 16, 20, 1 / 24, 1 / 16, vofsynth.stretched_dz(20, 1.0, 1.3), bc)
+    us, vs, ws = vofsynth.random_faces(g.shape, 1, g.bc)
+    lower = _lower_planes(g, 7)
+    phat = vofsynth.gaussian_field(g.shape, 21)
+    C, _ = vofsynth.sphere_vof(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, seed=2)
+    rho = 1000.0 * C + 1.0 * (1 - C)
+    mag, _ = vofsynth.grad_mag_central(C, g.dx, g.dy, g.dzf, g.bc)
+    s = 1e-2 * mag
+    u, v, w, p, low = oracle.project(us, vs, ws, phat, rho, 1.0, s, 0.37, g, lower=lower)
+    d = oracle.div(u, v, w, g, low)
+    scale = np.abs(oracle.div(us, vs, ws, g, lower)).max()
+    assert np.abs(d - s).max() <= 1e-12 * scale
+    # the lower faces did change, by the correction with p = 0 on the face
+    gpl, ghl = oracle.grad_lower(p, g), oracle.grad_lower(phat, g)
+    rl = oracle.face_density_lower(rho, g)
+    for a, b, gp, gh, r in zip(low, lower, gpl, ghl, rl):
+        if a is not None:
+            want = b - 0.37 * (gp / 1.0 + (1.0 / r - 1.0) * gh)
+            assert np.abs(a - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_static_extension_lower_outflow():
+    """'DDD': u = G psi on every face (the lower faces from their planes) and
+    s = L_h psi: the extension returns phi = psi and u_1^e = 0, lower faces
+    included."""
+    g = oracle.Grid(16, 12, 20, 1 / 16, 1 / 12, vofsynth.stretched_dz(20, 1.0, 1.2), "DDD")
+    psi = vofsynth.gaussian_field(g.shape, 4)
+    u = oracle.grad(psi, g)
+    lower = oracle.grad_lower(psi, g)
+    s = oracle.lap(psi, g)
+    out = oracle.extend(u[0], u[1], u[2], s, g, lower=lower)
+    ue, ve, we, phi, low = out[0], out[1], out[2], out[6], out[7]
+    assert np.abs(phi - psi).max() <= 1e-11 * np.abs(psi).max()
+    scale = max(np.abs(a).max() for a in u)
+    for a in (ue, ve, we) + tuple(low):
+        assert np.abs(a).max() <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("axis,bc", [(2, "DNPPPP"), (0, "PPPPDN")])
+def test_projection_layered_lower_outflow_face_density(axis, bc):
+    """The layered closed form of the upper-outflow test, mirrored: a wall at
+    the upper end and an outflow at the lower end, u* = 0 (lower face too),
+    s = 0.  Every face velocity stays zero, so on the lower outflow face
+    p_0 = -(rho0/rho_0 - 1) p_hat_0 (rho of the first cell on that face) and
+    p_{i+1} = p_i - rho0 (1/rho_f - 1/rho0)(p_hat_{i+1} - p_hat_i)."""
+    n = 12
+    shape = [3, 4, 5]
+    shape[axis] = n
+    nz, ny, nx = shape
+    dzf = (np.random.default_rng(44).uniform(0.5, 1.5, nz) / nz if axis == 0
+           else np.full(nz, 1.0 / nz))
+    g = oracle.Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, dzf, bc)
+    r = np.random.default_rng(45 + axis)
+    rl = r.uniform(1.0, 50.0, n)
+    pl = r.standard_normal(n)
+    bshape = [1, 1, 1]
+    bshape[axis] = n
+    rho = np.broadcast_to(rl.reshape(bshape), g.shape).copy()
+    phat = np.broadcast_to(pl.reshape(bshape), g.shape).copy()
+    z = np.zeros(g.shape)
+    lower = tuple(None if lo != "D" else np.zeros(
+        {0: (g.nz, g.ny), 1: (g.nz, g.nx), 2: (g.ny, g.nx)}[d]) for d, (lo, _) in enumerate(g.ends))
+    rho0 = 1.0
+    u, v, w, p, low = oracle.project(z, z, z, phat, rho, rho0, z, 0.4, g, lower=lower)
+    expect = np.zeros(n)
+    expect[0] = -(rho0 / rl[0] - 1.0) * pl[0]
+    for i in range(n - 1):
+        rf = 0.5 * (rl[i] + rl[i + 1])
+        expect[i + 1] = expect[i] - rho0 * (1.0 / rf - 1.0 / rho0) * (pl[i + 1] - pl[i])
+    want = np.broadcast_to(expect.reshape(bshape), g.shape)
+    assert np.abs(p - want).max() <= 1e-11 * np.abs(expect).max()
+    for vel in (u, v, w) + tuple(a for a in low if a is not None):
+        assert np.abs(vel).max() <= 1e-10 * np.abs(pl).max() * n
