@@ -82,9 +82,12 @@ typedef struct poisson_plan poisson_plan;
  *            Every direction takes P or any pair of N and D (a wall at one
  *            end and an outflow at the other: a quarter-wave cosine
  *            transform in x and y, the tridiagonal pass in z).
- *            project, extend_liquid_velocity(_batched) and vof_step return
- *            VP_EUNSUPPORTED for a plan with an outflow at a lower end (the
- *            face -1/2 has no storage); the solves accept every combination;
+ *            The face at -1/2 of an outflow at a lower end has no slot in
+ *            the face arrays: project, extend_liquid_velocity(_batched) and
+ *            vof_step return VP_EUNSUPPORTED for such a plan, whose face
+ *            stencils take the velocities of those faces as planes through
+ *            project_lf, extend_liquid_velocity_lf and vof_step_lf; the
+ *            solves accept every combination;
  *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 transforms and
  *            FP32 tridiagonal storage with FP64 pivots, refined by FP64
  *            residual / defect-correction steps, see poisson_plan_set_mixed);
@@ -163,6 +166,32 @@ int project(poisson_plan* plan, double* u, double* v, double* w,
             const double* src, double dt, double* p, void* hip_stream);
 
 /*
+ * Velocities on the faces at -1/2 of the outflow ends at a lower end (the
+ * zero-pressure outflow boundaries of section 4 on every side of a box): the
+ * face arrays hold the faces i+1/2 .. n-1/2 only, so each such face set is a
+ * DEVICE plane of its own, caller-owned:
+ *   u : x = -1/2, ny*nz values, face (j, k) at j + ny*k;
+ *   v : y = -1/2, nx*nz values, face (i, k) at i + nx*k;
+ *   w : z = -1/2, nx*ny values, face (i, j) at i + nx*j.
+ * An input set holds a plane exactly for the directions whose lower end is an
+ * outflow (NULL for the others; VP_EINVAL otherwise); an output set may leave
+ * such a plane NULL (not written).  On those faces p, p_hat and phi are 0
+ * (G q = (q_first - 0) / (h/2), h the first cell's width) and rho is the first
+ * cell's, as at an upper outflow face.
+ */
+typedef struct vp_lower_faces {
+  double *u, *v, *w;
+} vp_lower_faces;
+
+/*
+ * project with the lower outflow faces' velocities: `lower` (in u*, out
+ * u^{n+1}, in place) as described above; otherwise as project.
+ */
+int project_lf(poisson_plan* plan, double* u, double* v, double* w,
+               const vp_lower_faces* lower, const double* phat, const double* rho,
+               double rho0, const double* src, double dt, double* p, void* hip_stream);
+
+/*
  * Liquid-velocity extension of section 3.6:
  *   phi = Poisson solve of src;  u_1^e = u - G phi;  u_Gamma = u_1^e - q.
  *   u, v, w   : device input velocity (one-fluid, after projection);
@@ -180,6 +209,19 @@ int extend_liquid_velocity(poisson_plan* plan, const double* u, const double* v,
                            double* ue, double* ve, double* we,
                            double* ug, double* vg, double* wg,
                            double* phi, void* hip_stream);
+
+/*
+ * extend_liquid_velocity with the lower outflow faces: `lower` (in, u on
+ * those faces) and `lower_e` (out, u_1^e there, which is also u_Gamma: q is 0
+ * on a non-periodic boundary face; may alias `lower`); otherwise as
+ * extend_liquid_velocity.
+ */
+int extend_liquid_velocity_lf(poisson_plan* plan, const double* u, const double* v,
+                              const double* w, const vp_lower_faces* lower,
+                              const double* src, const double* qx, const double* qy,
+                              const double* qz, double* ue, double* ve, double* we,
+                              const vp_lower_faces* lower_e, double* ug, double* vg,
+                              double* wg, double* phi, void* hip_stream);
 
 /* The device fields of one extension (same meaning as the arguments above). */
 typedef struct vp_extend_fields {
@@ -216,6 +258,19 @@ int vof_step(poisson_plan* plan, double* u, double* v, double* w, const double* 
              const double* src_ext, const double* qx, const double* qy, const double* qz,
              double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
              double* phi, void* hip_stream);
+
+/*
+ * vof_step with the lower outflow faces: `lower` (in u*, out u^{n+1}, in
+ * place) and `lower_e` (out u_1^e = u_Gamma on those faces, may be NULL);
+ * otherwise as vof_step.
+ */
+int vof_step_lf(poisson_plan* plan, double* u, double* v, double* w,
+                const vp_lower_faces* lower, const double* phat, const double* rho,
+                double rho0, const double* src_p, double dt, double* p,
+                const double* src_ext, const double* qx, const double* qy,
+                const double* qz, double* ue, double* ve, double* we,
+                const vp_lower_faces* lower_e, double* ug, double* vg, double* wg,
+                double* phi, void* hip_stream);
 
 /*
  * Interface terms from the volume fraction (section 3.2: the regularised
@@ -268,17 +323,19 @@ int interface_terms(poisson_plan* plan, const double* C, const double* mdot, dou
  *   C      : device volume fraction C^n (cell centres);
  *   ug,vg,wg : device interface velocity on the faces (u_Gamma of
  *            extend_liquid_velocity / vof_step), zero on wall faces;
+ *   lower  : u_Gamma on the faces at -1/2 of lower outflow ends (an input
+ *            set, see vp_lower_faces), NULL for a plan without them;
  *   dt > 0 : time step, with |V| dt at most the upwind cell's width along
  *            each sweep (one cell per step; larger steps are clamped to it);
  *   beta > 0 : sharpness of the tanh profile (1 is the usual choice);
  *   deflation : 1 (the paper's method) or 0;
  *   C_new  : device output C^{n+1} (must not alias C).
  * Uses workspace slot 0 of the plan (C** between the sweeps).  VP_EUNSUPPORTED
- * for a plan with an outflow at a lower end (the face -1/2 has no storage).
+ * for a plan with an outflow at a lower end and lower == NULL.
  */
 int vof_advect(poisson_plan* plan, const double* C, const double* ug, const double* vg,
-               const double* wg, double dt, double beta, int deflation, double* C_new,
-               void* hip_stream);
+               const double* wg, const vp_lower_faces* lower, double dt, double beta,
+               int deflation, double* C_new, void* hip_stream);
 
 /*
  * Mixed-precision control (plans created with VP_PRECISION_MIXED).  A mixed

@@ -81,6 +81,26 @@ class Plan:
             raise ValueError(f"{name} must be contiguous with shape {self.shape}")
         return ctypes.c_void_p(t.data_ptr())
 
+    def _lower(self, planes, name):
+        """vp_lower_faces from (x, y, z) device planes or None entries; None if
+        planes is None."""
+        import torch
+        if planes is None:
+            return None
+        nz, ny, nx = self.shape
+        shapes = ((nz, ny), (nz, nx), (ny, nx))
+        ptrs = []
+        for t, shp in zip(planes, shapes):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or \
+                    t.dtype != torch.float64 or tuple(t.shape) != shp or not t.is_contiguous():
+                raise ValueError(f"{name}: planes are contiguous float64 device tensors shaped "
+                                 f"{shapes}")
+            ptrs.append(t.data_ptr())
+        return ctypes.byref(_lib.LowerFaces(*ptrs))
+
     def _new(self, like):
         import torch
         return torch.empty(self.shape, dtype=torch.float64, device=like.device)
@@ -151,21 +171,30 @@ class Plan:
     def device_bytes(self) -> int:
         return int(_lib.lib.poisson_plan_device_bytes(self._h))
 
-    def project(self, u, v, w, phat, rho, rho0, src, dt, p=None, stream=None):
-        """In-place projection of (u, v, w) = u*; returns (u, v, w, p)."""
+    def project(self, u, v, w, phat, rho, rho0, src, dt, p=None, lower=None, stream=None):
+        """In-place projection of (u, v, w) = u*; returns (u, v, w, p).  `lower`:
+        (x, y, z) planes of the faces at -1/2 of lower outflow ends (None
+        elsewhere), updated in place (project_lf)."""
         if p is None:
             p = self._new(u)
-        check(_lib.lib.project(self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
-                               self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
-                               self._ptr(src, "src", optional=True), float(dt),
-                               self._ptr(p, "p"), _stream_ptr(stream)), "project")
+        args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w")]
+        rest = [self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
+                self._ptr(src, "src", optional=True), float(dt), self._ptr(p, "p"),
+                _stream_ptr(stream)]
+        if lower is None:
+            check(_lib.lib.project(*args, *rest), "project")
+        else:
+            check(_lib.lib.project_lf(*args, self._lower(lower, "lower"), *rest), "project_lf")
         return u, v, w, p
 
-    def extend(self, u, v, w, src, q=None, out=None, gamma=None, phi=None, stream=None):
+    def extend(self, u, v, w, src, q=None, out=None, gamma=None, phi=None, lower=None,
+               lower_out=None, stream=None):
         """u_1^e = u - G phi (phi = L^+ src), u_Gamma = u_1^e - q.
 
         Returns (ue, ve, we, ug, vg, wg, phi); the u_Gamma entries are None
-        without q.
+        without q.  `lower` / `lower_out`: (x, y, z) planes of u and of u_1^e
+        (= u_Gamma) on the faces at -1/2 of lower outflow ends
+        (extend_liquid_velocity_lf).
         """
         if out is None:
             out = (self._new(u), self._new(u), self._new(u))
@@ -177,11 +206,17 @@ class Plan:
         gs = (None, None, None) if gamma is None else gamma
         args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
                 self._ptr(src, "src")]
-        args += [self._ptr(t, "q", optional=True) for t in qs]
-        args += [self._ptr(t, "out") for t in out]
-        args += [self._ptr(t, "gamma", optional=True) for t in gs]
-        args += [self._ptr(phi, "phi", optional=True), _stream_ptr(stream)]
-        check(_lib.lib.extend_liquid_velocity(*args), "extend_liquid_velocity")
+        qa = [self._ptr(t, "q", optional=True) for t in qs]
+        oa = [self._ptr(t, "out") for t in out]
+        ga = [self._ptr(t, "gamma", optional=True) for t in gs]
+        tail = [self._ptr(phi, "phi", optional=True), _stream_ptr(stream)]
+        if lower is None and lower_out is None:
+            check(_lib.lib.extend_liquid_velocity(*args, *qa, *oa, *ga, *tail),
+                  "extend_liquid_velocity")
+        else:
+            check(_lib.lib.extend_liquid_velocity_lf(
+                args[0], args[1], args[2], args[3], self._lower(lower, "lower"), args[4], *qa, *oa,
+                self._lower(lower_out, "lower_out"), *ga, *tail), "extend_liquid_velocity_lf")
         return (*out, *gs, phi)
 
     def interface_terms(self, C, mdot, rho1, rho2, phase=1, out=None, stream=None):
@@ -196,22 +231,27 @@ class Plan:
         check(_lib.lib.interface_terms(*args, _stream_ptr(stream)), "interface_terms")
         return tuple(out)
 
-    def advect(self, C, ug, vg, wg, dt, beta=1.0, deflation=True, out=None, stream=None):
+    def advect(self, C, ug, vg, wg, dt, beta=1.0, deflation=True, out=None, lower=None,
+               stream=None):
         """C^{n+1} from C^n and the interface velocity on the faces (vof_advect:
-        directional split, MTHINC flux, volume deflation when `deflation`)."""
+        directional split, MTHINC flux, volume deflation when `deflation`);
+        `lower`: the interface velocity's (x, y, z) planes at lower outflow ends."""
         if out is None:
             out = self._new(C)
         check(_lib.lib.vof_advect(self._h, self._ptr(C, "C"), self._ptr(ug, "ug"),
-                                  self._ptr(vg, "vg"), self._ptr(wg, "wg"), float(dt),
-                                  float(beta), 1 if deflation else 0, self._ptr(out, "out"),
+                                  self._ptr(vg, "vg"), self._ptr(wg, "wg"),
+                                  self._lower(lower, "lower"), float(dt), float(beta),
+                                  1 if deflation else 0, self._ptr(out, "out"),
                                   _stream_ptr(stream)), "vof_advect")
         return out
 
     def step(self, u, v, w, phat, rho, rho0, src_p, dt, src_ext, p=None, phi=None, q=None,
-             out=None, gamma=None, stream=None):
+             out=None, gamma=None, lower=None, lower_e=None, stream=None):
         """One time step: projection of (u, v, w) = u* (in place) and extension of the
         projected velocity.  Returns (u, v, w, p, phi, ue, ve, we, ug, vg, wg); ue.. are
-        None unless `out` is given, ug.. None without q."""
+        None unless `out` is given, ug.. None without q.  `lower` (in u*, out u^{n+1})
+        and `lower_e` (out u_1^e = u_Gamma): (x, y, z) planes of the faces at -1/2 of
+        lower outflow ends (vof_step_lf)."""
         if p is None:
             p = self._new(u)
         if phi is None:
@@ -221,15 +261,19 @@ class Plan:
         qs = (None, None, None) if q is None else q
         es = (None, None, None) if out is None else out
         gs = (None, None, None) if gamma is None else gamma
-        args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
-                self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
-                self._ptr(src_p, "src_p", optional=True), float(dt), self._ptr(p, "p"),
-                self._ptr(src_ext, "src_ext")]
-        args += [self._ptr(t, "q", optional=True) for t in qs]
-        args += [self._ptr(t, "out", optional=True) for t in es]
-        args += [self._ptr(t, "gamma", optional=True) for t in gs]
-        args += [self._ptr(phi, "phi"), _stream_ptr(stream)]
-        check(_lib.lib.vof_step(*args), "vof_step")
+        head = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w")]
+        mid = [self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0),
+               self._ptr(src_p, "src_p", optional=True), float(dt), self._ptr(p, "p"),
+               self._ptr(src_ext, "src_ext")]
+        mid += [self._ptr(t, "q", optional=True) for t in qs]
+        ea = [self._ptr(t, "out", optional=True) for t in es]
+        tail = [self._ptr(t, "gamma", optional=True) for t in gs]
+        tail += [self._ptr(phi, "phi"), _stream_ptr(stream)]
+        if lower is None and lower_e is None:
+            check(_lib.lib.vof_step(*head, *mid, *ea, *tail), "vof_step")
+        else:
+            check(_lib.lib.vof_step_lf(*head, self._lower(lower, "lower"), *mid, *ea,
+                                       self._lower(lower_e, "lower_e"), *tail), "vof_step_lf")
         return (u, v, w, p, phi, *es, *gs)
 
     def set_mixed(self, dc_steps: int, tol=None):

@@ -37,6 +37,13 @@ class ExtendFields(ctypes.Structure):
                  "phi")]
 
 
+class LowerFaces(ctypes.Structure):
+    """vp_lower_faces: device planes of the faces at -1/2 of lower outflow ends."""
+    _fields_ = [(n, ctypes.c_void_p) for n in ("u", "v", "w")]
+
+
+_lf = ctypes.POINTER(LowerFaces)
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "poisson_plan_create": (_p, [_i, _i, _i, _d, _d, ctypes.POINTER(_d), ctypes.c_char_p, _i, _i,
@@ -51,7 +58,12 @@ SIGNATURES = {
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "interface_terms": (_i, [_p, _p, _p, _d, _d, _i, _p, _p, _p, _p, _p]),
-    "vof_advect": (_i, [_p, _p, _p, _p, _p, _d, _d, _i, _p, _p]),
+    "vof_advect": (_i, [_p, _p, _p, _p, _p, _lf, _d, _d, _i, _p, _p]),
+    "project_lf": (_i, [_p, _p, _p, _p, _lf, _p, _p, _d, _p, _d, _p, _p]),
+    "extend_liquid_velocity_lf": (_i, [_p, _p, _p, _p, _lf, _p, _p, _p, _p, _p, _p, _p, _lf,
+                                       _p, _p, _p, _p, _p]),
+    "vof_step_lf": (_i, [_p, _p, _p, _p, _lf, _p, _p, _d, _p, _d, _p, _p, _p, _p, _p, _p, _p, _p,
+                         _lf, _p, _p, _p, _p, _p]),
     "poisson_plan_set_mixed": (_i, [_p, _i]),
     "poisson_plan_set_mixed_tol": (_i, [_p, _d]),
     "poisson_plan_mixed_report": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_d), _p]),

@@ -18,7 +18,9 @@
 // dt, the last xi = |V| dt / h of it (clamped to 1).  Cells with C within
 // 1e-8 of 0 or 1, or a change of C across the cell below 1e-12, are uniform
 // (H = C); ghost cells beyond a non-periodic end are uniform with the end
-// cell's C.
+// cell's C.  The face at -1/2 of a lower outflow end takes its velocity
+// from a plane (x: (j, k) at j + ny k; y: (i, k) at i + nx k; z: (i, j) at
+// i + nx j).
 //
 // Launch shape: one thread per cell, 256 per block.  Every face flux is
 // computed once and used by both cells sharing the face (LDS within the x and
@@ -252,7 +254,9 @@ __device__ __forceinline__ void update_cell(const GridArgs& g, const double* __r
                                             double vup, double flo, double fup, double* out,
                                             double dt, int deflation, const double* C1,
                                             const double* __restrict__ u,
-                                            const double* __restrict__ v) {
+                                            const double* __restrict__ v,
+                                            const double* __restrict__ lox,
+                                            const double* __restrict__ loy) {
 #pragma clang fp contract(off)
   const double delta = (vup - vlo) / h;
   const double cn = (C[idx] - (fup - flo) / h) / (1.0 - dt * delta);
@@ -260,10 +264,14 @@ __device__ __forceinline__ void update_cell(const GridArgs& g, const double* __r
     out[idx] = cn;
     return;
   }
+  const long P = (long)g.nx * g.ny, k = idx / P;
   const double uup = u[idx];
-  const double ulo = i > 0 ? u[idx - 1] : (g.bcx == 0 ? u[idx + g.nx - 1] : 0.0);
+  const double ulo = i > 0 ? u[idx - 1]
+                           : (g.bcx == 0 ? u[idx + g.nx - 1] : (lox ? lox[j + (long)g.ny * k] : 0.0));
   const double wy = v[idx];
-  const double wyl = j > 0 ? v[idx - g.nx] : (g.bcy == 0 ? v[idx + (long)(g.ny - 1) * g.nx] : 0.0);
+  const double wyl = j > 0 ? v[idx - g.nx]
+                           : (g.bcy == 0 ? v[idx + (long)(g.ny - 1) * g.nx]
+                                         : (loy ? loy[i + (long)g.nx * k] : 0.0));
   const double ddx = (uup - ulo) / g.dx, ddy = (wy - wyl) / g.dy;
   const double F = C1[idx] * ddx + C[idx] * ddy + cn * delta;
   const double r = cn - dt * F;
@@ -278,6 +286,7 @@ template <int AX>
 __global__ __launch_bounds__(256) void k_adv_xy(const GridArgs g, int tx,
                                                const double* __restrict__ C,
                                                const double* __restrict__ V,
+                                               const double* __restrict__ lo,
                                                double* __restrict__ out, double dt, double beta) {
 #pragma clang fp contract(off)
   __shared__ double fl[256 + 64];
@@ -301,14 +310,17 @@ __global__ __launch_bounds__(256) void k_adv_xy(const GridArgs g, int tx,
   double vup = 0.0, vlo = 0.0;
   if (own) {
     vup = V[idx];
-    vlo = s > 0 ? V[idx - stride] : (per ? V[idx + (long)(n - 1) * stride] : 0.0);
+    // the face at -1/2: wrapped, a lower outflow face (its plane), or a wall
+    const long lof = AX == 0 ? j + (long)g.ny * k : i + (long)g.nx * k;
+    vlo = s > 0 ? V[idx - stride]
+                : (per ? V[idx + (long)(n - 1) * stride] : (lo ? lo[lof] : 0.0));
     fl[up_slot] = face_flux<AX>(g, C, s + 1, i, j, k, vup, dt, beta);
     if (first) fl[lo_slot] = face_flux<AX>(g, C, s, i, j, k, vlo, dt, beta);
   }
   __syncthreads();
   if (!own) return;
   update_cell<AX, false>(g, C, idx, i, j, width<AX>(g, 0), vlo, vup, fl[lo_slot], fl[up_slot], out,
-                         dt, 0, nullptr, nullptr, nullptr);
+                         dt, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 // z sweep with the final correction: a TX x TY tile of the x-y plane marching
@@ -320,7 +332,10 @@ __global__ __launch_bounds__(256) void k_adv_z(const GridArgs g, int tx, int kc,
                                               const double* __restrict__ W, double* out,
                                               double dt, double beta, int deflation,
                                               const double* C1, const double* __restrict__ u,
-                                              const double* __restrict__ v) {
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ lox,
+                                              const double* __restrict__ loy,
+                                              const double* __restrict__ loz) {
 #pragma clang fp contract(off)
   const int ltx = __builtin_ctz(tx);
   const int ty = 256 >> ltx;
@@ -331,14 +346,15 @@ __global__ __launch_bounds__(256) void k_adv_z(const GridArgs g, int tx, int kc,
   const bool per = g.bcz == 0;
   const long P = (long)g.nx * g.ny;
   const long col = (long)i + (long)g.nx * j;
-  double vlo = kb > 0 ? W[col + (long)(kb - 1) * P] : (per ? W[col + (long)(g.nz - 1) * P] : 0.0);
+  double vlo = kb > 0 ? W[col + (long)(kb - 1) * P]
+                      : (per ? W[col + (long)(g.nz - 1) * P] : (loz ? loz[col] : 0.0));
   double flo = face_flux<2>(g, C, kb, i, j, kb, vlo, dt, beta);
   for (int k = kb; k < ke; ++k) {
     const long idx = col + (long)k * P;
     const double vup = W[idx];
     const double fup = face_flux<2>(g, C, k + 1, i, j, k, vup, dt, beta);
     update_cell<2, true>(g, C, idx, i, j, g.dzf[k], vlo, vup, flo, fup, out, dt, deflation, C1, u,
-                         v);
+                         v, lox, loy);
     vlo = vup;
     flo = fup;
   }
@@ -347,8 +363,8 @@ __global__ __launch_bounds__(256) void k_adv_z(const GridArgs g, int tx, int kc,
 }  // namespace
 
 hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
-                         const double* wg, double dt, double beta, int deflation, double* work,
-                         double* out, int sweep, hipStream_t st) {
+                         const double* wg, const double* const* lo, double dt, double beta,
+                         int deflation, double* work, double* out, int sweep, hipStream_t st) {
   if (g.txp < 1 || g.nx % g.txp) return hipErrorInvalidValue;
   // x sweep: 64-wide tiles (rows of faces, one extra face per row); y sweep:
   // 16-wide tiles, 16 rows (one extra row of faces per 16); z sweep: 64 x 4
@@ -359,14 +375,14 @@ hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, c
   // x: C -> out (C*); y: out -> work (C**); z: work -> out (C^{n+1}), with C* read from out
   if (sweep == 0) {
     hipLaunchKernelGGL((k_adv_xy<0>), dim3(bx, by, (unsigned)g.nz), dim3(256), 0, st, g, tx, C, ug,
-                       out, dt, beta);
+                       lo[0], out, dt, beta);
   } else if (sweep == 1) {
     hipLaunchKernelGGL((k_adv_xy<1>), dim3(bx, by, (unsigned)g.nz), dim3(256), 0, st, g, tx, out,
-                       vg, work, dt, beta);
+                       vg, lo[1], work, dt, beta);
   } else {
     const int kc = g.nz < 16 ? g.nz : 16;
     hipLaunchKernelGGL(k_adv_z, dim3(bx, by, (unsigned)((g.nz + kc - 1) / kc)), dim3(256), 0, st, g,
-                       tx, kc, work, wg, out, dt, beta, deflation, out, ug, vg);
+                       tx, kc, work, wg, out, dt, beta, deflation, out, ug, vg, lo[0], lo[1], lo[2]);
   }
   return hipGetLastError();
 }

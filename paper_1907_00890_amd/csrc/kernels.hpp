@@ -177,13 +177,21 @@ constexpr int kInterfaceThreads = 512;
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st);
+// Faces at -1/2 of a lower outflow end in direction dir (0 x, 1 y, 2 z):
+// their velocities uf (and ue on them, uef) as one plane; see stencils.hip.
+enum : int { LF_RHS = 0, LF_CORRECT = 1, LF_EXTEND = 2, LF_STEP = 3 };
+hipError_t launch_lower_faces(const GridArgs& g, int mode, int dir, double* uf, double* uef,
+                              double* b, const double* p, const double* ph, const double* rho,
+                              double rho0, double dt, const double* phi, hipStream_t st);
 // advect.hip: VoF advection of section 3.1 (directional split, MTHINC flux,
 // volume deflation).  sweep 0: x sweep C -> out; 1: y sweep out -> work;
 // 2: z sweep work -> out with the final correction (C* read back from out).
 // g.txp sets the tile width (one thread per cell, 256 per block).
+// lo[d]: the interface velocity on the faces at -1/2 of a lower outflow end
+// in direction d (a plane, as for launch_lower_faces), null elsewhere.
 hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
-                         const double* wg, double dt, double beta, int deflation, double* work,
-                         double* out, int sweep, hipStream_t st);
+                         const double* wg, const double* const* lo, double dt, double beta,
+                         int deflation, double* work, double* out, int sweep, hipStream_t st);
 // r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
 // r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);

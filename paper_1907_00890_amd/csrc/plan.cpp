@@ -621,28 +621,52 @@ int poisson_solve_noalloc(poisson_plan* P, const double* rhs, double* sol, void*
 
 namespace {
 // The face stencils hold one face per cell and direction (the upper one): an
-// outflow face at a lower end, whose velocity is free, has no storage.
+// outflow face at a lower end, whose velocity is free, lives in a plane of
+// its own (vp_lower_faces), which only the _lf entry points take.
+bool lower_out(const poisson_plan* P, int d) { return P->ends[2 * d] == 'D'; }
 bool faces_stored(const poisson_plan* P) {
-  return P->ends[0] != 'D' && P->ends[2] != 'D' && P->ends[4] != 'D';
+  return !lower_out(P, 0) && !lower_out(P, 1) && !lower_out(P, 2);
 }
-}  // namespace
+double* lf_plane(const vp_lower_faces* lf, int d) {
+  return lf ? (d == 0 ? lf->u : (d == 1 ? lf->v : lf->w)) : nullptr;
+}
+// an input / in-out set: a plane exactly for the lower outflow ends
+bool lower_in_ok(const poisson_plan* P, const vp_lower_faces* lf) {
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d) != (lf_plane(lf, d) != nullptr)) return false;
+  return true;
+}
+// an output set: planes only at lower outflow ends (null: not written)
+bool lower_out_ok(const poisson_plan* P, const vp_lower_faces* lf) {
+  for (int d = 0; d < 3; ++d)
+    if (!lower_out(P, d) && lf_plane(lf, d)) return false;
+  return true;
+}
 
-int project(poisson_plan* P, double* u, double* v, double* w, const double* phat,
-            const double* rho, double rho0, const double* src, double dt, double* p,
-            void* stream) {
-  if (!P || !u || !v || !w || !phat || !rho || !p || !(rho0 > 0) || !(dt > 0)) return VP_EINVAL;
-  if (!faces_stored(P)) return VP_EUNSUPPORTED;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+int project_impl(poisson_plan* P, double* u, double* v, double* w, const vp_lower_faces* lf,
+                 const double* phat, const double* rho, double rho0, const double* src, double dt,
+                 double* p, hipStream_t st) {
   // mixed precision keeps the FP64 right-hand side for its residuals
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src, dt, b, st), "rhs assembly", st);
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d))
+      VP_LAUNCH(P, K_RHS,
+                vp::launch_lower_faces(P->g, vp::LF_RHS, d, lf_plane(lf, d), nullptr, b, nullptr,
+                                       phat, rho, rho0, dt, nullptr, st),
+                "rhs lower faces", st);
   int s = solve_one(P, b, p, st);
   if (s) return s;
   VP_LAUNCH(P, K_CORRECT, vp::launch_correct(P->gs, u, v, w, p, phat, rho, rho0, dt, st), "correction", st);
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d))
+      VP_LAUNCH(P, K_CORRECT,
+                vp::launch_lower_faces(P->g, vp::LF_CORRECT, d, lf_plane(lf, d), nullptr, nullptr, p,
+                                       phat, rho, rho0, dt, nullptr, st),
+                "correction lower faces", st);
   return VP_OK;
 }
 
-namespace {
 int check_extend(const vp_extend_fields& a) {
   if (!a.u || !a.v || !a.w || !a.src || !a.ue || !a.ve || !a.we) return VP_EINVAL;
   const bool hq = a.qx && a.qy && a.qz, hg = a.ug && a.vg && a.wg;
@@ -651,12 +675,11 @@ int check_extend(const vp_extend_fields& a) {
   if (hq != hg) return VP_EINVAL;
   return VP_OK;
 }
-}  // namespace
 
-int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_fields* a,
-                                   void* stream) {
-  if (!P || !a || n < 0 || n > P->max_batch) return VP_EINVAL;
-  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+// n extensions; with n == 1, lin / lout are the member's lower-face planes
+// (u in, u_1^e out) at lower outflow ends
+int extend_impl(poisson_plan* P, int n, const vp_extend_fields* a, const vp_lower_faces* lin,
+                const vp_lower_faces* lout, hipStream_t st) {
   const long N = P->npts();
   const double* rhs[vp::kMaxBatch];
   double* phi[vp::kMaxBatch];
@@ -670,7 +693,6 @@ int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_field
     }
   }
   if (n == 0) return VP_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   int s = solve_any(P, n, rhs, phi, st);
   if (s) return s;
   for (int b = 0; b < n; ++b)
@@ -678,36 +700,29 @@ int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_field
               vp::launch_extend(P->gs, a[b].u, a[b].v, a[b].w, phi[b], a[b].qx, a[b].qy, a[b].qz,
                                 a[b].ue, a[b].ve, a[b].we, a[b].ug, a[b].vg, a[b].wg, st),
               "extension", st);
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d) && lf_plane(lout, d))
+      VP_LAUNCH(P, K_EXTEND,
+                vp::launch_lower_faces(P->g, vp::LF_EXTEND, d, lf_plane(lin, d), lf_plane(lout, d),
+                                       nullptr, nullptr, nullptr, nullptr, 1.0, 1.0, phi[0], st),
+                "extension lower faces", st);
   return VP_OK;
 }
 
-int extend_liquid_velocity(poisson_plan* P, const double* u, const double* v, const double* w,
-                           const double* src, const double* qx, const double* qy,
-                           const double* qz, double* ue, double* ve, double* we, double* ug,
-                           double* vg, double* wg, double* phi, void* stream) {
-  if (!P) return VP_EINVAL;
-  const vp_extend_fields a = {u, v, w, src, qx, qy, qz, ue, ve, we, ug, vg, wg, phi};
-  return extend_liquid_velocity_batched(P, 1, &a, stream);
-}
-
-int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* phat,
-             const double* rho, double rho0, const double* src_p, double dt, double* p,
-             const double* src_ext, const double* qx, const double* qy, const double* qz,
-             double* ue, double* ve, double* we, double* ug, double* vg, double* wg, double* phi,
-             void* stream) {
-  if (!P || !u || !v || !w || !phat || !rho || !p || !src_ext || !phi || !(rho0 > 0) || !(dt > 0))
-    return VP_EINVAL;
-  const bool hq = qx && qy && qz, hg = ug && vg && wg, he = ue && ve && we;
-  if ((qx || qy || qz) && !hq) return VP_EINVAL;
-  if ((ug || vg || wg) && !hg) return VP_EINVAL;
-  if ((ue || ve || we) && !he) return VP_EINVAL;
-  if (hq != hg) return VP_EINVAL;
-  if (phi == p) return VP_EINVAL;
-  if (!faces_stored(P)) return VP_EUNSUPPORTED;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+int step_impl(poisson_plan* P, double* u, double* v, double* w, const vp_lower_faces* lf,
+              const double* phat, const double* rho, double rho0, const double* src_p, double dt,
+              double* p, const double* src_ext, const double* qx, const double* qy,
+              const double* qz, double* ue, double* ve, double* we, const vp_lower_faces* lfe,
+              double* ug, double* vg, double* wg, double* phi, hipStream_t st) {
   double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),
             "rhs assembly", st);
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d))
+      VP_LAUNCH(P, K_RHS,
+                vp::launch_lower_faces(P->g, vp::LF_RHS, d, lf_plane(lf, d), nullptr, b, nullptr,
+                                       phat, rho, rho0, dt, nullptr, st),
+                "rhs lower faces", st);
   // the Stefan potential does not depend on the pressure: with room for two
   // fields both solves run as one batch (one launch per pass, the same bits)
   int s;
@@ -724,7 +739,100 @@ int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* pha
             vp::launch_step_epilogue(P->ge, u, v, w, p, phat, rho, rho0, dt, phi, qx, qy, qz, ue,
                                      ve, we, ug, vg, wg, st),
             "step epilogue", st);
+  for (int d = 0; d < 3; ++d)
+    if (lower_out(P, d))
+      VP_LAUNCH(P, K_EPILOGUE,
+                vp::launch_lower_faces(P->g, vp::LF_STEP, d, lf_plane(lf, d), lf_plane(lfe, d),
+                                       nullptr, p, phat, rho, rho0, dt, phi, st),
+                "step lower faces", st);
   return VP_OK;
+}
+
+int check_step(double* u, double* v, double* w, const double* phat, const double* rho,
+               double rho0, double dt, double* p, const double* src_ext, const double* qx,
+               const double* qy, const double* qz, double* ue, double* ve, double* we,
+               double* ug, double* vg, double* wg, double* phi) {
+  if (!u || !v || !w || !phat || !rho || !p || !src_ext || !phi || !(rho0 > 0) || !(dt > 0))
+    return VP_EINVAL;
+  const bool hq = qx && qy && qz, hg = ug && vg && wg, he = ue && ve && we;
+  if ((qx || qy || qz) && !hq) return VP_EINVAL;
+  if ((ug || vg || wg) && !hg) return VP_EINVAL;
+  if ((ue || ve || we) && !he) return VP_EINVAL;
+  if (hq != hg) return VP_EINVAL;
+  if (phi == p) return VP_EINVAL;
+  return VP_OK;
+}
+}  // namespace
+
+int project(poisson_plan* P, double* u, double* v, double* w, const double* phat,
+            const double* rho, double rho0, const double* src, double dt, double* p,
+            void* stream) {
+  if (!P || !u || !v || !w || !phat || !rho || !p || !(rho0 > 0) || !(dt > 0)) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  return project_impl(P, u, v, w, nullptr, phat, rho, rho0, src, dt, p,
+                      static_cast<hipStream_t>(stream));
+}
+
+int project_lf(poisson_plan* P, double* u, double* v, double* w, const vp_lower_faces* lower,
+               const double* phat, const double* rho, double rho0, const double* src, double dt,
+               double* p, void* stream) {
+  if (!P || !u || !v || !w || !phat || !rho || !p || !(rho0 > 0) || !(dt > 0)) return VP_EINVAL;
+  if (!lower_in_ok(P, lower)) return VP_EINVAL;
+  return project_impl(P, u, v, w, lower, phat, rho, rho0, src, dt, p,
+                      static_cast<hipStream_t>(stream));
+}
+
+int extend_liquid_velocity_batched(poisson_plan* P, int n, const vp_extend_fields* a,
+                                   void* stream) {
+  if (!P || !a || n < 0 || n > P->max_batch) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  return extend_impl(P, n, a, nullptr, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int extend_liquid_velocity(poisson_plan* P, const double* u, const double* v, const double* w,
+                           const double* src, const double* qx, const double* qy,
+                           const double* qz, double* ue, double* ve, double* we, double* ug,
+                           double* vg, double* wg, double* phi, void* stream) {
+  if (!P) return VP_EINVAL;
+  const vp_extend_fields a = {u, v, w, src, qx, qy, qz, ue, ve, we, ug, vg, wg, phi};
+  return extend_liquid_velocity_batched(P, 1, &a, stream);
+}
+
+int extend_liquid_velocity_lf(poisson_plan* P, const double* u, const double* v, const double* w,
+                              const vp_lower_faces* lower, const double* src, const double* qx,
+                              const double* qy, const double* qz, double* ue, double* ve,
+                              double* we, const vp_lower_faces* lower_e, double* ug, double* vg,
+                              double* wg, double* phi, void* stream) {
+  if (!P || !lower_in_ok(P, lower) || !lower_out_ok(P, lower_e)) return VP_EINVAL;
+  const vp_extend_fields a = {u, v, w, src, qx, qy, qz, ue, ve, we, ug, vg, wg, phi};
+  return extend_impl(P, 1, &a, lower, lower_e, static_cast<hipStream_t>(stream));
+}
+
+int vof_step(poisson_plan* P, double* u, double* v, double* w, const double* phat,
+             const double* rho, double rho0, const double* src_p, double dt, double* p,
+             const double* src_ext, const double* qx, const double* qy, const double* qz,
+             double* ue, double* ve, double* we, double* ug, double* vg, double* wg, double* phi,
+             void* stream) {
+  if (!P || check_step(u, v, w, phat, rho, rho0, dt, p, src_ext, qx, qy, qz, ue, ve, we, ug, vg,
+                       wg, phi))
+    return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  return step_impl(P, u, v, w, nullptr, phat, rho, rho0, src_p, dt, p, src_ext, qx, qy, qz, ue, ve,
+                   we, nullptr, ug, vg, wg, phi, static_cast<hipStream_t>(stream));
+}
+
+int vof_step_lf(poisson_plan* P, double* u, double* v, double* w, const vp_lower_faces* lower,
+                const double* phat, const double* rho, double rho0, const double* src_p,
+                double dt, double* p, const double* src_ext, const double* qx, const double* qy,
+                const double* qz, double* ue, double* ve, double* we,
+                const vp_lower_faces* lower_e, double* ug, double* vg, double* wg, double* phi,
+                void* stream) {
+  if (!P || check_step(u, v, w, phat, rho, rho0, dt, p, src_ext, qx, qy, qz, ue, ve, we, ug, vg,
+                       wg, phi))
+    return VP_EINVAL;
+  if (!lower_in_ok(P, lower) || !lower_out_ok(P, lower_e)) return VP_EINVAL;
+  return step_impl(P, u, v, w, lower, phat, rho, rho0, src_p, dt, p, src_ext, qx, qy, qz, ue, ve,
+                   we, lower_e, ug, vg, wg, phi, static_cast<hipStream_t>(stream));
 }
 
 int interface_terms(poisson_plan* P, const double* C, const double* mdot, double rho1,
@@ -742,20 +850,20 @@ int interface_terms(poisson_plan* P, const double* C, const double* mdot, double
 }
 
 int vof_advect(poisson_plan* P, const double* C, const double* ug, const double* vg,
-               const double* wg, double dt, double beta, int deflation, double* C_new,
-               void* stream) {
+               const double* wg, const vp_lower_faces* lower, double dt, double beta,
+               int deflation, double* C_new, void* stream) {
   if (!P || !C || !ug || !vg || !wg || !C_new || C_new == C || !(dt > 0) || !(beta > 0) ||
       (deflation != 0 && deflation != 1))
     return VP_EINVAL;
-  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  if (!lower_in_ok(P, lower)) return faces_stored(P) ? VP_EINVAL : VP_EUNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const double* lo[3] = {lf_plane(lower, 0), lf_plane(lower, 1), lf_plane(lower, 2)};
   // C** of the y sweep lives in workspace slot 0
-  VP_LAUNCH(P, K_ADV_X, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 0, st),
-            "advect x", st);
-  VP_LAUNCH(P, K_ADV_Y, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 1, st),
-            "advect y", st);
-  VP_LAUNCH(P, K_ADV_Z, vp::launch_advect(P->gs, C, ug, vg, wg, dt, beta, deflation, P->work64, C_new, 2, st),
-            "advect z", st);
+  for (int sw = 0; sw < 3; ++sw)
+    VP_LAUNCH(P, K_ADV_X + sw,
+              vp::launch_advect(P->gs, C, ug, vg, wg, lo, dt, beta, deflation, P->work64, C_new,
+                                sw, st),
+              "advect sweep", st);
   return VP_OK;
 }
 

@@ -1230,3 +1230,77 @@ hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, do
 }
 
 }  // namespace vp
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// Faces at -1/2 of a lower outflow end (p = 0 on the face, half a cell before
+// the first centre).  Their velocities live in one plane per direction
+// (x: (j, k) at j + ny k; y: (i, k) at i + nx k; z: (i, j) at i + nx j); the
+// face stencils above treat the lower end as a wall, and these kernels add
+// what the outflow face changes, one launch per direction (a corner cell
+// takes the terms of every direction in turn):
+//   LF_RHS     b_c += -rho0 f / h - (rho0 / dt) u*_f / h,
+//              f = (1/rho0 - 1/rho_c) G p_hat (rho on the face: the first cell's);
+//   LF_CORRECT u_f <- u*_f - dt [ (1/rho0) G p + (1/rho_c - 1/rho0) G p_hat ];
+//   LF_EXTEND  ue_f = u_f - G phi;
+//   LF_STEP    LF_CORRECT, then ue_f from the corrected u_f;
+// G q = (q_c - 0) / (h / 2) with h the first cell's width (dx, dy, dzf[0]).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_lower_faces(
+    const GridArgs g, int dir, double* __restrict__ uf, double* __restrict__ uef,
+    double* __restrict__ b, const double* __restrict__ p, const double* __restrict__ ph,
+    const double* __restrict__ rho, double rho0, double dt, const double* __restrict__ phi) {
+#pragma clang fp contract(off)
+  const long n1 = dir == 0 ? g.ny : g.nx, n2 = dir == 2 ? g.ny : g.nz;
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n1 * n2) return;
+  const long a = t % n1, c2 = t / n1;
+  const long P = (long)g.nx * g.ny;
+  // the first cell behind the face
+  const long c = dir == 0 ? a * g.nx + c2 * P : (dir == 1 ? a + c2 * P : a + c2 * g.nx);
+  const double h = dir == 0 ? g.dx : (dir == 1 ? g.dy : g.dzf[0]);
+  const double ih = 1.0 / h, ir0 = 1.0 / rho0;
+  if (MODE == LF_RHS) {
+    const double f = (ir0 - 1.0 / rho[c]) * (2.0 * ph[c] * ih);
+    b[c] = b[c] + (-rho0 * f * ih - (rho0 / dt) * uf[t] * ih);
+    return;
+  }
+  double u = uf[t];
+  if (MODE == LF_CORRECT || MODE == LF_STEP) {
+    u = u - dt * (ir0 * (2.0 * p[c] * ih) + (1.0 / rho[c] - ir0) * (2.0 * ph[c] * ih));
+    uf[t] = u;
+  }
+  if ((MODE == LF_EXTEND || MODE == LF_STEP) && uef) uef[t] = u - 2.0 * phi[c] * ih;
+}
+
+hipError_t launch_lower_faces(const GridArgs& g, int mode, int dir, double* uf, double* uef,
+                              double* b, const double* p, const double* ph, const double* rho,
+                              double rho0, double dt, const double* phi, hipStream_t st) {
+  const long n = (dir == 0 ? (long)g.ny : (long)g.nx) * (dir == 2 ? (long)g.ny : (long)g.nz);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  switch (mode) {
+    case LF_RHS:
+      hipLaunchKernelGGL(k_lower_faces<LF_RHS>, grid, dim3(256), 0, st, g, dir, uf, uef, b, p, ph,
+                         rho, rho0, dt, phi);
+      break;
+    case LF_CORRECT:
+      hipLaunchKernelGGL(k_lower_faces<LF_CORRECT>, grid, dim3(256), 0, st, g, dir, uf, uef, b, p,
+                         ph, rho, rho0, dt, phi);
+      break;
+    case LF_EXTEND:
+      hipLaunchKernelGGL(k_lower_faces<LF_EXTEND>, grid, dim3(256), 0, st, g, dir, uf, uef, b, p,
+                         ph, rho, rho0, dt, phi);
+      break;
+    case LF_STEP:
+      hipLaunchKernelGGL(k_lower_faces<LF_STEP>, grid, dim3(256), 0, st, g, dir, uf, uef, b, p, ph,
+                         rho, rho0, dt, phi);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vp
