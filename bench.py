@@ -41,7 +41,7 @@ ALG_BYTES_PER_POINT = {
     "x_forward": 16, "y_forward": 16, "z_solve": 16, "y_inverse": 16, "x_inverse": 16,
     "x_forward_f32": 12, "y_forward_f32": 8, "z_solve_f32": 8, "y_inverse_f32": 8,
     "x_inverse_f32": 12,          # FP32 in, FP64 out (accumulate: +8)
-    "residual": 24,               # f, p in; r out
+    "x_forward_residual_f32": 20,  # f, p in (FP64); FP32 x spectrum of f - m - L_h p out
     "rhs_assembly": 56,           # u*, v*, w*, p_hat, rho, s in; b out
     "correction": 72,             # u*, v*, w*, p, p_hat, rho in; u, v, w out
     "extension": 104,             # u, v, w, phi, qx, qy, qz in; ue, ve, we, ug, vg, wg out
@@ -715,7 +715,7 @@ def main():
         step()
     ms_graph = time_steps(graph.replay, args.steps)
 
-    # bare solves at the same size: FP64 and mixed (FP32 chain + 1 FP64 correction)
+    # bare solves at the same size: FP64 and mixed (FP32 chain + FP64 defect corrections)
     f = X["f"]
     out64 = torch.empty_like(f)
     for _ in range(3):
@@ -729,7 +729,11 @@ def main():
     torch.cuda.synchronize()
     ms64 = a.elapsed_time(b) / args.solve_reps
     # mixed: FP32 chain + FP64 defect correction, up to 3 steps, stopping on the
-    # device once the estimated error is at most 1e-11 (the library default)
+    # device once the estimated error is at most 1e-11 (the library default).
+    # Its byte model: the first FP32 chain moves 48 N bytes (x forward 8 in +
+    # 4 out, y / z / y 8 each, x inverse 4 in + 8 out); a correction 64 N (x
+    # forward of the defect 16 in + 4 out, y / z / y 8 each, accumulating x
+    # inverse 4 + 8 in + 8 out).
     mixed = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.dx, cfg.dy, cfg.dzf(), cfg.bc, precision="mixed")
     tuned_mixed = shape_plan(mixed, 1, args.tune_mixed, args.no_autotune)
     out32 = torch.empty_like(f)
@@ -744,6 +748,8 @@ def main():
     ms32 = a.elapsed_time(b) / args.solve_reps
     rel_mixed = (torch.linalg.vector_norm(out32 - out64) / torch.linalg.vector_norm(out64)).item()
     (dc_steps, dc_est), = mixed.mixed_report()
+    mixed_bytes = (48 + 64 * dc_steps) * n
+    mixed_gbs = mixed_bytes / (ms32 * 1e-3) / 1e9
 
     # roofline of the dominant kernel, timed over the timed steps; the other
     # kernels' times come from the fully bracketed pass
@@ -775,6 +781,10 @@ def main():
         "solve_mixed": {"ms": round(ms32, 4), "mpts_s": round(n / (ms32 * 1e-3) / 1e6, 1),
                         "dc_steps": dc_steps, "dc_error_estimate": dc_est,
                         "rel_l2_vs_fp64": rel_mixed,
+                        "roofline": {"bound": "hbm", "model_bytes": mixed_bytes,
+                                     "model": f"{48 + 64 * dc_steps}N",
+                                     "achieved": round(mixed_gbs, 1), "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": round(mixed_gbs / HBM_PEAK_GBS, 4)},
                         "speedup_vs_fp64": round(ms64 / ms32, 3)},
         "step_variants_ms": {"fused_timed_region": round(ms_step, 4), "fused": round(ms_eager, 4),
                              "fused_hip_graph": round(ms_graph, 4),

@@ -88,13 +88,14 @@ typedef struct poisson_plan poisson_plan;
  *            stencils take the velocities of those faces as planes through
  *            project_lf, extend_liquid_velocity_lf and vof_step_lf; the
  *            solves accept every combination;
- *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 transforms and
- *            FP32 tridiagonal storage with FP64 pivots, refined by FP64
- *            residual / defect-correction steps, see poisson_plan_set_mixed);
+ *   precision : VP_PRECISION_FP64, or VP_PRECISION_MIXED (FP32 storage of
+ *            the spectra between passes, FP64 arithmetic inside them,
+ *            refined by FP64 defect-correction steps, see
+ *            poisson_plan_set_mixed);
  *   max_batch : largest n accepted by the batched calls, 1..VP_MAX_BATCH.
  * Allocates the plan's device tables and workspace: one spectrum slot of
- * 8*nx*ny*nz bytes per batch member for FP64, plus FP32 spectra and FP64
- * residuals for mixed (poisson_plan_footprint gives the exact total).
+ * 8*nx*ny*nz bytes per batch member for FP64, plus an FP32 spectrum slot per
+ * member for mixed (poisson_plan_footprint gives the exact total).
  * Returns NULL and sets *status on failure (status may be NULL):
  * VP_EINVAL for bad arguments, VP_EUNSUPPORTED for sizes or boundary
  * conditions outside the limits above.
@@ -340,11 +341,14 @@ int vof_advect(poisson_plan* plan, const double* C, const double* ug, const doub
 /*
  * Mixed-precision control (plans created with VP_PRECISION_MIXED).  A mixed
  * solve is p_0 = S32(f) followed by at most dc_steps FP64 defect-correction
- * steps p_k = p_{k-1} + e_k, e_k = S32(f - L_h p_{k-1}) (FP64 residual and
- * update, FP32 transforms and storage, FP64 z pivots).  The relative error
- * left in p_k is bounded by |e_1| / |p_1| after the first step and estimated
- * as |e_k|^2 / (|e_{k-1}| |p_k|) after later ones (the contraction measured
- * between consecutive corrections); a member stops, on the device and
+ * steps p_k = p_{k-1} + e_k, e_k = S32(f - L_h p_{k-1}), where S32 is the
+ * solve with FP32 spectra stored between its passes (FP64 arithmetic and
+ * tables inside each pass) and the defect is formed in FP64 inside the first
+ * pass of the correction.  After each correction the relative error left by
+ * its FP32 solve is estimated as 2^-23 (G |f - L_h p_{k-1}| + |e_k|) / |p_k|,
+ * G a constant of the plan (the largest RMS of 1/|lambda| over the z modes
+ * of one (kx, ky) line: the FP32 rounding of the forward passes is
+ * independent along z within a line); a member stops, on the device and
  * without a host synchronisation, once that is at most the tolerance.
  *   poisson_plan_set_mixed     : the most steps, 0..8 (default 3);
  *   poisson_plan_set_mixed_tol : the tolerance (default 1e-11); <= 0 runs
@@ -394,7 +398,7 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 default: 256 threads' worth at radix 16; narrower tiles use
  *                 less LDS, so more blocks fit on a compute unit);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
- *                 and residual kernels (1..nz; default chosen for ~16k blocks);
+ *                 kernel (1..nz; default chosen for ~16k blocks);
  *   "stream_planes" : z-planes marched by one block of the correction and
  *                 extension kernels (1..nz, default 1);
  *   "epilogue_tiled", "epilogue_planes" : the fused epilogue of vof_step on

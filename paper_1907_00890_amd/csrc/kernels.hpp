@@ -47,18 +47,42 @@ inline Batch<T> batch_of(T* const* ptrs, int n) {
 // tab layout per direction and precision, (cos, sin) pairs: of 2 pi k/N for
 // k < N, then of pi m/(2N) for m <= N/2 (one 2-vector load per twiddle).
 int ypass_tile_cols(int nx, int ny);
-// Options of the FP32 passes of the mixed-precision chain:
-//   sub   : x forward reads member b as in[b] - sub[b] (FP64, before the
-//           conversion to FP32); null: unchanged;
-//   skip  : per-member flags; a member whose flag is set is left untouched
-//           (its blocks return at once); null: every member runs;
-//   norms : x inverse writes per-block sums of e^2 and p^2 (see k_xinv);
-//   nzm   : z-planes per member (y passes: member = plane / nzm);
-//   lines : y passes: column pairs per block (a power of two; 0: default).
+// Partial sums of the mixed chain's x passes: kNormSlots doubles per x
+// block of a batch member (layout in transforms_x.hip).
+constexpr int kNormSlots = 4;
+
+// Geometry of the mixed chain's x passes: plane widths for the weighted sums,
+// and the stencil of the residual mode of the x forward pass, which reads
+// f - m - L_h p (p: current iterate of each member, m: mean[b], or 0 where
+// mean is null) in place of f.
+struct ResidualArgs {
+  Batch<const double> p;
+  const double* mean;
+  const double* dzf;   // nz
+  const double* dzc;   // nz, as GridArgs::dzc
+  double idx2, idy2;   // 1 / dx^2, 1 / dy^2
+  int ny, nz;
+  int perx, pery, perz;  // periodic directions
+  int outflow;           // as GridArgs::outflow
+};
+
+// Options of the FP32 passes of the mixed-precision chain (FP32 spectra in
+// HBM, FP64 arithmetic, LDS and twiddle tables inside every pass):
+//   sub      : x inverse with accumulation subtracts sub[b] from member b's
+//              result (the weighted mean of the previous iterate);
+//   skip     : per-member flags; a member whose flag is set is left untouched
+//              (its blocks return at once); null: every member runs;
+//   norms    : x passes write their per-block partial sums (kNormSlots each);
+//   geo      : x passes of the mixed chain (required there);
+//   residual : x forward in residual mode;
+//   nzm      : z-planes per member (y passes: member = plane / nzm);
+//   lines    : y passes: column pairs per block (a power of two; 0: default).
 struct PassOpts {
   const double* sub = nullptr;
   const int* skip = nullptr;
   double* norms = nullptr;
+  const ResidualArgs* geo = nullptr;
+  bool residual = false;
   int nzm = 0;
   int lines = 0;
 };
@@ -73,11 +97,11 @@ hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& 
                            int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st);
 hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
-                           int nx, int bc, long nrows, const float* tab, int pt,
+                           int nx, int bc, long nrows, const double* tab, int pt,
                            const PassOpts& o, hipStream_t st);
 // accum: out += result - o.sub[b] for batch member b (o.sub may be null)
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, bool accum, const float* tab, int pt,
+                           int nx, int bc, long nrows, bool accum, const double* tab, int pt,
                            const PassOpts& o, hipStream_t st);
 // blocks per member of an x pass (the norms partial sums of the x inverse)
 long xpass_blocks(int nx, int bc, int pt, long nrows);
@@ -85,7 +109,7 @@ long xpass_blocks(int nx, int bc, int pt, long nrows);
 hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool fwd,
                         const double* tab, int pt, int lines, hipStream_t st);
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const float* tab, int pt, const PassOpts& o, hipStream_t st);
+                        const double* tab, int pt, const PassOpts& o, hipStream_t st);
 
 // spectral z pass for a uniform z grid with nz a transform length (2^k in
 // [8, 1024], 3 * 2^k in [24, 768] or 5 * 2^k in [40, 640]):
@@ -104,7 +128,7 @@ struct ZSpecArgs {
 };
 hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
                             hipStream_t st);
-hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, int pt, int nb,
+hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
                             const int* skip, hipStream_t st);
 
 // zsolve.hip -----------------------------------------------------------------
@@ -192,23 +216,19 @@ hipError_t launch_lower_faces(const GridArgs& g, int mode, int dir, double* uf, 
 hipError_t launch_advect(const GridArgs& g, const double* C, const double* ug, const double* vg,
                          const double* wg, const double* const* lo, double dt, double beta,
                          int deflation, double* work, double* out, int sweep, hipStream_t st);
-// r = f - L_h p; also mean_p[0], mean_r[0] = volume-weighted means of p and
-// r.  partial must hold 2 * kResidualMaxBlocks doubles.
 int stencil_blocks(const GridArgs& g);
 int rhs_blocks(const GridArgs& g);  // blocks of one launch_rhs
 int stencil_default_planes(int nx, int ny, int nz);
-// skip (may be null): a set flag skips the launch's work (device-side)
-hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
-                           double* partial, double* mean_p, double* mean_r, double dz_sum,
-                           const int* skip, hipStream_t st);
 // Defect-correction control of the mixed chain, per member b of a batch of
 // nb (state: 4 doubles per member, flags: one int per member).
-// dc_reset clears flags and state; dc_update reduces the x-inverse norms of
-// step `step` (0 = the first FP32 solve) and sets flag[b] once the error
-// estimate (|e_1| / |p_1| after the first step, |e_k|^2 / (|e_{k-1}| |p_k|)
-// after later ones) is at most tol (tol <= 0: never).
+// dc_reset clears flags and state; dc_update reduces the x-pass partial sums
+// of step `step` (0 = the first FP32 solve; nblk blocks per member), writes
+// pmean[b] (weighted mean of the iterate: sum dzf p / denom) and, at step 0,
+// fmean[b] (of f), and from step 1 on sets flag[b] once the error estimate
+// 2^-23 (gain |r| + |e|) / |p| of the step is at most tol (tol <= 0: never).
 hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st);
 hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
-                            double* state, int* flags, hipStream_t st);
+                            double gain, double denom, double* state, int* flags, double* pmean,
+                            double* fmean, hipStream_t st);
 
 }  // namespace vp

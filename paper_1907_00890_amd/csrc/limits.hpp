@@ -3,5 +3,4 @@
 
 namespace vp {
 constexpr int kMaxBatch = 16;             // fields per batched launch
-constexpr int kResidualMaxBlocks = 16384;  // partial sums of one residual launch
 }  // namespace vp

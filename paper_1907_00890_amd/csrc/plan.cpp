@@ -48,7 +48,8 @@ static_assert(K_NCLASS <= VP_NUM_KERNEL_CLASSES, "kernel classes of the C interf
 const char* const kClassNames[K_NCLASS] = {
     "x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse",
     "x_forward_f32", "y_forward_f32", "z_solve_f32", "y_inverse_f32", "x_inverse_f32",
-    "residual", "rhs_assembly", "correction", "extension", "step_epilogue", "interface_terms",
+    "x_forward_residual_f32", "rhs_assembly", "correction", "extension", "step_epilogue",
+    "interface_terms",
     "advect_x", "advect_y", "advect_z"};
 
 // Twiddle table of one direction, (cos, sin) pairs: of 2 pi k/N for k < N,
@@ -160,28 +161,28 @@ struct poisson_plan {
   long long bytes = 0;
   std::vector<void*> allocs;
 
+  // twiddle tables (FP64; the mixed chain computes in FP64 too and stores FP32)
   double *tabx64 = nullptr, *taby64 = nullptr;
-  float *tabx32 = nullptr, *taby32 = nullptr;
   double *lamx = nullptr, *lamy = nullptr, *za = nullptr, *zc = nullptr;
   // spectral z pass (uniform z, nz a power of two in [8, 1024])
   double *lamz = nullptr, *tabz64 = nullptr;
-  float* tabz32 = nullptr;
   vp::ZSpecArgs zs{};
   int z_spec_ok = 0, z_spec = 0, z_pt = 16;
   double *dzf = nullptr, *dzc = nullptr, *mean = nullptr;
   double* work64 = nullptr;
   float* work32 = nullptr;
-  double* res64 = nullptr;
-  double* partial = nullptr;
-  // mixed-precision correction control: per-member state, flags, and the
-  // x-inverse norm partial sums
+  // mixed-precision correction control: per-member state, flags, the x-pass
+  // partial sums, the stencil and plane widths of the FP32 x passes, and the
+  // noise gain of the error estimate
   double* dc_state = nullptr;
   int* dc_flags = nullptr;
   double* dc_norms = nullptr;
   double dc_tol = 1e-11;
+  vp::ResidualArgs rgeo{};
+  double noise_gain = 0.0;
 
   vp::ZArgs z{};
-  vp::GridArgs g{};   // marching stencils (right-hand side, residual)
+  vp::GridArgs g{};   // marching stencils (right-hand side)
   vp::GridArgs gs{};  // streaming stencils (correction, extension)
   vp::GridArgs ge{};  // fused step epilogue
   vp::GridArgs gi{};  // interface terms
@@ -255,6 +256,84 @@ namespace {
     }                                                                     \
   } while (0)
 
+// Noise gain of the mixed chain's error estimate: the RMS over z modes of
+// 1/|lambda| for the worst (kx, ky) line,
+//   G^2 = (1/nz) sum_{k: mu_k > 0} 1/mu_k^2  +  [z null mode] 1/(nz s^2),
+// mu_k the eigenvalues of the z operator -W^-1 S (W = diag(dzf), f below;
+// c: centre distances as in plan_init) and s the smallest non-zero
+// |lambda_x| + |lambda_y| (a line with s > 0 has 1/(s + mu_k)^2 <= 1/mu_k^2
+// for mu_k > 0 and 1/s^2 for a null mode).  The sum is the squared Frobenius
+// norm of the pseudo-inverse of the symmetric form M = W^-1/2 (-S) W^-1/2,
+// taken one column at a time with tridiagonal solves: where M is singular
+// (no outflow at a z end) its null vector v ~ sqrt(dzf) is projected out of
+// e_j, the first unknown is pinned to 0 (which drops the periodic couplings,
+// all through unknown 0) and v is projected out of the solution.
+double mixed_noise_gain(const std::vector<double>& f, const std::vector<double>& c, bool zper,
+                        bool lo_out, bool hi_out, const std::vector<double>& lx,
+                        const std::vector<double>& ly) {
+  const int nz = (int)f.size();
+  std::vector<double> d(nz, 0.0), e(nz, 0.0);  // diagonal, coupling k <-> k+1
+  for (int k = 0; k < nz; ++k) {
+    double a = 0.0;
+    if (k > 0) a += 1.0 / c[k - 1];
+    else if (zper) a += 1.0 / c[nz - 1];
+    if (k + 1 < nz) a += 1.0 / c[k];
+    else if (zper) a += 1.0 / c[nz - 1];
+    if (k == 0 && lo_out) a += 2.0 / f[0];
+    if (k == nz - 1 && hi_out) a += 2.0 / f[nz - 1];
+    d[k] = a / f[k];
+    if (k + 1 < nz) e[k] = -1.0 / (c[k] * std::sqrt(f[k] * f[k + 1]));
+  }
+  const bool sing = !lo_out && !hi_out;
+  std::vector<double> v(nz);
+  double vs = 0.0;
+  for (int k = 0; k < nz; ++k) vs += f[k];
+  for (int k = 0; k < nz; ++k) v[k] = std::sqrt(f[k] / vs);
+  // tridiagonal solve of rows/columns k0..nz-1 of M (Thomas, no pivoting:
+  // M restricted there is symmetric positive definite)
+  const int k0 = sing ? 1 : 0;
+  std::vector<double> cp(nz, 0.0), x(nz, 0.0), rhs(nz, 0.0);
+  double sum = 0.0;
+  for (int j = 0; j < nz; ++j) {
+    for (int k = 0; k < nz; ++k) rhs[k] = (k == j ? 1.0 : 0.0) - (sing ? v[k] * v[j] : 0.0);
+    x[0] = 0.0;
+    double den = 1.0;
+    for (int k = k0; k < nz; ++k) {
+      const double lo = k > k0 ? e[k - 1] : 0.0;
+      den = d[k] - (k > k0 ? lo * cp[k - 1] : 0.0);
+      cp[k] = k + 1 < nz ? e[k] / den : 0.0;
+      x[k] = (rhs[k] - (k > k0 ? lo * x[k - 1] : 0.0)) / den;
+    }
+    for (int k = nz - 2; k >= k0; --k) x[k] -= cp[k] * x[k + 1];
+    if (sing) {
+      double dot = 0.0;
+      for (int k = 0; k < nz; ++k) dot += v[k] * x[k];
+      for (int k = 0; k < nz; ++k) x[k] -= dot * v[k];
+    }
+    for (int k = 0; k < nz; ++k) sum += x[k] * x[k];
+  }
+  double g2 = sum / nz;
+  if (sing) {
+    auto min_pos = [](const std::vector<double>& l, double& mn) {
+      double mp = 0.0;
+      mn = std::fabs(l[0]);
+      for (double t : l) {
+        const double a = std::fabs(t);
+        mn = std::min(mn, a);
+        if (a > 0.0 && (mp == 0.0 || a < mp)) mp = a;
+      }
+      return mp;
+    };
+    double mx = 0.0, my = 0.0;
+    const double px = min_pos(lx, mx), py = min_pos(ly, my);
+    double smin = 0.0;
+    if (px > 0.0) smin = px + my;
+    if (py > 0.0 && (smin == 0.0 || py + mx < smin)) smin = py + mx;
+    if (smin > 0.0) g2 += 1.0 / (nz * smin * smin);
+  }
+  return std::sqrt(g2);
+}
+
 int plan_init(poisson_plan* P, const double* dz) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   int st;
@@ -262,13 +341,10 @@ int plan_init(poisson_plan* P, const double* dz) {
   const std::vector<double> tx = make_table(nx, P->bc[0]), ty = make_table(ny, P->bc[1]);
   if ((st = P->upload(&P->tabx64, tx, "table x"))) return st;
   if ((st = P->upload(&P->taby64, ty, "table y"))) return st;
-  if (P->precision == VP_PRECISION_MIXED) {
-    std::vector<float> fx(tx.begin(), tx.end()), fy(ty.begin(), ty.end());
-    if ((st = P->upload(&P->tabx32, fx, "table x f32"))) return st;
-    if ((st = P->upload(&P->taby32, fy, "table y f32"))) return st;
-  }
-  if ((st = P->upload(&P->lamx, make_lambda(nx, P->dx, P->bc[0]), "lambda x"))) return st;
-  if ((st = P->upload(&P->lamy, make_lambda(ny, P->dy, P->bc[1]), "lambda y"))) return st;
+  const std::vector<double> lx = make_lambda(nx, P->dx, P->bc[0]);
+  const std::vector<double> ly = make_lambda(ny, P->dy, P->bc[1]);
+  if ((st = P->upload(&P->lamx, lx, "lambda x"))) return st;
+  if ((st = P->upload(&P->lamy, ly, "lambda y"))) return st;
 
   // z grid: centre distances and the row-scaled tridiagonal coefficients
   const bool zper = P->bc[2] == vp::BC_P;
@@ -298,13 +374,12 @@ int plan_init(poisson_plan* P, const double* dz) {
   if ((st = P->alloc(&P->work64, n, "workspace"))) return st;
   if (P->precision == VP_PRECISION_MIXED) {
     if ((st = P->alloc(&P->work32, n, "workspace f32"))) return st;
-    if ((st = P->alloc(&P->res64, n, "residual"))) return st;
-    if ((st = P->alloc(&P->partial, (size_t)2 * vp::kResidualMaxBlocks * P->max_batch, "partial sums")))
-      return st;
     if ((st = P->alloc(&P->dc_state, 4 * vp::kMaxBatch, "dc state"))) return st;
     if ((st = P->alloc(&P->dc_flags, vp::kMaxBatch, "dc flags"))) return st;
-    // an x block owns at least two rows: at most ny*nz/2 blocks per member
+    // kNormSlots partial sums per x block; a block owns at least four rows
+    // (ny * nz is a multiple of 8), so ny * nz doubles per member hold them
     if ((st = P->alloc(&P->dc_norms, (size_t)P->ny * P->nz * P->max_batch, "dc norms"))) return st;
+    P->noise_gain = mixed_noise_gain(f, c, zper, P->ends[4] == 'D', P->ends[5] == 'D', lx, ly);
   }
 
   // z launch geometry: S segments of at most 16 rows (S <= 64)
@@ -356,10 +431,6 @@ int plan_init(poisson_plan* P, const double* dz) {
   if (P->z_spec_ok) {
     const std::vector<double> tz = make_table(nz, P->bc[2]);
     if ((st = P->upload(&P->tabz64, tz, "table z"))) return st;
-    if (P->precision == VP_PRECISION_MIXED) {
-      std::vector<float> fz(tz.begin(), tz.end());
-      if ((st = P->upload(&P->tabz32, fz, "table z f32"))) return st;
-    }
     if ((st = P->upload(&P->lamz, make_lambda(nz, f[0], P->bc[2]), "lambda z"))) return st;
     vp::ZSpecArgs& A = P->zs;
     A.nx = nx;
@@ -408,6 +479,19 @@ int plan_init(poisson_plan* P, const double* dz) {
     while (kc > 8 && tiles * ((nz + kc - 1) / kc) < 512) kc /= 2;
     P->gi.kc = kc < nz ? kc : nz;
   }
+  // geometry of the mixed chain's x passes (the iterates are set per solve)
+  vp::ResidualArgs& R = P->rgeo;
+  R.mean = nullptr;
+  R.dzf = P->dzf;
+  R.dzc = P->dzc;
+  R.idx2 = 1.0 / (P->dx * P->dx);
+  R.idy2 = 1.0 / (P->dy * P->dy);
+  R.ny = ny;
+  R.nz = nz;
+  R.perx = P->bc[0] == vp::BC_P;
+  R.pery = P->bc[1] == vp::BC_P;
+  R.perz = zper;
+  R.outflow = G.outflow;
   return VP_OK;
 }
 
@@ -431,58 +515,76 @@ int solve_f64(poisson_plan* P, int nb, const double* const* rhs, double* const* 
   return VP_OK;
 }
 
-// FP32 chain on FP64 right-hand sides rhs[b] - o.sub[b] (o.sub may be
-// null); out[b] = result, or with accum out[b] += result - asub[b].  o.skip
-// and o.norms as in vp::PassOpts.
-int solve_f32(poisson_plan* P, int nb, const double* const* rhs, double* const* out, bool accum,
-              const double* asub, vp::PassOpts o, hipStream_t st) {
+// FP32 chain (FP32 spectra, FP64 arithmetic) on FP64 inputs: with iter null
+// the x forward reads rhs[b]; otherwise it reads the defect
+// rhs[b] - fm[b] - L_h iter[b] (fm may be null: no shift).  out[b] = result,
+// or with accum out[b] += result - asub[b] (asub may be null).  o.skip and
+// o.norms as in vp::PassOpts.
+int solve_f32(poisson_plan* P, int nb, const double* const* rhs, const double* const* iter,
+              const double* fm, double* const* out, bool accum, const double* asub,
+              vp::PassOpts o, hipStream_t st) {
   const long nrows = (long)P->ny * P->nz, N = P->npts();
   float* w = P->work32;
   const vp::Batch<const double> in = vp::batch_of(rhs, nb);
   const vp::Batch<double> ob = vp::batch_of(out, nb);
+  vp::ResidualArgs geo = P->rgeo;
+  if (iter) {
+    geo.p = vp::batch_of(iter, nb);
+    geo.mean = fm;
+  }
   vp::ZArgs z = P->z;
   z.skip = o.skip;
   o.nzm = P->nz;
+  o.geo = &geo;
   vp::PassOpts fo = o, io = o;
-  fo.norms = nullptr;
+  fo.residual = iter != nullptr;
+  fo.sub = nullptr;
   io.sub = asub;
   vp::PassOpts mo = o;  // y passes: flags and tile width only
   mo.sub = nullptr;
   mo.norms = nullptr;
+  mo.geo = nullptr;
   mo.lines = P->y_lines;
-  VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx32, P->x_pt, fo, st), "x forward f32", st);
-  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby32, P->y_pt, mo, st), "y forward f32", st);
+  if (iter)
+    VP_LAUNCH(P, K_RESIDUAL, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, fo, st),
+              "x forward residual f32", st);
+  else
+    VP_LAUNCH(P, K_XFWD32, vp::launch_xfwd_f32(in, nb, w, N, P->nx, P->bc[0], nrows, P->tabx64, P->x_pt, fo, st),
+              "x forward f32", st);
+  VP_LAUNCH(P, K_YFWD32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], true, P->taby64, P->y_pt, mo, st), "y forward f32", st);
   if (P->z_spec)
-    VP_LAUNCH(P, K_Z32, vp::launch_zspec_f32(w, P->zs, P->tabz32, P->z_pt, nb, o.skip, st),
+    VP_LAUNCH(P, K_Z32, vp::launch_zspec_f32(w, P->zs, P->tabz64, P->z_pt, nb, o.skip, st),
               "z spectral f32", st);
   else
     VP_LAUNCH(P, K_Z32, vp::launch_zsolve_f32(w, z, nb, st), "z solve f32", st);
-  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby32, P->y_pt, mo, st), "y inverse f32", st);
-  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, ob, nb, P->nx, P->bc[0], nrows, accum, P->tabx32, P->x_pt, io, st),
+  VP_LAUNCH(P, K_YINV32, vp::launch_y_f32(w, P->nx, P->ny, P->nz * nb, P->bc[1], false, P->taby64, P->y_pt, mo, st), "y inverse f32", st);
+  VP_LAUNCH(P, K_XINV32, vp::launch_xinv_f32(w, N, ob, nb, P->nx, P->bc[0], nrows, accum, P->tabx64, P->x_pt, io, st),
             "x inverse f32", st);
   return VP_OK;
 }
 
 // Mixed precision: p_0 = S32(f), then up to dc_steps times
-//   r = f - L_h p (FP64, also giving mean_W(p) and mean_W(r)),
-//   e = S32(r - mean_W(r)) - mean_W(p),  p += e.
-// The FP32 chain cannot see the null (constant) mode, so the FP64 weighted
-// means are removed in every correction step instead: mean_W(r) equals
-// mean_W(f), which would otherwise dominate r and swamp its FP32 copy.  With
-// an outflow end there is no null mode: e = S32(r), nothing is removed.
-// Stopping, per member and on the device: the error left in p_k is bounded
-// by |e_1| after the first step and estimated as |e_k|^2 / |e_{k-1}| after
-// later ones, from norms the x-inverse pass reduces; once that is at most
-// dc_tol relative to |p| the member's flag is set and its later steps return
-// at once (no host synchronisation).
+//   e = S32(f - m - L_h p),  p <- p + e - mean_W(p),
+// with m = mean_W(f), removed in FP64 before any FP32 store (a right-hand
+// side with a non-zero mean would otherwise leave a defect dominated by it,
+// whose FP32 copy loses the part the correction needs); the FP32 chain cannot
+// see the constant mode, so the FP64 weighted mean of p is removed by each
+// correction instead.  With an outflow end there is no null mode and neither
+// mean is removed.  The defect is formed inside the x forward pass of the
+// correction (FP64 reads of f and p, FP32 store of its x spectrum); the
+// weighted sums behind both means and the norms of the error estimate come
+// from the x passes' per-block partial sums, reduced by the control kernel
+// after each solve.
+// Stopping, per member and on the device: after each correction the error
+// left by its FP32 solve is estimated from |defect|, |e| and |p| (see
+// k_dc_update) and once that is at most dc_tol the member's flag is set and
+// its later passes return at once (no host synchronisation).
 // Batch member b keeps f in place, or in work64 slot b when an output
-// overwrites it, and its residual in res64 slot b (work64 slot b when f
-// itself lies in res64 slot b).
+// overwrites it.
 int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const* sol,
                 hipStream_t st) {
   const long N = P->npts(), nrows = (long)P->ny * P->nz;
   const double* f[vp::kMaxBatch];
-  double* r[vp::kMaxBatch];
   for (int b = 0; b < nb; ++b) {
     f[b] = rhs[b];
     bool clobbered = false;
@@ -492,31 +594,31 @@ int solve_mixed(poisson_plan* P, int nb, const double* const* rhs, double* const
              "copy rhs");
       f[b] = P->work64 + b * N;
     }
-    r[b] = (f[b] == P->res64 + b * N) ? P->work64 + b * N : P->res64 + b * N;
   }
   double* const pmeans = P->mean + vp::kMaxBatch;      // FP64 weighted mean of p per member
-  double* const rmeans = P->mean + 2 * vp::kMaxBatch;  // and of the residual
+  double* const fmeans = P->mean + 2 * vp::kMaxBatch;  // and of f
   const long nblk = vp::xpass_blocks(P->nx, P->bc[0], P->x_pt, nrows);
+  if (nblk < 1 || vp::kNormSlots * nblk > nrows) {
+    g_last_error = "mixed solve: x-pass partial sums exceed their buffer";
+    return VP_EINVAL;
+  }
+  const double denom = (double)P->nx * (double)P->ny * P->dz_sum;
   VP_HIP(vp::launch_dc_reset(P->dc_state, P->dc_flags, nb, st), "dc reset");
   vp::PassOpts o;
   o.norms = P->dc_norms;
-  int s = solve_f32(P, nb, f, sol, false, nullptr, o, st);
+  int s = solve_f32(P, nb, f, nullptr, nullptr, sol, false, nullptr, o, st);
   if (s) return s;
-  VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, 0, P->dc_tol, P->dc_state, P->dc_flags, st),
+  VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, 0, P->dc_tol, P->noise_gain, denom,
+                              P->dc_state, P->dc_flags, pmeans, fmeans, st),
          "dc update");
-  o.sub = P->singular ? rmeans : nullptr;
   o.skip = P->dc_flags;
+  const double* const fm = P->singular ? fmeans : nullptr;
   const double* const asub = P->singular ? pmeans : nullptr;
   for (int it = 1; it <= P->dc_steps; ++it) {
-    for (int b = 0; b < nb; ++b)
-      VP_LAUNCH(P, K_RESIDUAL,
-                vp::launch_residual(P->g, f[b], sol[b], r[b],
-                                    P->partial + 2L * b * vp::kResidualMaxBlocks, pmeans + b,
-                                    rmeans + b, P->dz_sum, P->dc_flags + b, st),
-                "residual", st);
-    s = solve_f32(P, nb, r, sol, true, asub, o, st);
+    s = solve_f32(P, nb, f, sol, fm, sol, true, asub, o, st);
     if (s) return s;
-    VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, it, P->dc_tol, P->dc_state, P->dc_flags, st),
+    VP_HIP(vp::launch_dc_update(P->dc_norms, nblk, nb, it, P->dc_tol, P->noise_gain, denom,
+                                P->dc_state, P->dc_flags, pmeans, fmeans, st),
            "dc update");
   }
   return VP_OK;
@@ -646,8 +748,7 @@ bool lower_out_ok(const poisson_plan* P, const vp_lower_faces* lf) {
 int project_impl(poisson_plan* P, double* u, double* v, double* w, const vp_lower_faces* lf,
                  const double* phat, const double* rho, double rho0, const double* src, double dt,
                  double* p, hipStream_t st) {
-  // mixed precision keeps the FP64 right-hand side for its residuals
-  double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
+  double* b = P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src, dt, b, st), "rhs assembly", st);
   for (int d = 0; d < 3; ++d)
     if (lower_out(P, d))
@@ -714,7 +815,7 @@ int step_impl(poisson_plan* P, double* u, double* v, double* w, const vp_lower_f
               double* p, const double* src_ext, const double* qx, const double* qy,
               const double* qz, double* ue, double* ve, double* we, const vp_lower_faces* lfe,
               double* ug, double* vg, double* wg, double* phi, hipStream_t st) {
-  double* b = P->precision == VP_PRECISION_MIXED ? P->res64 : P->work64;
+  double* b = P->work64;
   VP_LAUNCH(P, K_RHS, vp::launch_rhs(P->g, u, v, w, phat, rho, rho0, src_p, dt, b, st),
             "rhs assembly", st);
   for (int d = 0; d < 3; ++d)
@@ -988,7 +1089,6 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     if (value < 1 || value > P->nz) return VP_EINVAL;
     vp::GridArgs g = P->g;
     g.kc = value;
-    if (vp::stencil_blocks(g) > vp::kResidualMaxBlocks) return VP_EINVAL;
     P->g.kc = value;
     return VP_OK;
   }
@@ -1077,12 +1177,20 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
   // x passes: forward + inverse
   s = pick(st, &P->x_pt, {16, 8}, [&]() -> int {
     if (mixed) {
-      const vp::PassOpts none{};
-      int e = hs(vp::launch_xfwd_f32(bin, nb, P->work32, N, P->nx, P->bc[0], nrows, P->tabx32,
-                                     P->x_pt, none, st));
+      // the x passes of a correction step: residual forward, accumulating
+      // inverse, both with their partial sums
+      vp::ResidualArgs geo = P->rgeo;
+      geo.p = bin;
+      vp::PassOpts o{};
+      o.geo = &geo;
+      o.norms = P->dc_norms;
+      o.residual = true;
+      int e = hs(vp::launch_xfwd_f32(bin, nb, P->work32, N, P->nx, P->bc[0], nrows, P->tabx64,
+                                     P->x_pt, o, st));
       if (e) return e;
-      return hs(vp::launch_xinv_f32(P->work32, N, bout, nb, P->nx, P->bc[0], nrows, false,
-                                    P->tabx32, P->x_pt, none, st));
+      o.residual = false;
+      return hs(vp::launch_xinv_f32(P->work32, N, bout, nb, P->nx, P->bc[0], nrows, true,
+                                    P->tabx64, P->x_pt, o, st));
     }
     int e = hs(vp::launch_xfwd_f64(bin, nb, P->work64, N, P->nx, P->bc[0], nrows, P->tabx64,
                                    P->x_pt, st));
@@ -1097,7 +1205,7 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
     yo.lines = P->y_lines;
     for (int fwd = 1; fwd >= 0; --fwd) {
       const int e = mixed ? hs(vp::launch_y_f32(P->work32, P->nx, P->ny, P->nz * nb, P->bc[1],
-                                                fwd != 0, P->taby32, P->y_pt, yo, st))
+                                                fwd != 0, P->taby64, P->y_pt, yo, st))
                           : hs(vp::launch_y_f64(P->work64, P->nx, P->ny, P->nz * nb, P->bc[1],
                                                 fwd != 0, P->taby64, P->y_pt, P->y_lines, st));
       if (e) return e;
@@ -1115,7 +1223,7 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
     P->z_spec = 0;
     auto zpass = [&]() -> int {
       if (P->z_spec)
-        return mixed ? hs(vp::launch_zspec_f32(P->work32, P->zs, P->tabz32, P->z_pt, nb, nullptr, st))
+        return mixed ? hs(vp::launch_zspec_f32(P->work32, P->zs, P->tabz64, P->z_pt, nb, nullptr, st))
                      : hs(vp::launch_zspec_f64(P->work64, P->zs, P->tabz64, P->z_pt, nb, st));
       return mixed ? hs(vp::launch_zsolve_f32(P->work32, P->z, nb, st))
                    : hs(vp::launch_zsolve_f64(P->work64, P->z, nb, st));
@@ -1160,14 +1268,13 @@ int poisson_plan_autotune(poisson_plan* P, int nb, void* stream, int* chosen) {
   }
   // marching stencils: planes per block of the right-hand-side kernel, when
   // the workspace has a second field to write to
-  double* second = mixed ? P->res64 : (P->max_batch > 1 ? P->work64 + N : nullptr);
+  double* second = P->max_batch > 1 ? P->work64 + N : nullptr;
   if (second) {
     std::vector<int> cands;
     for (int kc : {1, 2, 4, 8, 16, 32, vp::stencil_default_planes(P->nx, P->ny, P->nz)}) {
       vp::GridArgs g = P->g;
       g.kc = kc;
-      if (kc <= P->nz && vp::stencil_blocks(g) <= vp::kResidualMaxBlocks &&
-          std::find(cands.begin(), cands.end(), kc) == cands.end())
+      if (kc <= P->nz && std::find(cands.begin(), cands.end(), kc) == cands.end())
         cands.push_back(kc);
     }
     const double* f = P->work64;

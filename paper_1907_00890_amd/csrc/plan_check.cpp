@@ -66,8 +66,7 @@ long long poisson_plan_footprint(int nx, int ny, int nz, int precision, int max_
   const long long tables = 2LL * nx + 2 * (nx / 2 + 1) + 2LL * ny + 2 * (ny / 2 + 1);
   long long b = 8 * (tables + nx + ny + 4LL * nz + 3 * vp::kMaxBatch) + 8 * n;
   if (precision == VP_PRECISION_MIXED)
-    b += 4 * tables + 4 * n + 8 * n + 16LL * vp::kResidualMaxBlocks * max_batch +
-         8LL * 4 * vp::kMaxBatch + 4LL * vp::kMaxBatch + 8LL * ny * nz * max_batch;
+    b += 4 * n + 8LL * 4 * vp::kMaxBatch + 4LL * vp::kMaxBatch + 8LL * ny * nz * max_batch;
   return b;
 }
 

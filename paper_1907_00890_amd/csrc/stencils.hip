@@ -916,136 +916,6 @@ hipError_t launch_interface(const GridArgs& g, const double* C, const double* md
   return hipGetLastError();
 }
 
-// r = f - L_h p (FP64 residual of the defect-correction steps, any ends).  Each block
-// also sums dzf[k] * p and dzf[k] * r over its cells (fixed order, no
-// atomics) into partial[block] and partial[kResidualMaxBlocks + block], so
-// the weighted means of p and r cost no extra pass.  A block marches through
-// g.kc planes of a one-row tile; the loads of plane k+1 are issued before
-// plane k is computed, into the other of two register sets, and every load
-// is unconditional (the tile's neighbour offsets wrap to valid cells at
-// walls, where the value is not used), so the compiler waits only for the
-// plane it computes.
-__global__ __launch_bounds__(256) void k_residual(const GridArgs g, const double* __restrict__ f,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ dzf,
-                                                   const double* __restrict__ dzc,
-                                                   double* __restrict__ r,
-                                                   double* __restrict__ partial,
-                                                   const int* __restrict__ skip) {
-  __shared__ double red[2][256];
-  if (skip && skip[0]) return;
-  const Tile t = tile_of<64>(g);
-  double acc = 0.0, accr = 0.0;
-  if (t.ok) {
-    const long P = (long)g.nx * g.ny;
-    const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
-    int km = kminus(g, t.kb);
-    double pm = km >= 0 ? p[km * P + t.c0] : 0.0;
-    double pc = p[t.kb * P + t.c0];
-    // the loads of plane k: p of the z+1 neighbour (plane k itself at a
-    // wall), the four in-plane neighbours of p, and f
-    struct PlaneLoads {
-      double pp, xp, xm, yp, ym, fc;
-    };
-    auto issue = [&](int k, PlaneLoads& L) {
-      const long c = k * P + t.c0;
-      const int kp = kplus(g, k);
-      L.pp = p[(long)(kp >= 0 ? kp : k) * P + t.c0];
-      L.xp = p[c + t.xp];
-      L.xm = p[c + t.xm];
-      L.yp = p[c + t.yp];
-      L.ym = p[c + t.ym];
-      L.fc = f[c];
-    };
-    auto step = [&](int k, PlaneLoads& L, PlaneLoads& Ln, auto pref_c) {
-      if constexpr (decltype(pref_c)::value) issue(k + 1, Ln);
-      const long c = k * P + t.c0;
-      const int kp = kplus(g, k);
-      const double pp = kp >= 0 ? L.pp : 0.0;
-      // across an outflow face the ghost holds -pc
-      double lx = 0.0, ly = 0.0, lz = 0.0;
-      if (t.hxp) lx += L.xp - pc;
-      else if (g.outflow & 2) lx += -pc - pc;
-      if (t.hxm) lx -= pc - L.xm;
-      else if (g.outflow & 1) lx -= pc + pc;
-      if (t.hyp) ly += L.yp - pc;
-      else if (g.outflow & 8) ly += -pc - pc;
-      if (t.hym) ly -= pc - L.ym;
-      else if (g.outflow & 4) ly -= pc + pc;
-      if (kp >= 0) lz += (pp - pc) / dzc[k];
-      else if (g.outflow & 32) lz += (-pc - pc) / dzf[k];
-      if (km >= 0) lz -= (pc - pm) / dzc[km];
-      else if (g.outflow & 16) lz -= (pc + pc) / dzf[k];
-      const double rc = L.fc - (lx * idx2 + ly * idy2 + lz / dzf[k]);
-      r[c] = rc;
-      acc += dzf[k] * pc;
-      accr += dzf[k] * rc;
-      pm = pc;
-      pc = pp;
-      km = k;
-    };
-    using F = std::false_type;
-    using T = std::true_type;
-    PlaneLoads la, lb;
-    issue(t.kb, la);
-    int k = t.kb;
-    for (; k + 2 < t.ke; k += 2) {
-      step(k, la, lb, T{});
-      step(k + 1, lb, la, T{});
-    }
-    if (k + 1 < t.ke) {
-      step(k, la, lb, T{});
-      step(k + 1, lb, la, F{});
-    } else {
-      step(k, la, lb, F{});
-    }
-  }
-  red[0][threadIdx.x] = acc;
-  red[1][threadIdx.x] = accr;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const long b = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    partial[b] = red[0][0];
-    partial[kResidualMaxBlocks + b] = red[1][0];
-  }
-}
-
-// out_p[0], out_r[0] = (sums of the two partial-sum rows) / denom, one
-// block, fixed order
-__global__ __launch_bounds__(256) void k_mean_finish(const double* __restrict__ partial, int nb,
-                                                      double denom, double* __restrict__ out_p,
-                                                      double* __restrict__ out_r,
-                                                      const int* __restrict__ skip) {
-  __shared__ double red[2][256];
-  if (skip && skip[0]) return;
-  double acc = 0.0, accr = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) {
-    acc += partial[i];
-    accr += partial[kResidualMaxBlocks + i];
-  }
-  red[0][threadIdx.x] = acc;
-  red[1][threadIdx.x] = accr;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out_p[0] = red[0][0] / denom;
-    out_r[0] = red[1][0] / denom;
-  }
-}
-
 template <int TXMAX = 64>
 static inline dim3 tile_grid(const GridArgs& g) {
   const int tx = tile_w<TXMAX>(g);
@@ -1141,21 +1011,6 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const GridArgs& g, const double* f, const double* p, double* r,
-                           double* partial, double* mean_p, double* mean_r, double dz_sum,
-                           const int* skip, hipStream_t st) {
-  const int nb = stencil_blocks(g);
-  if (nb > kResidualMaxBlocks) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_residual, tile_grid(g), dim3(256), 0, st, g, f, p, g.dzf, g.dzc, r, partial,
-                     skip);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const double denom = (double)g.nx * (double)g.ny * dz_sum;
-  hipLaunchKernelGGL(k_mean_finish, dim3(1), dim3(256), 0, st, partial, nb, denom, mean_p, mean_r,
-                     skip);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // defect-correction control (mixed precision)
 // ---------------------------------------------------------------------------
@@ -1168,47 +1023,54 @@ __global__ __launch_bounds__(64) void k_dc_reset(double* __restrict__ state,
   }
 }
 
-// block b: member b.  state[4b + 0] = |e| of the previous step (|p_0| after
-// the first solve), [1] = last error estimate, [2] = corrections applied.
+// block b: member b.  Reduces the member's x-pass partial sums (kNormSlots per
+// block, nblk blocks) in a fixed order and updates state[4b + 0] = |e| of the
+// step, [1] = error estimate, [2] = corrections applied; pmean[b] = the
+// weighted mean of the new iterate, and after the first solve fmean[b] = the
+// weighted mean of f.
+//
+// Error estimate of the last FP32 solve (of r, adding e to p): the chain
+// rounds only what it stores, and the forward stores' rounding (at most u
+// |r| each, u = 2^-24) is independent along z within a (kx, ky) line, so the
+// solve amplifies it by at most `gain`, the RMS of 1/|lambda| over the z
+// modes of the worst line; the inverse stores add about u |e|.  Estimate =
+// 2u (gain |r| + |e|) / |p| with |r| the residual the step solved.
 __global__ __launch_bounds__(256) void k_dc_update(const double* __restrict__ norms, long nblk,
-                                                   int step, double tol,
-                                                   double* __restrict__ state,
-                                                   int* __restrict__ flags) {
-  __shared__ double red[2][256];
+                                                   int step, double tol, double gain,
+                                                   double denom, double* __restrict__ state,
+                                                   int* __restrict__ flags,
+                                                   double* __restrict__ pmean,
+                                                   double* __restrict__ fmean) {
+  __shared__ double red[kNormSlots][256];
   const int b = blockIdx.x;
   if (flags[b]) return;
-  double ee = 0.0, pp = 0.0;
-  for (long i = threadIdx.x; i < nblk; i += 256) {
-    ee += norms[2 * (b * nblk + i)];
-    pp += norms[2 * (b * nblk + i) + 1];
-  }
-  red[0][threadIdx.x] = ee;
-  red[1][threadIdx.x] = pp;
+  double v[kNormSlots] = {};
+  for (long i = threadIdx.x; i < nblk; i += 256)
+#pragma unroll
+    for (int j = 0; j < kNormSlots; ++j) v[j] += norms[kNormSlots * (b * nblk + i) + j];
+#pragma unroll
+  for (int j = 0; j < kNormSlots; ++j) red[j][threadIdx.x] = v[j];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+#pragma unroll
+      for (int j = 0; j < kNormSlots; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
   const double en = sqrt(red[0][0]), pn = sqrt(red[1][0]);
+  pmean[b] = red[2][0] / denom;
   double* s = state + 4 * b;
   if (step == 0) {
-    s[0] = en;  // e_0 is p_0 itself
+    fmean[b] = red[3][0] / denom;
+    s[0] = en;
     s[1] = 1.0;
     s[2] = 0.0;
     return;
   }
-  // Error left in p_k, relative to |p_k|.  After the first step only the
-  // bound |e_1| is safe (while the iteration contracts): p_0's error is
-  // smooth, the residual is not, and the FP32 chain is far less accurate on
-  // rough right-hand sides, so |e_1| / |p_0| says nothing about the
-  // contraction.  From the second step on the contraction is measured as
-  // |e_k| / |e_{k-1}|, so the error left is about |e_k|^2 / |e_{k-1}|.
-  double est = 0.0;
-  if (pn > 0.0) est = step == 1 ? en / pn : (s[0] > 0.0 ? en * en / (s[0] * pn) : 0.0);
+  const double rn = sqrt(red[3][0]);
+  const double est = pn > 0.0 ? 0x1p-23 * (gain * rn + en) / pn : 0.0;
   s[0] = en;
   s[1] = est;
   s[2] = (double)step;
@@ -1222,10 +1084,11 @@ hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st) {
 }
 
 hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
-                            double* state, int* flags, hipStream_t st) {
+                            double gain, double denom, double* state, int* flags, double* pmean,
+                            double* fmean, hipStream_t st) {
   if (nb < 1 || nb > kMaxBatch || nblk < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dc_update, dim3(nb), dim3(256), 0, st, norms, nblk, step, tol, state,
-                     flags);
+  hipLaunchKernelGGL(k_dc_update, dim3(nb), dim3(256), 0, st, norms, nblk, step, tol, gain, denom,
+                     state, flags, pmean, fmean);
   return hipGetLastError();
 }
 

@@ -6,43 +6,114 @@
 
 namespace vp {
 
-// block sums of e^2 and p^2 to norms[2 * (member * gridDim.x + block) + {0, 1}]
+// Sums over a block's threads of K per-thread values, written to out[0..K)
 // (fixed order, through the block's LDS, which the caller no longer needs;
-// XB threads, red holds 2 XB doubles)
-template <int XB>
-__device__ __forceinline__ void block_norms(double* red, double ee, double pp,
-                                            double* __restrict__ norms) {
+// XB threads, red holds K * XB doubles).
+template <int XB, int K>
+__device__ __forceinline__ void block_sums(double* red, const double (&v)[K],
+                                           double* __restrict__ out) {
   __syncthreads();
-  red[threadIdx.x] = ee;
-  red[XB + threadIdx.x] = pp;
+#pragma unroll
+  for (int i = 0; i < K; ++i) red[i * XB + threadIdx.x] = v[i];
   __syncthreads();
   for (int w = XB / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      red[XB + threadIdx.x] += red[XB + threadIdx.x + w];
+#pragma unroll
+      for (int i = 0; i < K; ++i) red[i * XB + threadIdx.x] += red[i * XB + threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const long o = 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x);
-    norms[o] = red[0];
-    norms[o + 1] = red[XB];
+#pragma unroll
+    for (int i = 0; i < K; ++i) out[i] = red[i * XB];
   }
+}
+
+// Partial sums of the mixed chain, kNormSlots doubles per x block of a
+// member, at norms + kNormSlots * (member * blocks + block):
+//   [0] sum e^2, [1] sum p^2, [2] sum dzf p   (x inverse: e added, p result)
+//   [3] sum dzf f (x forward of f) or sum r^2 (x forward in residual mode)
+// Element (x, row) of a field lies in z-plane row / ny, of width dzf[row / ny].
+
+// Residual mode of the x forward pass (ResidualArgs): element x of row
+// `row` (= y + ny z) is read as r = f - m - L_h p, the defect of the current
+// iterate p, in FP64 (L_h of every end type: periodic wrap, wall = no flux,
+// outflow = a zero value half a cell beyond the end; z faces at centre
+// distances dzc).
+// The y and z part of L_h at one row (everything but the x neighbours),
+// set up once per row: the neighbour rows' offsets (0 where there is none:
+// the difference then reads the row itself, with a zero weight), their
+// weights, and the diagonal an outflow end adds (a zero value half a cell
+// beyond the end cell).
+struct RowStencil {
+  long ym, yp, zm, zp;     // element offsets of the neighbour rows
+  double wym, wyp, wzm, wzp;
+  double dout;             // outflow ends of y and z
+};
+
+__device__ __forceinline__ RowStencil row_stencil(const ResidualArgs& a, int nx, int y, int z) {
+  RowStencil s;
+  const long P = (long)nx * a.ny;
+  const bool hym = y > 0 || a.pery, hyp = y + 1 < a.ny || a.pery;
+  s.ym = hym ? (y > 0 ? -(long)nx : P - nx) : 0;
+  s.yp = hyp ? (y + 1 < a.ny ? (long)nx : nx - P) : 0;
+  s.wym = hym ? a.idy2 : 0.0;
+  s.wyp = hyp ? a.idy2 : 0.0;
+  double d = 0.0;
+  if (!hym && (a.outflow & 4)) d += 2.0 * a.idy2;
+  if (!hyp && (a.outflow & 8)) d += 2.0 * a.idy2;
+  const double ihf = 1.0 / a.dzf[z];
+  const bool hzm = z > 0 || a.perz, hzp = z + 1 < a.nz || a.perz;
+  s.zm = hzm ? (z > 0 ? -P : (long)(a.nz - 1) * P) : 0;
+  s.zp = hzp ? (z + 1 < a.nz ? P : -(long)(a.nz - 1) * P) : 0;
+  s.wzm = hzm ? ihf / a.dzc[z > 0 ? z - 1 : a.nz - 1] : 0.0;
+  s.wzp = hzp ? ihf / a.dzc[z + 1 < a.nz ? z : a.nz - 1] : 0.0;
+  if (!hzm && (a.outflow & 16)) d += 2.0 * ihf * ihf;
+  if (!hzp && (a.outflow & 32)) d += 2.0 * ihf * ihf;
+  s.dout = d;
+  return s;
+}
+
+// f - m - L_h p at element x of a row starting at pr (p) with its y and z
+// part in rs, every flux as a difference of neighbouring values (the
+// rounding of L_h then scales with the differences, not with p); pym / pyp:
+// the y-neighbour values where the caller has them (OWN_YM / OWN_YP).
+template <int N, bool OWN_YM, bool OWN_YP>
+__device__ __forceinline__ double row_residual(const ResidualArgs& a, const double* __restrict__ pr,
+                                               const RowStencil& rs, double fc, double m, int x,
+                                               double pc, double pym, double pyp) {
+  double lx = 0.0;
+  if (x + 1 < N) lx += pr[x + 1] - pc;
+  else if (a.perx) lx += pr[x + 1 - N] - pc;
+  else if (a.outflow & 2) lx -= pc + pc;
+  if (x > 0) lx -= pc - pr[x - 1];
+  else if (a.perx) lx -= pc - pr[x - 1 + N];
+  else if (a.outflow & 1) lx -= pc + pc;
+  const double ym = OWN_YM ? pym : pr[x + rs.ym];
+  const double yp = OWN_YP ? pyp : pr[x + rs.yp];
+  const double lyz = rs.wyp * (yp - pc) - rs.wym * (pc - ym) + rs.wzp * (pr[x + rs.zp] - pc) -
+                     rs.wzm * (pc - pr[x + rs.zm]) - rs.dout * pc;
+  return fc - m - (a.idx2 * lx + lyz);
 }
 
 // ---------------------------------------------------------------------------
 // x kernels: a block owns 2*LPB consecutive rows (nrows is even);
 // x_block_threads<N>() threads, TPL per line pair
 // ---------------------------------------------------------------------------
-// SUB: member b's input is read as in[b] - sub[b] (FP64, before any
-// conversion to T); without it the kernel reads its input unchanged.
-template <typename TI, typename T, int N, int BC, bool SUB, int PTM>
-__global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __restrict__ out,
+// T: arithmetic and LDS type; TS: type of the stored spectrum (float in the
+// mixed chain, which computes in FP64 and rounds only what it stores).
+// RES: residual mode (above; `in` holds f); otherwise the input is read
+// unchanged.  With TS != T and `norms` set, slot 3 of the block's partial
+// sums receives sum dzf f, or sum r^2 in residual mode.
+template <typename TI, typename T, typename TS, int N, int BC, bool RES, int PTM>
+__global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, TS* __restrict__ out,
                                                long ostride, long nrows,
-                                               const T* __restrict__ tab,
-                                               const double* __restrict__ sub,
-                                               const int* __restrict__ skip) {
-  constexpr int TPL = FftShape<N, PTM>::TPL, LPB = x_block_threads<N>() / TPL;
+                                               const T* __restrict__ tab, const ResidualArgs res,
+                                               const int* __restrict__ skip,
+                                               double* __restrict__ norms) {
+  constexpr int XB = x_block_threads<N>(), TPL = FftShape<N, PTM>::TPL, LPB = XB / TPL;
+  constexpr bool SUMS = !std::is_same<T, TS>::value;
+  static_assert(2 * LPB * lds_len<N>() * sizeof(T) >= XB * sizeof(double), "LDS for the sums");
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
@@ -50,56 +121,100 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, T* __res
   const bool ok = ra < nrows;
   const TI* ga = in.p[blockIdx.y] + ra * N;
   const TI* gb = ga + N;
-  T* oa = out + blockIdx.y * ostride + ra * N;
-  T* ob = oa + N;
-  TI shift = TI(0);
-  if constexpr (SUB) shift = TI(sub[blockIdx.y]);
+  TS* oa = out + blockIdx.y * ostride + ra * N;
+  TS* ob = oa + N;
+  double acc = 0.0;
+  double m = 0.0, wz = 0.0;
+  // residual mode: rows a and b are y and y + 1 of one z-plane (ny even),
+  // each the other's y neighbour
+  const double* pa = nullptr;
+  const double* pb = nullptr;
+  RowStencil sa{}, sb{};
+  if constexpr (RES) {
+    if (res.mean) m = res.mean[blockIdx.y];
+    if (ok) {
+      pa = res.p.p[blockIdx.y] + ra * N;
+      pb = pa + N;
+      const int y = (int)(ra % res.ny), z = (int)(ra / res.ny);
+      sa = row_stencil(res, N, y, z);
+      sb = row_stencil(res, N, y + 1, z);
+    }
+  }
+  if constexpr (SUMS) {
+    if (ok && norms) wz = res.dzf[ra / res.ny];  // rows ra, ra + 1 share a plane (ny even)
+  }
   XLds<T, N> lds(lds_mem, q, LPB);
   forward_body<T, N, BC, PTM, true>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
-        if constexpr (SUB) {
-          r = ok ? T(ga[e] - shift) : T(0);
-          i = ok ? T(gb[e] - shift) : T(0);
+        if (!ok) {
+          r = T(0);
+          i = T(0);
+          return;
+        }
+        if constexpr (RES) {
+          const double ca = pa[e], cb = pb[e];
+          const double va = row_residual<N, false, true>(res, pa, sa, double(ga[e]), m, e, ca,
+                                                         0.0, cb);
+          const double vb = row_residual<N, true, false>(res, pb, sb, double(gb[e]), m, e, cb,
+                                                         ca, 0.0);
+          acc += va * va + vb * vb;
+          r = T(va);
+          i = T(vb);
         } else {
-          r = ok ? T(ga[e]) : T(0);
-          i = ok ? T(gb[e]) : T(0);
+          r = T(ga[e]);
+          i = T(gb[e]);
+          if constexpr (SUMS) acc += wz * (double(ga[e]) + double(gb[e]));
         }
       },
       [&](int c0, T a0, T b0, int c1, T a1, T b1) {
         if (!ok) return;
-        oa[c0] = a0;
-        ob[c0] = b0;
-        oa[c1] = a1;
-        ob[c1] = b1;
+        oa[c0] = TS(a0);
+        ob[c0] = TS(b0);
+        oa[c1] = TS(a1);
+        ob[c1] = TS(b1);
       });
+  if constexpr (SUMS) {
+    if (norms) {
+      const double v[1] = {acc};
+      block_sums<XB, 1>(reinterpret_cast<double*>(lds_mem), v,
+                        norms + kNormSlots * ((long)blockIdx.y * gridDim.x + blockIdx.x) + 3);
+    }
+  }
 }
 
-// With FP32 input (the mixed chain) and `norms` set, each block also writes
-// the sums of e^2 and p^2 over its rows to norms[2 * (member * gridDim.x +
-// block) + {0, 1}], where e is the value added (or stored) and p the result.
-template <typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
-__global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long istride,
+// With FP32 input (the mixed chain: TS = float, arithmetic in T) and `norms`
+// set, each block also writes its sums of e^2, p^2 and dzf p (slots 0-2 of
+// its partial sums), where e is the value added (or stored) and p the result.
+// ACCUM: out[b] += result - sub[b] (sub may be null); otherwise out = result.
+template <typename TS, typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
+__global__ __launch_bounds__(256) void k_xinv(const TS* __restrict__ in, long istride,
                                                const Batch<TO> out, long nrows,
                                                const T* __restrict__ tab,
                                                const double* __restrict__ sub,
                                                const int* __restrict__ skip,
-                                               double* __restrict__ norms) {
+                                               double* __restrict__ norms,
+                                               const double* __restrict__ dzf, int ny) {
   constexpr int XB = x_block_threads<N>(), TPL = FftShape<N, PTM>::TPL, LPB = XB / TPL;
-  constexpr bool NORMS = !std::is_same<T, TO>::value;
+  constexpr bool NORMS = !std::is_same<TS, TO>::value;
+  static_assert(2 * LPB * lds_len<N>() * sizeof(T) >= 3 * XB * sizeof(double), "LDS for the sums");
   __shared__ T lds_mem[2 * LPB * lds_len<N>()];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
-  double ee = 0.0, pp = 0.0;
+  double ee = 0.0, pp = 0.0, wp = 0.0;
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long ra = (long)blockIdx.x * 2 * LPB + 2 * q;
   const bool ok = ra < nrows;
-  const T* ia = in + blockIdx.y * istride + ra * N;
-  const T* ib = ia + N;
+  const TS* ia = in + blockIdx.y * istride + ra * N;
+  const TS* ib = ia + N;
   TO* oa = out.p[blockIdx.y] + ra * N;
   TO* ob = oa + N;
   TO shift = TO(0);
   if constexpr (ACCUM) {
     if (sub) shift = TO(sub[blockIdx.y]);
+  }
+  double wz = 0.0;
+  if constexpr (NORMS) {
+    if (ok && norms) wz = dzf[ra / ny];  // rows ra, ra + 1 share a plane (ny even)
   }
   XLds<T, N> lds(lds_mem, q, LPB);
   inverse_body<T, N, BC, PTM, true>(
@@ -108,21 +223,21 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
         if constexpr (BC == BC_P) {
           // the packed real DFT pairs positions c0 (even) and c1 = c0 + 1:
           // one vector load per row
-          using T2 = typename Vec2<T>::type;
-          T2 va{T(0), T(0)}, vb{T(0), T(0)};
+          using S2 = typename Vec2<TS>::type;
+          S2 va{TS(0), TS(0)}, vb{TS(0), TS(0)};
           if (ok) {
-            va = *reinterpret_cast<const T2*>(ia + c0);
-            vb = *reinterpret_cast<const T2*>(ib + c0);
+            va = *reinterpret_cast<const S2*>(ia + c0);
+            vb = *reinterpret_cast<const S2*>(ib + c0);
           }
-          a0 = va.x;
-          a1 = va.y;
-          b0 = vb.x;
-          b1 = vb.y;
+          a0 = T(va.x);
+          a1 = T(va.y);
+          b0 = T(vb.x);
+          b1 = T(vb.y);
         } else {
-          a0 = ok ? ia[c0] : T(0);
-          b0 = ok ? ib[c0] : T(0);
-          a1 = ok ? ia[c1] : T(0);
-          b1 = ok ? ib[c1] : T(0);
+          a0 = ok ? T(ia[c0]) : T(0);
+          b0 = ok ? T(ib[c0]) : T(0);
+          a1 = ok ? T(ia[c1]) : T(0);
+          b1 = ok ? T(ib[c1]) : T(0);
         }
       },
       [&](int e, T r, T i) {
@@ -141,72 +256,114 @@ __global__ __launch_bounds__(256) void k_xinv(const T* __restrict__ in, long ist
         if constexpr (NORMS) {
           ee += double(da) * double(da) + double(db) * double(db);
           pp += double(pa) * double(pa) + double(pb) * double(pb);
+          wp += wz * (double(pa) + double(pb));
         }
       });
   if constexpr (NORMS) {
     if (norms) {
-      // fixed-order block reduction through the (now free) LDS of the transform
-      block_norms<XB>(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
+      const double v[3] = {ee, pp, wp};
+      block_sums<XB, 3>(reinterpret_cast<double*>(lds_mem), v,
+                        norms + kNormSlots * ((long)blockIdx.y * gridDim.x + blockIdx.x));
     }
   }
 }
 
-template <typename TI, typename T, int N, int BC, bool SUB, int PTM>
-__global__ __launch_bounds__(256) void k_xqfwd(const Batch<const TI> in, T* __restrict__ out,
+template <typename TI, typename T, typename TS, int N, int BC, bool RES, int PTM>
+__global__ __launch_bounds__(256) void k_xqfwd(const Batch<const TI> in, TS* __restrict__ out,
                                                 long ostride, long nrows,
-                                                const T* __restrict__ tab,
-                                                const double* __restrict__ sub,
-                                                const int* __restrict__ skip) {
-  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = x_block_threads<N>() / TPL;
-  __shared__ T lds_mem[2 * LPB * lds_len<H>()];
+                                                const T* __restrict__ tab, const ResidualArgs res,
+                                                const int* __restrict__ skip,
+                                                double* __restrict__ norms) {
+  constexpr int XB = x_block_threads<N>();
+  constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = XB / TPL;
+  constexpr bool SUMS = !std::is_same<T, TS>::value;
+  constexpr int LDS_T = 2 * LPB * lds_len<H>();
+  constexpr int RED_T = XB * (int)sizeof(double) / (int)sizeof(T);
+  __shared__ T lds_mem[LDS_T > RED_T ? LDS_T : RED_T];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long row = (long)blockIdx.x * LPB + q;
   const bool ok = row < nrows;
   const TI* g = in.p[blockIdx.y] + row * N;
-  T* o = out + blockIdx.y * ostride + row * N;
-  TI shift = TI(0);
-  if constexpr (SUB) shift = TI(sub[blockIdx.y]);
+  TS* o = out + blockIdx.y * ostride + row * N;
+  double acc = 0.0;
+  double m = 0.0, wz = 0.0;
+  const double* pr = nullptr;
+  RowStencil rs{};
+  if constexpr (RES) {
+    if (res.mean) m = res.mean[blockIdx.y];
+    if (ok) {
+      pr = res.p.p[blockIdx.y] + row * N;
+      rs = row_stencil(res, N, (int)(row % res.ny), (int)(row / res.ny));
+    }
+  }
+  if constexpr (SUMS) {
+    if (ok && norms) wz = res.dzf[row / res.ny];
+  }
   XLds<T, H> lds(lds_mem, q, LPB);
   quarter_body<T, N, PTM>(
       lds, t, tab,
       [&](int e, T& v) {
-        if constexpr (SUB) v = ok ? T(g[qpos<N, BC>(e)] - shift) : T(0);
-        else v = ok ? T(g[qpos<N, BC>(e)]) : T(0);
+        if (!ok) {
+          v = T(0);
+          return;
+        }
+        const int x = qpos<N, BC>(e);
+        if constexpr (RES) {
+          const double r = row_residual<N, false, false>(res, pr, rs, double(g[x]), m, x, pr[x],
+                                                         0.0, 0.0);
+          acc += r * r;
+          v = T(r);
+        } else {
+          v = T(g[x]);
+          if constexpr (SUMS) acc += wz * double(g[x]);
+        }
       },
       [&](int c, T v) {
-        if (ok) o[c] = v;
+        if (ok) o[c] = TS(v);
       });
+  if constexpr (SUMS) {
+    if (norms) {
+      const double v[1] = {acc};
+      block_sums<XB, 1>(reinterpret_cast<double*>(lds_mem), v,
+                        norms + kNormSlots * ((long)blockIdx.y * gridDim.x + blockIdx.x) + 3);
+    }
+  }
 }
 
-template <typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
-__global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long istride,
+template <typename TS, typename T, typename TO, int N, int BC, bool ACCUM, int PTM>
+__global__ __launch_bounds__(256) void k_xqinv(const TS* __restrict__ in, long istride,
                                                 const Batch<TO> out, long nrows,
                                                 const T* __restrict__ tab,
                                                 const double* __restrict__ sub,
                                                 const int* __restrict__ skip,
-                                                double* __restrict__ norms) {
+                                                double* __restrict__ norms,
+                                                const double* __restrict__ dzf, int ny) {
   constexpr int XB = x_block_threads<N>();
   constexpr int H = N / 2, TPL = FftShape<H, PTM>::TPL, LPB = XB / TPL;
-  constexpr bool NORMS = !std::is_same<T, TO>::value;
-  // the norm reduction needs 512 doubles of LDS
+  constexpr bool NORMS = !std::is_same<TS, TO>::value;
+  // the sums need 3 XB doubles of LDS
   constexpr int LDS_T = 2 * LPB * lds_len<H>();
-  constexpr int RED_T = 2 * XB * (int)sizeof(double) / (int)sizeof(T);
+  constexpr int RED_T = 3 * XB * (int)sizeof(double) / (int)sizeof(T);
   __shared__ T lds_mem[LDS_T > RED_T ? LDS_T : RED_T];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
-  double ee = 0.0, pp = 0.0;
+  double ee = 0.0, pp = 0.0, wp = 0.0;
   const int q = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long row = (long)blockIdx.x * LPB + q;
   const bool ok = row < nrows;
-  const T* ia = in + blockIdx.y * istride + row * N;
+  const TS* ia = in + blockIdx.y * istride + row * N;
   TO* o = out.p[blockIdx.y] + row * N;
   TO shift = TO(0);
   if constexpr (ACCUM) {
     if (sub) shift = TO(sub[blockIdx.y]);
   }
+  double wz = 0.0;
+  if constexpr (NORMS) {
+    if (ok && norms) wz = dzf[row / ny];
+  }
   XLds<T, H> lds(lds_mem, q, LPB);
   quarter_body<T, N, PTM>(
-      lds, t, tab, [&](int c, T& v) { v = ok ? ia[c] : T(0); },
+      lds, t, tab, [&](int c, T& v) { v = ok ? T(ia[c]) : T(0); },
       [&](int e, T v) {
         if (!ok) return;
         const int p = qpos<N, BC>(e);
@@ -217,10 +374,15 @@ __global__ __launch_bounds__(256) void k_xqinv(const T* __restrict__ in, long is
         if constexpr (NORMS) {
           ee += double(d) * double(d);
           pp += double(pv) * double(pv);
+          wp += wz * double(pv);
         }
       });
   if constexpr (NORMS) {
-    if (norms) block_norms<XB>(reinterpret_cast<double*>(lds_mem), ee, pp, norms);
+    if (norms) {
+      const double v[3] = {ee, pp, wp};
+      block_sums<XB, 3>(reinterpret_cast<double*>(lds_mem), v,
+                        norms + kNormSlots * ((long)blockIdx.y * gridDim.x + blockIdx.x));
+    }
   }
 }
 
@@ -257,16 +419,17 @@ long xpass_blocks(int nx, int bc, int pt, long nrows) {
 }
 #endif
 
-template <typename TI, typename T, int BC, bool SUB, int PTM>
-static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
-                                 long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+template <typename TI, typename T, typename TS, int BC, bool RES, int PTM>
+static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, TS* out, long ostride, int n,
+                                 long nrows, const T* tab, const ResidualArgs& ra,
+                                 const int* skip, double* norms, hipStream_t st) {
 #define VP_XF(NN)                                                                           \
   case NN: {                                                                                \
     const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
-    hipLaunchKernelGGL((k_xfwd<TI, T, NN, BC, SUB, canon_ptm<NN, PTM>()>),                 \
+    hipLaunchKernelGGL((k_xfwd<TI, T, TS, NN, BC, RES, canon_ptm<NN, PTM>()>),             \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
-                       st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
+                       st, in, out, ostride, nrows, tab, ra, skip, norms);                  \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -278,16 +441,17 @@ static hipError_t launch_xfwd_pt(const Batch<const TI>& in, int nb, T* out, long
   return hipGetLastError();
 }
 
-template <typename TI, typename T, int BC, bool SUB, int PTM>
-static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
-                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+template <typename TI, typename T, typename TS, int BC, bool RES, int PTM>
+static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, TS* out, long ostride, int n,
+                                  long nrows, const T* tab, const ResidualArgs& ra,
+                                  const int* skip, double* norms, hipStream_t st) {
 #define VP_XQF(NN)                                                                          \
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
-    hipLaunchKernelGGL((k_xqfwd<TI, T, NN, BC, SUB, canon_ptm<NN, PTM>()>),                \
+    hipLaunchKernelGGL((k_xqfwd<TI, T, TS, NN, BC, RES, canon_ptm<NN, PTM>()>),            \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
-                       st, in, out, ostride, nrows, tab, o.sub, o.skip);                    \
+                       st, in, out, ostride, nrows, tab, ra, skip, norms);                  \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -299,30 +463,33 @@ static hipError_t launch_xqfwd_pt(const Batch<const TI>& in, int nb, T* out, lon
   return hipGetLastError();
 }
 
-template <typename TI, typename T, int BC, bool SUB>
-static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, T* out, long ostride, int n,
-                                 long nrows, const T* tab, int pt, const PassOpts& o,
-                                 hipStream_t st) {
+template <typename TI, typename T, typename TS, int BC, bool RES>
+static hipError_t launch_xfwd_bc(const Batch<const TI>& in, int nb, TS* out, long ostride, int n,
+                                 long nrows, const T* tab, int pt, const ResidualArgs& ra,
+                                 const int* skip, double* norms, hipStream_t st) {
   if constexpr (BC == BC_ND || BC == BC_DN)
-    return pt == 8
-               ? launch_xqfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
-               : launch_xqfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
+    return pt == 8 ? launch_xqfwd_pt<TI, T, TS, BC, RES, 8>(in, nb, out, ostride, n, nrows, tab,
+                                                            ra, skip, norms, st)
+                   : launch_xqfwd_pt<TI, T, TS, BC, RES, 16>(in, nb, out, ostride, n, nrows, tab,
+                                                             ra, skip, norms, st);
   else
-    return pt == 8
-               ? launch_xfwd_pt<TI, T, BC, SUB, 8>(in, nb, out, ostride, n, nrows, tab, o, st)
-               : launch_xfwd_pt<TI, T, BC, SUB, 16>(in, nb, out, ostride, n, nrows, tab, o, st);
+    return pt == 8 ? launch_xfwd_pt<TI, T, TS, BC, RES, 8>(in, nb, out, ostride, n, nrows, tab,
+                                                           ra, skip, norms, st)
+                   : launch_xfwd_pt<TI, T, TS, BC, RES, 16>(in, nb, out, ostride, n, nrows, tab,
+                                                            ra, skip, norms, st);
 }
 
-template <typename T, typename TO, int BC, bool ACCUM, int PTM>
-static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out, int nb, int n,
-                                 long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+template <typename TS, typename T, typename TO, int BC, bool ACCUM, int PTM>
+static hipError_t launch_xinv_pt(const TS* in, long istride, const Batch<TO>& out, int nb, int n,
+                                 long nrows, const T* tab, const PassOpts& o,
+                                 const double* dzf, int ny, hipStream_t st) {
 #define VP_XI(NN)                                                                           \
   case NN: {                                                                                \
     const long rpb = 2 * (x_block_threads<NN>() / FftShape<NN, PTM>::TPL);                 \
-    hipLaunchKernelGGL((k_xinv<T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),               \
+    hipLaunchKernelGGL((k_xinv<TS, T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),           \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
-                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
+                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms, dzf, ny);  \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -334,16 +501,17 @@ static hipError_t launch_xinv_pt(const T* in, long istride, const Batch<TO>& out
   return hipGetLastError();
 }
 
-template <typename T, typename TO, int BC, bool ACCUM, int PTM>
-static hipError_t launch_xqinv_pt(const T* in, long istride, const Batch<TO>& out, int nb, int n,
-                                  long nrows, const T* tab, const PassOpts& o, hipStream_t st) {
+template <typename TS, typename T, typename TO, int BC, bool ACCUM, int PTM>
+static hipError_t launch_xqinv_pt(const TS* in, long istride, const Batch<TO>& out, int nb, int n,
+                                  long nrows, const T* tab, const PassOpts& o,
+                                  const double* dzf, int ny, hipStream_t st) {
 #define VP_XQI(NN)                                                                          \
   case NN: {                                                                                \
     constexpr long rpb = xq_rows_per_block<NN, PTM>();                                      \
-    hipLaunchKernelGGL((k_xqinv<T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),              \
+    hipLaunchKernelGGL((k_xqinv<TS, T, TO, NN, BC, ACCUM, canon_ptm<NN, PTM>()>),          \
                        dim3((unsigned)((nrows + rpb - 1) / rpb), (unsigned)nb),                 \
                        dim3(x_block_threads<NN>()), 0,                                      \
-                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms);           \
+                       st, in, istride, out, nrows, tab, o.sub, o.skip, o.norms, dzf, ny);  \
     break;                                                                                  \
   }
   if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
@@ -355,28 +523,30 @@ static hipError_t launch_xqinv_pt(const T* in, long istride, const Batch<TO>& ou
   return hipGetLastError();
 }
 
-template <typename T, typename TO, int BC, bool ACCUM>
-static hipError_t launch_xinv_bc(const T* in, long istride, const Batch<TO>& out, int nb, int n,
+template <typename TS, typename T, typename TO, int BC, bool ACCUM>
+static hipError_t launch_xinv_bc(const TS* in, long istride, const Batch<TO>& out, int nb, int n,
                                  long nrows, const T* tab, int pt, const PassOpts& o,
-                                 hipStream_t st) {
+                                 const double* dzf, int ny, hipStream_t st) {
   if constexpr (BC == BC_ND || BC == BC_DN)
-    return pt == 8
-               ? launch_xqinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
-               : launch_xqinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
+    return pt == 8 ? launch_xqinv_pt<TS, T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab,
+                                                              o, dzf, ny, st)
+                   : launch_xqinv_pt<TS, T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows,
+                                                               tab, o, dzf, ny, st);
   else
-    return pt == 8
-               ? launch_xinv_pt<T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab, o, st)
-               : launch_xinv_pt<T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab, o, st);
+    return pt == 8 ? launch_xinv_pt<TS, T, TO, BC, ACCUM, 8>(in, istride, out, nb, n, nrows, tab,
+                                                             o, dzf, ny, st)
+                   : launch_xinv_pt<TS, T, TO, BC, ACCUM, 16>(in, istride, out, nb, n, nrows, tab,
+                                                              o, dzf, ny, st);
 }
 
 #if VP_IN_PART(1)
 hipError_t launch_xfwd_f64(const Batch<const double>& in, int nb, double* out, long ostride,
                            int nx, int bc, long nrows, const double* tab, int pt,
                            hipStream_t st) {
-  const PassOpts o{};
+  const ResidualArgs ra{};
   return with_bc(bc, [&](auto B) {
-    return launch_xfwd_bc<double, double, decltype(B)::value, false>(in, nb, out, ostride, nx,
-                                                                     nrows, tab, pt, o, st);
+    return launch_xfwd_bc<double, double, double, decltype(B)::value, false>(
+        in, nb, out, ostride, nx, nrows, tab, pt, ra, nullptr, nullptr, st);
   });
 }
 
@@ -385,36 +555,42 @@ hipError_t launch_xinv_f64(const double* in, long istride, const Batch<double>& 
                            hipStream_t st) {
   const PassOpts o{};
   return with_bc(bc, [&](auto B) {
-    return launch_xinv_bc<double, double, decltype(B)::value, false>(in, istride, out, nb, nx,
-                                                                     nrows, tab, pt, o, st);
+    return launch_xinv_bc<double, double, double, decltype(B)::value, false>(
+        in, istride, out, nb, nx, nrows, tab, pt, o, nullptr, 1, st);
   });
 }
 #endif
 
 #if VP_IN_PART(2)
 hipError_t launch_xfwd_f32(const Batch<const double>& in, int nb, float* out, long ostride,
-                           int nx, int bc, long nrows, const float* tab, int pt,
+                           int nx, int bc, long nrows, const double* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
+  if (!o.geo || (o.residual && !o.geo->dzc)) return hipErrorInvalidValue;
+  const ResidualArgs& ra = *o.geo;
   return with_bc(bc, [&](auto B) {
     constexpr int BC = decltype(B)::value;
-    return o.sub ? launch_xfwd_bc<double, float, BC, true>(in, nb, out, ostride, nx, nrows, tab,
-                                                           pt, o, st)
-                 : launch_xfwd_bc<double, float, BC, false>(in, nb, out, ostride, nx, nrows, tab,
-                                                            pt, o, st);
+    return o.residual
+               ? launch_xfwd_bc<double, double, float, BC, true>(in, nb, out, ostride, nx, nrows,
+                                                                 tab, pt, ra, o.skip, o.norms, st)
+               : launch_xfwd_bc<double, double, float, BC, false>(in, nb, out, ostride, nx, nrows,
+                                                                  tab, pt, ra, o.skip, o.norms, st);
   });
 }
 #endif
 
 #if VP_IN_PART(3)
 hipError_t launch_xinv_f32(const float* in, long istride, const Batch<double>& out, int nb,
-                           int nx, int bc, long nrows, bool accum, const float* tab, int pt,
+                           int nx, int bc, long nrows, bool accum, const double* tab, int pt,
                            const PassOpts& o, hipStream_t st) {
+  if (!o.geo) return hipErrorInvalidValue;
+  const double* dzf = o.geo->dzf;
+  const int ny = o.geo->ny;
   return with_bc(bc, [&](auto B) {
     constexpr int BC = decltype(B)::value;
-    return accum ? launch_xinv_bc<float, double, BC, true>(in, istride, out, nb, nx, nrows, tab,
-                                                           pt, o, st)
-                 : launch_xinv_bc<float, double, BC, false>(in, istride, out, nb, nx, nrows, tab,
-                                                            pt, o, st);
+    return accum ? launch_xinv_bc<float, double, double, BC, true>(in, istride, out, nb, nx, nrows,
+                                                                   tab, pt, o, dzf, ny, st)
+                 : launch_xinv_bc<float, double, double, BC, false>(in, istride, out, nb, nx,
+                                                                    nrows, tab, pt, o, dzf, ny, st);
   });
 }
 #endif

@@ -12,76 +12,80 @@ namespace vp {
 // (x forward, z) wrote the last planes last, so they are the likeliest to
 // still sit in the Infinity Cache when the y pass starts (measured at 256^3,
 // two fields per launch: y forward 100 -> 91 us).
+// T: arithmetic and LDS type; TS: type of the data in HBM (float in the mixed
+// chain, which computes in FP64 and rounds only what it stores).
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC, int PTM>
-__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yfwd(T* __restrict__ data, int nx,
+template <typename T, typename TS, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yfwd(TS* __restrict__ data, int nx,
                                                                long plane, int llines,
                                                                const T* __restrict__ tab,
                                                                int nzm,
                                                                const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
+  using S2 = typename Vec2<TS>::type;
   extern __shared__ unsigned char smem_raw[];
   const int by = gridDim.y - 1 - blockIdx.y;  // plane, last first
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
-  T2* col = reinterpret_cast<T2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
+  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
                                   2 * q);
-  const int nx2 = nx >> 1;  // row stride in T2 units
+  const int nx2 = nx >> 1;  // row stride in S2 units
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   forward_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
-        const T2 v = col[(long)e * nx2];
-        r = v.x;
-        i = v.y;
+        const S2 v = col[(long)e * nx2];
+        r = T(v.x);
+        i = T(v.y);
       },
       [&](int c0, T a0, T b0, int c1, T a1, T b1) {
-        T2 v0, v1;
-        v0.x = a0;
-        v0.y = b0;
-        v1.x = a1;
-        v1.y = b1;
+        S2 v0, v1;
+        v0.x = TS(a0);
+        v0.y = TS(b0);
+        v1.x = TS(a1);
+        v1.y = TS(b1);
         col[(long)c0 * nx2] = v0;
         col[(long)c1 * nx2] = v1;
       });
 }
 
-template <typename T, int N, int BC, int PTM>
-__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(T* __restrict__ data, int nx,
+template <typename T, typename TS, int N, int BC, int PTM>
+__global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(TS* __restrict__ data, int nx,
                                                                long plane, int llines,
                                                                const T* __restrict__ tab,
                                                                int nzm,
                                                                const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
+  using S2 = typename Vec2<TS>::type;
   extern __shared__ unsigned char smem_raw[];
   const int by = gridDim.y - 1 - blockIdx.y;  // plane, last first
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
-  T2* col = reinterpret_cast<T2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
+  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
                                   2 * q);
   const int nx2 = nx >> 1;
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   inverse_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int c0, int c1, T& a0, T& b0, T& a1, T& b1) {
-        const T2 v0 = col[(long)c0 * nx2], v1 = col[(long)c1 * nx2];
-        a0 = v0.x;
-        b0 = v0.y;
-        a1 = v1.x;
-        b1 = v1.y;
+        const S2 v0 = col[(long)c0 * nx2], v1 = col[(long)c1 * nx2];
+        a0 = T(v0.x);
+        b0 = T(v0.y);
+        a1 = T(v1.x);
+        b1 = T(v1.y);
       },
       [&](int e, T r, T i) {
-        T2 v;
-        v.x = r;
-        v.y = i;
+        S2 v;
+        v.x = TS(r);
+        v.y = TS(i);
         col[(long)e * nx2] = v;
       });
 }
 
-template <typename T, int N, int BC, bool INV, int PTM>
-__global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long plane, int lcols,
+template <typename T, typename TS, int N, int BC, bool INV, int PTM>
+__global__ __launch_bounds__(512) void k_yq(TS* __restrict__ data, int nx, long plane, int lcols,
                                              const T* __restrict__ tab, int nzm,
                                              const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
@@ -90,16 +94,16 @@ __global__ __launch_bounds__(512) void k_yq(T* __restrict__ data, int nx, long p
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int cols = 1 << lcols;
   const int q = threadIdx.x & (cols - 1), t = threadIdx.x >> lcols;
-  T* col = data + (long)by * plane + (long)blockIdx.x * cols + q;
+  TS* col = data + (long)by * plane + (long)blockIdx.x * cols + q;
   YLds<T, N / 2> lds(reinterpret_cast<T2*>(smem_raw), q, cols);
   if constexpr (INV) {
     quarter_body<T, N, PTM>(
-        lds, t, tab, [&](int c, T& v) { v = col[(long)c * nx]; },
-        [&](int e, T v) { col[(long)qpos<N, BC>(e) * nx] = T(2) * v; });
+        lds, t, tab, [&](int c, T& v) { v = T(col[(long)c * nx]); },
+        [&](int e, T v) { col[(long)qpos<N, BC>(e) * nx] = TS(T(2) * v); });
   } else {
     quarter_body<T, N, PTM>(
-        lds, t, tab, [&](int e, T& v) { v = col[(long)qpos<N, BC>(e) * nx]; },
-        [&](int c, T v) { col[(long)c * nx] = v; });
+        lds, t, tab, [&](int e, T& v) { v = T(col[(long)qpos<N, BC>(e) * nx]); },
+        [&](int c, T v) { col[(long)c * nx] = TS(v); });
   }
 }
 
@@ -115,8 +119,8 @@ int ypass_tile_cols(int nx, int ny) { return 2 * ypass_lines(nx, ny); }
 #endif
 
 // quarter-wave y pass: one column per line, 2*lines columns per block
-template <typename T, int BC, bool FWD, int PTM>
-static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+template <typename T, typename TS, int BC, bool FWD, int PTM>
+static hipError_t launch_yq_pt(TS* data, int nx, int ny, int nplanes, const T* tab, int lines,
                                int nzm, const int* skip, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
   const int cols = 2 * lines;
@@ -128,7 +132,7 @@ static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* ta
   case NN: {                                                                       \
     const int nthr = cols * FftShape<NN / 2, PTM>::TPL;                            \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN / 2>() * (cols + 1);        \
-    auto kern = &k_yq<T, NN, BC, !FWD, canon_ptm<NN, PTM>()>;                              \
+    auto kern = &k_yq<T, TS, NN, BC, !FWD, canon_ptm<NN, PTM>()>;                              \
     if (nthr > 512) return hipErrorInvalidValue;                                   \
     if (shm > 65536) {                                                             \
       const hipError_t e = allow_large_lds(kern);                                  \
@@ -145,8 +149,8 @@ static hipError_t launch_yq_pt(T* data, int nx, int ny, int nplanes, const T* ta
   return hipGetLastError();
 }
 
-template <typename T, int BC, bool FWD, int PTM>
-static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* tab, int lines,
+template <typename T, typename TS, int BC, bool FWD, int PTM>
+static hipError_t launch_ystd_pt(TS* data, int nx, int ny, int nplanes, const T* tab, int lines,
                                  int nzm, const PassOpts& o, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
   int ll = 0;
@@ -158,7 +162,7 @@ static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* 
     const int nthr = lines * FftShape<NN, PTM>::TPL;                               \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);           \
     constexpr int PC = canon_ptm<NN, PTM>();                                               \
-    auto kern = FWD ? &k_yfwd<T, NN, BC, PC> : &k_yinv<T, NN, BC, PC>;                     \
+    auto kern = FWD ? &k_yfwd<T, TS, NN, BC, PC> : &k_yinv<T, TS, NN, BC, PC>;                     \
     if (shm > 65536) {                                                             \
       const hipError_t e = allow_large_lds(kern);                                  \
       if (e != hipSuccess) return e;                                               \
@@ -175,23 +179,23 @@ static hipError_t launch_ystd_pt(T* data, int nx, int ny, int nplanes, const T* 
   return hipGetLastError();
 }
 
-template <typename T, int BC, bool FWD, int PTM>
-static hipError_t launch_y_pt(T* data, int nx, int ny, int nplanes, const T* tab,
+template <typename T, typename TS, int BC, bool FWD, int PTM>
+static hipError_t launch_y_pt(TS* data, int nx, int ny, int nplanes, const T* tab,
                               const PassOpts& o, hipStream_t st) {
   int lines = ypass_lines(nx, ny);
   if (o.lines > 0 && o.lines < lines) lines = o.lines;
   const int nzm = o.nzm > 0 ? o.nzm : nplanes;
   if constexpr (BC == BC_ND || BC == BC_DN)
-    return launch_yq_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o.skip, st);
+    return launch_yq_pt<T, TS, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o.skip, st);
   else
-    return launch_ystd_pt<T, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o, st);
+    return launch_ystd_pt<T, TS, BC, FWD, PTM>(data, nx, ny, nplanes, tab, lines, nzm, o, st);
 }
 
-template <typename T, int BC, bool FWD>
-static hipError_t launch_y_bc(T* data, int nx, int ny, int nplanes, const T* tab, int pt,
+template <typename T, typename TS, int BC, bool FWD>
+static hipError_t launch_y_bc(TS* data, int nx, int ny, int nplanes, const T* tab, int pt,
                               const PassOpts& o, hipStream_t st) {
-  return pt == 8 ? launch_y_pt<T, BC, FWD, 8>(data, nx, ny, nplanes, tab, o, st)
-                 : launch_y_pt<T, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
+  return pt == 8 ? launch_y_pt<T, TS, BC, FWD, 8>(data, nx, ny, nplanes, tab, o, st)
+                 : launch_y_pt<T, TS, BC, FWD, 16>(data, nx, ny, nplanes, tab, o, st);
 }
 
 #if VP_IN_PART(1)
@@ -201,19 +205,19 @@ hipError_t launch_y_f64(double* data, int nx, int ny, int nplanes, int bc, bool 
   o.lines = lines;
   return with_bc(bc, [&](auto B) {
     constexpr int BC = decltype(B)::value;
-    return fwd ? launch_y_bc<double, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
-               : launch_y_bc<double, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+    return fwd ? launch_y_bc<double, double, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<double, double, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
   });
 }
 #endif
 
 #if VP_IN_PART(2)
 hipError_t launch_y_f32(float* data, int nx, int ny, int nplanes, int bc, bool fwd,
-                        const float* tab, int pt, const PassOpts& o, hipStream_t st) {
+                        const double* tab, int pt, const PassOpts& o, hipStream_t st) {
   return with_bc(bc, [&](auto B) {
     constexpr int BC = decltype(B)::value;
-    return fwd ? launch_y_bc<float, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
-               : launch_y_bc<float, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
+    return fwd ? launch_y_bc<double, float, BC, true>(data, nx, ny, nplanes, tab, pt, o, st)
+               : launch_y_bc<double, float, BC, false>(data, nx, ny, nplanes, tab, pt, o, st);
   });
 }
 #endif

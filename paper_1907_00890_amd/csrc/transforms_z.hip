@@ -11,30 +11,32 @@ namespace vp {
 //   x <- x * scale / (lamx[kx] + lamy[ky] + lamz[c]),  0 where that is 0
 // (only the constant mode), which is the pseudo-inverse; the removed
 // constant (the coefficient times scale: the mean) goes to mean_out[member].
+// T: arithmetic and LDS type; TS: type of the data in HBM.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int BC, int PTM>
+template <typename T, typename TS, int N, int BC, int PTM>
 __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
-    T* __restrict__ data, int nx, long plane, int llines, const T* __restrict__ tab,
+    TS* __restrict__ data, int nx, long plane, int llines, const T* __restrict__ tab,
     const double* __restrict__ lamx, const double* __restrict__ lamy,
     const double* __restrict__ lamz, double scale, long batch_stride,
     double* __restrict__ mean_out, const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
+  using S2 = typename Vec2<TS>::type;
   extern __shared__ unsigned char smem_raw[];
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
   const long pos = (long)blockIdx.x * 2 * lines + 2 * q;  // line a; line b = pos + 1
-  T2* col = reinterpret_cast<T2*>(data + blockIdx.y * batch_stride + pos);
-  const long pstride = plane >> 1;  // z stride in T2 units
+  S2* col = reinterpret_cast<S2*>(data + blockIdx.y * batch_stride + pos);
+  const long pstride = plane >> 1;  // z stride in S2 units
   const double la = lamx[pos % nx] + lamy[pos / nx];
   const double lb = lamx[(pos + 1) % nx] + lamy[(pos + 1) / nx];
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   spectral_body<T, N, BC, PTM>(
       lds, t, tab,
       [&](int e, T& r, T& i) {
-        const T2 v = col[(long)e * pstride];
-        r = v.x;
-        i = v.y;
+        const S2 v = col[(long)e * pstride];
+        r = T(v.x);
+        i = T(v.y);
       },
       [&](int c, T& a, T& b) {
         const double lz = lamz[c];
@@ -48,15 +50,15 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
         b = T(double(b) * (scale / db));
       },
       [&](int e, T r, T i) {
-        T2 v;
-        v.x = r;
-        v.y = i;
+        S2 v;
+        v.x = TS(r);
+        v.y = TS(i);
         col[(long)e * pstride] = v;
       });
 }
 
-template <typename T, int BC, int PTM>
-static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int nb,
+template <typename T, typename TS, int BC, int PTM>
+static hipError_t launch_zspec_pt(TS* data, const ZSpecArgs& a, const T* tab, int nb,
                                   const int* skip, hipStream_t st) {
   using T2 = typename Vec2<T>::type;
   const long plane = (long)a.nx * a.ny;
@@ -72,7 +74,7 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   case NN: {                                                                               \
     const int nthr = lines * FftShape<NN, PTM>::TPL;                                       \
     const size_t shm = sizeof(T2) * (size_t)lds_len<NN>() * (lines + 1);                   \
-    auto kern = &k_zspec<T, NN, BC, canon_ptm<NN, PTM>()>;                                 \
+    auto kern = &k_zspec<T, TS, NN, BC, canon_ptm<NN, PTM>()>;                                 \
     if (shm > 65536) {                                                                     \
       const hipError_t e = allow_large_lds(kern);                                          \
       if (e != hipSuccess) return e;                                                       \
@@ -89,30 +91,30 @@ static hipError_t launch_zspec_pt(T* data, const ZSpecArgs& a, const T* tab, int
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_zspec_t(T* data, const ZSpecArgs& a, const T* tab, int pt, int nb,
+template <typename T, typename TS>
+static hipError_t launch_zspec_t(TS* data, const ZSpecArgs& a, const T* tab, int pt, int nb,
                                  const int* skip, hipStream_t st) {
   return with_bc(a.bcz, [&](auto B) -> hipError_t {
     constexpr int BC = decltype(B)::value;
     if constexpr (BC == BC_ND || BC == BC_DN)
       return hipErrorInvalidValue;  // the tridiagonal pass takes these
     else
-      return pt == 8 ? launch_zspec_pt<T, BC, 8>(data, a, tab, nb, skip, st)
-                     : launch_zspec_pt<T, BC, 16>(data, a, tab, nb, skip, st);
+      return pt == 8 ? launch_zspec_pt<T, TS, BC, 8>(data, a, tab, nb, skip, st)
+                     : launch_zspec_pt<T, TS, BC, 16>(data, a, tab, nb, skip, st);
   });
 }
 
 #if VP_IN_PART(1)
 hipError_t launch_zspec_f64(double* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
                             hipStream_t st) {
-  return launch_zspec_t<double>(data, a, tab, pt, nb, nullptr, st);
+  return launch_zspec_t<double, double>(data, a, tab, pt, nb, nullptr, st);
 }
 #endif
 
 #if VP_IN_PART(2)
-hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const float* tab, int pt, int nb,
+hipError_t launch_zspec_f32(float* data, const ZSpecArgs& a, const double* tab, int pt, int nb,
                             const int* skip, hipStream_t st) {
-  return launch_zspec_t<float>(data, a, tab, pt, nb, skip, st);
+  return launch_zspec_t<double, float>(data, a, tab, pt, nb, skip, st);
 }
 #endif
 

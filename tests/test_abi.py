@@ -120,7 +120,7 @@ def test_null_plan_calls(lib):
 def test_footprint(lib):
     n = 64 * 64 * 64
     assert lib.poisson_plan_footprint(64, 64, 64, 0, 1) >= 8 * n
-    assert lib.poisson_plan_footprint(64, 64, 64, 1, 1) >= 20 * n
+    assert lib.poisson_plan_footprint(64, 64, 64, 1, 1) >= 12 * n
     assert lib.poisson_plan_footprint(0, 64, 64, 0, 1) < 0
     # one workspace slot per batch member
     one = lib.poisson_plan_footprint(64, 64, 64, 0, 1)

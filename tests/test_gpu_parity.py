@@ -249,11 +249,12 @@ def test_mixed_parity(torch_dev, case, dc):
     err = rel_l2(p.cpu().numpy(), ref)
     print(f"mixed {case} dc={dc}: rel L2 {err:.3e}")
     assert err <= MIXED_TOL, err
-    # planes marched per block by the residual (one, an odd count, all)
-    for kc in (1, 3, nz):
-        plan.tune("stencil_planes", kc)
+    # both radix schedules of the x passes (the correction's x forward forms
+    # the defect itself)
+    for xr in (8, 16):
+        plan.tune("x_radix", xr)
         q = plan.solve(_dev(torch, f)).cpu().numpy()
-        assert rel_l2(q, ref) <= MIXED_TOL, kc
+        assert rel_l2(q, ref) <= MIXED_TOL, xr
 
 
 RADIX8_CASES = [
@@ -297,8 +298,8 @@ def test_radix8_schedule_parity(torch_dev, case):
                                   (64, 64, 64, "PPP", None)],
                          ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
 def test_mixed_stops_on_error_estimate(torch_dev, case):
-    """Long FP32 lines need a second correction: the device-side stopping rule
-    takes it where needed and stops after one step where that suffices."""
+    """The device-side stopping rule: its estimate bounds the error left after
+    the steps it takes (one where that suffices), and after one fixed step."""
     torch = torch_dev
     nx, ny, nz, bc, beta = case
     g = _grid(nx, ny, nz, bc, beta)
@@ -310,16 +311,16 @@ def test_mixed_stops_on_error_estimate(torch_dev, case):
     err = rel_l2(p, ref)
     print(f"mixed {case}: {steps} steps, estimate {est:.2e}, error {err:.2e}")
     assert err <= MIXED_TOL and 1 <= steps <= 3 and est <= 1e-11
-    # the estimate bounds the error it predicts (within a factor of 10, above
-    # the FP64 parity floor)
-    assert err <= 10 * est + FP64_TOL
+    # the estimate bounds the error it predicts (above the FP64 parity floor)
+    assert err <= est + FP64_TOL
     # fixed single step: the estimate exposes what one step leaves
     plan.set_mixed(1, tol=0.0)
     p1 = plan.solve(_dev(torch, f)).cpu().numpy()
     (s1, e1), = plan.mixed_report()
     assert s1 == 1
     err1 = rel_l2(p1, ref)
-    assert err1 <= 10 * e1 + FP64_TOL
+    print(f"mixed {case}, one step: estimate {e1:.2e}, error {err1:.2e}")
+    assert err1 <= e1 + FP64_TOL
 
 
 @pytest.mark.parametrize("case", [(32, 32, 32, "PPP", None), (128, 128, 128, "PPN", None),
