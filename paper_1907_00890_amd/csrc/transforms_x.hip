@@ -6,26 +6,36 @@
 
 namespace vp {
 
-// Sums over a block's threads of K per-thread values, written to out[0..K)
-// (fixed order, through the block's LDS, which the caller no longer needs;
-// XB threads, red holds K * XB doubles).
+// Sums over a block's threads of K per-thread values, written to out[0..K):
+// a butterfly over the 64 lanes of each wave, then one LDS step over the
+// XB / 64 waves (fixed order; red: K * XB / 64 doubles of the block's LDS,
+// which the caller no longer needs).
 template <int XB, int K>
 __device__ __forceinline__ void block_sums(double* red, const double (&v)[K],
                                            double* __restrict__ out) {
-  __syncthreads();
+  constexpr int NW = XB / 64;
+  double w[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) red[i * XB + threadIdx.x] = v[i];
-  __syncthreads();
-  for (int w = XB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
+  for (int i = 0; i < K; ++i) {
+    w[i] = v[i];
 #pragma unroll
-      for (int i = 0; i < K; ++i) red[i * XB + threadIdx.x] += red[i * XB + threadIdx.x + w];
-    }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) w[i] += __shfl_xor(w[i], o, 64);
   }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) red[i * NW + wid] = w[i];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < K; ++i) out[i] = red[i * XB];
+    for (int i = 0; i < K; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) t += red[i * NW + j];
+      out[i] = t;
+    }
   }
 }
 
@@ -169,10 +179,23 @@ __global__ __launch_bounds__(256) void k_xfwd(const Batch<const TI> in, TS* __re
       },
       [&](int c0, T a0, T b0, int c1, T a1, T b1) {
         if (!ok) return;
-        oa[c0] = TS(a0);
-        ob[c0] = TS(b0);
-        oa[c1] = TS(a1);
-        ob[c1] = TS(b1);
+        if constexpr (BC == BC_P) {
+          // the packed real DFT pairs positions c0 (even) and c1 = c0 + 1:
+          // one vector store per row
+          using S2 = typename Vec2<TS>::type;
+          S2 va, vb;
+          va.x = TS(a0);
+          va.y = TS(a1);
+          vb.x = TS(b0);
+          vb.y = TS(b1);
+          *reinterpret_cast<S2*>(oa + c0) = va;
+          *reinterpret_cast<S2*>(ob + c0) = vb;
+        } else {
+          oa[c0] = TS(a0);
+          ob[c0] = TS(b0);
+          oa[c1] = TS(a1);
+          ob[c1] = TS(b1);
+        }
       });
   if constexpr (SUMS) {
     if (norms) {
