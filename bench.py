@@ -81,7 +81,7 @@ def parse():
                     help="the same for the main workload's mixed plan")
     ap.add_argument("--cpu-sample", default="ppn256",
                     help="workload the CPU oracle is timed on (bounded sample)")
-    ap.add_argument("--serve-rates", default="1000",
+    ap.add_argument("--serve-rates", default="sweep",
                     help="comma-separated request rates (req/s) of the serving mix; "
                          "'sweep' for 50,100,200,500,1000,2000; 'none' to skip")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -297,7 +297,8 @@ def serve_bench(torch, dev, rates, n, lanes, max_batch):
             early.pop(t, None) or srv.wait(t, -1)
         mix.release()
         for rate in rates:
-            r = serve_run(srv, mix, rate, n, seed=5)
+            # about 10 s of arrivals per rate, 500 to n requests
+            r = serve_run(srv, mix, rate, int(min(n, max(500, 10 * rate))), seed=5)
             print(f"[serve] rate {rate} req/s: p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms, "
                   f"{r['throughput_req_s']} req/s, mean batch {r['mean_batch']}",
                   file=sys.stderr, flush=True)
@@ -460,7 +461,36 @@ def interface_outflow_run(torch, dev, steps, no_autotune):
     b.record()
     torch.cuda.synchronize()
     ms_step = a.elapsed_time(b) / steps
+    # the same step with the interface terms formed inside its first and last
+    # passes (vof_step_interface: s in the right-hand side, q in the epilogue)
+    sv = torch.empty_like(dC)
+
+    def step_fused():
+        plan.step_interface(us, vs, ws, phat, rho, rho2, dC, dm, rho1, rho2, 1.0, p=p, phi=phi,
+                            s=sv, out=ue, gamma=ug)
+
+    for _ in range(2):
+        step_fused()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        step_fused()
+    b.record()
+    torch.cuda.synchronize()
+    ms_fused = a.elapsed_time(b) / steps
     plan.kernel_times()
+    plan.set_profiling(True, classes=["rhs_assembly", "step_epilogue"])
+    for _ in range(steps):
+        step_fused()
+    torch.cuda.synchronize()
+    kf = plan.kernel_times()
+    plan.set_profiling(False)
+    plan.set_profiling(True, classes=["rhs_assembly", "step_epilogue"])
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ks = plan.kernel_times()
+    plan.set_profiling(False)
     plan.set_profiling(True, classes=["interface_terms"])
     for _ in range(steps):
         plan.interface_terms(dC, dm, rho1, rho2, out=terms)
@@ -474,7 +504,17 @@ def interface_outflow_run(torch, dev, steps, no_autotune):
            "interface_terms": {"ms": round(ms_if, 4), "alg_bytes": 48 * npts,
                                "gbs": round(48 * npts / (ms_if * 1e-3) / 1e9, 1),
                                "planes": knobs["interface_planes"], "tile": knobs["interface_tile"]},
-           "step_with_interface_terms_ms": round(ms_step, 4), "tuning": tuned, "solve_ms": {}}
+           "step_with_interface_terms_ms": round(ms_step, 4),
+           "step_interface_fused_ms": round(ms_fused, 4),
+           "fused_vs_separate": {
+               "separate": {"interface_terms_ms": round(ms_if, 4),
+                            "rhs_ms": round(ks["rhs_assembly"][0] / ks["rhs_assembly"][1], 4),
+                            "epilogue_ms": round(ks["step_epilogue"][0] / ks["step_epilogue"][1], 4),
+                            "model_bytes_N": "48 + 56 + 152"},
+               "fused": {"rhs_with_s_ms": round(kf["rhs_assembly"][0] / kf["rhs_assembly"][1], 4),
+                         "epilogue_with_q_ms": round(kf["step_epilogue"][0] / kf["step_epilogue"][1], 4),
+                         "model_bytes_N": "72 + 144"}},
+           "tuning": tuned, "solve_ms": {}}
     out = torch.empty_like(f)
     for bc in ("NNNNND", "DDD", "PPN"):
         sp = Plan(n, n, n, 1.0 / n, 1.0 / n, dz, bc)
@@ -591,16 +631,19 @@ def mixed512_run(torch, dev, reps, no_autotune):
     return res
 
 
-def cpu_baseline(sample_name):
-    """Time the FP64 oracle's project + extend step on a bounded sample."""
+def cpu_baseline(sample_name, runs=3):
+    """Time the FP64 oracle's project + extend step on a bounded sample: the
+    median of `runs` runs with the host's BLAS threads, and of `runs` runs on
+    one thread (the oracle's FFTs run on one thread either way)."""
     import numpy as np
 
     import oracle
     import vofsynth
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = 1
     cfg = vofsynth.config(sample_name)
     g = oracle.Grid.from_config(cfg)
@@ -611,15 +654,30 @@ def cpu_baseline(sample_name):
     s = 1e-2 * vofsynth.grad_mag_central(C, g.dx, g.dy, dzf, cfg.bc)[0]
     q = vofsynth.interface_normal_faces(C, g.dx, g.dy, dzf, cfg.bc, 1e-5)
     phat = vofsynth.gaussian_field(cfg.shape, 101)
-    t0 = time.perf_counter()
-    u, v, w, p = oracle.project(us, vs, ws, phat, rho, 1.0, s, 1.0, g)
-    oracle.extend(u, v, w, s, g, q=q)
-    t = time.perf_counter() - t0
-    return {"value": round(2 * cfg.npts / t / 1e6, 3), "unit": "Mpts/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"one project + extend step of the same recipe on {cfg.nx}x{cfg.ny}x{cfg.nz} "
-                      f"{cfg.bc} (FP64 numpy/scipy oracle, {t:.1f} s)",
-            "host_cpus": os.cpu_count()}
+
+    def one():
+        t0 = time.perf_counter()
+        u, v, w, p = oracle.project(us, vs, ws, phat, rho, 1.0, s, 1.0, g)
+        oracle.extend(u, v, w, s, g, q=q)
+        return time.perf_counter() - t0
+
+    t_all = sorted(one() for _ in range(runs))
+    t_one = []
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t_one = sorted(one() for _ in range(runs))
+    med = t_all[len(t_all) // 2]
+    out = {"value": round(2 * cfg.npts / med / 1e6, 3), "unit": "Mpts/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": f"one project + extend step of the same recipe on {cfg.nx}x{cfg.ny}x{cfg.nz} "
+                     f"{cfg.bc} (FP64 numpy/scipy oracle), median of {runs} runs "
+                     f"({', '.join(f'{t:.1f}' for t in t_all)} s)",
+           "host_cpus": os.cpu_count()}
+    if t_one:
+        med1 = t_one[len(t_one) // 2]
+        out["one_thread"] = {"value": round(2 * cfg.npts / med1 / 1e6, 3), "cores": 1,
+                             "runs_s": [round(t, 2) for t in t_one]}
+    return out
 
 
 def main():

@@ -305,6 +305,29 @@ int interface_terms(poisson_plan* plan, const double* C, const double* mdot, dou
                     void* hip_stream);
 
 /*
+ * vof_step with the interface terms formed inside the step's first and last
+ * passes (sections 3.2 and 3.6; the same terms as interface_terms): the
+ * right-hand-side pass takes |grad C| by Youngs' differences and writes
+ * s = mdot (1/rho2 - 1/rho1) |grad C| to `s` (the source of the pressure
+ * equation and the right-hand side of the Stefan potential), then the two
+ * solves run, then the epilogue forms q = (mdot / rho_e) n on the faces from
+ * C and mdot and writes u_Gamma = u_1^e - q.  The fields s and q never make
+ * a separate pass.  Same bits as interface_terms followed by vof_step with
+ * src_p = src_ext = s and that q.
+ *   u, v, w : u* in, u^{n+1} out (in place); phat, rho, rho0, dt as vof_step;
+ *   C, mdot, rho1, rho2, phase : as interface_terms;
+ *   p, phi, s : device outputs (distinct); ue, ve, we : optional (all or none);
+ *   ug, vg, wg : required.
+ * VP_EUNSUPPORTED for a plan with an outflow at a lower end (use
+ * interface_terms and vof_step_lf), VP_EINVAL for bad arguments.
+ */
+int vof_step_interface(poisson_plan* plan, double* u, double* v, double* w, const double* phat,
+                       const double* rho, double rho0, const double* C, const double* mdot,
+                       double rho1, double rho2, int phase, double dt, double* p, double* s,
+                       double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
+                       double* phi, void* hip_stream);
+
+/*
  * VoF advection of section 3.1: C^{n+1} from C^n and the interface velocity
  * u_Gamma of section 3.6 (eq. cadv) by directional splitting, x then y then
  * z, each sweep implicit in its own result through the divergence of its

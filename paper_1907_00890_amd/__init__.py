@@ -276,6 +276,32 @@ class Plan:
                                        self._lower(lower_e, "lower_e"), *tail), "vof_step_lf")
         return (u, v, w, p, phi, *es, *gs)
 
+    def step_interface(self, u, v, w, phat, rho, rho0, C, mdot, rho1, rho2, dt, phase=1,
+                       p=None, phi=None, s=None, out=None, gamma=None, stream=None):
+        """One time step with the interface terms formed inside its first and last
+        passes (vof_step_interface): s from C and mdot in the right-hand-side pass
+        (returned; the Stefan potential's right-hand side), q in the epilogue.
+        Returns (u, v, w, p, phi, s, ue, ve, we, ug, vg, wg); ue.. are None unless
+        `out` is given.  Same bits as interface_terms followed by step."""
+        if p is None:
+            p = self._new(u)
+        if phi is None:
+            phi = self._new(u)
+        if s is None:
+            s = self._new(u)
+        if gamma is None:
+            gamma = (self._new(u), self._new(u), self._new(u))
+        es = (None, None, None) if out is None else out
+        args = [self._h, self._ptr(u, "u"), self._ptr(v, "v"), self._ptr(w, "w"),
+                self._ptr(phat, "phat"), self._ptr(rho, "rho"), float(rho0), self._ptr(C, "C"),
+                self._ptr(mdot, "mdot"), float(rho1), float(rho2), int(phase), float(dt),
+                self._ptr(p, "p"), self._ptr(s, "s")]
+        args += [self._ptr(t, "out", optional=True) for t in es]
+        args += [self._ptr(t, "gamma") for t in gamma]
+        args += [self._ptr(phi, "phi"), _stream_ptr(stream)]
+        check(_lib.lib.vof_step_interface(*args), "vof_step_interface")
+        return (u, v, w, p, phi, s, *es, *gamma)
+
     def set_mixed(self, dc_steps: int, tol=None):
         """Mixed plans: at most dc_steps FP64 defect-correction steps, stopping per
         member once the estimated error is at most tol (tol <= 0: every step)."""

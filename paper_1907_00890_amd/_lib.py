@@ -58,6 +58,8 @@ SIGNATURES = {
     "extend_liquid_velocity_batched": (_i, [_p, _i, ctypes.POINTER(ExtendFields), _p]),
     "vof_step": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _d, _p] + [_p] * 11 + [_p]),
     "interface_terms": (_i, [_p, _p, _p, _d, _d, _i, _p, _p, _p, _p, _p]),
+    "vof_step_interface": (_i, [_p, _p, _p, _p, _p, _p, _d, _p, _p, _d, _d, _i, _d, _p, _p]
+                           + [_p] * 7 + [_p]),
     "vof_advect": (_i, [_p, _p, _p, _p, _p, _lf, _d, _d, _i, _p, _p]),
     "project_lf": (_i, [_p, _p, _p, _p, _lf, _p, _p, _d, _p, _d, _p, _p]),
     "extend_liquid_velocity_lf": (_i, [_p, _p, _p, _p, _lf, _p, _p, _p, _p, _p, _p, _p, _lf,

@@ -201,6 +201,34 @@ constexpr int kInterfaceThreads = 512;
 hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
                             double rho2, double rho_e, double* s, double* qx, double* qy,
                             double* qz, hipStream_t st);
+// The interface terms fused into the step's first and last passes (the
+// march of launch_interface carrying a second stencil):
+//   launch_rhs_interface      : s (written) and the pressure right-hand side b
+//                               = launch_rhs with src = s; reads u, v, w, ph, rho;
+//   launch_epilogue_interface : launch_step_epilogue with q the face means of
+//                               a = (mdot / rho_e) n, in place on uo, vo, wo;
+//                               ue.. optional, ug.. required.
+struct IfStepArgs {
+  const double* u = nullptr;  // u*, v*, w* (right-hand side)
+  const double* v = nullptr;
+  const double* w = nullptr;
+  double* uo = nullptr;       // u*, v*, w* in, u^{n+1} out (epilogue)
+  double* vo = nullptr;
+  double* wo = nullptr;
+  const double* ph = nullptr;
+  const double* rho = nullptr;
+  double rho0 = 1.0, dt = 1.0;
+  double* b = nullptr;
+  const double* p = nullptr;
+  const double* phi = nullptr;
+  double *ue = nullptr, *ve = nullptr, *we = nullptr;
+  double *ug = nullptr, *vg = nullptr, *wg = nullptr;
+};
+hipError_t launch_rhs_interface(const GridArgs& g, const double* C, const double* mdot,
+                                double rho1, double rho2, double* s, const IfStepArgs& a,
+                                hipStream_t st);
+hipError_t launch_epilogue_interface(const GridArgs& g, const double* C, const double* mdot,
+                                     double rho_e, const IfStepArgs& a, hipStream_t st);
 // Faces at -1/2 of a lower outflow end in direction dir (0 x, 1 y, 2 z):
 // their velocities uf (and ue on them, uef) as one plane; see stencils.hip.
 enum : int { LF_RHS = 0, LF_CORRECT = 1, LF_EXTEND = 2, LF_STEP = 3 };

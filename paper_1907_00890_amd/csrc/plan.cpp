@@ -936,6 +936,62 @@ int vof_step_lf(poisson_plan* P, double* u, double* v, double* w, const vp_lower
                    we, lower_e, ug, vg, wg, phi, static_cast<hipStream_t>(stream));
 }
 
+int vof_step_interface(poisson_plan* P, double* u, double* v, double* w, const double* phat,
+                       const double* rho, double rho0, const double* C, const double* mdot,
+                       double rho1, double rho2, int phase, double dt, double* p, double* s,
+                       double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
+                       double* phi, void* stream) {
+  if (!P || !u || !v || !w || !phat || !rho || !C || !mdot || !p || !s || !phi || !ug || !vg ||
+      !wg || !(rho0 > 0) || !(dt > 0) || !(rho1 > 0) || !(rho2 > 0) || (phase != 1 && phase != 2))
+    return VP_EINVAL;
+  if ((ue || ve || we) && !(ue && ve && we)) return VP_EINVAL;
+  if (phi == p || s == p || s == phi) return VP_EINVAL;
+  if (!faces_stored(P)) return VP_EUNSUPPORTED;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* b = P->work64;
+  vp::IfStepArgs a;
+  a.u = u;
+  a.v = v;
+  a.w = w;
+  a.ph = phat;
+  a.rho = rho;
+  a.rho0 = rho0;
+  a.dt = dt;
+  a.b = b;
+  VP_LAUNCH(P, K_RHS, vp::launch_rhs_interface(P->gi, C, mdot, rho1, rho2, s, a, st),
+            "rhs with interface terms", st);
+  int e;
+  if (P->max_batch >= 2) {
+    const double* rhs2[2] = {b, s};
+    double* sol2[2] = {p, phi};
+    e = solve_any(P, 2, rhs2, sol2, st);
+  } else {
+    e = solve_one(P, b, p, st);
+    if (!e) e = solve_one(P, s, phi, st);
+  }
+  if (e) return e;
+  vp::IfStepArgs q;
+  q.uo = u;
+  q.vo = v;
+  q.wo = w;
+  q.ph = phat;
+  q.rho = rho;
+  q.rho0 = rho0;
+  q.dt = dt;
+  q.p = p;
+  q.phi = phi;
+  q.ue = ue;
+  q.ve = ve;
+  q.we = we;
+  q.ug = ug;
+  q.vg = vg;
+  q.wg = wg;
+  VP_LAUNCH(P, K_EPILOGUE,
+            vp::launch_epilogue_interface(P->gi, C, mdot, phase == 1 ? rho1 : rho2, q, st),
+            "step epilogue with interface terms", st);
+  return VP_OK;
+}
+
 int interface_terms(poisson_plan* P, const double* C, const double* mdot, double rho1,
                     double rho2, int phase, double* s, double* qx, double* qy, double* qz,
                     void* stream) {

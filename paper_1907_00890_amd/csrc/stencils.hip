@@ -715,11 +715,111 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic) {
 }
 }  // namespace
 
-template <bool FULL>
+// The march above can also carry one of the step's stencils (the interface
+// terms fused into the step's first and last passes):
+//   IF_RHS : at each plane p, s = mdot (1/rho2 - 1/rho1) |grad C| and the
+//            pressure right-hand side b with that s (k_rhs's arithmetic);
+//            s and b are written, q is not formed;
+//   IF_EPI : one plane behind (plane p-1 at step p, once a of plane p is
+//            known), the fused step epilogue with q = the face means of a
+//            (k_step_epilogue's arithmetic); s and q are not written.
+// The neighbours of a cell in the other fields are read through the caches.
+enum : int { IF_TERMS = 0, IF_RHS = 1, IF_EPI = 2 };
+
+// b at cell c = k P + j nx + i of plane k (k_rhs's arithmetic, term for term)
+__device__ __forceinline__ double rhs_at(const GridArgs& g, const IfStepArgs& a, int i, int j,
+                                         int k, double sv) {
+  const long P = (long)g.nx * g.ny;
+  const long c = k * P + (long)j * g.nx + i;
+  const double ir0 = 1.0 / a.rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, r0dt = a.rho0 / a.dt;
+  const bool hxp = i + 1 < g.nx || g.bcx == 0, hxm = i > 0 || g.bcx == 0;
+  const bool hyp = j + 1 < g.ny || g.bcy == 0, hym = j > 0 || g.bcy == 0;
+  const long xp = i + 1 < g.nx ? 1 : -(long)(g.nx - 1), xm = i > 0 ? -1 : (long)(g.nx - 1);
+  const long yp = j + 1 < g.ny ? (long)g.nx : -(long)(g.ny - 1) * g.nx;
+  const long ym = j > 0 ? -(long)g.nx : (long)(g.ny - 1) * g.nx;
+  const int kp = kplus(g, k), km = kminus(g, k);
+  const bool zph = kp >= 0 || ztop_out(g, k);
+  const double phc = a.ph[c], rhc = a.rho[c];
+  double php = 0.0, rhp = 0.0;
+  if (kp >= 0) {
+    php = a.ph[kp * P + (c - k * P)];
+    rhp = a.rho[kp * P + (c - k * P)];
+  } else if (zph) {
+    php = -phc;
+    rhp = rhc;
+  }
+  double phm = 0.0, rhm = 0.0, wm = 0.0;
+  if (km >= 0) {
+    const long n = km * P + (c - k * P);
+    phm = a.ph[n];
+    rhm = a.rho[n];
+    wm = a.w[n];
+  }
+  const RhsNbr nxp = hxp ? RhsNbr{a.ph[c + xp], a.rho[c + xp], true}
+                         : RhsNbr{-phc, rhc, xtop_out(g)};
+  const RhsNbr nxm{hxm ? a.ph[c + xm] : 0.0, hxm ? a.rho[c + xm] : 0.0, hxm};
+  const RhsNbr nyp = hyp ? RhsNbr{a.ph[c + yp], a.rho[c + yp], true}
+                         : RhsNbr{-phc, rhc, ytop_out(g)};
+  const RhsNbr nym{hym ? a.ph[c + ym] : 0.0, hym ? a.rho[c + ym] : 0.0, hym};
+  const RhsNbr nzp{php, rhp, zph}, nzm{phm, rhm, km >= 0};
+  const double um = hxm ? a.u[c + xm] : 0.0;
+  const double vm = hym ? a.v[c + ym] : 0.0;
+  return rhs_cell(a.rho0, ir0, idx, idy, r0dt, phc, rhc, nxp, nxm, nyp, nym, nzp,
+                  zph ? 1.0 / g.dzc[k] : 1.0, nzm, km >= 0 ? 1.0 / g.dzc[km] : 1.0,
+                  1.0 / g.dzf[k], a.u[c], um, a.v[c], vm, a.w[c], wm, sv);
+}
+
+// the fused epilogue at cell (i, j, k) with the face values q of its "+"
+// faces given (k_step_epilogue's arithmetic, term for term)
+__device__ __forceinline__ void epi_at(const GridArgs& g, const IfStepArgs& a, int i, int j, int k,
+                                       double qxv, double qyv, double qzv) {
+  const long P = (long)g.nx * g.ny;
+  const long c0 = (long)j * g.nx + i, c = k * P + c0;
+  const double ir0 = 1.0 / a.rho0, idx = 1.0 / g.dx, idy = 1.0 / g.dy, dt = a.dt;
+  const bool hxp = i + 1 < g.nx || g.bcx == 0, hyp = j + 1 < g.ny || g.bcy == 0;
+  const long xp = i + 1 < g.nx ? 1 : -(long)(g.nx - 1);
+  const long yp = j + 1 < g.ny ? (long)g.nx : -(long)(g.ny - 1) * g.nx;
+  const int kp = kplus(g, k);
+  const double pc = a.p[c], hc = a.ph[c], rc = a.rho[c], fc = a.phi[c];
+  double un = a.uo[c], vn = a.vo[c], wn = a.wo[c];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (hxp) {
+    const long n = c + xp;
+    un = epi_face(un, dt, ir0, a.p[n], pc, a.rho[n], rc, a.ph[n], hc, a.phi[n], fc, idx, &gx);
+  } else if (xtop_out(g)) {
+    un = epi_face(un, dt, ir0, -pc, pc, rc, rc, -hc, hc, -fc, fc, idx, &gx);
+  }
+  if (hyp) {
+    const long n = c + yp;
+    vn = epi_face(vn, dt, ir0, a.p[n], pc, a.rho[n], rc, a.ph[n], hc, a.phi[n], fc, idy, &gy);
+  } else if (ytop_out(g)) {
+    vn = epi_face(vn, dt, ir0, -pc, pc, rc, rc, -hc, hc, -fc, fc, idy, &gy);
+  }
+  double pp = 0.0, hp = 0.0, rp = 0.0, fp = 0.0;
+  const bool zph = kp >= 0 || ztop_out(g, k);
+  if (kp >= 0) {
+    const long n = kp * P + c0;
+    pp = a.p[n];
+    hp = a.ph[n];
+    rp = a.rho[n];
+    fp = a.phi[n];
+  } else if (zph) {
+    pp = -pc;
+    hp = -hc;
+    rp = rc;
+    fp = -fc;
+  }
+  if (zph) wn = epi_face(wn, dt, ir0, pp, pc, rp, rc, hp, hc, fp, fc, 1.0 / g.dzc[k], &gz);
+  epi_store(un, vn, wn, gx, gy, gz, c, a.uo, a.vo, a.wo, nullptr, nullptr, nullptr, qxv, qyv, qzv,
+            true, a.ue, a.ve, a.we, a.ug, a.vg, a.wg);
+}
+
+template <bool FULL, int MODE>
 __global__ __launch_bounds__(kIfThreads) void k_interface(
     const GridArgs g, const double* __restrict__ C, const double* __restrict__ mdot,
     const double* __restrict__ dzc, double rho1, double rho2, double rho_e, double* __restrict__ s,
-    double* __restrict__ qx, double* __restrict__ qy, double* __restrict__ qz) {
+    double* __restrict__ qx, double* __restrict__ qy, double* __restrict__ qz,
+    const IfStepArgs sa_args) {
   __shared__ double cs[4][kIfMaxC];
   __shared__ double sdx[kIfMaxC], sdy[kIfMaxC], zd[kIfMaxC];
   __shared__ double sax[kIfMaxA], say[kIfMaxA], saz[kIfMaxA], ssrc[kIfMaxA];
@@ -858,7 +958,7 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(
   fetch(min(kb + 4, ke + 1), sb);
   fetch_m(kb, ma);
   fetch_m(kb + 1, mb);
-  double az_prev = 0.0;
+  double az_prev = 0.0, qx_prev = 0.0, qy_prev = 0.0;
   const int ea = lj * aw + li;  // this thread's cell in the a region
   auto step = [&](int p, double* sr, double* mr, auto first_c, auto last_c) {
     constexpr bool first = decltype(first_c)::value, last = decltype(last_c)::value;
@@ -871,15 +971,29 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(
     const double az = saz[ea];
     if (own) {
       const long c = p * P + (long)j * g.nx + i;
-      if constexpr (!last) {
-        __builtin_nontemporal_store(ssrc[ea], s + c);
-        __builtin_nontemporal_store(
-            (i + 1 < g.nx || px) ? 0.5 * (sax[ea] + sax[ea + 1]) : 0.0, qx + c);
-        __builtin_nontemporal_store(
-            (j + 1 < g.ny || py) ? 0.5 * (say[ea] + say[ea + aw]) : 0.0, qy + c);
+      const double qxc = (i + 1 < g.nx || px) ? 0.5 * (sax[ea] + sax[ea + 1]) : 0.0;
+      const double qyc = (j + 1 < g.ny || py) ? 0.5 * (say[ea] + say[ea + aw]) : 0.0;
+      if constexpr (MODE == IF_TERMS) {
+        if constexpr (!last) {
+          __builtin_nontemporal_store(ssrc[ea], s + c);
+          __builtin_nontemporal_store(qxc, qx + c);
+          __builtin_nontemporal_store(qyc, qy + c);
+        }
+        if constexpr (!first)
+          __builtin_nontemporal_store((p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0, qz + c - P);
+      } else if constexpr (MODE == IF_RHS) {
+        if constexpr (!last) {
+          const double sv = ssrc[ea];
+          __builtin_nontemporal_store(sv, s + c);
+          __builtin_nontemporal_store(rhs_at(g, sa_args, i, j, p, sv), sa_args.b + c);
+        }
+      } else {
+        if constexpr (!first)
+          epi_at(g, sa_args, i, j, p - 1, qx_prev, qy_prev,
+                 (p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0);
       }
-      if constexpr (!first)
-        __builtin_nontemporal_store((p < g.nz || pz) ? 0.5 * (az_prev + az) : 0.0, qz + c - P);
+      qx_prev = qxc;
+      qy_prev = qyc;
     }
     az_prev = az;
     put(p + 3, sr);  // beyond ke + 1: a clamped plane no step reads
@@ -903,17 +1017,42 @@ __global__ __launch_bounds__(kIfThreads) void k_interface(
   }
 }
 
-hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
-                            double rho2, double rho_e, double* s, double* qx, double* qy,
-                            double* qz, hipStream_t st) {
+template <int MODE>
+static hipError_t launch_interface_mode(const GridArgs& g, const double* C, const double* mdot,
+                                        double rho1, double rho2, double rho_e, double* s,
+                                        double* qx, double* qy, double* qz, const IfStepArgs& a,
+                                        hipStream_t st) {
   const int tx = tile_w<64>(g), ty = kIfThreads / tx;
   if (tx < 8 || g.nx % tx || g.kc < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(g.nx / tx), (unsigned)((g.ny + ty - 1) / ty),
                   (unsigned)((g.nz + g.kc - 1) / g.kc));
-  auto kern = g.ny % ty == 0 ? &k_interface<true> : &k_interface<false>;
+  auto kern = g.ny % ty == 0 ? &k_interface<true, MODE> : &k_interface<false, MODE>;
   hipLaunchKernelGGL(kern, grid, dim3(kIfThreads), 0, st, g, C, mdot, g.dzc, rho1, rho2, rho_e, s,
-                     qx, qy, qz);
+                     qx, qy, qz, a);
   return hipGetLastError();
+}
+
+hipError_t launch_interface(const GridArgs& g, const double* C, const double* mdot, double rho1,
+                            double rho2, double rho_e, double* s, double* qx, double* qy,
+                            double* qz, hipStream_t st) {
+  return launch_interface_mode<IF_TERMS>(g, C, mdot, rho1, rho2, rho_e, s, qx, qy, qz,
+                                         IfStepArgs{}, st);
+}
+
+hipError_t launch_rhs_interface(const GridArgs& g, const double* C, const double* mdot,
+                                double rho1, double rho2, double* s, const IfStepArgs& a,
+                                hipStream_t st) {
+  if (!a.u || !a.v || !a.w || !a.ph || !a.rho || !a.b) return hipErrorInvalidValue;
+  return launch_interface_mode<IF_RHS>(g, C, mdot, rho1, rho2, rho1, s, nullptr, nullptr,
+                                       nullptr, a, st);
+}
+
+hipError_t launch_epilogue_interface(const GridArgs& g, const double* C, const double* mdot,
+                                     double rho_e, const IfStepArgs& a, hipStream_t st) {
+  if (!a.uo || !a.vo || !a.wo || !a.p || !a.ph || !a.rho || !a.phi || !a.ug || !a.vg || !a.wg)
+    return hipErrorInvalidValue;
+  return launch_interface_mode<IF_EPI>(g, C, mdot, 1.0, 1.0, rho_e, nullptr, nullptr, nullptr,
+                                       nullptr, a, st);
 }
 
 template <int TXMAX = 64>

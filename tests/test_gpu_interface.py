@@ -124,3 +124,82 @@ def test_interface_terms_feed_the_step(torch_dev):
     for name, a, b in [("u", u, u1), ("p", p, p1), ("phi", phi, ref[6]), ("we", we, ref[2]),
                        ("ug", ug, ref[3]), ("wg", wg, ref[5])]:
         assert rel_l2(a, b) <= FP64_TOL, name
+
+
+STEP_IF_CASES = [
+    # (nx, ny, nz, bc, beta, max_batch, precision)
+    (64, 32, 48, "PPN", 1.5, 2, "fp64"),
+    (32, 32, 24, "NNNNND", None, 2, "fp64"),   # the container: outflow top
+    (8, 40, 12, "PNN", None, 1, "fp64"),       # tall tiles beyond ny, one field per solve
+    (64, 16, 20, "NPP", 1.2, 2, "mixed"),
+    (32, 16, 1, "PPN", None, 2, "fp64"),       # one-cell slab
+]
+
+
+@pytest.mark.parametrize("case", STEP_IF_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}-{c[6]}")
+def test_step_interface_same_bits(torch_dev, case):
+    """vof_step_interface (s in the right-hand-side pass, q in the epilogue)
+    gives the bits of interface_terms followed by vof_step, and the oracle's
+    step with the oracle's interface terms."""
+    torch = torch_dev
+    from paper_1907_00890_amd import Plan
+    nx, ny, nz, bc, beta, mb, prec = case
+    dzf = vofsynth.uniform_dz(nz, 1.0) if beta is None else vofsynth.stretched_dz(nz, 1.0, beta)
+    g = oracle.Grid(nx, ny, nz, 1.0 / nx, 1.0 / ny, dzf, bc)
+    C, mdot = _inputs(g, "sphere", 11 + nz)
+    rho1, rho2 = 1000.0, 1.0
+    us, vs, ws = vofsynth.random_faces(g.shape, 12, g.bc)
+    phat = vofsynth.gaussian_field(g.shape, 13)
+    rho = rho1 * C + rho2 * (1 - C)
+    dt = 0.2
+    plan = Plan(nx, ny, nz, g.dx, g.dy, dzf, g.bc, precision=prec, max_batch=mb)
+    T = lambda a: _dev(torch, a)  # noqa: E731
+    dC, dm = T(C), T(mdot)
+    for phase in (1, 2):
+        s, qx, qy, qz = plan.interface_terms(dC, dm, rho1, rho2, phase=phase)
+        ref = plan.step(T(us), T(vs), T(ws), T(phat), T(rho), rho2, s, dt, s, q=(qx, qy, qz),
+                        out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+        got = plan.step_interface(T(us), T(vs), T(ws), T(phat), T(rho), rho2, dC, dm, rho1, rho2,
+                                  dt, phase=phase,
+                                  out=tuple(T(np.zeros(g.shape)) for _ in range(3)))
+        torch.cuda.synchronize()
+        names = ("u", "v", "w", "p", "phi", "ue", "ve", "we", "ug", "vg", "wg")
+        want = dict(zip(names, (a.cpu().numpy() for a in ref)))
+        have = dict(zip(names[:5], (a.cpu().numpy() for a in got[:5])))
+        have.update(zip(names[5:], (a.cpu().numpy() for a in got[6:])))
+        assert np.array_equal(got[5].cpu().numpy(), s.cpu().numpy()), (phase, "s")
+        for name in names:
+            assert np.array_equal(have[name], want[name]), (phase, name)
+    # and the oracle's step with the oracle's terms (liquid phase)
+    if prec == "fp64":
+        s_ref, rqx, rqy, rqz, _ = oi.interface_terms(C, mdot, rho1, rho2, g)
+        u1, v1, w1, p1 = oracle.project(us, vs, ws, phat, rho, rho2, s_ref, dt, g)
+        ext = oracle.extend(u1, v1, w1, s_ref, g, q=(rqx, rqy, rqz))
+        got = plan.step_interface(T(us), T(vs), T(ws), T(phat), T(rho), rho2, dC, dm, rho1, rho2,
+                                  dt)
+        torch.cuda.synchronize()
+        for name, a, b in [("u", got[0], u1), ("p", got[3], p1), ("phi", got[4], ext[6]),
+                           ("s", got[5], s_ref), ("ug", got[9], ext[3]), ("wg", got[11], ext[5])]:
+            if not np.any(b):
+                assert not np.any(a.cpu().numpy()), name
+                continue
+            err = rel_l2(a.cpu().numpy(), b)
+            print(f"step_interface {case} {name}: {err:.3e}")
+            assert err <= FP64_TOL, (name, err)
+    plan.close()
+
+
+def test_step_interface_refusals(torch_dev):
+    torch = torch_dev
+    from paper_1907_00890_amd import Plan, VofPoissonError, _lib
+    g = oracle.Grid(16, 16, 8, 1 / 16, 1 / 16, vofsynth.uniform_dz(8, 1.0), "DNPPNN")
+    plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, g.bc)
+    z = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(VofPoissonError) as e:  # outflow at a lower end: the _lf calls
+        plan.step_interface(z.clone(), z.clone(), z.clone(), z, z + 1, 1.0, z, z, 2.0, 1.0, 0.1)
+    assert e.value.status == _lib.VP_EUNSUPPORTED
+    g = oracle.Grid(16, 16, 8, 1 / 16, 1 / 16, vofsynth.uniform_dz(8, 1.0), "PPN")
+    plan = Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dzf, g.bc)
+    with pytest.raises(VofPoissonError):
+        plan.step_interface(z.clone(), z.clone(), z.clone(), z, z + 1, 1.0, z, z, 2.0, 1.0, 0.1,
+                            phase=3)
