@@ -55,7 +55,8 @@ STEP_BATCH = 2
 SOLVE_PASSES = ("x_forward", "y_forward", "z_solve", "y_inverse", "x_inverse")
 KERNEL_SOURCES = {
     "x_forward": "transforms_x.hip", "y_forward": "transforms_y.hip",
-    "y_inverse": "transforms_y.hip", "x_inverse": "transforms_x.hip", "z_solve": "zsolve.hip",
+    "y_inverse": "transforms_y.hip", "x_inverse": "transforms_x.hip",
+    "z_solve": ("zsolve.hip", "transforms_z.hip"),
     "rhs_assembly": "stencils.hip",
     "correction": "stencils.hip", "extension": "stencils.hip", "step_epilogue": "stencils.hip",
 }
@@ -111,10 +112,13 @@ def shape_plan(plan, batch, spec, no_autotune):
     return plan.autotune(batch=batch)
 
 
-def source_sha(name):
-    path = os.path.join(ROOT, "paper_1907_00890_amd", "csrc", name)
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def source_sha(names):
+    """First 16 hex digits of the SHA-256 of the kernel source file(s)."""
+    h = hashlib.sha256()
+    for name in (names,) if isinstance(names, str) else names:
+        with open(os.path.join(ROOT, "paper_1907_00890_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):

@@ -422,8 +422,10 @@ long long poisson_plan_device_bytes(const poisson_plan* plan);
  *                 less LDS, so more blocks fit on a compute unit);
  *   "stencil_planes" : z-planes marched by one block of the right-hand-side
  *                 kernel (1..nz; default chosen for ~16k blocks);
- *   "stream_planes" : z-planes marched by one block of the correction and
- *                 extension kernels (1..nz, default 1);
+ *   "stream_planes", "stream_tiled" : the correction and extension kernels
+ *                 of project / extend_liquid_velocity: z-planes marched by one
+ *                 block (1..nz, default 1) and LDS-staged 64 x 8 (or 16) tiles
+ *                 where they fit (default 8; 0: plain one-row tiles; same bits);
  *   "epilogue_tiled", "epilogue_planes" : the fused epilogue of vof_step on
  *                 LDS-staged 64 x 8 (or 16) tiles marching that many planes
  *                 (defaults 8 and 1; tiled 0: plain one-row tiles; results

@@ -325,7 +325,8 @@ class Plan:
         return out.value
 
     TUNING_KEYS = ("x_radix", "y_radix", "z_lines", "stencil_planes", "z_spectral", "z_radix",
-                   "y_lines", "z_spectral_lines", "stream_planes", "rhs_tiled", "epilogue_tiled",
+                   "y_lines", "z_spectral_lines", "stream_planes", "stream_tiled", "rhs_tiled",
+                   "epilogue_tiled",
                    "epilogue_planes", "interface_planes", "z_segment", "interface_tile")
     AUTOTUNED_KEYS = TUNING_KEYS[:8]
 

@@ -459,9 +459,10 @@ int plan_init(poisson_plan* P, const double* dz) {
   G.dzf = P->dzf; G.dzc = P->dzc;
   G.kc = vp::stencil_default_planes(nx, ny, nz);
   G.tiled = 8;
+  // the correction and the extension alone run as the epilogue's kinds on
+  // the same LDS-staged tiles where they fit, one plane per block
   P->gs = G;
   P->gs.kc = 1;
-  P->gs.tiled = 0;
   // the epilogue runs on LDS-staged 64 x 8 tiles where they fit, one plane
   // per block (measured at 256^3: 485 us against 525 us for one-row tiles;
   // marching more planes gains nothing)
@@ -1141,10 +1142,13 @@ int poisson_plan_tune(poisson_plan* P, const char* key, int value) {
     P->gs.kc = value;
     return VP_OK;
   }
+  if (k == "stream_tiled") {
+    if (value != 0 && value != 8 && value != 16) return VP_EINVAL;
+    P->gs.tiled = value;
+    return VP_OK;
+  }
   if (k == "stencil_planes") {
     if (value < 1 || value > P->nz) return VP_EINVAL;
-    vp::GridArgs g = P->g;
-    g.kc = value;
     P->g.kc = value;
     return VP_OK;
   }
@@ -1356,6 +1360,7 @@ int poisson_plan_get_tuning(poisson_plan* P, const char* key, int* value) {
   else if (k == "z_lines") *value = P->z.lines;
   else if (k == "stencil_planes") *value = P->g.kc;
   else if (k == "stream_planes") *value = P->gs.kc;
+  else if (k == "stream_tiled") *value = P->gs.tiled;
   else if (k == "rhs_tiled") *value = P->g.tiled;
   else if (k == "z_spectral") *value = P->z_spec;
   else if (k == "z_radix") *value = P->z_pt;

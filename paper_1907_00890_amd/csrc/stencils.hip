@@ -342,8 +342,21 @@ __global__ __launch_bounds__(256) void k_rhs_tiled(
   }
 }
 
+// One "+" face of the fused epilogue: the corrected velocity from u* and the
+// jumps of p, p_hat, rho and phi across the face (hinv = 1/dx, 1/dy or the
+// inverse centre distance 1/dzc), and the gradient of phi through *gphi.
+// Contraction is off inside: every kernel variant gives the same bits.
+__device__ __forceinline__ double epi_face(double un, double dt, double ir0, double pn, double pc,
+                                           double rn, double rc, double hn, double hc, double fn,
+                                           double fc, double hinv, double* gphi) {
+#pragma clang fp contract(off)
+  *gphi = (fn - fc) * hinv;
+  return un - dt * (ir0 * (pn - pc) * hinv + (inv_face_rho(rc, rn) - ir0) * (hn - hc) * hinv);
+}
+
 // u <- u* - dt [ (1/rho0) G p + (1/rho_f - 1/rho0) G p_hat ] on the cell's
-// three "plus" faces
+// three "plus" faces (epi_face's arithmetic: the LDS-tiled variant, the
+// epilogue's correction kind, gives the same bits)
 __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __restrict__ u,
                                                   double* __restrict__ v, double* __restrict__ w,
                                                   const double* __restrict__ p,
@@ -369,30 +382,31 @@ __global__ __launch_bounds__(256) void k_correct(const GridArgs g, double* __res
       hp = -hc;
       rp = rc;
     }
+    double gnone;  // epi_face's phi gradient, unused here (no phi)
     if (t.hxp || xtop_out(g)) {
       const double pn = t.hxp ? p[c + t.xp] : -pc, hn = t.hxp ? ph[c + t.xp] : -hc;
       const double rn = t.hxp ? rho[c + t.xp] : rc;
-      const double gp = (pn - pc) * idx, gh = (hn - hc) * idx;
-      __builtin_nontemporal_store(u[c] - dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh), u + c);
+      __builtin_nontemporal_store(
+          epi_face(u[c], dt, ir0, pn, pc, rn, rc, hn, hc, 0.0, 0.0, idx, &gnone), u + c);
     }
     if (t.hyp || ytop_out(g)) {
       const double pn = t.hyp ? p[c + t.yp] : -pc, hn = t.hyp ? ph[c + t.yp] : -hc;
       const double rn = t.hyp ? rho[c + t.yp] : rc;
-      const double gp = (pn - pc) * idy, gh = (hn - hc) * idy;
-      __builtin_nontemporal_store(v[c] - dt * (ir0 * gp + (inv_face_rho(rc, rn) - ir0) * gh), v + c);
+      __builtin_nontemporal_store(
+          epi_face(v[c], dt, ir0, pn, pc, rn, rc, hn, hc, 0.0, 0.0, idy, &gnone), v + c);
     }
-    if (zph) {
-      const double ih = 1.0 / g.dzc[k];
-      const double gp = (pp - pc) * ih, gh = (hp - hc) * ih;
-      __builtin_nontemporal_store(w[c] - dt * (ir0 * gp + (inv_face_rho(rc, rp) - ir0) * gh), w + c);
-    }
+    if (zph)
+      __builtin_nontemporal_store(
+          epi_face(w[c], dt, ir0, pp, pc, rp, rc, hp, hc, 0.0, 0.0, 1.0 / g.dzc[k], &gnone),
+          w + c);
     pc = pp;
     hc = hp;
     rc = rp;
   }
 }
 
-// u_1^e = u - G phi ; u_Gamma = u_1^e - q
+// u_1^e = u - G phi ; u_Gamma = u_1^e - q (the differences of epi_face, as
+// the LDS-tiled variant takes them)
 __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* __restrict__ u,
                                                  const double* __restrict__ v,
                                                  const double* __restrict__ w,
@@ -427,18 +441,6 @@ __global__ __launch_bounds__(256) void k_extend(const GridArgs g, const double* 
     }
     fc = fp;
   }
-}
-
-// One "+" face of the fused epilogue: the corrected velocity from u* and the
-// jumps of p, p_hat, rho and phi across the face (hinv = 1/dx, 1/dy or the
-// inverse centre distance 1/dzc), and the gradient of phi through *gphi.
-// Contraction is off inside: every kernel variant gives the same bits.
-__device__ __forceinline__ double epi_face(double un, double dt, double ir0, double pn, double pc,
-                                           double rn, double rc, double hn, double hc, double fn,
-                                           double fc, double hinv, double* gphi) {
-#pragma clang fp contract(off)
-  *gphi = (fn - fc) * hinv;
-  return un - dt * (ir0 * (pn - pc) * hinv + (inv_face_rho(rc, rn) - ir0) * (hn - hc) * hinv);
 }
 
 __device__ __forceinline__ void epi_store(double un, double vn, double wn, double gx, double gy,
@@ -537,7 +539,13 @@ __global__ __launch_bounds__(256) void k_step_epilogue(
 // first: the x inverse before it writes p and phi in row order, so the last
 // rows are the likeliest to still sit in the Infinity Cache (measured at
 // 256^3: 487 -> 479 us).  The per-face arithmetic is k_step_epilogue's.
-template <int TY>
+// KIND: EPI_STEP (the fused epilogue), EPI_CORRECT (the correction alone:
+// p, p_hat, rho staged; u, v, w updated in place, nothing else written) or
+// EPI_EXTEND (the extension alone: phi staged; u, v, w read, ue.. and, with q,
+// ug.. written).
+enum : int { EPI_STEP = 0, EPI_CORRECT = 1, EPI_EXTEND = 2 };
+
+template <int TY, int KIND>
 __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
     const GridArgs g, double* __restrict__ u, double* __restrict__ v, double* __restrict__ w,
     const double* __restrict__ p, const double* __restrict__ ph, const double* __restrict__ rho,
@@ -546,6 +554,7 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
     double* __restrict__ ve, double* __restrict__ we, double* __restrict__ ug,
     double* __restrict__ vg, double* __restrict__ wg) {
   constexpr int TX = 64, W = TX + 1, RPT = TY / 4, AREA = (TY + 1) * W;
+  constexpr bool PHR = KIND != EPI_EXTEND, PHI = KIND != EPI_CORRECT;  // fields staged
   __shared__ double sm[4 * AREA];  // p, p_hat, rho, phi
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int by = gridDim.y - 1 - blockIdx.y, bz = gridDim.z - 1 - blockIdx.z;  // last first
@@ -570,17 +579,19 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
   }
   long c0[RPT];
   bool hyp[RPT];
-  double pc[RPT], hc[RPT], rc[RPT], fc[RPT];
+  double pc[RPT] = {}, hc[RPT] = {}, rc[RPT] = {}, fc[RPT] = {};
 #pragma unroll
   for (int m = 0; m < RPT; ++m) {
     const int j = j0 + ty + 4 * m;
     c0[m] = (long)j * g.nx + i;
     hyp[m] = j + 1 < g.ny || g.bcy == 0;
     const long c = kb * P + c0[m];
-    pc[m] = p[c];
-    hc[m] = ph[c];
-    rc[m] = rho[c];
-    fc[m] = phi[c];
+    if constexpr (PHR) {
+      pc[m] = p[c];
+      hc[m] = ph[c];
+      rc[m] = rho[c];
+    }
+    if constexpr (PHI) fc[m] = phi[c];
   }
   for (int k = kb; k < ke; ++k) {
     const int kp = kplus(g, k);
@@ -593,10 +604,12 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
       pp[m] = hp[m] = rp[m] = fp[m] = 0.0;
       if (kp >= 0) {
         const long n = kp * P + c0[m];
-        pp[m] = p[n];
-        hp[m] = ph[n];
-        rp[m] = rho[n];
-        fp[m] = phi[n];
+        if constexpr (PHR) {
+          pp[m] = p[n];
+          hp[m] = ph[n];
+          rp[m] = rho[n];
+        }
+        if constexpr (PHI) fp[m] = phi[n];
       } else if (zph) {
         pp[m] = -pc[m];
         hp[m] = -hc[m];
@@ -607,23 +620,27 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
       un[m] = __builtin_nontemporal_load(u + c);
       vn[m] = __builtin_nontemporal_load(v + c);
       wn[m] = __builtin_nontemporal_load(w + c);
-      if (ug) {
+      if (KIND != EPI_CORRECT && ug) {
         qxv[m] = __builtin_nontemporal_load(qx + c);
         qyv[m] = __builtin_nontemporal_load(qy + c);
         qzv[m] = __builtin_nontemporal_load(qz + c);
       }
       const int sl = (ty + 4 * m) * W + tx;
-      sm[sl] = pc[m];
-      sm[AREA + sl] = hc[m];
-      sm[2 * AREA + sl] = rc[m];
-      sm[3 * AREA + sl] = fc[m];
+      if constexpr (PHR) {
+        sm[sl] = pc[m];
+        sm[AREA + sl] = hc[m];
+        sm[2 * AREA + sl] = rc[m];
+      }
+      if constexpr (PHI) sm[3 * AREA + sl] = fc[m];
     }
     if (hslot >= 0) {
       const long n = k * P + hoff;
-      sm[hslot] = p[n];
-      sm[AREA + hslot] = ph[n];
-      sm[2 * AREA + hslot] = rho[n];
-      sm[3 * AREA + hslot] = phi[n];
+      if constexpr (PHR) {
+        sm[hslot] = p[n];
+        sm[AREA + hslot] = ph[n];
+        sm[2 * AREA + hslot] = rho[n];
+      }
+      if constexpr (PHI) sm[3 * AREA + hslot] = phi[n];
     }
     __syncthreads();
 #pragma unroll
@@ -631,27 +648,51 @@ __global__ __launch_bounds__(256) void k_step_epilogue_tiled(
       const long c = k * P + c0[m];
       const int sl = (ty + 4 * m) * W + tx;
       double gx = 0.0, gy = 0.0, gz = 0.0;
-      if (hxp) {
-        const int n = sl + 1;
-        un[m] = epi_face(un[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
-                         sm[3 * AREA + n], fc[m], idx, &gx);
-      } else if (xtop_out(g)) {
-        un[m] = epi_face(un[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m], fc[m],
-                         idx, &gx);
+      if constexpr (KIND == EPI_EXTEND) {
+        // the gradient of phi alone (epi_face's differences)
+        if (hxp) gx = (sm[3 * AREA + sl + 1] - fc[m]) * idx;
+        else if (xtop_out(g)) gx = (-fc[m] - fc[m]) * idx;
+        if (hyp[m]) gy = (sm[3 * AREA + sl + W] - fc[m]) * idy;
+        else if (ytop_out(g)) gy = (-fc[m] - fc[m]) * idy;
+        if (zph) gz = (fp[m] - fc[m]) * (1.0 / g.dzc[k]);
+        const double ex = un[m] - gx, ey = vn[m] - gy, ez = wn[m] - gz;
+        __builtin_nontemporal_store(ex, ue + c);
+        __builtin_nontemporal_store(ey, ve + c);
+        __builtin_nontemporal_store(ez, we + c);
+        if (ug) {
+          __builtin_nontemporal_store(ex - qxv[m], ug + c);
+          __builtin_nontemporal_store(ey - qyv[m], vg + c);
+          __builtin_nontemporal_store(ez - qzv[m], wg + c);
+        }
+      } else {
+        if (hxp) {
+          const int n = sl + 1;
+          un[m] = epi_face(un[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n],
+                           hc[m], PHI ? sm[3 * AREA + n] : 0.0, fc[m], idx, &gx);
+        } else if (xtop_out(g)) {
+          un[m] = epi_face(un[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m],
+                           fc[m], idx, &gx);
+        }
+        if (hyp[m]) {
+          const int n = sl + W;
+          vn[m] = epi_face(vn[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n],
+                           hc[m], PHI ? sm[3 * AREA + n] : 0.0, fc[m], idy, &gy);
+        } else if (ytop_out(g)) {
+          vn[m] = epi_face(vn[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m],
+                           fc[m], idy, &gy);
+        }
+        if (zph)
+          wn[m] = epi_face(wn[m], dt, ir0, pp[m], pc[m], rp[m], rc[m], hp[m], hc[m], fp[m], fc[m],
+                           1.0 / g.dzc[k], &gz);
+        if constexpr (KIND == EPI_STEP) {
+          epi_store(un[m], vn[m], wn[m], gx, gy, gz, c, u, v, w, qx, qy, qz, qxv[m], qyv[m],
+                    qzv[m], true, ue, ve, we, ug, vg, wg);
+        } else {
+          __builtin_nontemporal_store(un[m], u + c);
+          __builtin_nontemporal_store(vn[m], v + c);
+          __builtin_nontemporal_store(wn[m], w + c);
+        }
       }
-      if (hyp[m]) {
-        const int n = sl + W;
-        vn[m] = epi_face(vn[m], dt, ir0, sm[n], pc[m], sm[2 * AREA + n], rc[m], sm[AREA + n], hc[m],
-                         sm[3 * AREA + n], fc[m], idy, &gy);
-      } else if (ytop_out(g)) {
-        vn[m] = epi_face(vn[m], dt, ir0, -pc[m], pc[m], rc[m], rc[m], -hc[m], hc[m], -fc[m], fc[m],
-                         idy, &gy);
-      }
-      if (zph)
-        wn[m] = epi_face(wn[m], dt, ir0, pp[m], pc[m], rp[m], rc[m], hp[m], hc[m], fp[m], fc[m],
-                         1.0 / g.dzc[k], &gz);
-      epi_store(un[m], vn[m], wn[m], gx, gy, gz, c, u, v, w, qx, qy, qz, qxv[m], qyv[m], qzv[m],
-                true, ue, ve, we, ug, vg, wg);
       pc[m] = pp[m];
       hc[m] = hp[m];
       rc[m] = rp[m];
@@ -1112,9 +1153,28 @@ hipError_t launch_rhs(const GridArgs& g, const double* u, const double* v, const
 // the streaming stencils (correction, extension, step epilogue) take the
 // planes per block from g.kc (the plan passes its own count for them, one
 // plane by default: more independent loads in flight than a march)
+// LDS-staged 64 x g.tiled tiles where they fit (nx % 64 == 0, ny % g.tiled
+// == 0), as the fused epilogue
+static bool epi_tiles_fit(const GridArgs& g) {
+  return (g.tiled == 8 || g.tiled == 16) && g.nx % 64 == 0 && g.ny % g.tiled == 0;
+}
+
+static dim3 epi_tile_grid(const GridArgs& g) {
+  return dim3((unsigned)(g.nx / 64), (unsigned)(g.ny / g.tiled),
+              (unsigned)((g.nz + g.kc - 1) / g.kc));
+}
+
 hipError_t launch_correct(const GridArgs& g, double* u, double* v, double* w, const double* p,
                           const double* phat, const double* rho, double rho0, double dt,
                           hipStream_t st) {
+  if (epi_tiles_fit(g)) {
+    auto kern = g.tiled == 16 ? &k_step_epilogue_tiled<16, EPI_CORRECT>
+                              : &k_step_epilogue_tiled<8, EPI_CORRECT>;
+    hipLaunchKernelGGL(kern, epi_tile_grid(g), dim3(256), 0, st, g, u, v, w, p, phat, rho, rho0,
+                       dt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_correct, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, p, phat, rho,
                      rho0, dt);
   return hipGetLastError();
@@ -1124,6 +1184,15 @@ hipError_t launch_extend(const GridArgs& g, const double* u, const double* v, co
                          const double* phi, const double* qx, const double* qy, const double* qz,
                          double* ue, double* ve, double* we, double* ug, double* vg, double* wg,
                          hipStream_t st) {
+  if (epi_tiles_fit(g)) {
+    auto kern = g.tiled == 16 ? &k_step_epilogue_tiled<16, EPI_EXTEND>
+                              : &k_step_epilogue_tiled<8, EPI_EXTEND>;
+    // u, v, w are read only in this kind
+    hipLaunchKernelGGL(kern, epi_tile_grid(g), dim3(256), 0, st, g, const_cast<double*>(u),
+                       const_cast<double*>(v), const_cast<double*>(w), nullptr, nullptr, nullptr,
+                       1.0, 1.0, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_extend, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, phi, qx, qy, qz,
                      ue, ve, we, ug, vg, wg);
   return hipGetLastError();
@@ -1134,15 +1203,11 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
                                 const double* phi, const double* qx, const double* qy,
                                 const double* qz, double* ue, double* ve, double* we, double* ug,
                                 double* vg, double* wg, hipStream_t st) {
-  if ((g.tiled == 8 || g.tiled == 16) && g.nx % 64 == 0 && g.ny % g.tiled == 0) {
-    const dim3 grid((unsigned)(g.nx / 64), (unsigned)(g.ny / g.tiled),
-                    (unsigned)((g.nz + g.kc - 1) / g.kc));
-    if (g.tiled == 16)
-      hipLaunchKernelGGL(k_step_epilogue_tiled<16>, grid, dim3(256), 0, st, g, u, v, w, p, phat,
-                         rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
-    else
-      hipLaunchKernelGGL(k_step_epilogue_tiled<8>, grid, dim3(256), 0, st, g, u, v, w, p, phat,
-                         rho, rho0, dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
+  if (epi_tiles_fit(g)) {
+    auto kern = g.tiled == 16 ? &k_step_epilogue_tiled<16, EPI_STEP>
+                              : &k_step_epilogue_tiled<8, EPI_STEP>;
+    hipLaunchKernelGGL(kern, epi_tile_grid(g), dim3(256), 0, st, g, u, v, w, p, phat, rho, rho0,
+                       dt, phi, qx, qy, qz, ue, ve, we, ug, vg, wg);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_step_epilogue, tile_grid<256>(g), dim3(256), 0, st, g, u, v, w, p, phat,

@@ -569,6 +569,25 @@ def test_fused_step_parity(torch_dev, shape, bc, beta):
         torch.cuda.synchronize()
         for a, b in zip(out3, (u, v, w, p, phi, ue, ve, we, ug, vg, wg)):
             assert np.array_equal(a.cpu().numpy(), b), (tiled, planes)
+    # project and extend alone: the correction and extension kernels on plain
+    # or LDS-staged tiles, several planes per block, give the same bits, and
+    # the oracle's projection and extension
+    sep = {}
+    for tiled, planes in ((0, 1), (8, 1), (8, 3), (16, 2), (0, 4)):
+        plan.tune("stream_tiled", tiled)
+        plan.tune("stream_planes", min(planes, g.nz))
+        pu, pv, pw, pp_ = plan.project(T(us), T(vs), T(ws), T(phat), T(rho), rho0, T(s), dt)
+        ext = plan.extend(pu, pv, pw, T(s), q=tuple(T(a) for a in q), phi=torch.empty_like(pu))
+        torch.cuda.synchronize()
+        sep[(tiled, planes)] = [a.cpu().numpy() for a in (pu, pv, pw, pp_, *ext)]
+    base = sep[(0, 1)]
+    for key, val in sep.items():
+        for a, b in zip(val, base):
+            assert np.array_equal(a, b), key
+    for name, a, b in [("u", base[0], u1), ("w", base[2], w1), ("ue", base[4], ref[0]),
+                       ("we", base[6], ref[2]), ("ug", base[7], ref[3]), ("wg", base[9], ref[5]),
+                       ("phi", base[10], ref[6])]:
+        assert rel_l2(a, b) <= FP64_TOL, ("separate", name)
 
 
 def test_fused_step_graph_replay(torch_dev):
