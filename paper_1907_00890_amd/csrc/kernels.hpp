@@ -249,12 +249,12 @@ int rhs_blocks(const GridArgs& g);  // blocks of one launch_rhs
 int stencil_default_planes(int nx, int ny, int nz);
 // Defect-correction control of the mixed chain, per member b of a batch of
 // nb (state: 4 doubles per member, flags: one int per member).
-// dc_reset clears flags and state; dc_update reduces the x-pass partial sums
+// dc_update reduces the x-pass partial sums
 // of step `step` (0 = the first FP32 solve; nblk blocks per member), writes
 // pmean[b] (weighted mean of the iterate: sum dzf p / denom) and, at step 0,
-// fmean[b] (of f), and from step 1 on sets flag[b] once the error estimate
+// fmean[b] (of f) and a cleared flag[b]; from step 1 on it sets flag[b] once
+// the error estimate
 // 2^-23 (gain |r| + |e|) / |p| of the step is at most tol (tol <= 0: never).
-hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st);
 hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
                             double gain, double denom, double* state, int* flags, double* pmean,
                             double* fmean, hipStream_t st);

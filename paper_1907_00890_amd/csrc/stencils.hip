@@ -1218,15 +1218,6 @@ hipError_t launch_step_epilogue(const GridArgs& g, double* u, double* v, double*
 // ---------------------------------------------------------------------------
 // defect-correction control (mixed precision)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_dc_reset(double* __restrict__ state,
-                                                  int* __restrict__ flags, int nb) {
-  const int b = threadIdx.x;
-  if (b < nb) {
-    flags[b] = 0;
-    for (int i = 0; i < 4; ++i) state[4 * b + i] = 0.0;
-  }
-}
-
 // block b: member b.  Reduces the member's x-pass partial sums (kNormSlots per
 // block, nblk blocks) in a fixed order and updates state[4b + 0] = |e| of the
 // step, [1] = error estimate, [2] = corrections applied; pmean[b] = the
@@ -1247,7 +1238,9 @@ __global__ __launch_bounds__(256) void k_dc_update(const double* __restrict__ no
                                                    double* __restrict__ fmean) {
   __shared__ double red[kNormSlots][256];
   const int b = blockIdx.x;
-  if (flags[b]) return;
+  // step 0 starts a solve: the member's flag (left by an earlier solve) is
+  // cleared below; no pass has read it yet
+  if (step > 0 && flags[b]) return;
   double v[kNormSlots] = {};
   for (long i = threadIdx.x; i < nblk; i += 256)
 #pragma unroll
@@ -1271,6 +1264,7 @@ __global__ __launch_bounds__(256) void k_dc_update(const double* __restrict__ no
     s[0] = en;
     s[1] = 1.0;
     s[2] = 0.0;
+    flags[b] = 0;
     return;
   }
   const double rn = sqrt(red[3][0]);
@@ -1279,12 +1273,6 @@ __global__ __launch_bounds__(256) void k_dc_update(const double* __restrict__ no
   s[1] = est;
   s[2] = (double)step;
   if (tol > 0.0 && est <= tol) flags[b] = 1;
-}
-
-hipError_t launch_dc_reset(double* state, int* flags, int nb, hipStream_t st) {
-  if (nb < 1 || nb > kMaxBatch) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dc_reset, dim3(1), dim3(64), 0, st, state, flags, nb);
-  return hipGetLastError();
 }
 
 hipError_t launch_dc_update(const double* norms, long nblk, int nb, int step, double tol,
