@@ -32,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "Mpts/s per Poisson solve at 256^3 (FP64 vs mixed) + %HBM peak; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (non-matrix) arithmetic
 
 # Algorithmic HBM bytes per launch, in units of N = nx*ny*nz FP64 values of 8 B:
 # every transform / z pass reads and writes one field once; the stencils read
@@ -62,7 +63,7 @@ KERNEL_SOURCES = {
 }
 
 
-EXTRAS = ("stretched", "mixed512", "interface", "droplet", "advect")
+EXTRAS = ("stretched", "mixed512", "interface", "droplet", "advect", "graphs")
 
 
 def parse():
@@ -133,6 +134,19 @@ def load_traffic(kernel, workload):
     if not rec or rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("bytes_per_launch")
+
+
+def load_alu_counts(workload):
+    """FP64 operations per launch of the advection sweeps, from rocprofv3
+    instruction counters (committed summary), for those taken on the current
+    advect.hip; {} if absent."""
+    path = os.path.join(ROOT, "profiles", "alu_counts.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        data = json.load(fh).get(workload, {})
+    sha = source_sha("advect.hip")
+    return {k: v["fp64_flops_per_launch"] for k, v in data.items() if v.get("source_sha") == sha}
 
 
 def make_inputs(cfg, torch, dev):
@@ -583,12 +597,27 @@ def advect_run(torch, dev, steps):
         alg = ALG_BYTES_PER_POINT[name] * n
         kern[name] = {"avg_ms": round(per, 5), "alg_bytes": alg,
                       "gbs": round(alg / (per * 1e-3) / 1e9, 1)}
+    # FP64 operations per launch from rocprofv3 instruction counters of this same
+    # sequence (committed, checked against the kernel source): the sweeps are
+    # bound by FP64 arithmetic in the interface band, not by HBM
+    flops = load_alu_counts("ppn256")
+    for name, k in kern.items():
+        fl = flops.get(name)
+        if fl:
+            k["fp64_flops_per_launch"] = fl
+            k["tflops"] = round(fl / (k["avg_ms"] * 1e-3) / 1e12, 3)
+    roof = None
+    dom_k = max(kern, key=lambda k: kern[k]["avg_ms"]) if kern else None
+    if dom_k and "tflops" in kern[dom_k]:
+        roof = {"bound": "alu", "kernel": dom_k, "achieved": kern[dom_k]["tflops"],
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(kern[dom_k]["tflops"] / FP64_VECTOR_PEAK_TFLOPS, 4)}
     band = ((bufs[0] > 1e-8) & (bufs[0] < 1 - 1e-8)).sum().item()
     res = {"workload": "256x256x256 PPN: the sphere's C advected by the step's interface "
                        "velocity, CFL 0.4, MTHINC beta = 1, deflation on", "steps": steps,
            "ms_per_advect": round(ms, 4), "mpts_s": round(n / (ms * 1e-3) / 1e6, 1),
            "alg_bytes_96N": 96 * n, "gbs_96N": round(96 * n / (ms * 1e-3) / 1e9, 1),
-           "band_cells": int(band), "kernels": kern}
+           "band_cells": int(band), "roofline": roof, "kernels": kern}
     del X, plan, bufs, ug
     torch.cuda.empty_cache()
     return res
@@ -633,6 +662,58 @@ def mixed512_run(torch, dev, reps, no_autotune):
     del out, f
     torch.cuda.empty_cache()
     return res
+
+
+def graph_replay_run(torch, dev, reps=200):
+    """Per-request latency of the serving mix's small classes (64^3, 128^3,
+    1024^2 slab; solve and extension, FP64 and mixed): eager launches against
+    the same call replayed from a captured HIP graph on fixed buffers, the
+    caller synchronising after each call (median and 99th percentile, us)."""
+    import vofsynth
+    from paper_1907_00890_amd import Plan
+
+    def lat(fn):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts.sort()
+        return {"p50_us": round(ts[len(ts) // 2] * 1e6, 1),
+                "p99_us": round(ts[int(len(ts) * 0.99)] * 1e6, 1)}
+
+    out = {}
+    for name, (nx, ny, nz, lz) in {"64^3": (64, 64, 64, 1.0), "128^3": (128, 128, 128, 1.0),
+                                   "1024^2 slab": (1024, 1024, 1, 1.0 / 1024)}.items():
+        dz = vofsynth.uniform_dz(nz, lz)
+        for prec in ("fp64", "mixed"):
+            plan = Plan(nx, ny, nz, 1.0 / nx, 1.0 / ny, dz, "PPN", precision=prec)
+            f = torch.randn((nz, ny, nx), dtype=torch.float64, device=dev)
+            f -= f.mean()
+            sol = torch.empty_like(f)
+            u = [torch.randn_like(f) for _ in range(3)]
+            eo = [torch.empty_like(f) for _ in range(3)]
+            phi = torch.empty_like(f)
+            st = torch.cuda.Stream()
+            res = {}
+            with torch.cuda.stream(st):
+                for kind, fn in (("solve", lambda: plan.solve(f, out=sol, stream=st)),
+                                 ("extend", lambda: plan.extend(*u, f, out=eo, phi=phi,
+                                                                stream=st))):
+                    res[kind] = {"eager": lat(fn)}
+                    g = torch.cuda.CUDAGraph()
+                    fn()
+                    torch.cuda.synchronize()
+                    with torch.cuda.graph(g, stream=st):
+                        fn()
+                    res[kind]["graph"] = lat(g.replay)
+            out[f"{name} {prec}"] = res
+            plan.close()
+    return out
 
 
 def cpu_baseline(sample_name, runs=3):
@@ -872,6 +953,8 @@ def main():
         line["droplet_320x320x640"] = droplet_grid_run(torch, dev, 10, args.no_autotune)
     if "advect" in extras:
         line["advect_256"] = advect_run(torch, dev, 10)
+    if "graphs" in extras:
+        line["graph_replay_small_classes"] = graph_replay_run(torch, dev)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:
