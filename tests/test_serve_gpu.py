@@ -95,24 +95,30 @@ def test_results_same_alone_and_in_the_mix(torch_dev):
             res = srv.wait(_submit(srv, r, outs), 60000)
             assert res is not None and res["status"] == 0 and res["batch"] == 1
             alone.append(_host(outs))
-        # in the mix: everything at once, twice, in a shuffled order
+        # in the mix: everything at once, in a shuffled order.  The scheduler
+        # starts a batch whenever a lane has room, so requests share a batch
+        # only when they arrive faster than the lanes drain: the outputs are
+        # allocated before the burst and the burst is repeated (every
+        # repetition checked bit for bit) until one of them has batched.
         rng = np.random.default_rng(7)
-        for rep in range(2):
+        batched_total = 0
+        for rep in range(8):
             order = rng.permutation(len(reqs))
-            outs = {}
-            tickets = {}
-            for i in order:
-                outs[i] = _outputs(torch, reqs[i])
-                tickets[i] = _submit(srv, reqs[i], outs[i])
+            outs = {i: _outputs(torch, reqs[i]) for i in order}
+            torch.cuda.synchronize()
+            tickets = {i: _submit(srv, reqs[i], outs[i]) for i in order}
             batched = 0
             for i in order:
                 res = srv.wait(tickets[i], 60000)
                 assert res is not None and res["status"] == 0, (rep, reqs[i]["id"])
                 batched += res["batch"] > 1
-            assert batched > 0  # the mix did batch requests together
             for i in order:
                 for a, b in zip(_host(outs[i]), alone[i]):
                     assert np.array_equal(a, b), (rep, reqs[i]["id"], reqs[i]["kind"])
+            batched_total += batched
+            if rep >= 1 and batched_total > 0:
+                break
+        assert batched_total > 0  # some repetition did batch requests together
         st = srv.stats()
         assert st["failed"] == 0 and st["plans_resident"] >= len(CLASSES)
     # and the results are right
