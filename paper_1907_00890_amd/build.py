@@ -27,7 +27,7 @@ LIB = os.path.join(HERE, "libvofpoisson.so")
 # instantiations of one file spread over parallel jobs).  Heaviest first
 # (compiled in parallel, in this order).
 SOURCES = [("transforms_x.hip", 3), ("transforms_y.hip", 2), ("transforms_z.hip", 2),
-           ("zsolve.hip", 1), ("stencils.hip", 1), ("advect.hip", 1), ("plan.cpp", 1),
+           ("zsolve.hip", 2), ("stencils.hip", 1), ("advect.hip", 1), ("plan.cpp", 1),
            ("serve.cpp", 1),
            ("plan_check.cpp", 1)]
 JOBS = [(src, k if n > 1 else 0) for src, n in SOURCES for k in range(1, n + 1)]

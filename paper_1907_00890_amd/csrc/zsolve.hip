@@ -8,17 +8,22 @@
 // za[0] = zc[nz-1] = 0, periodic z wraps both ends (a cyclic system).
 //
 // Partitioned solve (no per-element scratch in HBM): each line is cut into S
-// segments; a lane owns one segment in registers and eliminates its interior
-// rows for the data and for the two couplings to the segment's end values
-// (x_i = alpha_i + beta_i x_first + gamma_i x_last).  The end values of all
-// segments then satisfy a tridiagonal system of 2S unknowns, which the S
-// lanes of the line solve in LDS by parallel cyclic reduction (ceil(log2 2S)
-// strides instead of S dependent rows); each lane finally rebuilds its
-// interior.  Lines run on
-// consecutive lanes, so every load and store of a z-plane row is coalesced.
-// When every segment has exactly M rows and/or the z grid is uniform, the
-// kernel is specialised at compile time (no per-row guards, constant
-// coefficients).
+// segments; a lane owns one segment in registers.  Its interior rows satisfy
+// x_i = alpha_i + beta_i x_first + gamma_i x_last in terms of the segment's
+// end values; the end values of all segments then satisfy a tridiagonal
+// system of 2S unknowns whose rows need alpha, gamma at the first interior
+// row and alpha, beta at the last.  A forward elimination of the interior
+// ends at the last interior row with its final values (and keeps its
+// reciprocal pivots), an elimination from the bottom ends at the first
+// interior row; the two are independent chains.  The S lanes of the line
+// solve the reduced system by parallel cyclic reduction (ceil(log2 2S)
+// strides instead of S dependent rows), and each lane rebuilds its interior
+// by forward and back substitution with the kept pivots, its end values
+// entering as the outer unknowns.  A lane thus holds two M-long arrays (the
+// right-hand side and the pivots).  Lines run on consecutive lanes, so every
+// load and store of a z-plane row is coalesced.  When every segment has
+// exactly M rows and/or the z grid is uniform, the kernel is specialised at
+// compile time (no per-row guards, constant coefficients).
 //
 // Accuracy.  B = -(A + lambda I) is an M-matrix whose rows all sum to
 // ell = -lambda > 0 (walls and periodic ends alike: A annihilates constants).
@@ -26,7 +31,8 @@
 // Taksar-Heyman elimination: with off-diagonal magnitudes l_r, u_r and row
 // sum rho_r, the pivot U_r = u_r + sigma_r with
 //     sigma_r = rho_r + l_r sigma_{r-1} / U_{r-1},
-// a sum of positive terms.  Forming the diagonal lambda - a - c instead
+// a sum of positive terms (the elimination from the bottom mirrors it, with
+// the roles of l and u exchanged).  Forming the diagonal lambda - a - c instead
 // rounds lambda against terms ~1/dz^2 and loses up to five digits on lines
 // with small |lambda|.  The reduced rows keep the same form: their row sums
 // are ell (1 + c tau_1) and ell (1 + a tau_{m-2}) with tau = B_int^-1 1, a
@@ -57,87 +63,108 @@
 
 #include "kernels.hpp"
 
+#ifndef VP_PART
+#define VP_PART 0  // built in two parts: 1 the FP64 kernels, 2 the FP32-storage ones
+#endif
+#define VP_IN_PART(k) (VP_PART == 0 || VP_PART == (k))
+
 namespace vp {
 
-// Reduced system of line l (rows r*LB + l) in M-matrix form,
+// Reduced system of line l in M-matrix form,
 //   -lo_r u_{r-1} + (rho_r + lo_r + up_r) u_r - up_r u_{r+1} = R_r,
 // with one or two right-hand sides (R1, and R2 when `two`), solved by
 // parallel cyclic reduction with every lane of the line at work: lane s owns
-// rows 2s and 2s+1.  At stride d each row
-// eliminates its neighbours at distance d,
-//   a = lo_i / D_{i-d},  b = up_i / D_{i+d}   (D = lo + up + rho),
-//   lo_i <- a lo_{i-d},  up_i <- b up_{i+d},  rho_i <- rho_i + a rho_{i-d} + b rho_{i+d},
-//   R_i <- R_i + a R_{i-d} + b R_{i+d},
+// rows 2s and 2s+1 and keeps them in registers (index q = 0, 1).  At stride d
+// every row publishes itself scaled by 1/D, D = lo + up + rho (one reciprocal
+// per row and stride):
+//   pa = (lo/D, up/D),  pb = (rho/D, R1/D),  pc = R2/D,
+// and then eliminates its neighbours at distance d (old lo_i, up_i on the right):
+//   rho_i <- rho_i + lo_i (rho/D)_{i-d} + up_i (rho/D)_{i+d},  R likewise,
+//   lo_i <- lo_i (lo/D)_{i-d},  up_i <- up_i (up/D)_{i+d},
 // which keeps every row in row-sum form (D a sum of positive terms); after
 // ceil(log2 nr) strides the rows decouple and R_i / rho_i is the solution,
-// written to R1 (and R2 when `two`).  All lanes of the block call this.
-template <int LB>
-__device__ __forceinline__ void red_pcr(double* lo, double* up, double* rho, double* R1,
-                                        double* R2, bool two, int nr, int l, int s) {
+// left in R1 (and R2 when `two`).  With NB = 2 the published values are
+// double-buffered (buffers of nr * LB entries) and one barrier per stride
+// suffices: a lane overwrites a buffer two strides later, after a barrier that
+// every reader of it has passed; with NB = 1 a second barrier ends each stride.
+// All lanes of the block call this.
+template <int LB, int NB>
+__device__ __forceinline__ void red_pcr(double2* pa, double2* pb, double* pc, double (&lo)[2],
+                                        double (&up)[2], double (&rho)[2], double (&R1)[2],
+                                        double (&R2)[2], bool two, int nr, int l, int s) {
+  const int ne = nr * LB;
+  int buf = 0;
   for (int d = 1; d < nr; d <<= 1) {
-    double nlo[2], nup[2], nrh[2], n1[2], n2[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int i = 2 * s + q;
-      const int o = i * LB + l;
-      double rh = rho[o], a1 = R1[o], a2 = two ? R2[o] : 0.0, l2 = 0.0, u2 = 0.0;
-      if (i - d >= 0) {
-        const int m = (i - d) * LB + l;
-        const double a = lo[o] * rcp64(lo[m] + up[m] + rho[m]);
-        l2 = a * lo[m];
-        rh += a * rho[m];
-        a1 += a * R1[m];
-        if (two) a2 += a * R2[m];
-      }
-      if (i + d < nr) {
-        const int p = (i + d) * LB + l;
-        const double b = up[o] * rcp64(lo[p] + up[p] + rho[p]);
-        u2 = b * up[p];
-        rh += b * rho[p];
-        a1 += b * R1[p];
-        if (two) a2 += b * R2[p];
-      }
-      nlo[q] = l2;
-      nup[q] = u2;
-      nrh[q] = rh;
-      n1[q] = a1;
-      n2[q] = a2;
-    }
-    __syncthreads();
+    double2* qa = pa + buf * ne;
+    double2* qb = pb + buf * ne;
+    double* qc = pc + buf * ne;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int o = (2 * s + q) * LB + l;
-      lo[o] = nlo[q];
-      up[o] = nup[q];
-      rho[o] = nrh[q];
-      R1[o] = n1[q];
-      if (two) R2[o] = n2[q];
+      const double id = rcp64(lo[q] + up[q] + rho[q]);
+      qa[o] = make_double2(lo[q] * id, up[q] * id);
+      qb[o] = make_double2(rho[q] * id, R1[q] * id);
+      if (two) qc[o] = R2[q] * id;
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = 2 * s + q;
+      const double a = lo[q], b = up[q];
+      double nl = 0.0, nu = 0.0;
+      if (i - d >= 0) {
+        const int m = (i - d) * LB + l;
+        const double2 v = qb[m];
+        nl = a * qa[m].x;
+        rho[q] += a * v.x;
+        R1[q] += a * v.y;
+        if (two) R2[q] += a * qc[m];
+      }
+      if (i + d < nr) {
+        const int p = (i + d) * LB + l;
+        const double2 v = qb[p];
+        nu = b * qa[p].y;
+        rho[q] += b * v.x;
+        R1[q] += b * v.y;
+        if (two) R2[q] += b * qc[p];
+      }
+      lo[q] = nl;
+      up[q] = nu;
+    }
+    if (NB == 2)
+      buf ^= 1;
+    else
+      __syncthreads();  // one buffer: every read done before the next stride writes
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int o = (2 * s + q) * LB + l;
-    const double ir = rcp64(rho[o]);
-    R1[o] *= ir;
-    if (two) R2[o] *= ir;
+    const double ir = rcp64(rho[q]);
+    R1[q] *= ir;
+    if (two) R2[q] *= ir;
   }
 }
 
+// Largest block of the M-row kernel: 8-row segments pair with up to 1024 lanes
+// (their two M-long register arrays leave room for four waves per SIMD).
+constexpr int zsolve_max_threads(int M) { return M == 8 ? 1024 : 512; }
+
 // US: every segment has exactly M rows.  UZ: uniform z spacing (interior
-// coefficients a = c = A.hz2).
-template <typename T, int M, int LB, bool US, bool UZ>
-__global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A) {
-  extern __shared__ double zsm[];
+// coefficients a = c = A.hz2).  NB: buffers of the reduced system in LDS (2:
+// one barrier per stride; 1 where two would not leave room for a second block).
+template <typename T, int M, int LB, bool US, bool UZ, int NB>
+__global__ __launch_bounds__(zsolve_max_threads(M)) void k_zsolve(T* __restrict__ x,
+                                                                   const ZArgs A) {
+  extern __shared__ __align__(16) double zsm[];
   const int S = A.nseg, nr = 2 * S;
-  double* lo = zsm;
-  double* up = lo + nr * LB;
-  double* rho = up + nr * LB;
-  double* R1 = rho + nr * LB;
-  double* R2 = R1 + nr * LB;
-  double* red = R2 + nr * LB;  // [S][LB] partial sums (singular line)
+  const bool per = A.periodic != 0;
+  // published rows of the reduced system (red_pcr)
+  double2* pa = reinterpret_cast<double2*>(zsm);
+  double2* pb = pa + NB * nr * LB;
+  double* pc = reinterpret_cast<double*>(pb + NB * nr * LB);  // periodic z only
+  double* red = pc + (per ? NB * nr * LB : 0);  // [S][LB] partial sums (singular line)
+  double* fin = red + S * LB;  // [4][LB] end values of a periodic line
   // stretched z: the row coefficients, shared by every line, staged once
-  double* cza = red + S * LB;
+  double* cza = fin + 4 * LB;
   double* czc = cza + A.nz;
   if (!UZ) {
     for (int k = threadIdx.x; k < A.nz; k += blockDim.x) {
@@ -149,39 +176,44 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
 
   if (A.skip && A.skip[blockIdx.y]) return;  // member already converged (whole block)
   const int l = threadIdx.x % LB, s = threadIdx.x / LB;
-  const long line = (long)blockIdx.x * LB + l;
   x += blockIdx.y * A.batch_stride;
-  const bool valid = line < A.plane;
-  const bool blk0 = blockIdx.x == 0;
-  const bool sing = blk0 && l == 0 && A.singular;  // line 0: lambda_x + lambda_y == 0
-  const bool gen = valid && !sing;
-  const bool per = A.periodic != 0;
   const long P = A.plane;
-  double lam = 0.0;
-  if (valid) lam = A.lamx[line % A.nx] + A.lamy[line / A.nx];
-  const double ell = -lam;
   const int k0 = US ? s * M : s * A.seg_base + (s < A.seg_rem ? s : A.seg_rem);
   const int m = US ? M : A.seg_base + (s < A.seg_rem ? 1 : 0);
   const int k1 = k0 + m - 1;
-  T* xs = x + (long)k0 * P + line;
+  auto coef_a = [&](int i) { return UZ ? A.hz2 : cza[k0 + i]; };
+  auto coef_c = [&](int i) { return UZ ? A.hz2 : czc[k0 + i]; };
+  // the segment of line t * LB + l, scaled (zero past the last line)
+  auto load = [&](long t, double (&v)[M]) {
+    const long ln = t * LB + l;
+    const T* src = x + (long)k0 * P + ln;
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+      v[i] = ((US || i < m) && ln < P) ? double(src[(long)i * P]) * A.scale : 0.0;
+  };
 
-  double al[M], be[M], cg[M], ta[M];
+  // tiles of LB lines, walked with a stride of gridDim.x
+  const long ntiles = (P + LB - 1) / LB;
+  // the segment's right-hand side, and the reciprocal pivots of its interior
+  double r[M], iu[M];
+  long t = blockIdx.x;
+  load(t, r);
+  for (; t < ntiles; t += gridDim.x) {
+  const long tn = t + gridDim.x;
+  const long line = t * LB + l;
+  const bool valid = line < P;
+  const bool blk0 = t == 0;
+  const bool sing = blk0 && l == 0 && A.singular;  // line 0: lambda_x + lambda_y == 0
+  const bool gen = valid && !sing;
+  double lam = 0.0;
+  if (valid) lam = A.lamx[line % A.nx] + A.lamy[line / A.nx];
+  const double ell = -lam;
+  T* xs = x + (long)k0 * P + line;
   double rlast = 0.0;
 #pragma unroll
-  for (int i = 0; i < M; ++i) {
-    double v = 0.0;
-    if ((US || i < m) && valid) v = double(xs[(long)i * P]) * A.scale;
-    al[i] = v;
-    be[i] = 0.0;
-    cg[i] = 0.0;
-    ta[i] = 0.0;
-    if (US) {
-      if (i == M - 1) rlast = v;
-    } else if (i == m - 1) {
-      rlast = v;
-    }
-  }
-  const double rfirst = al[0];
+  for (int i = 0; i < M; ++i)
+    if (US ? i == M - 1 : i == m - 1) rlast = r[i];
+  const double rfirst = r[0];
 
   // ---- singular line (block 0, lanes l == 0): segmented running sums ----
   if (blk0 && A.singular) {
@@ -206,23 +238,24 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
     if (sing) {
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        if (i < m) acc += A.dzf[k0 + i] * al[i];
+        if (i < m) acc += A.dzf[k0 + i] * r[i];
     }
     const double rbar = line_sum(acc) / A.dz_sum;
     if (sing && s == 0 && A.mean_out) A.mean_out[blockIdx.y] = rbar;
+    // face fluxes F[k+1/2] (held in iu)
     double run = 0.0;
     if (sing) {
 #pragma unroll
       for (int i = 0; i < M; ++i)
         if (i < m) {
-          run += A.dzf[k0 + i] * (al[i] - rbar);
-          be[i] = run;  // flux F[k+1/2]
+          run += A.dzf[k0 + i] * (r[i] - rbar);
+          iu[i] = run;
         }
     }
     double off = line_excl(run);
     if (sing) {
 #pragma unroll
-      for (int i = 0; i < M; ++i) be[i] += off;
+      for (int i = 0; i < M; ++i) iu[i] += off;
     }
     if (per) {
       // the constant flux that makes p periodic: sum_k dzc[k] F[k+1/2] = 0
@@ -230,21 +263,22 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
       if (sing) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
-          if (i < m) a2 += A.dzc[k0 + i] * be[i];
+          if (i < m) a2 += A.dzc[k0 + i] * iu[i];
       }
       const double c0 = -line_sum(a2) / A.dz_sum;
       if (sing) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) be[i] += c0;
+        for (int i = 0; i < M; ++i) iu[i] += c0;
       }
     }
+    // values p[k] relative to the segment start (held in r: the data is used up)
     run = 0.0;
     if (sing) {
 #pragma unroll
       for (int i = 0; i < M; ++i)
         if (i < m) {
-          cg[i] = run;  // value p[k] relative to the segment start
-          run += A.dzc[k0 + i] * be[i];
+          r[i] = run;
+          run += A.dzc[k0 + i] * iu[i];
         }
     }
     off = line_excl(run);
@@ -253,139 +287,151 @@ __global__ __launch_bounds__(512) void k_zsolve(T* __restrict__ x, const ZArgs A
 #pragma unroll
       for (int i = 0; i < M; ++i)
         if (i < m) {
-          cg[i] += off;
-          acc += A.dzf[k0 + i] * cg[i];
+          r[i] += off;
+          acc += A.dzf[k0 + i] * r[i];
         }
     }
     const double pm = line_sum(acc) / A.dz_sum;
     if (sing) {
 #pragma unroll
       for (int i = 0; i < M; ++i)
-        if (i < m) xs[(long)i * P] = T(cg[i] - pm);
+        if (i < m) xs[(long)i * P] = T(r[i] - pm);
     }
   }
 
-  // ---- interior rows 1..m-2 of B: x_i = alpha_i + beta_i x_first + gamma_i x_last,
-  //      tau = B_int^-1 1 ----
-  double a1 = 0.0, b1 = 0.0, g1 = 1.0, t1 = 0.0, aL = 0.0, bL = 1.0, gL = 0.0, tL = 0.0;
+  // ---- interior rows 1..m-2 of B, x_i = alpha_i + beta_i x_first + gamma_i x_last
+  //      with tau = B_int^-1 1: the reduced rows need alpha, gamma, tau at row 1
+  //      and alpha, beta, tau at row m-2.  A forward elimination ends at row m-2
+  //      with its final values and keeps its reciprocal pivots for the rebuild; an
+  //      elimination from the bottom (its own row-sum pivots, an independent
+  //      chain) ends at row 1.  The right-hand side of B is -r. ----
+  double a1 = 0.0, g1 = 1.0, t1 = 0.0, aL = 0.0, bL = 1.0, tL = 0.0;
   {
     double ratio = 1.0, ya = 0.0, yb = 0.0, yt = 0.0;
+    double rb = 1.0, za = 0.0, zg = 0.0, zt = 0.0;
+    // one row of each elimination: forward row i (pivot kept), backward row j
+    auto fwd = [&](int i) {
+      const double a = coef_a(i), c = coef_c(i);
+      const double sig = ell + a * ratio;
+      const double iv = rcp64(c + sig);
+      ratio = sig * iv;
+      ya = (a * ya - r[i]) * iv;
+      yb = (i == 1 ? a : a * yb) * iv;
+      yt = (1.0 + a * yt) * iv;
+      iu[i] = iv;
+    };
+    auto bwd = [&](int j, bool last) {
+      const double a = coef_a(j), c = coef_c(j);
+      const double sig = ell + c * rb;
+      const double iv = rcp64(a + sig);
+      rb = sig * iv;
+      za = (c * za - r[j]) * iv;
+      zg = (last ? c : c * zg) * iv;
+      zt = (1.0 + c * zt) * iv;
+    };
+    if (US) {
+      // equal segments: both chains in one loop (each coefficient used as loaded)
 #pragma unroll
-    for (int i = 1; i < M - 1; ++i) {
-      if (US || i < m - 1) {
-        double a, c;
-        if (UZ) {
-          a = A.hz2;
-          c = A.hz2;
-        } else {
-          a = cza[k0 + i];
-          c = czc[k0 + i];
-        }
-        const double sig = ell + a * ratio;
-        const double iu = rcp64(c + sig);
-        ratio = sig * iu;
-        ya = (a * ya - al[i]) * iu;  // right-hand side of B is -r
-        yb = (i == 1 ? a : a * yb) * iu;
-        yt = (1.0 + a * yt) * iu;
-        al[i] = ya;
-        be[i] = yb;
-        ta[i] = yt;
-        cg[i] = c * iu;
+      for (int k = 1; k < M - 1; ++k) {
+        fwd(k);
+        bwd(M - 1 - k, k == 1);
       }
-    }
-    double an = 0.0, bn = 0.0, gn = 0.0, tn = 0.0;
+    } else {
 #pragma unroll
-    for (int i = M - 2; i >= 1; --i) {
-      if (US || i <= m - 2) {
-        const double f = cg[i];
-        double gc;
-        if ((US && i == M - 2) || (!US && i == m - 2)) {
-          gc = f;
-          aL = al[i];
-          bL = be[i];
-          gL = gc;
-          tL = ta[i];
-        } else {
-          al[i] += f * an;
-          be[i] += f * bn;
-          ta[i] += f * tn;
-          gc = f * gn;
-        }
-        cg[i] = gc;
-        an = al[i];
-        bn = be[i];
-        gn = gc;
-        tn = ta[i];
-      }
+      for (int i = 1; i < M - 1; ++i)
+        if (i < m - 1) fwd(i);
+#pragma unroll
+      for (int i = M - 2; i >= 1; --i)
+        if (i <= m - 2) bwd(i, i == m - 2);
     }
     if (US ? (M >= 3) : (m >= 3)) {
-      a1 = al[1];
-      b1 = be[1];
-      g1 = cg[1];
-      t1 = ta[1];
+      a1 = za;
+      g1 = zg;
+      t1 = zt;
+      aL = ya;
+      bL = yb;
+      tL = yt;
     }
   }
 
   // ---- reduced system: first and last unknown of every segment ----
-  {
-    const int oF = (2 * s) * LB + l, oE = (2 * s + 1) * LB + l;
-    if (gen) {
-      double a0, c0, aE, cE;
-      if (UZ) {
-        a0 = k0 == 0 ? 0.0 : A.hz2;
-        c0 = A.hz2;
-        aE = A.hz2;
-        cE = k1 == A.nz - 1 ? 0.0 : A.hz2;
-      } else {
-        a0 = cza[k0];
-        c0 = czc[k0];
-        aE = cza[k1];
-        cE = czc[k1];
-      }
-      lo[oF] = a0;
-      up[oF] = c0 * g1;
-      rho[oF] = ell * (1.0 + c0 * t1) + (k0 == 0 ? A.dlo : 0.0);
-      R1[oF] = c0 * a1 - rfirst;
-      lo[oE] = aE * bL;
-      up[oE] = cE;
-      rho[oE] = ell * (1.0 + aE * tL) + (k1 == A.nz - 1 ? A.dhi : 0.0);
-      R1[oE] = aE * aL - rlast;
-      // periodic: unit wrap flux entering at the first cell, leaving at the last
-      R2[oF] = (per && s == 0) ? -1.0 / A.dzf[0] : 0.0;
-      R2[oE] = (per && s == S - 1) ? 1.0 / A.dzf[A.nz - 1] : 0.0;
-    } else {
-      lo[oF] = 0.0; up[oF] = 0.0; rho[oF] = 1.0; R1[oF] = 0.0; R2[oF] = 0.0;
-      lo[oE] = 0.0; up[oE] = 0.0; rho[oE] = 1.0; R1[oE] = 0.0; R2[oE] = 0.0;
-    }
+  double rlo[2] = {0.0, 0.0}, rup[2] = {0.0, 0.0}, rrho[2] = {1.0, 1.0}, rR1[2] = {0.0, 0.0},
+         rR2[2] = {0.0, 0.0};
+  if (gen) {
+    const double a0 = UZ ? (k0 == 0 ? 0.0 : A.hz2) : cza[k0];
+    const double c0 = UZ ? A.hz2 : czc[k0];
+    const double aE = UZ ? A.hz2 : cza[k1];
+    const double cE = UZ ? (k1 == A.nz - 1 ? 0.0 : A.hz2) : czc[k1];
+    rlo[0] = a0;
+    rup[0] = c0 * g1;
+    rrho[0] = ell * (1.0 + c0 * t1) + (k0 == 0 ? A.dlo : 0.0);
+    rR1[0] = c0 * a1 - rfirst;
+    rlo[1] = aE * bL;
+    rup[1] = cE;
+    rrho[1] = ell * (1.0 + aE * tL) + (k1 == A.nz - 1 ? A.dhi : 0.0);
+    rR1[1] = aE * aL - rlast;
+    // periodic: unit wrap flux entering at the first cell, leaving at the last
+    if (per && s == 0) rR2[0] = -1.0 / A.dzf[0];
+    if (per && s == S - 1) rR2[1] = 1.0 / A.dzf[A.nz - 1];
   }
-  __syncthreads();
-  red_pcr<LB>(lo, up, rho, R1, R2, per, nr, l, s);
-  __syncthreads();
+  red_pcr<LB, NB>(pa, pb, pc, rlo, rup, rrho, rR1, rR2, per, nr, l, s);
+  if (per) {
+    // the end values of every line, for the wrap flux
+    if (s == 0) {
+      fin[l] = rR1[0];
+      fin[LB + l] = rR2[0];
+    }
+    if (s == S - 1) {
+      fin[2 * LB + l] = rR1[1];
+      fin[3 * LB + l] = rR2[1];
+    }
+    __syncthreads();
+  }
 
   if (gen) {
-    const int oF = (2 * s) * LB + l, oE = (2 * s + 1) * LB + l;
-    double Ft = R1[oF], Et = R1[oE];
+    double Ft = rR1[0], Et = rR1[1];
     if (per) {
-      const double xr0 = R1[l], xrn = R1[(nr - 1) * LB + l];
-      const double xd0 = R2[l], xdn = R2[(nr - 1) * LB + l];
+      const double xr0 = fin[l], xrn = fin[2 * LB + l];
+      const double xd0 = fin[LB + l], xdn = fin[3 * LB + l];
       const double fw = (xr0 - xrn) / (A.dzc_wrap - (xd0 - xdn));
-      Ft += fw * R2[oF];
-      Et += fw * R2[oE];
+      Ft += fw * rR2[0];
+      Et += fw * rR2[1];
+    }
+    // interior: forward and back substitution with the stored pivots, the end
+    // values entering as x_0 = Ft and x_{m-1} = Et
+    double y = Ft;
+#pragma unroll
+    for (int i = 1; i < M - 1; ++i) {
+      if (US || i < m - 1) {
+        y = (coef_a(i) * y - r[i]) * iu[i];
+        r[i] = y;
+      }
+    }
+    double xn = Et;
+#pragma unroll
+    for (int i = M - 2; i >= 1; --i) {
+      if (US || i <= m - 2) {
+        xn = r[i] + coef_c(i) * iu[i] * xn;
+        r[i] = xn;
+      }
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (US || i < m) {
-        double v;
+        double v = r[i];
         if (i == 0)
           v = Ft;
         else if ((US && i == M - 1) || (!US && i == m - 1))
           v = Et;
-        else
-          v = al[i] + be[i] * Ft + cg[i] * Et;
         xs[(long)i * P] = T(v);
       }
     }
   }
+  if (tn < ntiles) load(tn, r);
+  // the next tile reuses the LDS of this one (the reduced system's buffers,
+  // fin): every lane has finished reading them
+  if (tn < ntiles) __syncthreads();
+  }  // tiles
 }
 
 // nz == 1: every line is a single unknown, x = r / (lambda - dlo - dhi)
@@ -405,28 +451,53 @@ __global__ __launch_bounds__(256) void k_z1(T* __restrict__ x, const ZArgs A) {
   }
 }
 
-template <typename T, int LB, bool US, bool UZ>
+// LDS of one block: the reduced system's published rows (NB buffers of nr * LB
+// entries: two double2 arrays, one double array when z is periodic), the
+// singular line's partial sums, a periodic line's end values, and the row
+// coefficients of a stretched grid.
+static size_t zsolve_lds(const ZArgs& a, int lb, int nbuf, bool uz) {
+  const size_t ne = (size_t)2 * a.nseg * lb;
+  return sizeof(double) * ((4 + (a.periodic ? 1 : 0)) * (size_t)nbuf * ne +
+                           (size_t)a.nseg * lb + 4 * (size_t)lb + (uz ? 0 : 2 * (size_t)a.nz));
+}
+
+template <typename T, int M, int LB, bool US, bool UZ>
 static hipError_t launch_z_shape(T* data, const ZArgs& a, int nb, hipStream_t st) {
-  const int nr = 2 * a.nseg;
-  const size_t shm = sizeof(double) * ((size_t)5 * nr * LB + (size_t)a.nseg * LB +
-                                        (UZ ? 0 : 2 * (size_t)a.nz));
+  const int threads = LB * a.nseg;
+  if (threads > zsolve_max_threads(M)) return hipErrorInvalidValue;
+  // two buffers where they leave room for as many blocks as the lanes allow
+  // (four waves per SIMD, 160 KB of LDS per CU)
+  const int blocks_cu = threads >= 1024 ? 1 : 1024 / threads;
+  const bool two = zsolve_lds(a, LB, 2, UZ) * blocks_cu <= 163840;
+  const size_t shm = zsolve_lds(a, LB, two ? 2 : 1, UZ);
   const dim3 grid((unsigned)((a.plane + LB - 1) / LB), (unsigned)nb);
-  const dim3 block((unsigned)(LB * a.nseg));
-  if ((a.seg != 16 && a.seg != 8) || LB * a.nseg > 512) return hipErrorInvalidValue;
-  auto kern = a.seg == 8 ? &k_zsolve<T, 8, LB, US, UZ> : &k_zsolve<T, 16, LB, US, UZ>;
+  auto kern = two ? &k_zsolve<T, M, LB, US, UZ, 2> : &k_zsolve<T, M, LB, US, UZ, 1>;
+  if (shm > 163840) return hipErrorInvalidValue;
   if (shm > 65536 && allow_large_lds(kern) != hipSuccess) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kern, grid, block, shm, st, data, a);
+  hipLaunchKernelGGL(kern, grid, dim3((unsigned)threads), shm, st, data, a);
   return hipGetLastError();
 }
 
-template <typename T, int LB>
+template <typename T, int M, int LB>
 static hipError_t launch_z_lb(T* data, const ZArgs& a, int nb, hipStream_t st) {
-  const bool us = a.seg_rem == 0 && a.seg_base == a.seg;
+  const bool us = a.seg_rem == 0 && a.seg_base == M;
   if (us)
-    return a.uniform_z ? launch_z_shape<T, LB, true, true>(data, a, nb, st)
-                       : launch_z_shape<T, LB, true, false>(data, a, nb, st);
-  return a.uniform_z ? launch_z_shape<T, LB, false, true>(data, a, nb, st)
-                     : launch_z_shape<T, LB, false, false>(data, a, nb, st);
+    return a.uniform_z ? launch_z_shape<T, M, LB, true, true>(data, a, nb, st)
+                       : launch_z_shape<T, M, LB, true, false>(data, a, nb, st);
+  return a.uniform_z ? launch_z_shape<T, M, LB, false, true>(data, a, nb, st)
+                     : launch_z_shape<T, M, LB, false, false>(data, a, nb, st);
+}
+
+template <typename T, int M>
+static hipError_t launch_z_m(T* data, const ZArgs& a, int nb, hipStream_t st) {
+  // LB lines x S segments per block; a.lines picks LB, halved until the block
+  // fits
+  int lb = a.lines;
+  while (lb > 8 && lb * a.nseg > zsolve_max_threads(M)) lb /= 2;
+  if (lb * a.nseg > zsolve_max_threads(M)) return hipErrorInvalidValue;
+  if (lb >= 32) return launch_z_lb<T, M, 32>(data, a, nb, st);
+  if (lb == 16) return launch_z_lb<T, M, 16>(data, a, nb, st);
+  return launch_z_lb<T, M, 8>(data, a, nb, st);
 }
 
 template <typename T>
@@ -437,20 +508,23 @@ static hipError_t launch_z(T* data, const ZArgs& a, int nb, hipStream_t st) {
     hipLaunchKernelGGL((k_z1<T>), grid, dim3(256), 0, st, data, a);
     return hipGetLastError();
   }
-  // LB lines x S segments per block, at most 512 lanes; a.lines picks LB
-  int lb = a.lines;
-  while (lb > 8 && lb * a.nseg > 512) lb /= 2;
-  if (lb >= 32) return launch_z_lb<T, 32>(data, a, nb, st);
-  if (lb == 16) return launch_z_lb<T, 16>(data, a, nb, st);
-  if (lb * a.nseg > 512) return hipErrorInvalidValue;
-  return launch_z_lb<T, 8>(data, a, nb, st);
+  if (a.seg_base > a.seg || (a.seg_base == a.seg && a.seg_rem > 0)) return hipErrorInvalidValue;
+  switch (a.seg) {
+    case 8: return launch_z_m<T, 8>(data, a, nb, st);
+    case 16: return launch_z_m<T, 16>(data, a, nb, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
+#if VP_IN_PART(1)
 hipError_t launch_zsolve_f64(double* data, const ZArgs& a, int nb, hipStream_t st) {
   return launch_z<double>(data, a, nb, st);
 }
+#endif
+#if VP_IN_PART(2)
 hipError_t launch_zsolve_f32(float* data, const ZArgs& a, int nb, hipStream_t st) {
   return launch_z<float>(data, a, nb, st);
 }
+#endif
 
 }  // namespace vp
