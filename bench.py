@@ -63,7 +63,7 @@ KERNEL_SOURCES = {
 }
 
 
-EXTRAS = ("stretched", "mixed512", "interface", "droplet", "advect", "graphs")
+EXTRAS = ("stretched", "mixed512", "interface", "droplet", "advect", "graphs", "hbm")
 
 
 def parse():
@@ -91,7 +91,8 @@ def parse():
                     help="skip the extra workloads (same as --extra none)")
     ap.add_argument("--extra", default="all",
                     help="comma-separated extra workloads after the main line: stretched, "
-                         "mixed512, interface, droplet, advect; 'all' (default) or 'none'")
+                         "mixed512, interface, droplet, advect, graphs, hbm; 'all' (default) "
+                         "or 'none'")
     ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -664,6 +665,38 @@ def mixed512_run(torch, dev, reps, no_autotune):
     return res
 
 
+def hbm_ceiling_run(torch, dev, reps=10):
+    """Streaming rates of plain device kernels (torch's own) on 2 GiB FP64 tensors,
+    far above the 256 MB Infinity Cache: read (a sum), write (a fill), copy.  The
+    practical HBM ceiling of this device, beside the 8 TB/s peak that the roofline
+    fractions are taken against."""
+    n = (2 << 30) // 8
+    a = torch.zeros(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    h = n // 2
+
+    def rate(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return {"ms": round(ms, 4), "tb_s": round(8 * n / (ms * 1e-3) / 1e12, 3)}
+
+    out = {"bytes_moved": 8 * n,
+           "read": rate(lambda: a.sum()),
+           "write": rate(lambda: b.fill_(1.0)),
+           "copy": rate(lambda: b[:h].copy_(a[:h]))}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def graph_replay_run(torch, dev, reps=200):
     """Per-request latency of the serving mix's small classes (64^3, 128^3,
     1024^2 slab; solve and extension, FP64 and mixed): eager launches against
@@ -955,6 +988,8 @@ def main():
         line["advect_256"] = advect_run(torch, dev, 10)
     if "graphs" in extras:
         line["graph_replay_small_classes"] = graph_replay_run(torch, dev)
+    if "hbm" in extras:
+        line["hbm_ceiling"] = hbm_ceiling_run(torch, dev)
     rates = {"none": [], "sweep": [50, 100, 200, 500, 1000, 2000]}.get(
         args.serve_rates, None)
     if rates is None:
