@@ -7,6 +7,29 @@
 
 namespace vp {
 
+// Tile of hardware block h of a one-dimensional grid of G blocks.  Blocks are
+// dispatched to the eight XCDs in turn (h % 8), each XCD with its own L2; here
+// XCD x takes the contiguous tiles [x G/8, (x+1) G/8) (one more for the first
+// G % 8 XCDs) in order, so that neighbouring tiles whose rows share 128-byte
+// cache lines (tiles narrower than a line) are read through one L2, one after
+// the other, instead of by two XCDs at once.  A bijection of [0, G).
+__device__ __forceinline__ unsigned xcd_tile(unsigned h, unsigned G) {
+  const unsigned q = G / 8, r = G % 8, x = h % 8;
+  return x * q + (x < r ? x : r) + h / 8;
+}
+
+// (tile, layer) of hardware block (bx, by) of a two-dimensional grid of gx
+// tiles by gy layers, for passes that walk the layers in order: XCD x takes
+// the layers x, x+8, x+16, ... whole, their tiles in order, so neighbouring
+// tiles of a layer share one L2 and the layers still run in their order.  The
+// last gy % 8 layers keep their ids.  A bijection of the grid.
+__device__ __forceinline__ uint2 xcd_layer(unsigned bx, unsigned by, unsigned gx, unsigned gy) {
+  const unsigned h = bx + gx * by;
+  if (h >= (gy / 8) * 8 * gx) return make_uint2(bx, by);
+  const unsigned j = h / 8, L = ((j / gx) * 8 + h % 8) * gx + j % gx;
+  return make_uint2(L % gx, L / gx);
+}
+
 // 1/x for a positive normal x: hardware reciprocal estimate refined by two
 // Newton-Raphson steps (r <- r + r (1 - x r)), accurate to about one ulp
 // (five instructions against about ten for an IEEE division).

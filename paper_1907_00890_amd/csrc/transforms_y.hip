@@ -24,12 +24,12 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yfwd(TS* __restrict__ 
   using T2 = typename Vec2<T>::type;
   using S2 = typename Vec2<TS>::type;
   extern __shared__ unsigned char smem_raw[];
-  const int by = gridDim.y - 1 - blockIdx.y;  // plane, last first
+  const uint2 tl = xcd_layer(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+  const int by = gridDim.y - 1 - tl.y;  // plane, last first
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
-  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
-                                  2 * q);
+  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)tl.x * 2 * lines + 2 * q);
   const int nx2 = nx >> 1;  // row stride in S2 units
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   forward_body<T, N, BC, PTM>(
@@ -59,12 +59,12 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_yinv(TS* __restrict__ 
   using T2 = typename Vec2<T>::type;
   using S2 = typename Vec2<TS>::type;
   extern __shared__ unsigned char smem_raw[];
-  const int by = gridDim.y - 1 - blockIdx.y;  // plane, last first
+  const uint2 tl = xcd_layer(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+  const int by = gridDim.y - 1 - tl.y;  // plane, last first
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
-  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)blockIdx.x * 2 * lines +
-                                  2 * q);
+  S2* col = reinterpret_cast<S2*>(data + (long)by * plane + (long)tl.x * 2 * lines + 2 * q);
   const int nx2 = nx >> 1;
   YLds<T, N> lds(reinterpret_cast<T2*>(smem_raw), q, lines);
   inverse_body<T, N, BC, PTM>(
@@ -90,11 +90,12 @@ __global__ __launch_bounds__(512) void k_yq(TS* __restrict__ data, int nx, long 
                                              const int* __restrict__ skip) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ unsigned char smem_raw[];
-  const int by = gridDim.y - 1 - blockIdx.y;  // plane, last first
+  const uint2 tl = xcd_layer(blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+  const int by = gridDim.y - 1 - tl.y;  // plane, last first
   if (skip && skip[by / nzm]) return;  // member already converged (whole block)
   const int cols = 1 << lcols;
   const int q = threadIdx.x & (cols - 1), t = threadIdx.x >> lcols;
-  TS* col = data + (long)by * plane + (long)blockIdx.x * cols + q;
+  TS* col = data + (long)by * plane + (long)tl.x * cols + q;
   YLds<T, N / 2> lds(reinterpret_cast<T2*>(smem_raw), q, cols);
   if constexpr (INV) {
     quarter_body<T, N, PTM>(

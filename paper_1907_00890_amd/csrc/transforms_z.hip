@@ -25,7 +25,7 @@ __global__ __launch_bounds__(PTM == 8 ? 512 : 256) void k_zspec(
   if (skip && skip[blockIdx.y]) return;  // member already converged (whole block)
   const int lines = 1 << llines;
   const int q = threadIdx.x & (lines - 1), t = threadIdx.x >> llines;
-  const long pos = (long)blockIdx.x * 2 * lines + 2 * q;  // line a; line b = pos + 1
+  const long pos = (long)xcd_tile(blockIdx.x, gridDim.x) * 2 * lines + 2 * q;  // line a; b: pos + 1
   S2* col = reinterpret_cast<S2*>(data + blockIdx.y * batch_stride + pos);
   const long pstride = plane >> 1;  // z stride in S2 units
   const double la = lamx[pos % nx] + lamy[pos / nx];

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(zsolve_max_threads(M)) void k_zsolve(T* __restrict_
   const long ntiles = (P + LB - 1) / LB;
   // the segment's right-hand side, and the reciprocal pivots of its interior
   double r[M], iu[M];
-  long t = blockIdx.x;
+  long t = xcd_tile(blockIdx.x, gridDim.x);
   load(t, r);
   for (; t < ntiles; t += gridDim.x) {
   const long tn = t + gridDim.x;
