@@ -107,9 +107,10 @@ __device__ void youngs_scaled(const GridArgs& g, const double* __restrict__ C, i
 }
 
 // Integral of H over the box that is [s0, s1] along axis `ax` and the whole
-// cell along the other two; also its derivative with respect to d.
+// cell along the other two; also its first and second derivatives with
+// respect to d (d tanh/dx = 1 - tanh^2).
 __device__ void box_integral(const Rec& r, int ax, double s0, double s1, double beta, double& val,
-                             double& dval) {
+                             double& dval, double& d2val) {
 #pragma clang fp contract(off)
   const int a = r.a;
   const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
@@ -121,7 +122,7 @@ __device__ void box_integral(const Rec& r, int ax, double s0, double s1, double 
   const double c1 = 0.5 * (lo1 + hi1), r1 = hi1 - lo1;
   const double c2 = 0.5 * (lo2 + hi2), r2 = hi2 - lo2;
   const double inv = 1.0 / (2.0 * beta * ma);
-  double tot = 0.0, dtot = 0.0;
+  double tot = 0.0, dtot = 0.0, d2tot = 0.0;
 #pragma unroll
   for (int p = -1; p <= 1; p += 2)
 #pragma unroll
@@ -138,22 +139,27 @@ __device__ void box_integral(const Rec& r, int ax, double s0, double s1, double 
       const double t1 = copysign((1.0 - e1) / (1.0 + e1), x1);
       const double t0 = copysign((1.0 - e0) / (1.0 + e0), x0);
       const double dJ = (t1 - t0) * (beta * inv);
+      const double d2J = (t0 - t1) * (t0 + t1) * (beta * beta * inv);
       tot = tot + 0.25 * r1 * r2 * J;
       dtot = dtot + 0.25 * r1 * r2 * dJ;
+      d2tot = d2tot + 0.25 * r1 * r2 * d2J;
     }
   val = tot;
   dval = dtot;
+  d2val = d2tot;
 }
 
-// d with the integral of H over the cell equal to C: safeguarded Newton
-// from the one-dimensional closed form along the dominant axis, inside the
-// bracket [-(2 + 25 / beta), 2 + 25 / beta] (bisection where a step leaves
-// it).  The volume error falls quadratically from the first guess (about
-// 1e-2) to the rounding level of its O(10)-sized terms (a few 1e-15) in four
-// to six steps.  The solve stops one Newton step after the error is below
-// 1e-13 or a step below 1e-8 (1 + |d|), or when a step vanishes in rounding;
-// a step landing on a bracket end is a Newton step (the end is the last
-// iterate once the step is below half an ulp), not a reason to bisect.
+// d with the integral of H over the cell equal to C: safeguarded Halley
+// iteration (the second derivative of the volume comes with the first, from
+// the same tanh values) from the one-dimensional closed form along the
+// dominant axis, inside the bracket [-(2 + 25 / beta), 2 + 25 / beta]
+// (bisection where a step leaves it or the Halley denominator is not
+// positive).  The volume error falls cubically from the first guess (about
+// 1e-2) to the rounding level of its O(10)-sized terms (a few 1e-15).  The
+// solve stops one step after the error is below 1e-13 or a step below
+// 1e-8 (1 + |d|), or when a step vanishes in rounding; a step landing on a
+// bracket end is a regular step (the end is the last iterate once the step
+// is below half an ulp), not a reason to bisect.
 __device__ double solve_d(Rec& r, double C, double beta) {
 #pragma clang fp contract(off)
   const double ma = fabs(comp(r, r.a));
@@ -166,20 +172,21 @@ __device__ double solve_d(Rec& r, double C, double beta) {
   bool done = false;
   for (int it = 0; it < 40; ++it) {
     r.d = d;
-    double f, df;
-    box_integral(r, 0, -0.5, 0.5, beta, f, df);
+    double f, df, d2f;
+    box_integral(r, 0, -0.5, 0.5, beta, f, df, d2f);
     f = f - C;
     if (f == 0.0) break;
     if (f < 0.0) lo = d;
     else hi = d;
-    double dn = d - f / df;
-    const bool newton = df > 0.0 && dn >= lo && dn <= hi;
-    if (!newton) dn = 0.5 * (lo + hi);
+    const double den = 2.0 * df * df - f * d2f;
+    double dn = d - 2.0 * f * df / den;
+    const bool regular = df > 0.0 && den > 0.0 && dn >= lo && dn <= hi;
+    if (!regular) dn = 0.5 * (lo + hi);
     if (dn == d) break;
     const double step = fabs(dn - d);
     d = dn;
     if (done) break;
-    done = newton && (fabs(f) <= 1e-13 || step <= 1e-8 * (1.0 + fabs(d)));
+    done = regular && (fabs(f) <= 1e-13 || step <= 1e-8 * (1.0 + fabs(d)));
   }
   r.d = d;
   return d;
@@ -231,9 +238,9 @@ __device__ double face_flux(const GridArgs& g, const double* __restrict__ C, int
   const double big = fmax(a0, fmax(a1, a2)) * (1.0 - kAxisTol);
   r.a = a0 >= big ? 0 : (a1 >= big ? 1 : 2);
   solve_d(r, cu, beta);
-  double I, dI;
-  if (pos) box_integral(r, AX, 0.5 - xi, 0.5, beta, I, dI);
-  else box_integral(r, AX, -0.5, -0.5 + xi, beta, I, dI);
+  double I, dI, d2I;
+  if (pos) box_integral(r, AX, 0.5 - xi, 0.5, beta, I, dI, d2I);
+  else box_integral(r, AX, -0.5, -0.5 + xi, beta, I, dI, d2I);
   return sgn * h * I;
 }
 
