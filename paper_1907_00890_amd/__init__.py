@@ -346,11 +346,17 @@ class Plan:
 
     def autotune(self, batch: int = 1, stream=None) -> dict:
         """Time every candidate of each tuning key on this plan's workspace and keep
-        the fastest (see poisson_plan_autotune); returns the chosen values."""
+        the fastest (see poisson_plan_autotune); returns the chosen values, with the
+        z segment length that the autotuner picks together with z_lines."""
         chosen = (ctypes.c_int * 8)()
         check(_lib.lib.poisson_plan_autotune(self._h, int(batch), _stream_ptr(stream), chosen),
               "poisson_plan_autotune")
-        return dict(zip(self.AUTOTUNED_KEYS, list(chosen)))
+        out = dict(zip(self.AUTOTUNED_KEYS, list(chosen)))
+        v = ctypes.c_int(0)
+        check(_lib.lib.poisson_plan_get_tuning(self._h, b"z_segment", ctypes.byref(v)),
+              "poisson_plan_get_tuning")
+        out["z_segment"] = v.value
+        return out
 
     def set_profiling(self, enable=True, classes=None):
         """Bracket kernel launches of this plan with HIP events: every class when
