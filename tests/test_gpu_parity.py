@@ -653,11 +653,14 @@ def test_fused_step_batches_its_two_solves(torch_dev, prec):
 
 
 @pytest.mark.parametrize("case", [(32, 32, 256, "PPN", None), (16, 16, 300, "NNP", 1.5),
-                                  (16, 8, 512, "PPN", 1.3), (8, 8, 40, "NNNNND", None)],
+                                  (16, 8, 512, "PPN", 1.3), (8, 8, 40, "NNNNND", None),
+                                  (16, 16, 256, "PPP", 1.5)],
                          ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}{c[3]}")
 def test_z_segment_lengths(torch_dev, case):
-    """Segments of 8 or 16 rows in the partitioned z solve (a tuning knob):
-    both match the oracle."""
+    """Segments of 8 or 16 rows and 8, 16 or 32 lines per block in the
+    partitioned z solve (tuning knobs): every shape matches the oracle.  With
+    8-row segments and 32 lines a 256-long line takes a 1024-lane block; on a
+    periodic z line that block keeps one LDS buffer for the reduced system."""
     torch = torch_dev
     nx, ny, nz, bc, beta = case
     g = _grid(nx, ny, nz, bc, beta)
@@ -666,7 +669,11 @@ def test_z_segment_lengths(torch_dev, case):
     plan = _plan(g)
     plan.tune("z_spectral", 0) if plan.tuning()["z_spectral"] else None
     for seg in (8, 16):
-        plan.tune("z_segment", seg)
-        assert plan.tuning()["z_segment"] == seg
-        p = plan.solve(_dev(torch, f)).cpu().numpy()
-        assert rel_l2(p, ref) <= FP64_TOL, seg
+        for lines in (8, 16, 32):
+            plan.tune("z_segment", seg)
+            plan.tune("z_lines", lines)
+            assert plan.tuning()["z_segment"] == seg
+            p = plan.solve(_dev(torch, f)).cpu().numpy()
+            err = rel_l2(p, ref)
+            print(f"z segments {case} seg {seg} lines {lines}: {err:.3e}", flush=True)
+            assert err <= FP64_TOL, (seg, lines)
