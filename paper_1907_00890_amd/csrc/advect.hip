@@ -156,10 +156,12 @@ __device__ void box_integral(const Rec& r, int ax, double s0, double s1, double 
 // (bisection where a step leaves it or the Halley denominator is not
 // positive).  The volume error falls cubically from the first guess (about
 // 1e-2) to the rounding level of its O(10)-sized terms (a few 1e-15).  The
-// solve stops one step after the error is below 1e-13 or a step below
-// 1e-8 (1 + |d|), or when a step vanishes in rounding; a step landing on a
-// bracket end is a regular step (the end is the last iterate once the step
-// is below half an ulp), not a reason to bisect.
+// solve stops after the regular step taken from a volume error below 1e-13
+// or after a regular step below 1e-8 (1 + |d|): with cubic convergence that
+// step's result is already at the rounding level; or when a step vanishes in
+// rounding.  A step landing on a bracket end is a regular step (the end is
+// the last iterate once the step is below half an ulp), not a reason to
+// bisect.
 __device__ double solve_d(Rec& r, double C, double beta) {
 #pragma clang fp contract(off)
   const double ma = fabs(comp(r, r.a));
@@ -169,7 +171,6 @@ __device__ double solve_d(Rec& r, double C, double beta) {
   const double span = 2.0 + 25.0 / beta;
   double lo = -span, hi = span;
   if (!(d > lo && d < hi)) d = 0.0;
-  bool done = false;
   for (int it = 0; it < 40; ++it) {
     r.d = d;
     double f, df, d2f;
@@ -185,8 +186,7 @@ __device__ double solve_d(Rec& r, double C, double beta) {
     if (dn == d) break;
     const double step = fabs(dn - d);
     d = dn;
-    if (done) break;
-    done = regular && (fabs(f) <= 1e-13 || step <= 1e-8 * (1.0 + fabs(d)));
+    if (regular && (fabs(f) <= 1e-13 || step <= 1e-8 * (1.0 + fabs(d)))) break;
   }
   r.d = d;
   return d;
