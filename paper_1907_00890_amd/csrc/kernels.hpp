@@ -2,6 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "bc.hpp"
 #include "limits.hpp"
 
@@ -41,14 +45,27 @@ __device__ __forceinline__ double rcp64(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU (needed for
-// launches above 64 KB); done once per kernel instantiation.
+// Raise a kernel's dynamic-LDS limit to the 160 KB of a gfx950 CU (for
+// launches above 64 KB); done once per kernel and device (kernels of one
+// signature are distinct entries: the key is the kernel's address).
+inline hipError_t allow_large_lds_fn(const void* kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, hipError_t> done;
+  int dev = 0;
+  const hipError_t ge = hipGetDevice(&dev);
+  if (ge != hipSuccess) return ge;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dev, kernel);
+  const auto it = done.find(key);
+  if (it != done.end()) return it->second;
+  const hipError_t e =
+      hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  done.emplace(key, e);
+  return e;
+}
 template <typename K>
 inline hipError_t allow_large_lds(K* kernel) {
-  static hipError_t once = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               160 * 1024);
-  return once;
+  return allow_large_lds_fn(reinterpret_cast<const void*>(kernel));
 }
 
 // Up to kMaxBatch independent fields go through one launch of each pass: the
